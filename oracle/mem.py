@@ -15,9 +15,18 @@ fluid cell, CLI falls back to BB for that link.  Static-wall links always use BB
 with the wall velocity.
 
 Link force (Eq. MEM_Force, dx = dt = 1):
-  F^q = (c_q - v) f~_q(x, t) - (c_qbar - v) f_qbar(x, t+1) = (c_q - v) f~_q + (c_q + v) f_qbar,
-evaluated with the full PDFs f = w + g.  Totals, Eqs. MEM_TotForce/TotTorque:
-  F = sum F^q,  T = sum (x_b - X_p) x F^q.
+  F^q = (c_q - v) f~_q(x, t) - (c_qbar - v) f_qbar(x, t+1) = (c_q - v) f~_q + (c_q + v) f_qbar
+      = 2 w_q c_q + (c_q - v) g~_q + (c_q + v) g_qbar          (f = w + g, w_q = w_qbar).
+Totals, Eqs. MEM_TotForce/TotTorque: F = sum F^q, T = sum (x_b - X_p) x F^q.
+The constant part 2 w_q c_q sums to zero over the links of one closed body:
+every lattice line that enters the body along c_q leaves it along c_qbar, and
+both links lie on that line, so their constant forces cancel and so do their
+torques ((x_b - x'_b) is parallel to c_q).  The totals are therefore formed
+from the deviation part only, which keeps them accurate to the rounding of the
+deviations rather than of w_q.  This needs each body's solid run on every
+lattice line to be bounded by fluid cells (particles not in contact; the
+paper defines no contact model); ``check_link_balance`` verifies the
+necessary per-direction link balance.
 
 Refill (Sec. 2.2.3, Eq. MEM_Reconstruction).  Readings (parity unpinned where
 noted):
@@ -118,11 +127,18 @@ def link_boundary(gt, gn, L, scheme):
     cli = gtq + k0 * gt[q, L["bz"], L["by"], L["bx"]] - k0 * gt[qb, iz, iy, ix] - 3.0 * alpha * wq * vc
     val = np.where(use_cli, cli, bb)
     gn[qb, iz, iy, ix] = val
-    ft = wq + gtq
-    fn = W[qb] + val
-    Fq = (c - v) * ft[:, None] + (c + v) * fn[:, None]
+    Fq = (c - v) * gtq[:, None] + (c + v) * val[:, None]
     Tq = np.cross(arm, Fq)
     return Fq, Tq
+
+
+def check_link_balance(L, P):
+    """Per particle, the number of links along c_q equals that along c_qbar."""
+    for p in range(P):
+        qs = L["q"][L["p"] == p]
+        cnt = np.bincount(qs, minlength=19)
+        if not np.array_equal(cnt, cnt[OPP]):
+            raise ValueError("unbalanced links for particle %d: particles in contact are not supported" % p)
 
 
 def refill_cell(g, owner, newmask, cell, Xp, Up, Omp, fext, box_shape):

@@ -120,6 +120,8 @@ class OracleSim:
             self.overlaps = [geo.overlap_cells(self.shape, p["X"], p["D"] / 2.0, self.eps_n, self.eps_recursive)
                              for p in self.parts]
         self.links = mm.build_links(self.owner, self.parts, self._radii(), self.shape, self.v_walls)
+        if self.coupling.startswith("mem"):
+            mm.check_link_balance(self.links, len(self.parts))
 
     # --- sweeps -------------------------------------------------------------
     def _sweep_mem(self):

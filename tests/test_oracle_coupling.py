@@ -168,11 +168,20 @@ def test_mem_momentum_identity(scheme):
         assert np.abs((P1 - P0) - expect).max() < 1e-12 * np.abs(s.F[0]).max()
 
 
-def test_link_counts_balance():
-    s = _mem_sim("mem_cli")
-    q = s.links["q"]
-    for k in range(1, 19):
-        assert (q == k).sum() == (q == OPP[k]).sum()
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_constant_link_force_part_cancels(seed):
+    # the 2 w_q c_q part of Eq. MEM_Force cancels over a closed body: exactly for the
+    # force (integer link counts per direction), to rounding for the torque
+    rng = np.random.default_rng(seed)
+    s = _mem_sim("mem_cli", X=tuple(rng.uniform(6, 10, 3)), D=rng.uniform(4, 9))
+    L = s.links
+    cnt = np.bincount(L["q"], minlength=19)
+    assert np.array_equal(cnt, cnt[OPP])
+    c = CF[L["q"]]
+    const = 2.0 * W[L["q"]][:, None] * c
+    for delta in (np.full(len(L["q"]), 0.5), L["delta"]):
+        arm = L["d"] + delta[:, None] * c
+        assert np.abs(np.cross(arm, const).sum(0)).max() < 1e-13
 
 
 # --------------------------------------------------------------------------- refill
