@@ -1,10 +1,12 @@
 """Lattice Boltzmann fluid core (Sec. 2.1), FP64, in deviation variables.
 
-With g_q = f_q - w_q and sum_q w_q = 1, sum_q w_q c_q = 0:
-  rho_f = sum_q f_q = 1 + sum_q g_q,   U = sum_q f_q c_q / rho0 = sum_q g_q c_q.
+With g_q = f_q - w_q and sum_q w_q = 1, sum_q w_q c_q = 0, and the density
+written as rho_f = rho0 + drho_f (Sec. 2.1, rho0 = 1):
+  drho_f = sum_q g_q,   U = sum_q f_q c_q / rho0 = sum_q g_q c_q.
 Equilibrium (Eq. LBM_EQ, rho0 = 1, c_s^2 = 1/3):
-  f^eq_q = w_q (rho + 3 c.U + 9/2 (c.U)^2 - 3/2 U.U),  so
-  g^eq_q = f^eq_q - w_q = w_q (rho - 1 + 3 c.U + 9/2 (c.U)^2 - 3/2 U.U).
+  f^eq_q = w_q (rho0 + drho_f + 3 c.U + 9/2 (c.U)^2 - 3/2 U.U),  so
+  g^eq_q = f^eq_q - w_q = w_q (drho_f + 3 c.U + 9/2 (c.U)^2 - 3/2 U.U).
+The fluctuation drho_f is carried as its own variable (never through 1 + drho_f).
 Collision operators act on f - f^eq = g - g^eq, so they read identically in g.
 All arrays are g[q, z, y, x]; vectors are U[a, z, y, x] with a = 0 (x), 1 (y), 2 (z).
 """
@@ -14,19 +16,21 @@ from .lattice import CF, W, OPP, Q
 
 
 def moments(g):
-    """Density and velocity moments (the moment definitions after Eq. LBM_EQ)."""
-    rho = 1.0 + g.sum(axis=0)
+    """Density fluctuation drho_f = rho_f - rho0 and velocity U (the moment
+    definitions after Eq. LBM_EQ)."""
+    drho = g.sum(axis=0)
     U = np.tensordot(CF.T, g, axes=([1], [0]))  # (3, ...)
-    return rho, U
+    return drho, U
 
 
-def geq(rho, U, cu=None):
-    """Deviation of the incompressible equilibrium, Eq. LBM_EQ, from w_q."""
+def geq(drho, U, cu=None):
+    """Deviation of the incompressible equilibrium, Eq. LBM_EQ, from w_q, as a
+    function of the density fluctuation drho_f and the velocity U."""
     if cu is None:
         cu = np.tensordot(CF, U, axes=([1], [0]))  # (19, ...)
     uu = (U * U).sum(axis=0)
     wq = W.reshape((Q,) + (1,) * (cu.ndim - 1))
-    return wq * ((rho - 1.0 - 1.5 * uu) + cu * (3.0 + 4.5 * cu))
+    return wq * ((drho - 1.5 * uu) + cu * (3.0 + 4.5 * cu))
 
 
 def forcing(U, fext, cu=None):
@@ -60,9 +64,9 @@ def trt_rates(tau, magic):
 def collide_bgk(g, tau, fext):
     """Eq. LBM_Collide with the BGK operator, Eq. LBM_SRT:
     f~ = f + (f^eq - f)/tau + F."""
-    rho, U = moments(g)
+    drho, U = moments(g)
     cu = np.tensordot(CF, U, axes=([1], [0]))
-    return g + (geq(rho, U, cu) - g) / tau + forcing(U, fext, cu)
+    return g + (geq(drho, U, cu) - g) / tau + forcing(U, fext, cu)
 
 
 def collide_trt(g, lam_p, lam_m, fext):
@@ -71,18 +75,18 @@ def collide_trt(g, lam_p, lam_m, fext):
     with f^+- = (f_q +- f_qbar)/2.  Since w_q = w_qbar, f - f^eq = g - g^eq and
     the split reads the same in g:  with n = g - g^eq,
     lambda_+ n^+ + lambda_- n^- = (lambda_+ + lambda_-)/2 n_q + (lambda_+ - lambda_-)/2 n_qbar."""
-    rho, U = moments(g)
+    drho, U = moments(g)
     cu = np.tensordot(CF, U, axes=([1], [0]))
-    n = g - geq(rho, U, cu)
+    n = g - geq(drho, U, cu)
     c = (0.5 * (lam_p + lam_m)) * n + (0.5 * (lam_p - lam_m)) * n[OPP]
     return g + c + forcing(U, fext, cu)
 
 
-def fluid_operator(g, rho, U, collision, tau, magic):
+def fluid_operator(g, drho, U, collision, tau, magic):
     """The collision operator C_q alone (no forcing): BGK, Eq. LBM_SRT, or TRT,
     Eq. MEM_TRT (same arithmetic as ``collide_bgk`` / ``collide_trt``).  Used as
     the fluid part of the PSM operator, Eq. PSM."""
-    ge = geq(rho, U)
+    ge = geq(drho, U)
     if collision == "bgk":
         return (ge - g) / tau
     lam_p, lam_m = trt_rates(tau, magic)

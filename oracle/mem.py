@@ -36,7 +36,8 @@ noted):
 * sources x + k c_qn (k = 1, 2, 3) must be fluid cells that were fluid before
   the remap; with three: 3 f1 - 3 f2 + f3, with two: 2 f1 - f2, with one: f1,
   with none: f^eq(rho_bar, v(x)) where rho_bar is the mean density of the old-fluid
-  neighbours among the 18 directions (1 if there are none) -- parity unpinned;
+  neighbours among the 18 directions (rho0 if there are none; carried as the
+  mean fluctuation) -- parity unpinned;
 * velocity constraint: in the orthogonal D3Q19 moment basis the momentum rows
   are c_qa with norm sum_q c_qa^2 = 10, so f_q += c_q.(j* - j)/10 sets the
   momentum j = sum f c to j* and leaves every other orthogonal moment unchanged;
@@ -175,14 +176,14 @@ def refill_cell(g, owner, newmask, cell, Xp, Up, Omp, fext, box_shape):
     elif len(src) == 1:
         out = src[0].copy()
     else:
-        rhos = []
+        drhos = []
         for q in range(1, 19):
             c = C[q]
             z, y, x = (iz + c[2]) % nz, (iy + c[1]) % ny, (ix + c[0]) % nx
             if ok(z, y, x):
-                rhos.append(1.0 + g[:, z, y, x].sum())
-        rho_bar = float(np.mean(rhos)) if rhos else 1.0
-        out = geq(np.array(rho_bar), v.reshape(3))
+                drhos.append(g[:, z, y, x].sum())
+        drho_bar = float(np.mean(drhos)) if drhos else 0.0
+        out = geq(np.array(drho_bar), v.reshape(3))
     j = CF.T @ out
     jstar = v - 0.5 * np.asarray(fext, dtype=np.float64)
     out = out + (CF @ (jstar - j)) / 10.0

@@ -1,6 +1,7 @@
 """Partially saturated cells method (Sec. 2.3), FP64, in deviation variables.
 
-Solid collision operators (Eqs. PSM_M1..M3), with rho = rho_f of the cell and
+Solid collision operators (Eqs. PSM_M1..M3), with rho = rho_f of the cell
+(carried as drho_f, see ``fluid``) and
 v_s the particle surface velocity (Eq. bodyVelocity) at the cell centre; since
 w_q = w_qbar every bracket f - f^eq equals g - g^eq:
   M1: Omega_q = [f_qbar - f^eq_qbar(rho,U)] - [f_q - f^eq_q(rho,v_s)]
@@ -30,10 +31,10 @@ def weight(eps, tau, bsel):
     return eps * t / ((1.0 - eps) + t)
 
 
-def solid_operator(gc, rho, U, vs, tau, msel):
-    """Omega for cells given as columns: gc (19, n), rho (n,), U (3, n), vs (3, n)."""
-    ge_u = geq(rho, U)
-    ge_v = geq(rho, vs)
+def solid_operator(gc, drho, U, vs, tau, msel):
+    """Omega for cells given as columns: gc (19, n), drho (n,), U (3, n), vs (3, n)."""
+    ge_u = geq(drho, U)
+    ge_v = geq(drho, vs)
     if msel == 1:
         return (gc[OPP] - ge_u[OPP]) - (gc - ge_v)
     if msel == 2:
@@ -51,8 +52,8 @@ def psm_collide(g, overlaps, parts, collision, tau, magic, fext, msel, bsel):
     Returns (g_post, F (P,3), T (P,3), Bfield, sum_s B_s v_s field)."""
     shape = g.shape[1:]
     nz, ny, nx = shape
-    rho, U = moments(g)
-    Cf = fluid_operator(g, rho, U, collision, tau, magic)
+    drho, U = moments(g)
+    Cf = fluid_operator(g, drho, U, collision, tau, magic)
     Fq = forcing(U, fext)
 
     Braw = np.zeros(shape)
@@ -78,7 +79,7 @@ def psm_collide(g, overlaps, parts, collision, tau, magic, fext, msel, bsel):
                       centre_disp(iz, p["X"][2], nz)], axis=-1)  # (n, 3) = x_s - X_p
         vs = surface_velocity(p["U"], p["Om"], r).T  # (3, n)
         gc = g[:, iz, iy, ix]
-        om = solid_operator(gc, rho[iz, iy, ix], U[:, iz, iy, ix], vs, tau, msel)
+        om = solid_operator(gc, drho[iz, iy, ix], U[:, iz, iy, ix], vs, tau, msel)
         np.add.at(B, (iz, iy, ix), Bs)
         for q in range(19):
             np.add.at(solid_sum[q], (iz, iy, ix), Bs * om[q])

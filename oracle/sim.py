@@ -59,7 +59,7 @@ class OracleSim:
     # --- set-up -------------------------------------------------------------
     def init_equilibrium(self, rho=1.0, u=(0.0, 0.0, 0.0)):
         U = np.asarray(u, dtype=np.float64).reshape(3, 1, 1, 1) * np.ones((3,) + self.shape)
-        self.g = fl.geq(np.full(self.shape, float(rho)), U)
+        self.g = fl.geq(np.full(self.shape, float(rho) - 1.0), U)
         self._mask_solid()
 
     def set_pdfs(self, g):
@@ -204,7 +204,8 @@ class OracleSim:
     def fields(self):
         """Density and macroscopic velocity: Eq. MacVel in fluid cells, zero in
         solid MEM cells, Eq. MacVel_PSM with the current solid fractions for PSM."""
-        rho, U = fl.moments(self.g)
+        drho, U = fl.moments(self.g)
+        rho = 1.0 + drho
         if self.coupling == "psm":
             # B and sum B_s v_s at the current time level
             _, _, _, B, vB = ps.psm_collide(self.g, self.overlaps, self.parts, self.collision, self.tau, self.magic,

@@ -1,0 +1,72 @@
+"""The C-ABI library loads and exports every entry point declared in
+include/lbmps.h; pure (non-GPU) calls behave as documented."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1702_04910_amd import lbmps
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    txt = open(os.path.join(ROOT, "include", "lbmps.h")).read()
+    return sorted(set(re.findall(r"\b(lbmps_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = lbmps.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_velocity_table():
+    c = lbmps.velocities()
+    assert c.shape == (19, 3) and (c[0] == 0).all()
+    for q in range(1, 19, 2):
+        assert (c[q] == -c[q + 1]).all()
+    assert sorted((c * c).sum(1).tolist()) == [0] + [1] * 6 + [2] * 12
+
+
+def test_workspace_bytes_valid_and_invalid():
+    cfg = lbmps.make_config(32, 32, 64, 0.1, coupling="psm", max_particles=1, max_diameter=8.0)
+    n = lbmps.workspace_bytes(cfg)
+    # two PDF buffers of 19 doubles per cell at least
+    assert n >= 2 * 19 * 8 * 32 * 32 * 64
+    f32 = lbmps.workspace_bytes(lbmps.make_config(32, 32, 64, 0.1, precision="fp32"))
+    f16 = lbmps.workspace_bytes(lbmps.make_config(32, 32, 64, 0.1, precision="fp16"))
+    assert f16 < f32 < n
+    bad = [
+        lbmps.make_config(0, 32, 64, 0.1),
+        lbmps.make_config(32, 32, 64, -0.1),
+        lbmps.make_config(32, 32, 64, 0.1, coupling="psm", psm_m=4),
+        lbmps.make_config(32, 32, 64, 0.1, max_particles=1, max_diameter=30.0),
+        lbmps.make_config(32, 32, 64, 0.1, eps_n=6, eps_mode=lbmps.EPS_RECURSIVE),
+        lbmps.make_config(32, 32, 64, 0.1, block_threads=100),
+        lbmps.make_config(32, 32, 64, 0.1, coupling="psm", n_sub=2),
+    ]
+    for b in bad:
+        assert lbmps.workspace_bytes(b) == 0
+
+
+def test_batch_rules():
+    a = lbmps.make_config(24, 24, 48, 0.05, coupling="mem_cli", precision="fp32", max_particles=1, max_diameter=8)
+    b = lbmps.make_config(36, 36, 72, 0.05, coupling="psm", psm_m=3, psm_b=2, precision="fp32", max_particles=1,
+                          max_diameter=12)
+    assert lbmps.workspace_bytes([a, b]) > lbmps.workspace_bytes(b)
+    c = lbmps.make_config(24, 24, 48, 0.05, precision="fp64")
+    assert lbmps.workspace_bytes([a, c]) == 0  # mixed precision in one batch
+
+
+def test_create_rejects_small_workspace():
+    L = lbmps.lib()
+    cfg = lbmps.make_config(8, 8, 8, 0.1)
+    ctx = ctypes.c_void_p()
+    st = L.lbmps_create(ctypes.addressof(cfg), None, 0, None, ctypes.byref(ctx))
+    assert st == -2 and not ctx.value
+    assert L.lbmps_status_string(-4) == b"numerical instability"

@@ -144,7 +144,7 @@ def test_cli_at_half_delta_is_bounce_back_bitwise():
 def test_comoving_uniform_flow_is_fixed_point(scheme):
     V = np.array([0.02, -0.01, 0.015])
     s = _mem_sim(scheme, fext=(0, 0, 0), U=V)
-    g0 = fl.geq(np.ones(s.shape), V.reshape(3, 1, 1, 1) * np.ones((3,) + s.shape))
+    g0 = fl.geq(np.zeros(s.shape), V.reshape(3, 1, 1, 1) * np.ones((3,) + s.shape))
     s.set_pdfs(g0)
     fluid = s.owner == mm.FLUID
     s.step(4)
@@ -287,7 +287,7 @@ def test_psm_force_torque_closed_form(m, b):
 def test_psm_comoving_uniform_flow_is_fixed_point(m, b):
     V = np.array([0.02, 0.01, -0.01])
     s = _psm_sim(m, b, U=V, fext=(0, 0, 0))
-    g0 = fl.geq(np.ones(s.shape), V.reshape(3, 1, 1, 1) * np.ones((3,) + s.shape))
+    g0 = fl.geq(np.zeros(s.shape), V.reshape(3, 1, 1, 1) * np.ones((3,) + s.shape))
     s.set_pdfs(g0)
     s.step(2)
     assert np.abs(s.g - g0).max() < 1e-17
