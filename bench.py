@@ -1,0 +1,184 @@
+#!/usr/bin/env python3
+"""Throughput of the lattice Boltzmann particle-coupling hot path on one MI355X.
+
+Workload (default): one settling sphere, D = 24 cells, in a 192x192x384
+periodic box (14.16 M cells), density ratio and Galileo number from seed 0,
+nu = 0.01, TRT (Lambda = 3/16), momentum exchange with CLI links and refill,
+two LBM sweeps per rigid-body step, PDFs stored as FP32 deviations.  A bench
+"step" is one rigid-body step: two fused collide-push sweeps over the box, the
+link rule and link forces, the force/torque reduction, the rigid-body update,
+the remap with refill and the rebuild of the link list.
+
+Printed (one JSON line): whole-job MLUPS (cells x sweeps / s), the sweep
+kernel's achieved HBM bandwidth (algorithmic bytes 2*19*s per cell, averaged
+over HIP-event-timed launches inside the timed region) against the 8 TB/s
+peak, the other storage forms and couplings with their sphere-velocity and
+force error against the FP64 run, and the FP64 CPU oracle timed on a bounded
+sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS + % HBM roofline; FP16-storage/batched vs FP32 at stated velocity error"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_sim(lbmps, inp, coupling, precision, psm=(3, 2), eps_n=8, **launch):
+    cfg = lbmps.make_config(inp["nx"], inp["ny"], inp["nz"], inp["nu"], collision="trt", coupling=coupling,
+                            psm_m=psm[0], psm_b=psm[1], eps_n=eps_n, eps_mode=lbmps.EPS_RECURSIVE,
+                            precision=precision, max_particles=1, max_diameter=inp["D"], f_ext=inp["f_ext"],
+                            gravity=inp["gravity"], **launch)
+    sim = lbmps.Sim(cfg)
+    sim.init_equilibrium()
+    sim.set_particles([inp["X"]], [[0, 0, 0]], [[0, 0, 0]], [inp["D"]], [inp["rho"]], [False])
+    return sim
+
+
+def timed_run(torch, sim, steps, warmup, n_sub, timing=True):
+    sim.step(warmup * n_sub)
+    sim.sync()
+    torch.cuda.synchronize()
+    sim.set_timing(timing)
+    t0 = time.perf_counter()
+    sim.step(steps * n_sub)
+    sim.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms, launches = sim.timing() if timing else (0.0, 0)
+    sim.set_timing(False)
+    return t1 - t0, ms, launches
+
+
+def cpu_baseline(inp, steps=30):
+    """The FP64 oracle on a sub-box of the same workload (same sphere
+    resolution, half the box in each horizontal direction)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    from oracle.sim import OracleSim
+
+    nx, ny, nz = inp["nx"] // 2, inp["ny"] // 2, inp["nz"] // 2
+    with threadpool_limits(limits=1):
+        s = OracleSim(nx, ny, nz, inp["nu"], collision="trt", coupling="mem_cli", fext=inp["f_ext"],
+                      gravity=inp["gravity"])
+        s.init_equilibrium()
+        X = np.array([nx / 2.0, ny / 2.0, nz * 0.75]) + (np.asarray(inp["X"]) - np.array(
+            [inp["nx"] / 2.0, inp["ny"] / 2.0, inp["nz"] * 0.75]))
+        s.set_particles([X], [[0, 0, 0]], [[0, 0, 0]], [inp["D"]], [inp["rho"]], [False])
+        s.step(2)
+        t0 = time.perf_counter()
+        s.step(steps)
+        dt = time.perf_counter() - t0
+    cells = nx * ny * nz
+    return {"value": round(cells * steps / dt / 1e6, 3), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+            "sample": "FP64 numpy oracle, MEM-CLI TRT settling sphere D=%g in a %dx%dx%d sub-box, %d sweeps (%.1f s)"
+                      % (inp["D"], nx, ny, nz, steps, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200, help="timed rigid-body steps (2 sweeps each)")
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-forms", action="store_true", help="only the primary FP32 MEM-CLI run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1702_04910_amd import inputs, lbmps
+
+    inp = inputs.c2_scale(args.seed)
+    N = inp["nx"] * inp["ny"] * inp["nz"]
+    n_sub = 2
+
+    # ---- primary: FP32 MEM-CLI
+    log("primary: c2 FP32 MEM-CLI")
+    sim = build_sim(lbmps, inp, "mem_cli", "fp32")
+    wall, ms, launches = timed_run(torch, sim, args.steps, args.warmup, n_sub)
+    sweeps = args.steps * n_sub
+    mlups = N * sweeps / wall / 1e6
+    sweep_s = ms / 1e3 / launches
+    alg_bytes = 2 * 19 * 4 * N
+    achieved = alg_bytes / sweep_s / 1e9
+    p32 = sim.particles()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+
+    line = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "settling sphere, 192x192x384 periodic, D=24, MEM-CLI, TRT, FP32 deviation storage",
+                   "cells": N, "sweeps_per_step": n_sub, "rho_p": round(inp["rho"], 4), "Re_target": round(inp["re"], 2),
+                   "Ga": round(inp["ga"], 3), "nu": inp["nu"], "seed": args.seed},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "sweep_kernel<float>", "alg_bytes_per_launch": alg_bytes,
+                     "avg_launch_us": round(sweep_s * 1e6, 2), "launches": launches},
+    }
+
+    # ---- storage forms and couplings against the FP64 run
+    if not args.no_forms:
+        forms = {}
+        ref = None
+        for name, coupling, prec in [("fp64_mem_cli", "mem_cli", "fp64"), ("fp32_mem_cli", "mem_cli", "fp32"),
+                                     ("fp16_mem_cli", "mem_cli", "fp16"), ("bf16_mem_cli", "mem_cli", "bf16"),
+                                     ("fp32_mem_bb", "mem_bb", "fp32"), ("fp32_psm_m3b2", "psm", "fp32"),
+                                     ("fp64_psm_m3b2", "psm", "fp64"), ("fp16_psm_m3b2", "psm", "fp16")]:
+            log("form", name)
+            s = build_sim(lbmps, inp, coupling, prec)
+            ns = n_sub if coupling.startswith("mem") else 1
+            steps = args.steps * n_sub // ns
+            w, ms_f, l_f = timed_run(torch, s, steps, args.warmup * n_sub // ns, ns)
+            pf = s.particles()
+            s.close()
+            del s
+            torch.cuda.empty_cache()
+            sb = lbmps.STORAGE_BYTES[lbmps.PRECISION[prec]]
+            ent = {"MLUPS": round(N * steps * ns / w / 1e6, 1),
+                   "sweep_GBs": round(2 * 19 * sb * N / (ms_f / 1e3 / l_f) / 1e9, 1),
+                   "U_p": [float(v) for v in pf["U"][0]], "F": [float(v) for v in pf["F"][0]]}
+            forms[name] = (ent, pf, coupling)
+        out = {}
+        for name, (ent, pf, coupling) in forms.items():
+            refname = "fp64_mem_cli" if coupling.startswith("mem") else "fp64_psm_m3b2"
+            if refname in forms and coupling == forms[refname][2]:
+                r = forms[refname][1]
+                ent["velocity_error_vs_fp64"] = float(np.linalg.norm(pf["U"][0] - r["U"][0]) / np.linalg.norm(r["U"][0]))
+                ent["force_error_vs_fp64"] = float(np.linalg.norm(pf["F"][0] - r["F"][0]) / np.linalg.norm(r["F"][0]))
+            out[name] = ent
+        line["forms"] = out
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        line["cpu_baseline"] = cpu_baseline(inp)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,194 @@
+/*
+ * lbmps -- lattice Boltzmann particle suspensions on one AMD MI355X (gfx950).
+ *
+ * C-ABI of the hot path of Rettinger & Ruede, "A comparative study of
+ * fluid-particle coupling methods for fully resolved lattice Boltzmann
+ * simulations" (arXiv:1702.04910): the D3Q19 stream-collide sweep (Sec. 2.1)
+ * coupled to rigid spheres by the momentum exchange method (Sec. 2.2: BB,
+ * CLI, refill) or the partially saturated cells method (Sec. 2.3: M1B1, M2B2,
+ * M3B2), the per-particle force/torque reduction and the explicit Euler
+ * rigid-body update (Sec. 4.1).
+ *
+ * Conventions
+ *  - Lattice units: dx = dt = rho0 = 1, c_s^2 = 1/3 (Sec. 2.1).  The box is
+ *    periodic in x, y and z; cell (i, j, k) has its centre at (i+1/2, j+1/2, k+1/2).
+ *  - Velocity order q = 0..18 (see lbmps_velocities): rest, then opposite pairs
+ *    (q odd, q + 1).  Weights 1/3, 1/18 (axis), 1/36 (diagonal).
+ *  - Host PDF arrays hold deviations g_q = f_q - w_q, FP64, index
+ *    [q][z][y][x] (x fastest), i.e. g[q*N + (z*ny + y)*nx + x], N = nx*ny*nz.
+ *    They are the canonical PDFs f(x, t): after streaming and boundary
+ *    handling, before collision.  Solid MEM cells and wall cells read as 0.
+ *  - Vectors are (x, y, z).  Host field arrays: rho[N], u[3][N].
+ *  - Device memory: the library allocates none.  The caller passes one device
+ *    workspace of at least lbmps_workspace_bytes() bytes (e.g. a torch uint8
+ *    CUDA tensor) that must outlive the context, and a hipStream_t on which
+ *    every kernel and copy is enqueued.  Host buffers are caller-owned and are
+ *    copied before the call returns.
+ *  - Calls on one context are not thread-safe; distinct contexts are
+ *    independent.  No C++ exception crosses this interface.
+ *  - Errors: every call returns an lbmps_status; lbmps_last_error() gives the
+ *    message of the last failure on that context.  Device-side conditions
+ *    (capacity overflow, instability) are detected asynchronously and reported
+ *    by the next synchronising call (get_*, lbmps_sync).
+ */
+#ifndef LBMPS_H
+#define LBMPS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lbmps_status;
+#define LBMPS_OK 0
+#define LBMPS_EINVAL (-1)       /* invalid argument or configuration */
+#define LBMPS_ENOMEM (-2)       /* workspace too small or a list capacity exceeded */
+#define LBMPS_EDEVICE (-3)      /* HIP runtime error */
+#define LBMPS_EUNSTABLE (-4)    /* non-finite force/velocity or a particle moving >= 1 cell per rigid-body step */
+#define LBMPS_ESTATE (-5)       /* call out of order */
+#define LBMPS_EUNSUPPORTED (-6) /* feature not available in this build */
+
+/* collision operator of the fluid (Eq. LBM_SRT / Eq. MEM_TRT) */
+#define LBMPS_BGK 0
+#define LBMPS_TRT 1
+/* coupling (Sec. 2.2 / Sec. 2.3) */
+#define LBMPS_NONE 0
+#define LBMPS_MEM_BB 1  /* momentum exchange, bounce-back, Eq. MEM_BB */
+#define LBMPS_MEM_CLI 2 /* momentum exchange, central linear interpolation, Eq. MEM_CLI */
+#define LBMPS_PSM 3     /* partially saturated cells, Eq. PSM with psm_m, psm_b */
+/* PDF storage precision (compute is FP64 for FP64 storage, FP32 otherwise) */
+#define LBMPS_FP64 0
+#define LBMPS_FP32 1
+#define LBMPS_FP16_DEV 2 /* IEEE half deviations g = f - w, round to nearest even */
+#define LBMPS_BF16_DEV 3 /* bfloat16 deviations g = f - w, round to nearest even */
+/* solid-fraction estimator (Sec. 2.3.2) */
+#define LBMPS_EPS_FLAT 0      /* eps_n^3 sub-cell sample points, every point tested */
+#define LBMPS_EPS_RECURSIVE 1 /* same points, octree blocks classified at once (eps_n power of 2) */
+
+typedef struct lbmps_config {
+  int32_t nx, ny, nz;  /* periodic box (cells) */
+  int32_t collision;   /* LBMPS_BGK or LBMPS_TRT */
+  int32_t coupling;    /* LBMPS_NONE, LBMPS_MEM_BB, LBMPS_MEM_CLI, LBMPS_PSM */
+  int32_t psm_m;       /* 1, 2, 3: solid operator, Eqs. PSM_M1..M3 */
+  int32_t psm_b;       /* 1, 2: weighting, Eqs. PSM_B1, PSM_B2 */
+  int32_t n_sub;       /* LBM sweeps per rigid-body step; 0 = 2 for MEM (Sec. 2.2.4), 1 otherwise */
+  int32_t eps_n;       /* supersampling points per axis (default 8) */
+  int32_t eps_mode;    /* LBMPS_EPS_FLAT or LBMPS_EPS_RECURSIVE */
+  int32_t precision;   /* LBMPS_FP64 .. LBMPS_BF16_DEV */
+  int32_t max_particles;
+  int32_t tile_rows;     /* x-rows per sweep workgroup (0 = automatic) */
+  int32_t block_threads; /* sweep workgroup size, <= 256 (0 = 256) */
+  int32_t grid_blocks;   /* sweep workgroups; 0 = one per tile, > 0 = persistent grid of that size */
+  int32_t wall_link_cap; /* capacity of static-wall links (0 = automatic) */
+  double max_diameter;   /* largest particle diameter that will be set (cells) */
+  double nu;             /* kinematic viscosity, nu = (tau - 1/2)/3 (Eq. Viscosity) */
+  double magic;          /* TRT parameter Lambda (default 3/16 when 0) */
+  double f_ext[3];       /* body force density (Eq. Forcing) */
+  double gravity[3];     /* gravitational acceleration acting on (rho_p - 1) V of each particle */
+} lbmps_config;
+
+typedef struct lbmps_particle {
+  double X[3];     /* centre */
+  double U[3];     /* translational velocity */
+  double Omega[3]; /* angular velocity */
+  double D;        /* diameter (cells) */
+  double rho_p;    /* density (fluid density is 1) */
+  int32_t fixed;   /* 1: held in place (no rigid-body update) */
+  int32_t pad;
+} lbmps_particle;
+
+typedef struct lbmps_particle_state {
+  double F[3];     /* hydrodynamic force of the last rigid-body step, averaged over its n_sub sweeps */
+  double T[3];     /* hydrodynamic torque, same averaging */
+  double U[3], Omega[3], X[3];
+} lbmps_particle_state;
+
+typedef struct lbmps_ctx lbmps_ctx;
+
+/* Velocity table of the library's q order: c[q][0..2]. */
+void lbmps_velocities(int32_t c[19][3]);
+
+/* Bytes of device workspace needed by one instance / a batch of n instances.
+ * Pure; returns 0 for an invalid configuration. */
+size_t lbmps_workspace_bytes(const lbmps_config* cfg);
+size_t lbmps_batch_workspace_bytes(int32_t n, const lbmps_config* cfgs);
+
+/* Create a context for one instance (lbmps_create) or for n independent
+ * instances advanced together by every lbmps_step (lbmps_batch_create; all
+ * instances share the storage precision; MEM instances share n_sub).
+ * dev_workspace: caller-owned device memory of `bytes` >= the size above.
+ * hip_stream: a hipStream_t (may be NULL for the default stream).
+ * Errors: EINVAL (config), ENOMEM (workspace too small), EDEVICE. */
+lbmps_status lbmps_create(const lbmps_config* cfg, void* dev_workspace, size_t bytes, void* hip_stream,
+                          lbmps_ctx** out);
+lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* dev_workspace, size_t bytes,
+                                void* hip_stream, lbmps_ctx** out);
+void lbmps_destroy(lbmps_ctx* ctx);
+
+/* Set every fluid cell of instance `inst` (0 for lbmps_create contexts) to the
+ * equilibrium f^eq(rho, u) of Eq. LBM_EQ.  Asynchronous. */
+lbmps_status lbmps_init_equilibrium(lbmps_ctx* ctx, int32_t inst, double rho, const double u[3]);
+
+/* Mark the cells with host_mask[cell] != 0 as one group of static wall cells
+ * moving with v_wall, handled by half-way bounce-back (Eq. MEM_BB).  Call
+ * before lbmps_set_particles.  Up to 16 groups per instance.
+ * Errors: EINVAL, ENOMEM (wall_link_cap exceeded). */
+lbmps_status lbmps_set_static_solid(lbmps_ctx* ctx, int32_t inst, const uint8_t* host_mask, const double v_wall[3]);
+
+/* Replace the particles of instance `inst` (n <= max_particles) and map them
+ * into the lattice (MEM: solid cells and links; PSM: solid fractions).
+ * Positions are wrapped into the box.  Particles must not touch each other
+ * (there is no contact model).
+ * Errors: EINVAL if n > max_particles, D <= 0, D > max_diameter,
+ * D + 6 > min(nx, ny, nz), rho_p <= 0 or any value is non-finite. */
+lbmps_status lbmps_set_particles(lbmps_ctx* ctx, int32_t inst, int32_t n, const lbmps_particle* host);
+
+/* Advance every instance by n_steps LBM time steps (Alg. 1 / Alg. 2); for MEM
+ * instances n_steps must be a multiple of n_sub.  Asynchronous. */
+lbmps_status lbmps_step(lbmps_ctx* ctx, int32_t n_steps);
+
+/* Block until the stream is idle; report device-side errors. */
+lbmps_status lbmps_sync(lbmps_ctx* ctx);
+
+/* Particle state of instance `inst` (n must equal the number set).  Synchronising. */
+lbmps_status lbmps_get_particles(lbmps_ctx* ctx, int32_t inst, int32_t n, lbmps_particle_state* host);
+
+/* rho[N] and u[3][N] of instance `inst`: Eq. MacVel in fluid cells, Eq. MacVel_PSM
+ * in cells overlapped by PSM particles, rho = 1, u = 0 in solid MEM and wall
+ * cells.  Synchronising. */
+lbmps_status lbmps_get_fields(lbmps_ctx* ctx, int32_t inst, double* rho, double* u);
+
+/* Canonical PDF deviations of instance `inst` (19*N doubles, layout above).
+ * get: solid and wall cells read 0.  set: overwrites every cell.  Synchronising. */
+lbmps_status lbmps_get_pdfs(lbmps_ctx* ctx, int32_t inst, double* host_g);
+lbmps_status lbmps_set_pdfs(lbmps_ctx* ctx, int32_t inst, const double* host_g);
+
+/* Current boundary links (MEM) of all instances: cell index, q (x + c_q is
+ * solid), particle (global index) and delta_q; n_out receives the count.
+ * Writes at most cap entries.  Synchronising. */
+lbmps_status lbmps_get_links(lbmps_ctx* ctx, int64_t cap, int32_t* cell, int32_t* q, int32_t* particle,
+                             double* delta, int64_t* n_out);
+/* Current PSM overlaps of all instances: cell, particle (global index), eps_s. */
+lbmps_status lbmps_get_overlaps(lbmps_ctx* ctx, int64_t cap, int32_t* cell, int32_t* particle, double* eps,
+                                int64_t* n_out);
+
+/* Measurement hook: when enabled, every sweep-kernel launch of lbmps_step is
+ * bracketed by HIP events recorded on the context's stream.  set_timing resets
+ * the totals; get_timing synchronises and returns the summed kernel time (ms)
+ * and the number of launches timed. */
+lbmps_status lbmps_set_timing(lbmps_ctx* ctx, int32_t enable);
+lbmps_status lbmps_get_timing(lbmps_ctx* ctx, double* sweep_ms, int64_t* launches);
+
+/* Global index of particle 0 of instance `inst`. */
+int32_t lbmps_particle_base(const lbmps_ctx* ctx, int32_t inst);
+
+const char* lbmps_status_string(lbmps_status s);
+const char* lbmps_last_error(const lbmps_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMPS_H */

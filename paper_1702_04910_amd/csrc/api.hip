@@ -1,0 +1,896 @@
+// C-ABI layer of lbmps: workspace layout, validation, and the host-side
+// schedule of one LBM time step (Alg. 1 for MEM, Alg. 2 for PSM):
+//
+//   sweep (collide + push, every instance)            -- sweep.hip
+//   PSM overlapped cells: solid operator, re-push      -- psm.hip
+//   link rule + link force (MEM particles, walls)      -- mem.hip
+//   per-particle force/torque sums                      -- particles.hip
+//   every n_sub sweeps: rigid-body step, then remap with refill and new links
+//   (MEM) / new solid fractions (PSM).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbmps.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace lbm;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+size_t storage_size(int prec) {
+  switch (prec) {
+    case PREC_FP64: return 8;
+    case PREC_FP32: return 4;
+    case PREC_FP16:
+    case PREC_BF16: return 2;
+  }
+  return 0;
+}
+
+struct Layout {
+  bool ok = false;
+  std::string err;
+  int n = 0, prec = 0, side = 0, ptotal = 0, mem_nsub = 0;
+  size_t ssz = 0;
+  std::vector<long long> pdf_off, owner_off, cellmap_off, ncell;
+  std::vector<int> part_begin;
+  long long pdf_elems = 0, owner_elems = 0, cellmap_elems = 0;
+  int link_cap = 0, wall_cap = 0, pair_cap = 0, refill_cap = 0;
+  long long slot_elems = 0;
+  int box_total = 0;  // ptotal * side
+  long long chunk = 0;
+  // byte offsets
+  size_t o_bufA, o_bufB, o_owner, o_cellmap, o_inst, o_parts, o_plists, o_slots, o_totals, o_offsets, o_ranges,
+      o_counts, o_links, o_wallv, o_pairs, o_refill, o_scratch, o_tiles, total;
+  int ntiles = 0;
+};
+
+bool valid_cfg(const lbmps_config& c, std::string& err) {
+  if (c.nx < 1 || c.ny < 1 || c.nz < 1) { err = "box dimensions must be positive"; return false; }
+  if ((long long)c.nx * c.ny * c.nz >= (1LL << 31)) { err = "box too large (>= 2^31 cells)"; return false; }
+  if (c.collision != LBMPS_BGK && c.collision != LBMPS_TRT) { err = "collision must be BGK or TRT"; return false; }
+  if (c.coupling < LBMPS_NONE || c.coupling > LBMPS_PSM) { err = "unknown coupling"; return false; }
+  if (c.coupling == LBMPS_PSM && (c.psm_m < 1 || c.psm_m > 3 || c.psm_b < 1 || c.psm_b > 2)) {
+    err = "psm_m must be 1..3 and psm_b 1..2"; return false;
+  }
+  if (c.precision < LBMPS_FP64 || c.precision > LBMPS_BF16_DEV) { err = "unknown precision"; return false; }
+  if (!(c.nu > 0.0) || !std::isfinite(c.nu)) { err = "nu must be positive"; return false; }
+  if (c.max_particles < 0) { err = "max_particles must be >= 0"; return false; }
+  if (c.max_particles > 0 && !(c.max_diameter > 0.0)) { err = "max_diameter must be positive"; return false; }
+  if (c.max_particles > 0 && c.max_diameter + 6 > std::min(c.nx, std::min(c.ny, c.nz))) {
+    err = "max_diameter + 6 exceeds the smallest box dimension"; return false;
+  }
+  const int en = c.eps_n ? c.eps_n : 8;
+  if (en < 1 || en > 64) { err = "eps_n must be 1..64"; return false; }
+  if (c.eps_mode == LBMPS_EPS_RECURSIVE && (en & (en - 1))) { err = "recursive supersampling needs eps_n = 2^k"; return false; }
+  if (c.eps_mode < 0 || c.eps_mode > 1) { err = "unknown eps_mode"; return false; }
+  if (c.block_threads < 0 || c.block_threads > 256 || (c.block_threads % 64)) { err = "block_threads must be a multiple of 64, <= 256"; return false; }
+  if (c.n_sub < 0) { err = "n_sub must be >= 0"; return false; }
+  if (c.coupling == LBMPS_PSM && c.n_sub > 1) { err = "PSM uses one sweep per rigid-body step (n_sub = 1)"; return false; }
+  return true;
+}
+
+int eff_nsub(const lbmps_config& c) {
+  if (c.coupling == LBMPS_MEM_BB || c.coupling == LBMPS_MEM_CLI) return c.n_sub ? c.n_sub : 2;
+  return 1;
+}
+
+int eff_tile_rows(const lbmps_config& c) {
+  if (c.tile_rows > 0) return c.tile_rows;
+  return std::max(1, 1024 / c.nx);
+}
+
+Layout make_layout(int n, const lbmps_config* cfgs) {
+  Layout L;
+  if (n < 1 || !cfgs) { L.err = "need at least one configuration"; return L; }
+  L.n = n;
+  L.prec = cfgs[0].precision;
+  double dmax = 0.0;
+  for (int i = 0; i < n; ++i) {
+    if (!valid_cfg(cfgs[i], L.err)) return L;
+    if (cfgs[i].precision != L.prec) { L.err = "all instances of a batch must share the precision"; return L; }
+    const bool mem = cfgs[i].coupling == LBMPS_MEM_BB || cfgs[i].coupling == LBMPS_MEM_CLI;
+    if (mem) {
+      if (L.mem_nsub && L.mem_nsub != eff_nsub(cfgs[i])) { L.err = "MEM instances of a batch must share n_sub"; return L; }
+      L.mem_nsub = eff_nsub(cfgs[i]);
+    }
+    if (cfgs[i].max_particles > 0) dmax = std::max(dmax, cfgs[i].max_diameter);
+  }
+  L.ssz = storage_size(L.prec);
+  L.side = (int)std::ceil(dmax) + 6;
+  long long pdf = 0, own = 0, cm = 0;
+  double rmax = 0.5 * dmax;
+  long long pairs = 0, links = 0, refill = 0, walls = 0;
+  long long cmax = 0;
+  for (int i = 0; i < n; ++i) {
+    const lbmps_config& c = cfgs[i];
+    const long long N = (long long)c.nx * c.ny * c.nz;
+    L.ncell.push_back(N);
+    L.pdf_off.push_back(pdf);
+    pdf += (19 * N + 63) / 64 * 64;
+    L.owner_off.push_back(own);
+    own += (N + 63) / 64 * 64;
+    if (c.coupling == LBMPS_PSM) {
+      L.cellmap_off.push_back(cm);
+      cm += (N + 63) / 64 * 64;
+    } else {
+      L.cellmap_off.push_back(-1);
+    }
+    L.part_begin.push_back(L.ptotal);
+    L.ptotal += c.max_particles;
+    const long long sd = L.side;
+    links += (long long)c.max_particles * 40 * sd * sd;
+    pairs += (long long)c.max_particles * (long long)std::ceil(4.2 * std::pow(rmax + 1.8, 3));
+    refill += (long long)c.max_particles * 6 * sd * sd;
+    walls += c.wall_link_cap > 0 ? c.wall_link_cap
+                                 : 10LL * ((long long)c.nx * c.ny + (long long)c.ny * c.nz + (long long)c.nz * c.nx);
+    cmax = std::max(cmax, N);
+    L.ntiles += (c.ny * c.nz + eff_tile_rows(c) - 1) / eff_tile_rows(c);
+  }
+  if (links + walls >= (1LL << 31) || pairs >= (1LL << 31)) { L.err = "list capacities exceed 2^31"; return L; }
+  L.pdf_elems = pdf;
+  L.owner_elems = own;
+  L.cellmap_elems = cm;
+  L.link_cap = (int)links;
+  L.wall_cap = (int)walls;
+  L.pair_cap = (int)pairs;
+  L.refill_cap = (int)refill;
+  L.slot_elems = (long long)L.ptotal * L.side * L.side * L.side;
+  L.box_total = L.ptotal * L.side;
+  L.chunk = std::min<long long>(cmax, 1LL << 22);
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+  L.o_bufA = take(L.pdf_elems * L.ssz);
+  L.o_bufB = take(L.pdf_elems * L.ssz);
+  L.o_owner = take(L.owner_elems * 4);
+  L.o_cellmap = take(L.cellmap_elems * 4);
+  L.o_inst = take(sizeof(InstDev) * n);
+  L.o_parts = take((size_t)L.ptotal * (3 * 9 + 2 + 6) * 8 + (size_t)L.ptotal * 2 * 4);
+  L.o_plists = take((size_t)L.ptotal * 2 * 4);
+  L.o_slots = take((size_t)L.slot_elems * 4);
+  L.o_totals = take((size_t)L.box_total * 4);
+  L.o_offsets = take((size_t)L.box_total * 4);
+  L.o_ranges = take((size_t)L.ptotal * 6 * 4);
+  L.o_counts = take(16 * 4);
+  L.o_links = take((size_t)(L.link_cap + L.wall_cap) * (5 * 4 + 8 + 6 * 8) + 2 * ALIGN);
+  L.o_wallv = take((size_t)n * 16 * 3 * 8);
+  L.o_pairs = take((size_t)L.pair_cap * (3 * 4 + 2 * 8 + 6 * 8) + 2 * ALIGN);
+  L.o_refill = take((size_t)L.refill_cap * 2 * 4);
+  L.o_scratch = take((size_t)L.chunk * 4 * 8);
+  L.o_tiles = take((size_t)L.ntiles * sizeof(int4));
+  L.total = o;
+  L.ok = true;
+  return L;
+}
+
+}  // namespace
+
+struct lbmps_ctx {
+  hipStream_t st = nullptr;
+  Layout L;
+  std::vector<lbmps_config> cfg;
+  std::vector<InstDev> inst_h;
+  char* ws = nullptr;
+  void* buf[2] = {nullptr, nullptr};
+  int cur = 0;  // buf[cur] holds the canonical PDFs
+  int* owner = nullptr;
+  int* cellmap = nullptr;
+  InstDev* inst_d = nullptr;
+  int4* tiles_d = nullptr;
+  int ntiles = 0, grid = 0, block = 256;
+  PartDev parts{};
+  int* plist_d = nullptr;  // [0, n_mem) MEM particles, then PSM particles
+  std::vector<int> n_active;
+  std::vector<int> fixed_h;  // per global particle
+  std::vector<int> coupling_of_part;
+  int n_mem = 0, n_psm = 0;
+  bool mem_moving = false, psm_moving = false;
+  int* slots = nullptr;
+  int* totals = nullptr;
+  int* offsets = nullptr;
+  int *lbeg = nullptr, *lend = nullptr, *pbeg = nullptr, *pend = nullptr, *rbeg = nullptr, *rend = nullptr;
+  int* counts = nullptr;  // [0] links, [1] pairs, [2] refill, [4] error bits (unsigned)
+  LinkDev links{};
+  int n_wall = 0;
+  std::vector<int> wall_groups;  // per instance
+  double* wall_v = nullptr;
+  PairDev pairs{};
+  int* rcell = nullptr;
+  int* rpart = nullptr;
+  double* scratch = nullptr;
+  long long sweeps = 0;
+  bool have_psm = false, have_links_inst = false;
+  // optional per-launch timing of the sweep kernel (HIP events on the stream)
+  bool timing = false;
+  std::vector<hipEvent_t> ev;  // pairs (start, stop)
+  size_t ev_used = 0;
+  double sweep_ms = 0.0;
+  long long sweep_launches = 0;
+  std::string last;
+};
+
+namespace {
+
+lbmps_status fail(lbmps_ctx* c, lbmps_status s, const std::string& msg) {
+  if (c) c->last = msg;
+  return s;
+}
+
+#define HIPCHK(ctx, expr)                                                                       \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess)                                                                       \
+      return fail(ctx, LBMPS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+unsigned* err_word(lbmps_ctx* c) { return (unsigned*)(c->counts + 4); }
+
+lbmps_status check_device_errors(lbmps_ctx* c) {
+  unsigned e = 0;
+  HIPCHK(c, hipMemcpyAsync(&e, err_word(c), sizeof(unsigned), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  if (e & ERR_UNSTABLE) return fail(c, LBMPS_EUNSTABLE, "non-finite particle state or a particle moved >= 1 cell per rigid-body step");
+  if (e & ERR_LINK_CAP) return fail(c, LBMPS_ENOMEM, "boundary-link capacity exceeded");
+  if (e & ERR_PAIR_CAP) return fail(c, LBMPS_ENOMEM, "overlap-pair capacity exceeded");
+  if (e & ERR_REFILL_CAP) return fail(c, LBMPS_ENOMEM, "refill-list capacity exceeded");
+  return LBMPS_OK;
+}
+
+int* mem_list(lbmps_ctx* c) { return c->plist_d; }
+int* psm_list(lbmps_ctx* c) { return c->plist_d + c->n_mem; }
+
+// Rebuild links of every MEM particle (after mapping); refill first when `refill`.
+lbmps_status rebuild_mem(lbmps_ctx* c, bool refill) {
+  const Layout& L = c->L;
+  if (c->n_mem == 0) return LBMPS_OK;
+  unsigned* err = err_word(c);
+  if (refill) {
+    HIPCHK(c, launch_mem_count(1, mem_list(c), c->n_mem, L.side, c->inst_d, c->parts, c->owner, c->slots, c->totals, c->st));
+    HIPCHK(c, launch_scan(c->totals, c->offsets, c->n_mem * L.side, L.side, c->n_mem, c->rbeg, c->rend, c->counts + 2,
+                          L.refill_cap, err, ERR_REFILL_CAP, c->st));
+    HIPCHK(c, launch_mem_fill_refill(mem_list(c), c->n_mem, L.side, c->inst_d, c->parts, c->owner, c->slots, c->offsets,
+                                     L.refill_cap, c->rcell, c->rpart, c->st));
+    HIPCHK(c, launch_mem_refill(L.prec, c->counts + 2, L.refill_cap, c->rcell, c->rpart, c->inst_d, c->parts, c->owner,
+                                c->buf[c->cur], c->st));
+  }
+  HIPCHK(c, launch_mem_count(0, mem_list(c), c->n_mem, L.side, c->inst_d, c->parts, c->owner, c->slots, c->totals, c->st));
+  HIPCHK(c, launch_scan(c->totals, c->offsets, c->n_mem * L.side, L.side, c->n_mem, c->lbeg, c->lend, c->counts + 0,
+                        L.link_cap, err, ERR_LINK_CAP, c->st));
+  HIPCHK(c, launch_mem_fill_links(mem_list(c), c->n_mem, L.side, c->inst_d, c->parts, c->owner, c->slots, c->offsets,
+                                  c->n_wall, L.link_cap, c->links, c->st));
+  HIPCHK(c, launch_mem_clear_was(mem_list(c), c->n_mem, L.side, c->inst_d, c->parts, c->owner, c->st));
+  return LBMPS_OK;
+}
+
+lbmps_status remap_mem(lbmps_ctx* c) {
+  HIPCHK(c, launch_mem_unmap(mem_list(c), c->n_mem, c->L.side, c->inst_d, c->parts, c->owner, c->st));
+  HIPCHK(c, launch_mem_map(mem_list(c), c->n_mem, c->L.side, c->inst_d, c->parts, c->owner, c->st));
+  return rebuild_mem(c, true);
+}
+
+lbmps_status rebuild_psm(lbmps_ctx* c) {
+  const Layout& L = c->L;
+  if (c->n_psm == 0) return LBMPS_OK;
+  unsigned* err = err_word(c);
+  HIPCHK(c, launch_psm_cellmap(0, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap, c->st));
+  HIPCHK(c, launch_psm_count(psm_list(c), c->n_psm, L.side, c->inst_d, c->parts, nullptr, c->slots, c->totals, c->st));
+  HIPCHK(c, launch_scan(c->totals, c->offsets, c->n_psm * L.side, L.side, c->n_psm, c->pbeg, c->pend, c->counts + 1,
+                        L.pair_cap, err, ERR_PAIR_CAP, c->st));
+  HIPCHK(c, launch_psm_fill(psm_list(c), c->n_psm, L.side, c->inst_d, c->parts, c->slots, c->offsets, L.pair_cap,
+                            c->pairs, c->st));
+  HIPCHK(c, launch_psm_cellmap(1, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap, c->st));
+  HIPCHK(c, launch_psm_cellmap(2, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap, c->st));
+  return LBMPS_OK;
+}
+
+__global__ void fill_int_kernel(int* a, long long n, int v) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+__global__ void reset_owner_kernel(int* a, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && a[i] > OWN_FLUID) a[i] = OWN_FLUID;
+}
+
+lbmps_status fill_int(lbmps_ctx* c, int* a, long long n, int v) {
+  if (n <= 0) return LBMPS_OK;
+  hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->st, a, n, v);
+  HIPCHK(c, hipGetLastError());
+  return LBMPS_OK;
+}
+
+// Accumulate the elapsed time of every recorded (start, stop) event pair.
+lbmps_status harvest_timing(lbmps_ctx* c) {
+  if (c->ev_used == 0) return LBMPS_OK;
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  for (size_t k = 0; k < c->ev_used; k += 2) {
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev[k], c->ev[k + 1]));
+    c->sweep_ms += ms;
+    c->sweep_launches++;
+  }
+  c->ev_used = 0;
+  return LBMPS_OK;
+}
+
+lbmps_status check_inst(lbmps_ctx* c, int inst) {
+  if (!c) return LBMPS_EINVAL;
+  if (inst < 0 || inst >= c->L.n) return fail(c, LBMPS_EINVAL, "instance index out of range");
+  return LBMPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lbmps_velocities(int32_t c[19][3]) {
+  for (int q = 0; q < 19; ++q) {
+    c[q][0] = cx(q);
+    c[q][1] = cy(q);
+    c[q][2] = cz(q);
+  }
+}
+
+size_t lbmps_workspace_bytes(const lbmps_config* cfg) { return lbmps_batch_workspace_bytes(1, cfg); }
+
+size_t lbmps_batch_workspace_bytes(int32_t n, const lbmps_config* cfgs) {
+  Layout L = make_layout(n, cfgs);
+  return L.ok ? L.total : 0;
+}
+
+lbmps_status lbmps_create(const lbmps_config* cfg, void* ws, size_t bytes, void* stream, lbmps_ctx** out) {
+  return lbmps_batch_create(1, cfg, ws, bytes, stream, out);
+}
+
+lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* ws, size_t bytes, void* stream,
+                                lbmps_ctx** out) {
+  if (!out) return LBMPS_EINVAL;
+  *out = nullptr;
+  Layout L = make_layout(n, cfgs);
+  if (!L.ok) return LBMPS_EINVAL;
+  if (!ws || bytes < L.total) return LBMPS_ENOMEM;
+  lbmps_ctx* c = new lbmps_ctx();
+  c->st = (hipStream_t)stream;
+  c->L = L;
+  c->cfg.assign(cfgs, cfgs + n);
+  char* w = (char*)ws;
+  c->ws = w;
+  c->buf[0] = w + L.o_bufA;
+  c->buf[1] = w + L.o_bufB;
+  c->owner = (int*)(w + L.o_owner);
+  c->cellmap = (int*)(w + L.o_cellmap);
+  c->inst_d = (InstDev*)(w + L.o_inst);
+  c->tiles_d = (int4*)(w + L.o_tiles);
+  {
+    double* d = (double*)(w + L.o_parts);
+    const size_t P = L.ptotal;
+    c->parts.X = d; d += 3 * P;
+    c->parts.U = d; d += 3 * P;
+    c->parts.Om = d; d += 3 * P;
+    c->parts.F = d; d += 3 * P;
+    c->parts.T = d; d += 3 * P;
+    c->parts.Facc = d; d += 3 * P;
+    c->parts.Tacc = d; d += 3 * P;
+    c->parts.Xold = d; d += 3 * P;
+    d += 3 * P;  // spare
+    c->parts.D = d; d += P;
+    c->parts.rho = d; d += P;
+    d += 6 * P;
+    int* ip = (int*)d;
+    c->parts.fixed = ip; ip += P;
+    c->parts.inst = ip;
+  }
+  c->plist_d = (int*)(w + L.o_plists);
+  c->slots = (int*)(w + L.o_slots);
+  c->totals = (int*)(w + L.o_totals);
+  c->offsets = (int*)(w + L.o_offsets);
+  {
+    int* r = (int*)(w + L.o_ranges);
+    const int P = L.ptotal;
+    c->lbeg = r; c->lend = r + P; c->pbeg = r + 2 * P; c->pend = r + 3 * P; c->rbeg = r + 4 * P; c->rend = r + 5 * P;
+  }
+  c->counts = (int*)(w + L.o_counts);
+  {
+    const size_t nl = (size_t)L.link_cap + L.wall_cap;
+    char* b = w + L.o_links;
+    c->links.cell = (int*)b; b += nl * 4;
+    c->links.q = (int*)b; b += nl * 4;
+    c->links.p = (int*)b; b += nl * 4;
+    c->links.inst = (int*)b; b += nl * 4;
+    c->links.cli_ok = (int*)b; b += nl * 4;
+    b = w + L.o_links + align_up(nl * 20);
+    c->links.delta = (double*)b; b += nl * 8;
+    c->links.out = (double*)b;
+  }
+  c->wall_v = (double*)(w + L.o_wallv);
+  {
+    const size_t np = L.pair_cap;
+    char* b = w + L.o_pairs;
+    c->pairs.cell = (int*)b; b += np * 4;
+    c->pairs.p = (int*)b; b += np * 4;
+    c->pairs.next = (int*)b; b += np * 4;
+    b = w + L.o_pairs + align_up(np * 12);
+    c->pairs.eps = (double*)b; b += np * 8;
+    c->pairs.B = (double*)b; b += np * 8;
+    c->pairs.out = (double*)b;
+  }
+  c->rcell = (int*)(w + L.o_refill);
+  c->rpart = c->rcell + L.refill_cap;
+  c->scratch = (double*)(w + L.o_scratch);
+
+  // instance table and sweep tiles
+  std::vector<int4> tiles;
+  for (int i = 0; i < n; ++i) {
+    const lbmps_config& cf = cfgs[i];
+    InstDev I{};
+    I.nx = cf.nx; I.ny = cf.ny; I.nz = cf.nz;
+    I.coupling = cf.coupling;
+    I.collision = cf.collision;
+    I.psm_m = cf.psm_m; I.psm_b = cf.psm_b;
+    I.n_sub = eff_nsub(cf);
+    I.ncell = L.ncell[i];
+    I.pdf_off = L.pdf_off[i];
+    I.owner_off = L.owner_off[i];
+    I.cellmap_off = L.cellmap_off[i];
+    I.tau = 3.0 * cf.nu + 0.5;
+    I.mag = cf.magic > 0 ? cf.magic : 3.0 / 16.0;
+    I.lam_p = -1.0 / I.tau;
+    if (cf.collision == LBMPS_TRT) {
+      const double inv_m = I.mag / (0.5 + 1.0 / I.lam_p) - 0.5;
+      I.lam_m = 1.0 / inv_m;
+    } else {
+      I.lam_m = I.lam_p;
+    }
+    for (int k = 0; k < 3; ++k) { I.fext[k] = cf.f_ext[k]; I.grav[k] = cf.gravity[k]; }
+    I.part_begin = L.part_begin[i];
+    I.part_count = 0;
+    I.eps_n = cf.eps_n ? cf.eps_n : 8;
+    I.eps_mode = cf.eps_mode;
+    c->inst_h.push_back(I);
+    const int tr = eff_tile_rows(cf);
+    const int rows = cf.ny * cf.nz;
+    for (int r0 = 0; r0 < rows; r0 += tr) tiles.push_back(make_int4(i, r0, std::min(tr, rows - r0), 0));
+    if (cf.coupling == LBMPS_PSM) c->have_psm = true;
+  }
+  c->ntiles = (int)tiles.size();
+  c->block = cfgs[0].block_threads ? cfgs[0].block_threads : 256;
+  c->grid = cfgs[0].grid_blocks > 0 ? std::min(cfgs[0].grid_blocks, c->ntiles) : c->ntiles;
+  c->n_active.assign(n, 0);
+  c->wall_groups.assign(n, 0);
+  c->fixed_h.assign(L.ptotal, 1);
+  c->coupling_of_part.assign(L.ptotal, 0);
+  lbmps_status s = LBMPS_OK;
+  auto bail = [&](hipError_t e, const char* what) {
+    if (e != hipSuccess) { s = LBMPS_EDEVICE; c->last = std::string(what) + ": " + hipGetErrorString(e); }
+  };
+  bail(hipMemcpyAsync(c->inst_d, c->inst_h.data(), sizeof(InstDev) * n, hipMemcpyHostToDevice, c->st), "copy instances");
+  bail(hipMemcpyAsync(c->tiles_d, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, c->st), "copy tiles");
+  bail(hipMemsetAsync(c->counts, 0, 16 * 4, c->st), "clear counters");
+  bail(hipMemsetAsync(w + L.o_parts, 0, L.o_plists - L.o_parts, c->st), "clear particles");
+  if (s == LBMPS_OK) s = fill_int(c, c->owner, L.owner_elems, OWN_FLUID);
+  if (s == LBMPS_OK) s = fill_int(c, c->cellmap, L.cellmap_elems, 0x7fffffff);
+  if (s == LBMPS_OK) {
+    const double u0[3] = {0, 0, 0};
+    for (int i = 0; i < n && s == LBMPS_OK; ++i) {
+      hipError_t e = launch_init_eq(L.prec, (char*)c->buf[0] + L.pdf_off[i] * L.ssz, L.ncell[i], 1.0, u0, c->st);
+      bail(e, "init");
+    }
+  }
+  if (s == LBMPS_OK) bail(hipStreamSynchronize(c->st), "synchronise");
+  if (s != LBMPS_OK) {
+    *out = c;  // keep the context so that lbmps_last_error can be read
+    return s;
+  }
+  *out = c;
+  return LBMPS_OK;
+}
+
+void lbmps_destroy(lbmps_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->st);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  delete c;
+}
+
+int32_t lbmps_particle_base(const lbmps_ctx* c, int32_t inst) {
+  if (!c || inst < 0 || inst >= c->L.n) return -1;
+  return c->L.part_begin[inst];
+}
+
+lbmps_status lbmps_init_equilibrium(lbmps_ctx* c, int32_t inst, double rho, const double u[3]) {
+  lbmps_status s = check_inst(c, inst);
+  if (s) return s;
+  if (!u || !std::isfinite(rho) || !std::isfinite(u[0]) || !std::isfinite(u[1]) || !std::isfinite(u[2]))
+    return fail(c, LBMPS_EINVAL, "non-finite initial state");
+  HIPCHK(c, launch_init_eq(c->L.prec, (char*)c->buf[c->cur] + c->L.pdf_off[inst] * c->L.ssz, c->L.ncell[inst], rho, u,
+                           c->st));
+  return LBMPS_OK;
+}
+
+lbmps_status lbmps_set_static_solid(lbmps_ctx* c, int32_t inst, const uint8_t* mask, const double v_wall[3]) {
+  lbmps_status s = check_inst(c, inst);
+  if (s) return s;
+  if (!mask || !v_wall) return fail(c, LBMPS_EINVAL, "null argument");
+  if (c->n_mem + c->n_psm > 0) return fail(c, LBMPS_ESTATE, "set static walls before any particles");
+  if (c->wall_groups[inst] >= 16) return fail(c, LBMPS_EINVAL, "at most 16 wall groups per instance");
+  const lbmps_config& cf = c->cfg[inst];
+  const int nx = cf.nx, ny = cf.ny, nz = cf.nz;
+  const long long N = c->L.ncell[inst];
+  // host owner copy of this instance
+  std::vector<int> own(N);
+  HIPCHK(c, hipMemcpyAsync(own.data(), c->owner + c->L.owner_off[inst], N * 4, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  const int gid = inst * 16 + c->wall_groups[inst];
+  for (long long i = 0; i < N; ++i)
+    if (mask[i]) own[i] = -2 - gid;
+  // rebuild every wall link of every instance from the host owner fields
+  std::vector<int> lc, lq, lp, li;
+  for (int k = 0; k < c->L.n; ++k) {
+    const lbmps_config& ck = c->cfg[k];
+    std::vector<int> ok;
+    const std::vector<int>* o = &own;
+    if (k != inst) {
+      if (c->wall_groups[k] == 0) continue;
+      ok.resize(c->L.ncell[k]);
+      HIPCHK(c, hipMemcpy(ok.data(), c->owner + c->L.owner_off[k], c->L.ncell[k] * 4, hipMemcpyDeviceToHost));
+      o = &ok;
+    }
+    for (int z = 0; z < ck.nz; ++z)
+      for (int y = 0; y < ck.ny; ++y)
+        for (int x = 0; x < ck.nx; ++x) {
+          const int cell = (z * ck.ny + y) * ck.nx + x;
+          if ((*o)[cell] != OWN_FLUID) continue;
+          for (int q = 1; q < 19; ++q) {
+            const int xi = (x + cx(q) + ck.nx) % ck.nx, yi = (y + cy(q) + ck.ny) % ck.ny, zi = (z + cz(q) + ck.nz) % ck.nz;
+            const int nb = (*o)[(zi * ck.ny + yi) * ck.nx + xi];
+            if (nb <= -2) {
+              lc.push_back(cell); lq.push_back(q); lp.push_back(nb); li.push_back(k);
+            }
+          }
+        }
+  }
+  (void)nx; (void)ny; (void)nz;
+  if ((long long)lc.size() > c->L.wall_cap) return fail(c, LBMPS_ENOMEM, "wall_link_cap exceeded");
+  c->wall_groups[inst]++;
+  const double v[3] = {v_wall[0], v_wall[1], v_wall[2]};
+  HIPCHK(c, hipMemcpyAsync(c->wall_v + 3 * gid, v, 3 * 8, hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->owner + c->L.owner_off[inst], own.data(), N * 4, hipMemcpyHostToDevice, c->st));
+  const size_t nl = lc.size();
+  std::vector<int> zeros(nl, 0);
+  std::vector<double> half(nl, 0.5);
+  if (nl) {
+    HIPCHK(c, hipMemcpyAsync(c->links.cell, lc.data(), nl * 4, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->links.q, lq.data(), nl * 4, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->links.p, lp.data(), nl * 4, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->links.inst, li.data(), nl * 4, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->links.cli_ok, zeros.data(), nl * 4, hipMemcpyHostToDevice, c->st));
+    HIPCHK(c, hipMemcpyAsync(c->links.delta, half.data(), nl * 8, hipMemcpyHostToDevice, c->st));
+  }
+  c->n_wall = (int)nl;
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  return LBMPS_OK;
+}
+
+lbmps_status lbmps_set_particles(lbmps_ctx* c, int32_t inst, int32_t n, const lbmps_particle* hp) {
+  lbmps_status s = check_inst(c, inst);
+  if (s) return s;
+  const lbmps_config& cf = c->cfg[inst];
+  if (n < 0 || n > cf.max_particles) return fail(c, LBMPS_EINVAL, "particle count exceeds max_particles");
+  if (n > 0 && !hp) return fail(c, LBMPS_EINVAL, "null particle array");
+  const int mind = std::min(cf.nx, std::min(cf.ny, cf.nz));
+  const double L3[3] = {(double)cf.nx, (double)cf.ny, (double)cf.nz};
+  const int P = c->L.ptotal;
+  const int base = c->L.part_begin[inst];
+  std::vector<double> X(3 * n), U(3 * n), Om(3 * n), D(n), rho(n);
+  std::vector<int> fixed(n), pinst(n, inst);
+  for (int i = 0; i < n; ++i) {
+    const lbmps_particle& p = hp[i];
+    bool fin = std::isfinite(p.D) && std::isfinite(p.rho_p);
+    for (int k = 0; k < 3; ++k) fin = fin && std::isfinite(p.X[k]) && std::isfinite(p.U[k]) && std::isfinite(p.Omega[k]);
+    if (!fin) return fail(c, LBMPS_EINVAL, "non-finite particle value");
+    if (!(p.D > 0) || p.D > cf.max_diameter || p.D + 6 > mind) return fail(c, LBMPS_EINVAL, "invalid particle diameter");
+    if (!(p.rho_p > 0)) return fail(c, LBMPS_EINVAL, "particle density must be positive");
+    for (int k = 0; k < 3; ++k) {
+      double x = std::fmod(p.X[k], L3[k]);
+      if (x < 0) x += L3[k];
+      if (x >= L3[k]) x -= L3[k];
+      X[3 * i + k] = x;
+      U[3 * i + k] = p.U[k];
+      Om[3 * i + k] = p.Omega[k];
+    }
+    D[i] = p.D;
+    rho[i] = p.rho_p;
+    fixed[i] = p.fixed ? 1 : 0;
+  }
+  (void)P;
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  HIPCHK(c, hipMemcpy(c->parts.X + 3 * base, X.data(), 24 * n, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->parts.Xold + 3 * base, X.data(), 24 * n, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->parts.U + 3 * base, U.data(), 24 * n, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->parts.Om + 3 * base, Om.data(), 24 * n, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->parts.D + base, D.data(), 8 * n, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->parts.rho + base, rho.data(), 8 * n, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->parts.fixed + base, fixed.data(), 4 * n, hipMemcpyHostToDevice));
+  HIPCHK(c, hipMemcpy(c->parts.inst + base, pinst.data(), 4 * n, hipMemcpyHostToDevice));
+  std::vector<double> z(3 * std::max(n, 1), 0.0);
+  if (n) {
+    HIPCHK(c, hipMemcpy(c->parts.F + 3 * base, z.data(), 24 * n, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->parts.T + 3 * base, z.data(), 24 * n, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->parts.Facc + 3 * base, z.data(), 24 * n, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->parts.Tacc + 3 * base, z.data(), 24 * n, hipMemcpyHostToDevice));
+  }
+  c->n_active[inst] = n;
+  for (int i = 0; i < n; ++i) {
+    c->fixed_h[base + i] = fixed[i];
+    c->coupling_of_part[base + i] = cf.coupling;
+  }
+  c->inst_h[inst].part_count = n;
+  HIPCHK(c, hipMemcpy(c->inst_d + inst, &c->inst_h[inst], sizeof(InstDev), hipMemcpyHostToDevice));
+  // particle lists: MEM particles first, then PSM, in global index order
+  std::vector<int> lm, lps;
+  c->mem_moving = c->psm_moving = false;
+  for (int k = 0; k < c->L.n; ++k) {
+    const int b = c->L.part_begin[k];
+    const int cp = c->cfg[k].coupling;
+    for (int i = 0; i < c->n_active[k]; ++i) {
+      if (cp == LBMPS_MEM_BB || cp == LBMPS_MEM_CLI) {
+        lm.push_back(b + i);
+        if (!c->fixed_h[b + i]) c->mem_moving = true;
+      } else if (cp == LBMPS_PSM) {
+        lps.push_back(b + i);
+        if (!c->fixed_h[b + i]) c->psm_moving = true;
+      }
+    }
+  }
+  c->n_mem = (int)lm.size();
+  c->n_psm = (int)lps.size();
+  std::vector<int> all(lm);
+  all.insert(all.end(), lps.begin(), lps.end());
+  if (!all.empty()) HIPCHK(c, hipMemcpy(c->plist_d, all.data(), 4 * all.size(), hipMemcpyHostToDevice));
+  // mapping
+  if (cf.coupling == LBMPS_MEM_BB || cf.coupling == LBMPS_MEM_CLI) {
+    hipLaunchKernelGGL(reset_owner_kernel, dim3((unsigned)((c->L.ncell[inst] + 255) / 256)), dim3(256), 0, c->st,
+                       c->owner + c->L.owner_off[inst], c->L.ncell[inst]);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, launch_mem_map(mem_list(c), c->n_mem, c->L.side, c->inst_d, c->parts, c->owner, c->st));
+    s = rebuild_mem(c, false);
+    if (s) return s;
+  } else if (cf.coupling == LBMPS_PSM) {
+    s = rebuild_psm(c);
+    if (s) return s;
+  }
+  return check_device_errors(c);
+}
+
+lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
+  if (!c) return LBMPS_EINVAL;
+  if (n < 0) return fail(c, LBMPS_EINVAL, "negative step count");
+  const Layout& L = c->L;
+  if (L.mem_nsub && (n % L.mem_nsub)) return fail(c, LBMPS_EINVAL, "MEM steps must be a multiple of n_sub");
+  unsigned* err = err_word(c);
+  for (int s = 0; s < n; ++s) {
+    void* src = c->buf[c->cur];
+    void* dst = c->buf[1 - c->cur];
+    if (c->timing) {
+      if (c->ev_used + 2 > c->ev.size()) {
+        lbmps_status r = harvest_timing(c);
+        if (r) return r;
+        while (c->ev.size() < 4096) {
+          hipEvent_t e;
+          HIPCHK(c, hipEventCreate(&e));
+          c->ev.push_back(e);
+        }
+      }
+      HIPCHK(c, hipEventRecord(c->ev[c->ev_used], c->st));
+    }
+    HIPCHK(c, launch_sweep(L.prec, c->inst_d, c->tiles_d, c->ntiles, c->grid, c->block, src, dst, c->st));
+    if (c->timing) {
+      HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->st));
+      c->ev_used += 2;
+    }
+    if (c->n_psm) {
+      HIPCHK(c, launch_psm_collide(L.prec, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap, src,
+                                   dst, c->st));
+      HIPCHK(c, launch_reduce(psm_list(c), c->n_psm, c->pbeg, c->pend, 0, c->pairs.out, c->parts, c->st));
+    }
+    if (c->n_mem || c->n_wall) {
+      HIPCHK(c, launch_links_bc(L.prec, c->n_wall, c->counts + 0, L.link_cap, c->links, c->wall_v, c->inst_d, c->parts,
+                                dst, c->st));
+      if (c->n_mem)
+        HIPCHK(c, launch_reduce(mem_list(c), c->n_mem, c->lbeg, c->lend, c->n_wall, c->links.out, c->parts, c->st));
+    }
+    c->cur = 1 - c->cur;
+    c->sweeps++;
+    if (c->n_psm) {
+      HIPCHK(c, launch_rigid(psm_list(c), c->n_psm, c->inst_d, c->parts, err, c->st));
+      if (c->psm_moving) {
+        lbmps_status r = rebuild_psm(c);
+        if (r) return r;
+      }
+    }
+    if (c->n_mem && (c->sweeps % L.mem_nsub) == 0) {
+      HIPCHK(c, launch_rigid(mem_list(c), c->n_mem, c->inst_d, c->parts, err, c->st));
+      if (c->mem_moving) {
+        lbmps_status r = remap_mem(c);
+        if (r) return r;
+      }
+    }
+  }
+  return LBMPS_OK;
+}
+
+lbmps_status lbmps_sync(lbmps_ctx* c) {
+  if (!c) return LBMPS_EINVAL;
+  return check_device_errors(c);
+}
+
+lbmps_status lbmps_get_particles(lbmps_ctx* c, int32_t inst, int32_t n, lbmps_particle_state* out) {
+  lbmps_status s = check_inst(c, inst);
+  if (s) return s;
+  if (n != c->n_active[inst]) return fail(c, LBMPS_EINVAL, "n must equal the number of particles set");
+  if (n == 0) return check_device_errors(c);
+  if (!out) return fail(c, LBMPS_EINVAL, "null output");
+  const int b = c->L.part_begin[inst];
+  std::vector<double> F(3 * n), T(3 * n), U(3 * n), Om(3 * n), X(3 * n);
+  HIPCHK(c, hipMemcpyAsync(F.data(), c->parts.F + 3 * b, 24 * n, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(T.data(), c->parts.T + 3 * b, 24 * n, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(U.data(), c->parts.U + 3 * b, 24 * n, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(Om.data(), c->parts.Om + 3 * b, 24 * n, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipMemcpyAsync(X.data(), c->parts.X + 3 * b, 24 * n, hipMemcpyDeviceToHost, c->st));
+  s = check_device_errors(c);
+  for (int i = 0; i < n; ++i)
+    for (int k = 0; k < 3; ++k) {
+      out[i].F[k] = F[3 * i + k];
+      out[i].T[k] = T[3 * i + k];
+      out[i].U[k] = U[3 * i + k];
+      out[i].Omega[k] = Om[3 * i + k];
+      out[i].X[k] = X[3 * i + k];
+    }
+  return s;
+}
+
+lbmps_status lbmps_get_fields(lbmps_ctx* c, int32_t inst, double* rho, double* u) {
+  lbmps_status s = check_inst(c, inst);
+  if (s) return s;
+  if (!rho || !u) return fail(c, LBMPS_EINVAL, "null output");
+  const Layout& L = c->L;
+  const long long N = L.ncell[inst];
+  const void* buf = (char*)c->buf[c->cur] + L.pdf_off[inst] * L.ssz;
+  const int* own = c->owner + L.owner_off[inst];
+  std::vector<double> h(4 * L.chunk);
+  for (long long c0 = 0; c0 < N; c0 += L.chunk) {
+    const long long n = std::min(L.chunk, N - c0);
+    HIPCHK(c, launch_fields(L.prec, buf, N, c0, n, own, c->inst_h[inst].fext, c->scratch, c->st));
+    if (c->cfg[inst].coupling == LBMPS_PSM && c->n_psm)
+      HIPCHK(c, launch_psm_fields(L.prec, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap,
+                                  c->buf[c->cur], inst, c0, n, c->scratch, c->st));
+    HIPCHK(c, hipMemcpyAsync(h.data(), c->scratch, 4 * n * 8, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+    std::memcpy(rho + c0, h.data(), n * 8);
+    for (int a = 0; a < 3; ++a) std::memcpy(u + a * N + c0, h.data() + (a + 1) * n, n * 8);
+  }
+  return check_device_errors(c);
+}
+
+lbmps_status lbmps_get_pdfs(lbmps_ctx* c, int32_t inst, double* g) {
+  lbmps_status s = check_inst(c, inst);
+  if (s) return s;
+  if (!g) return fail(c, LBMPS_EINVAL, "null output");
+  const Layout& L = c->L;
+  const long long N = L.ncell[inst];
+  const char* buf = (char*)c->buf[c->cur] + L.pdf_off[inst] * L.ssz;
+  const long long ch = 4 * L.chunk;
+  for (int q = 0; q < 19; ++q)
+    for (long long c0 = 0; c0 < N; c0 += ch) {
+      const long long n = std::min(ch, N - c0);
+      HIPCHK(c, launch_to_f64(L.prec, buf + ((long long)q * N + c0) * L.ssz, c->scratch, n, c->st));
+      HIPCHK(c, hipMemcpyAsync(g + (long long)q * N + c0, c->scratch, n * 8, hipMemcpyDeviceToHost, c->st));
+      HIPCHK(c, hipStreamSynchronize(c->st));
+    }
+  std::vector<int> own(N);
+  HIPCHK(c, hipMemcpy(own.data(), c->owner + L.owner_off[inst], N * 4, hipMemcpyDeviceToHost));
+  for (long long i = 0; i < N; ++i)
+    if (!own_is_fluid(own[i]))
+      for (int q = 0; q < 19; ++q) g[(long long)q * N + i] = 0.0;
+  return check_device_errors(c);
+}
+
+lbmps_status lbmps_set_pdfs(lbmps_ctx* c, int32_t inst, const double* g) {
+  lbmps_status s = check_inst(c, inst);
+  if (s) return s;
+  if (!g) return fail(c, LBMPS_EINVAL, "null input");
+  const Layout& L = c->L;
+  const long long N = L.ncell[inst];
+  char* buf = (char*)c->buf[c->cur] + L.pdf_off[inst] * L.ssz;
+  const long long ch = 4 * L.chunk;
+  for (int q = 0; q < 19; ++q)
+    for (long long c0 = 0; c0 < N; c0 += ch) {
+      const long long n = std::min(ch, N - c0);
+      HIPCHK(c, hipMemcpyAsync(c->scratch, g + (long long)q * N + c0, n * 8, hipMemcpyHostToDevice, c->st));
+      HIPCHK(c, launch_from_f64(L.prec, c->scratch, buf + ((long long)q * N + c0) * L.ssz, n, c->st));
+      HIPCHK(c, hipStreamSynchronize(c->st));
+    }
+  return LBMPS_OK;
+}
+
+lbmps_status lbmps_get_links(lbmps_ctx* c, int64_t cap, int32_t* cell, int32_t* q, int32_t* particle, double* delta,
+                             int64_t* n_out) {
+  if (!c || !n_out) return LBMPS_EINVAL;
+  int cnt = 0;
+  HIPCHK(c, hipMemcpyAsync(&cnt, c->counts + 0, 4, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  if (c->n_mem == 0) cnt = 0;
+  cnt = std::min(cnt, c->L.link_cap);
+  *n_out = cnt;
+  const long long n = std::min<long long>(cap, cnt);
+  const int b = c->n_wall;
+  if (n > 0) {
+    HIPCHK(c, hipMemcpy(cell, c->links.cell + b, n * 4, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(q, c->links.q + b, n * 4, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(particle, c->links.p + b, n * 4, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(delta, c->links.delta + b, n * 8, hipMemcpyDeviceToHost));
+  }
+  return check_device_errors(c);
+}
+
+lbmps_status lbmps_get_overlaps(lbmps_ctx* c, int64_t cap, int32_t* cell, int32_t* particle, double* eps,
+                                int64_t* n_out) {
+  if (!c || !n_out) return LBMPS_EINVAL;
+  int cnt = 0;
+  HIPCHK(c, hipMemcpyAsync(&cnt, c->counts + 1, 4, hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  if (c->n_psm == 0) cnt = 0;
+  cnt = std::min(cnt, c->L.pair_cap);
+  *n_out = cnt;
+  const long long n = std::min<long long>(cap, cnt);
+  if (n > 0) {
+    HIPCHK(c, hipMemcpy(cell, c->pairs.cell, n * 4, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(particle, c->pairs.p, n * 4, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(eps, c->pairs.eps, n * 8, hipMemcpyDeviceToHost));
+  }
+  return check_device_errors(c);
+}
+
+lbmps_status lbmps_set_timing(lbmps_ctx* c, int32_t enable) {
+  if (!c) return LBMPS_EINVAL;
+  lbmps_status s = harvest_timing(c);
+  if (s) return s;
+  c->timing = enable != 0;
+  c->sweep_ms = 0.0;
+  c->sweep_launches = 0;
+  return LBMPS_OK;
+}
+
+lbmps_status lbmps_get_timing(lbmps_ctx* c, double* sweep_ms, int64_t* launches) {
+  if (!c || !sweep_ms || !launches) return LBMPS_EINVAL;
+  lbmps_status s = harvest_timing(c);
+  if (s) return s;
+  *sweep_ms = c->sweep_ms;
+  *launches = c->sweep_launches;
+  return LBMPS_OK;
+}
+
+const char* lbmps_status_string(lbmps_status s) {
+  switch (s) {
+    case LBMPS_OK: return "ok";
+    case LBMPS_EINVAL: return "invalid argument";
+    case LBMPS_ENOMEM: return "workspace or capacity too small";
+    case LBMPS_EDEVICE: return "HIP runtime error";
+    case LBMPS_EUNSTABLE: return "numerical instability";
+    case LBMPS_ESTATE: return "call out of order";
+    case LBMPS_EUNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* lbmps_last_error(const lbmps_ctx* c) { return c ? c->last.c_str() : "null context"; }
+
+}  // extern "C"

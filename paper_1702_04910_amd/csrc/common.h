@@ -1,0 +1,129 @@
+// Shared device definitions of the lbmps HIP library (gfx950).
+//
+// Lattice: D3Q19 (Sec. 2.1), lattice units dx = dt = rho0 = 1, c_s^2 = 1/3.
+// Velocity order used by this library (and by every host array it exchanges):
+//   q = 0 rest; q = 1..18 in opposite pairs (q odd, q + 1):
+//   (1,0,0) (-1,0,0) (0,1,0) (0,-1,0) (0,0,1) (0,0,-1)
+//   (1,1,0) (-1,-1,0) (1,-1,0) (-1,1,0) (1,0,1) (-1,0,-1) (1,0,-1) (-1,0,1)
+//   (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1)
+// Weights 1/3, 1/18 (axis), 1/36 (diagonal).
+//
+// PDFs are stored as deviations g_q = f_q - w_q, structure of arrays
+// g[q][z][y][x] (x fastest), one array per buffer per instance.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int Q = 19;
+
+__host__ __device__ constexpr int cx(int q) {
+  return (q == 1 || q == 7 || q == 9 || q == 11 || q == 13) ? 1
+       : (q == 2 || q == 8 || q == 10 || q == 12 || q == 14) ? -1 : 0;
+}
+__host__ __device__ constexpr int cy(int q) {
+  return (q == 3 || q == 7 || q == 10 || q == 15 || q == 17) ? 1
+       : (q == 4 || q == 8 || q == 9 || q == 16 || q == 18) ? -1 : 0;
+}
+__host__ __device__ constexpr int cz(int q) {
+  return (q == 5 || q == 11 || q == 14 || q == 15 || q == 18) ? 1
+       : (q == 6 || q == 12 || q == 13 || q == 16 || q == 17) ? -1 : 0;
+}
+__host__ __device__ constexpr int opp(int q) { return q == 0 ? 0 : ((q & 1) ? q + 1 : q - 1); }
+__host__ __device__ constexpr int speed2(int q) { return cx(q) * cx(q) + cy(q) * cy(q) + cz(q) * cz(q); }
+__host__ __device__ constexpr double wq(int q) {
+  return q == 0 ? 1.0 / 3.0 : (speed2(q) == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// Coupling / collision / precision codes, identical to the public header.
+enum { COUP_NONE = 0, COUP_MEM_BB = 1, COUP_MEM_CLI = 2, COUP_PSM = 3 };
+enum { COLL_BGK = 0, COLL_TRT = 1 };
+enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP16 = 2, PREC_BF16 = 3 };
+enum { EPS_FLAT = 0, EPS_RECURSIVE = 1, EPS_MLP = 2 };
+
+// Owner field values (MEM): -1 fluid, <= -2 static wall group (-2 - k),
+// 0 <= p < WAS_BIT solid cell of particle p, WAS_BIT | p: was solid of p before
+// the current remap and is fluid now (cleared after refill).
+constexpr int OWN_FLUID = -1;
+constexpr int WAS_BIT = 1 << 30;
+__host__ __device__ inline bool own_is_fluid(int o) { return o == OWN_FLUID || (o >= WAS_BIT); }
+
+// Error flags (bit mask in the device status word).
+enum { ERR_LINK_CAP = 1, ERR_PAIR_CAP = 2, ERR_REFILL_CAP = 4, ERR_UNSTABLE = 8, ERR_CONTACT = 16 };
+
+// Per-instance parameters, read by every kernel.
+struct InstDev {
+  int nx, ny, nz, coupling;
+  int collision, psm_m, psm_b, n_sub;
+  long long ncell;
+  long long pdf_off;      // element offset of this instance's 19*ncell block in each PDF buffer
+  long long owner_off;    // int offset of the owner field (-1: none)
+  long long cellmap_off;  // int offset of the PSM cell map (-1: none)
+  double tau, lam_p, lam_m, mag;
+  double fext[3];
+  double grav[3];
+  int part_begin, part_count, eps_n, eps_mode;
+};
+
+// Particle state, structure of arrays of doubles, global over all instances.
+struct PartDev {
+  double *X, *U, *Om, *D, *rho;   // X,U,Om: 3 per particle
+  int *fixed, *inst;
+  double *F, *T;                   // subcycle-averaged force/torque of the last rigid-body step
+  double *Facc, *Tacc;             // running sums over the current subcycles
+  double *Xold;                    // position before the last rigid-body step
+};
+
+// Boundary links (x fluid, x + c_q solid), structure of arrays.
+struct LinkDev {
+  int *cell, *q, *p, *inst, *cli_ok;  // p >= 0 particle, p <= -2 wall group
+  double *delta;
+  double *out;                         // 6 per link: F^q (dev. part), (x_b - X_p) x F^q
+};
+
+// PSM (cell, particle) overlap pairs.
+struct PairDev {
+  int *cell, *p, *next;
+  double *eps, *B;
+  double *out;  // 6 per pair
+};
+
+// -------------------------------------------------------------------------- storage codecs
+template <typename S> struct Codec;
+template <> struct Codec<double> {
+  __device__ static inline double ld(double v) { return v; }
+  __device__ static inline double st(double v) { return v; }
+};
+template <> struct Codec<float> {
+  __device__ static inline float ld(float v) { return v; }
+  __device__ static inline float st(float v) { return v; }
+};
+template <> struct Codec<_Float16> {
+  __device__ static inline float ld(_Float16 v) { return (float)v; }
+  __device__ static inline _Float16 st(float v) { return (_Float16)v; }  // round to nearest even
+};
+template <> struct Codec<__bf16> {
+  __device__ static inline float ld(__bf16 v) { return (float)v; }
+  __device__ static inline __bf16 st(float v) { return (__bf16)v; }  // round to nearest even
+};
+
+// compute precision paired with each storage type
+template <typename S> struct CompOf { using type = float; };
+template <> struct CompOf<double> { using type = double; };
+
+// -------------------------------------------------------------------------- geometry helpers
+// Minimum-image displacement of coordinate a from b on a periodic axis of length L.
+__device__ inline double min_image(double d, double L) {
+  if (d >= 0.5 * L) d -= L;
+  if (d < -0.5 * L) d += L;
+  return d;
+}
+__device__ inline int wrapi(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+}  // namespace lbm

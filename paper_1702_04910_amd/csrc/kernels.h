@@ -1,0 +1,65 @@
+// Launchers of the lbmps device kernels (internal interface between the
+// kernel translation units and the C-ABI layer).
+#pragma once
+
+#include "common.h"
+
+namespace lbm {
+
+// ---- sweep.hip
+hipError_t launch_sweep(int prec, const InstDev* insts, const int4* tiles, int ntiles, int grid, int block,
+                        const void* src, void* dst, hipStream_t st);
+hipError_t launch_init_eq(int prec, void* buf, long long N, double rho, const double u[3], hipStream_t st);
+hipError_t launch_to_f64(int prec, const void* a, double* b, long long n, hipStream_t st);
+hipError_t launch_from_f64(int prec, const double* a, void* b, long long n, hipStream_t st);
+hipError_t launch_fields(int prec, const void* buf, long long N, long long c0, long long n, const int* owner,
+                         const double f[3], double* out, hipStream_t st);
+
+// ---- particles.hip
+// Exclusive scan of `totals` (length m) into `offsets`; writes the grand total to
+// *count and, for each of the nlist bounding boxes of `side` slabs, its record range
+// [begin, end).  Sets err_bit in *err when the total exceeds cap.
+hipError_t launch_scan(const int* totals, int* offsets, int m, int side, int nlist, int* begin, int* end, int* count,
+                       int cap, unsigned* err, unsigned err_bit, hipStream_t st);
+// Per-particle sum of 6-double records [begin[j], end[j]) (+ base) into Facc/Tacc of particle list[j].
+hipError_t launch_reduce(const int* list, int nlist, const int* begin, const int* end, int base, const double* out,
+                         PartDev parts, hipStream_t st);
+// Explicit Euler rigid-body step of the listed particles (averaging Facc over n_sub sweeps).
+hipError_t launch_rigid(const int* list, int nlist, const InstDev* insts, PartDev parts, unsigned* err,
+                        hipStream_t st);
+
+// ---- mem.hip
+hipError_t launch_mem_unmap(const int* list, int nlist, int side, const InstDev* insts, PartDev parts, int* owner,
+                            hipStream_t st);
+hipError_t launch_mem_map(const int* list, int nlist, int side, const InstDev* insts, PartDev parts, int* owner,
+                          hipStream_t st);
+// kind 0: links, kind 1: uncovered cells (refill list)
+hipError_t launch_mem_count(int kind, const int* list, int nlist, int side, const InstDev* insts, PartDev parts,
+                            const int* owner, int* slots, int* totals, hipStream_t st);
+hipError_t launch_mem_fill_links(const int* list, int nlist, int side, const InstDev* insts, PartDev parts,
+                                 int* owner, const int* slots, const int* offsets, int base, int cap, LinkDev links,
+                                 hipStream_t st);
+hipError_t launch_mem_fill_refill(const int* list, int nlist, int side, const InstDev* insts, PartDev parts,
+                                  int* owner, const int* slots, const int* offsets, int cap, int* rcell, int* rpart,
+                                  hipStream_t st);
+hipError_t launch_mem_refill(int prec, const int* count, int cap, const int* rcell, const int* rpart,
+                             const InstDev* insts, PartDev parts, const int* owner, void* buf, hipStream_t st);
+hipError_t launch_mem_clear_was(const int* list, int nlist, int side, const InstDev* insts, PartDev parts, int* owner,
+                                hipStream_t st);
+hipError_t launch_links_bc(int prec, int n_wall, const int* count, int cap, LinkDev links, const double* wall_v,
+                           const InstDev* insts, PartDev parts, void* buf, hipStream_t st);
+
+// ---- psm.hip
+hipError_t launch_psm_count(const int* list, int nlist, int side, const InstDev* insts, PartDev parts,
+                            const float* mlp_w, int* slots, int* totals, hipStream_t st);
+hipError_t launch_psm_fill(const int* list, int nlist, int side, const InstDev* insts, PartDev parts,
+                           const int* slots, const int* offsets, int cap, PairDev pairs, hipStream_t st);
+hipError_t launch_psm_cellmap(int stage, const int* count, int cap, const InstDev* insts, PartDev parts,
+                              PairDev pairs, int* cellmap, hipStream_t st);
+hipError_t launch_psm_collide(int prec, const int* count, int cap, const InstDev* insts, PartDev parts,
+                              PairDev pairs, const int* cellmap, const void* src, void* dst, hipStream_t st);
+hipError_t launch_psm_fields(int prec, const int* count, int cap, const InstDev* insts, PartDev parts, PairDev pairs,
+                             const int* cellmap, const void* buf, int inst, long long c0, long long n, double* out,
+                             hipStream_t st);
+
+}  // namespace lbm

@@ -1,0 +1,436 @@
+// Momentum exchange coupling (Sec. 2.2): binary particle mapping, boundary
+// links with their wall distance delta_q, the bounce-back (Eq. MEM_BB) and
+// central linear interpolation (Eq. MEM_CLI) link rules with the link force
+// of Eq. MEM_Force, and the refill of uncovered cells (Eq. MEM_Reconstruction
+// followed by the moment-space velocity constraint).
+//
+// The PDFs in the working buffer are canonical f(x, t+1) after the push sweep,
+// except at the link slots f_qbar(x, t+1) of fluid cells next to solid cells,
+// which the link kernel writes.  It reads, for a link (x, q) with x + c_q solid:
+//   f~_q(x, t)        -- pushed by x into the solid cell x + c_q, slot q;
+//   f~_q(x - c_q, t)  -- pushed by the fluid cell x - c_q into x, slot q;
+//   f~_qbar(x, t)     -- pushed by x into x - c_q, slot qbar.
+// None of these slots is written by another link, so links are independent.
+#include "common.h"
+#include "kernels.h"
+
+namespace lbm {
+
+__device__ __forceinline__ double sq3m(double x, double y, double z) {
+  return __dadd_rn(__dadd_rn(__dmul_rn(x, x), __dmul_rn(y, y)), __dmul_rn(z, z));
+}
+
+__device__ __forceinline__ void mem_bbox_lo(const PartDev& P, int p, int (&lo)[3]) {
+  const double R = 0.5 * P.D[p];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) lo[k] = (int)floor(P.X[3 * p + k] - R - 2.0);
+}
+
+__device__ __forceinline__ void disp(const InstDev& I, const PartDev& P, int p, int i, int j, int k, double (&d)[3]) {
+  d[0] = min_image(((double)i + 0.5) - P.X[3 * p + 0], (double)I.nx);
+  d[1] = min_image(((double)j + 0.5) - P.X[3 * p + 1], (double)I.ny);
+  d[2] = min_image(((double)k + 0.5) - P.X[3 * p + 2], (double)I.nz);
+}
+
+// Iterate the bounding-box cells of (list[blockIdx.y], slab blockIdx.x) in
+// contiguous per-thread chunks: body(c, i, j, k, linear cell index).
+#define MEM_BBOX_PROLOGUE                                                              \
+  const int jl = blockIdx.y, zs = blockIdx.x;                                          \
+  const int p = list[jl];                                                              \
+  const InstDev& I = insts[P.inst[p]];                                                 \
+  int lo[3];                                                                           \
+  mem_bbox_lo(P, p, lo);                                                               \
+  const int ncs = side * side;                                                         \
+  const int chunk = (ncs + 255) / 256;                                                 \
+  const int ca = min(ncs, (int)threadIdx.x * chunk), cb = min(ncs, ca + chunk);        \
+  int* own = owner + I.owner_off;                                                      \
+  (void)own;
+
+#define MEM_CELL_COORDS(c)                                             \
+  const int dy_ = (c) / side, dx_ = (c) - dy_ * side;                  \
+  const int ci = wrapi(lo[0] + dx_, I.nx), cj = wrapi(lo[1] + dy_, I.ny), \
+            ck = wrapi(lo[2] + zs, I.nz);                              \
+  const int cell = (ck * I.ny + cj) * I.nx + ci;
+
+__global__ __launch_bounds__(256) void mem_unmap_kernel(const int* __restrict__ list, int side,
+                                                        const InstDev* __restrict__ insts, PartDev P,
+                                                        int* __restrict__ owner) {
+  MEM_BBOX_PROLOGUE
+  for (int c = ca; c < cb; ++c) {
+    MEM_CELL_COORDS(c)
+    if (own[cell] == p) own[cell] = WAS_BIT | p;
+  }
+}
+
+__global__ __launch_bounds__(256) void mem_map_kernel(const int* __restrict__ list, int side,
+                                                      const InstDev* __restrict__ insts, PartDev P,
+                                                      int* __restrict__ owner) {
+  MEM_BBOX_PROLOGUE
+  const double R = 0.5 * P.D[p];
+  const double R2 = __dmul_rn(R, R);
+  for (int c = ca; c < cb; ++c) {
+    MEM_CELL_COORDS(c)
+    double d[3];
+    disp(I, P, p, ci, cj, ck, d);
+    if (sq3m(d[0], d[1], d[2]) <= R2 && own_is_fluid(own[cell])) own[cell] = p;
+  }
+}
+
+hipError_t launch_mem_unmap(const int* list, int nlist, int side, const InstDev* insts, PartDev parts, int* owner,
+                            hipStream_t st) {
+  if (nlist <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mem_unmap_kernel, dim3(side, nlist), dim3(256), 0, st, list, side, insts, parts, owner);
+  return hipGetLastError();
+}
+
+hipError_t launch_mem_map(const int* list, int nlist, int side, const InstDev* insts, PartDev parts, int* owner,
+                          hipStream_t st) {
+  if (nlist <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mem_map_kernel, dim3(side, nlist), dim3(256), 0, st, list, side, insts, parts, owner);
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ int mem_block_scan(int v, int* sh, int* total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int a = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += a;
+    __syncthreads();
+  }
+  const int incl = sh[t];
+  *total = sh[255];
+  __syncthreads();
+  return incl - v;
+}
+
+// kind 0: per fluid cell the mask of directions q whose neighbour x + c_q is a
+// solid cell of p (one link each); kind 1: 1 for a cell uncovered by p.
+__global__ __launch_bounds__(256) void mem_count_kernel(int kind, const int* __restrict__ list, int side,
+                                                        const InstDev* __restrict__ insts, PartDev P,
+                                                        int* __restrict__ owner, int* __restrict__ slots,
+                                                        int* __restrict__ totals) {
+  MEM_BBOX_PROLOGUE
+  int* slot = slots + ((long long)jl * side + zs) * ncs;
+  int local = 0;
+  for (int c = ca; c < cb; ++c) {
+    MEM_CELL_COORDS(c)
+    int v = 0;
+    if (kind == 0) {
+      if (own_is_fluid(own[cell])) {
+#pragma unroll
+        for (int q = 1; q < Q; ++q) {
+          const int ni = wrapi(ci + cx(q), I.nx), nj = wrapi(cj + cy(q), I.ny), nk = wrapi(ck + cz(q), I.nz);
+          if (own[(nk * I.ny + nj) * I.nx + ni] == p) v |= 1 << q;
+        }
+      }
+      local += __popc(v);
+    } else {
+      v = own[cell] == (WAS_BIT | p) ? 1 : 0;
+      local += v;
+    }
+    slot[c] = v;
+  }
+  __shared__ int sh[256];
+  int total;
+  mem_block_scan(local, sh, &total);
+  if (threadIdx.x == 0) totals[jl * side + zs] = total;
+}
+
+hipError_t launch_mem_count(int kind, const int* list, int nlist, int side, const InstDev* insts, PartDev parts,
+                            const int* owner, int* slots, int* totals, hipStream_t st) {
+  if (nlist <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mem_count_kernel, dim3(side, nlist), dim3(256), 0, st, kind, list, side, insts, parts,
+                     (int*)owner, slots, totals);
+  return hipGetLastError();
+}
+
+// Writes the links of each fluid cell in increasing q, with delta_q = the
+// smallest root in (0, 1] of |d + delta c|^2 = R^2 computed as e/(-b + sqrt(b^2 - a e))
+// (a = c.c, b = d.c, e = |d|^2 - R^2), and whether x - c_q is fluid (needed by
+// CLI).  Clears the "was solid" marks of the cells it visits afterwards.
+__global__ __launch_bounds__(256) void mem_fill_links_kernel(const int* __restrict__ list, int side,
+                                                             const InstDev* __restrict__ insts, PartDev P,
+                                                             int* __restrict__ owner, const int* __restrict__ slots,
+                                                             const int* __restrict__ offsets, int base, int cap,
+                                                             LinkDev L) {
+  MEM_BBOX_PROLOGUE
+  const int* slot = slots + ((long long)jl * side + zs) * ncs;
+  int local = 0;
+  for (int c = ca; c < cb; ++c) local += __popc(slot[c]);
+  __shared__ int sh[256];
+  int total;
+  int pos = base + offsets[jl * side + zs] + mem_block_scan(local, sh, &total);
+  const double R = 0.5 * P.D[p];
+  for (int c = ca; c < cb; ++c) {
+    const int m = slot[c];
+    if (m == 0) continue;
+    MEM_CELL_COORDS(c)
+    double d[3];
+    disp(I, P, p, ci, cj, ck, d);
+    const double e = sq3m(d[0], d[1], d[2]) - R * R;
+    for (int q = 1; q < Q; ++q) {
+      if (!(m & (1 << q))) continue;
+      if (pos < base + cap) {
+        const double a = (double)speed2(q);
+        const double b = d[0] * cx(q) + d[1] * cy(q) + d[2] * cz(q);
+        const double delta = e / (-b + sqrt(b * b - a * e));
+        const int bi = wrapi(ci - cx(q), I.nx), bj = wrapi(cj - cy(q), I.ny), bk = wrapi(ck - cz(q), I.nz);
+        L.cell[pos] = cell;
+        L.q[pos] = q;
+        L.p[pos] = p;
+        L.inst[pos] = P.inst[p];
+        L.delta[pos] = delta;
+        L.cli_ok[pos] = own_is_fluid(own[(bk * I.ny + bj) * I.nx + bi]) ? 1 : 0;
+      }
+      ++pos;
+    }
+  }
+}
+
+hipError_t launch_mem_fill_links(const int* list, int nlist, int side, const InstDev* insts, PartDev parts,
+                                 int* owner, const int* slots, const int* offsets, int base, int cap, LinkDev links,
+                                 hipStream_t st) {
+  if (nlist <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mem_fill_links_kernel, dim3(side, nlist), dim3(256), 0, st, list, side, insts, parts, owner,
+                     slots, offsets, base, cap, links);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void mem_clear_was_kernel(const int* __restrict__ list, int side,
+                                                            const InstDev* __restrict__ insts, PartDev P,
+                                                            int* __restrict__ owner) {
+  MEM_BBOX_PROLOGUE
+  for (int c = ca; c < cb; ++c) {
+    MEM_CELL_COORDS(c)
+    if (own[cell] >= WAS_BIT) own[cell] = OWN_FLUID;
+  }
+}
+
+hipError_t launch_mem_clear_was(const int* list, int nlist, int side, const InstDev* insts, PartDev parts, int* owner,
+                                hipStream_t st) {
+  if (nlist <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mem_clear_was_kernel, dim3(side, nlist), dim3(256), 0, st, list, side, insts, parts, owner);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void mem_fill_refill_kernel(const int* __restrict__ list, int side,
+                                                              const InstDev* __restrict__ insts, PartDev P,
+                                                              int* __restrict__ owner, const int* __restrict__ slots,
+                                                              const int* __restrict__ offsets, int cap,
+                                                              int* __restrict__ rcell, int* __restrict__ rpart) {
+  MEM_BBOX_PROLOGUE
+  const int* slot = slots + ((long long)jl * side + zs) * ncs;
+  int local = 0;
+  for (int c = ca; c < cb; ++c) local += slot[c];
+  __shared__ int sh[256];
+  int total;
+  int pos = offsets[jl * side + zs] + mem_block_scan(local, sh, &total);
+  for (int c = ca; c < cb; ++c) {
+    if (!slot[c]) continue;
+    MEM_CELL_COORDS(c)
+    if (pos < cap) {
+      rcell[pos] = cell;
+      rpart[pos] = p;
+    }
+    ++pos;
+  }
+}
+
+hipError_t launch_mem_fill_refill(const int* list, int nlist, int side, const InstDev* insts, PartDev parts,
+                                  int* owner, const int* slots, const int* offsets, int cap, int* rcell, int* rpart,
+                                  hipStream_t st) {
+  if (nlist <= 0) return hipSuccess;
+  hipLaunchKernelGGL(mem_fill_refill_kernel, dim3(side, nlist), dim3(256), 0, st, list, side, insts, parts, owner,
+                     slots, offsets, cap, rcell, rpart);
+  return hipGetLastError();
+}
+
+// Refill of one uncovered cell x (Sec. 2.2.3):
+//  * q_n maximises n.c_q/|c_q| with n along x - X_p (ties: largest (cx, cy, cz)
+//    lexicographically);
+//  * sources x + k c_qn, k = 1..3, must be fluid cells that were fluid before the
+//    remap; quadratic 3 f1 - 3 f2 + f3, else linear 2 f1 - f2, else constant f1,
+//    else f^eq(rho_bar, v(x)) with rho_bar the mean density of such neighbours;
+//  * velocity constraint: f_q += c_q.(j* - j)/10 with j* = v(x) - f_ext/2.
+template <typename S>
+__global__ void mem_refill_kernel(const int* __restrict__ count, int cap, const int* __restrict__ rcell,
+                                  const int* __restrict__ rpart, const InstDev* __restrict__ insts, PartDev P,
+                                  const int* __restrict__ owner, S* __restrict__ buf) {
+  const int n = min(*count, cap);
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    const int cell = rcell[r], p = rpart[r];
+    const InstDev& I = insts[P.inst[p]];
+    const int* own = owner + I.owner_off;
+    S* b = buf + I.pdf_off;
+    const long long N = I.ncell;
+    const int x = cell % I.nx, yz = cell / I.nx, y = yz % I.ny, z = yz / I.ny;
+    double d[3];
+    disp(I, P, p, x, y, z, d);
+    int qn = 1;
+    double best = -1e300;
+    int bx = -2, by = -2, bz = -2;
+    for (int q = 1; q < Q; ++q) {
+      const double dc = d[0] * cx(q) + d[1] * cy(q) + d[2] * cz(q);
+      const double score = speed2(q) == 1 ? dc : dc * 0.7071067811865476;
+      const bool better = score > best ||
+                          (score == best && (cx(q) > bx || (cx(q) == bx && (cy(q) > by || (cy(q) == by && cz(q) > bz)))));
+      if (better) {
+        best = score;
+        qn = q;
+        bx = cx(q);
+        by = cy(q);
+        bz = cz(q);
+      }
+    }
+    double src[3][Q];
+    int ns = 0;
+    for (int k = 1; k <= 3; ++k) {
+      const int xi = wrapi(x + k * cx(qn), I.nx), yi = wrapi(y + k * cy(qn), I.ny), zi = wrapi(z + k * cz(qn), I.nz);
+      const int c2 = (zi * I.ny + yi) * I.nx + xi;
+      if (own[c2] != OWN_FLUID) break;
+      for (int q = 0; q < Q; ++q) src[k - 1][q] = (double)Codec<S>::ld(b[(long long)q * N + c2]);
+      ++ns;
+    }
+    const double* Up = P.U + 3 * p;
+    const double* Wp = P.Om + 3 * p;
+    const double v[3] = {Up[0] + (Wp[1] * d[2] - Wp[2] * d[1]), Up[1] + (Wp[2] * d[0] - Wp[0] * d[2]),
+                         Up[2] + (Wp[0] * d[1] - Wp[1] * d[0])};
+    double o[Q];
+    if (ns == 3) {
+      for (int q = 0; q < Q; ++q) o[q] = 3.0 * src[0][q] - 3.0 * src[1][q] + src[2][q];
+    } else if (ns == 2) {
+      for (int q = 0; q < Q; ++q) o[q] = 2.0 * src[0][q] - src[1][q];
+    } else if (ns == 1) {
+      for (int q = 0; q < Q; ++q) o[q] = src[0][q];
+    } else {
+      // mean density fluctuation of the old-fluid neighbours (0 when there are none)
+      double rs = 0.0;
+      int nr = 0;
+      for (int q = 1; q < Q; ++q) {
+        const int xi = wrapi(x + cx(q), I.nx), yi = wrapi(y + cy(q), I.ny), zi = wrapi(z + cz(q), I.nz);
+        const int c2 = (zi * I.ny + yi) * I.nx + xi;
+        if (own[c2] != OWN_FLUID) continue;
+        double s = 0.0;
+        for (int qq = 0; qq < Q; ++qq) s += (double)Codec<S>::ld(b[(long long)qq * N + c2]);
+        rs += s;
+        ++nr;
+      }
+      const double drho = nr ? rs / nr : 0.0;
+      const double uu = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+      for (int q = 0; q < Q; ++q) {
+        const double cu = cx(q) * v[0] + cy(q) * v[1] + cz(q) * v[2];
+        o[q] = wq(q) * ((drho - 1.5 * uu) + cu * (3.0 + 4.5 * cu));
+      }
+    }
+    double j[3] = {0, 0, 0};
+    for (int q = 1; q < Q; ++q) {
+      j[0] += cx(q) * o[q];
+      j[1] += cy(q) * o[q];
+      j[2] += cz(q) * o[q];
+    }
+    const double dj[3] = {(v[0] - 0.5 * I.fext[0]) - j[0], (v[1] - 0.5 * I.fext[1]) - j[1],
+                          (v[2] - 0.5 * I.fext[2]) - j[2]};
+    for (int q = 0; q < Q; ++q) {
+      const double val = o[q] + (cx(q) * dj[0] + cy(q) * dj[1] + cz(q) * dj[2]) / 10.0;
+      b[(long long)q * N + cell] = Codec<S>::st((typename CompOf<S>::type)val);
+    }
+  }
+}
+
+#define LBM_DISPATCH(prec, CALL)                          \
+  switch (prec) {                                         \
+    case PREC_FP64: { using S = double; CALL; } break;    \
+    case PREC_FP32: { using S = float; CALL; } break;     \
+    case PREC_FP16: { using S = _Float16; CALL; } break;  \
+    case PREC_BF16: { using S = __bf16; CALL; } break;    \
+    default: return hipErrorInvalidValue;                 \
+  }
+
+hipError_t launch_mem_refill(int prec, const int* count, int cap, const int* rcell, const int* rpart,
+                             const InstDev* insts, PartDev parts, const int* owner, void* buf, hipStream_t st) {
+  LBM_DISPATCH(prec, hipLaunchKernelGGL(mem_refill_kernel<S>, dim3(64), dim3(128), 0, st, count, cap, rcell, rpart,
+                                        insts, parts, owner, (S*)buf));
+  return hipGetLastError();
+}
+
+// Link rule and link force for links [0, n_wall + *count).  Walls (p <= -2) use
+// BB with their wall velocity; particle links use BB or CLI (CLI falls back to
+// BB where x - c_q is not fluid).  Output per particle link: the deviation part
+// (c_q - v) g~_q + (c_q + v) g_qbar of Eq. MEM_Force and its torque about X_p.
+template <typename S>
+__global__ void links_bc_kernel(int n_wall, const int* __restrict__ count, int cap, LinkDev L,
+                                const double* __restrict__ wall_v, const InstDev* __restrict__ insts, PartDev P,
+                                S* __restrict__ buf) {
+  const int n = n_wall + min(*count, cap);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int inst = L.inst[i];
+    const InstDev& I = insts[inst];
+    const int cell = L.cell[i], q = L.q[i], p = L.p[i];
+    const int qb = opp(q);
+    const int x = cell % I.nx, yz = cell / I.nx, y = yz % I.ny, z = yz / I.ny;
+    const long long N = I.ncell;
+    S* b = buf + I.pdf_off;
+    const int c[3] = {cx(q), cy(q), cz(q)};
+    const int xs = wrapi(x + c[0], I.nx), ys = wrapi(y + c[1], I.ny), zs = wrapi(z + c[2], I.nz);
+    const double gtq = (double)Codec<S>::ld(b[(long long)q * N + ((long long)zs * I.ny + ys) * I.nx + xs]);
+    double v[3], arm[3] = {0, 0, 0};
+    bool cli = false;
+    double delta = 0.5;
+    if (p >= 0) {
+      cli = I.coupling == COUP_MEM_CLI && L.cli_ok[i];
+      if (cli) delta = L.delta[i];
+      double d[3];
+      disp(I, P, p, x, y, z, d);
+      for (int k = 0; k < 3; ++k) arm[k] = d[k] + delta * c[k];
+      const double* Up = P.U + 3 * p;
+      const double* Wp = P.Om + 3 * p;
+      v[0] = Up[0] + (Wp[1] * arm[2] - Wp[2] * arm[1]);
+      v[1] = Up[1] + (Wp[2] * arm[0] - Wp[0] * arm[2]);
+      v[2] = Up[2] + (Wp[0] * arm[1] - Wp[1] * arm[0]);
+    } else {
+      const int gid = -2 - p;
+      v[0] = wall_v[3 * gid];
+      v[1] = wall_v[3 * gid + 1];
+      v[2] = wall_v[3 * gid + 2];
+    }
+    const double vc = v[0] * c[0] + v[1] * c[1] + v[2] * c[2];
+    const double w = wq(q);
+    double val;
+    if (cli) {
+      const double k0 = (1.0 - 2.0 * delta) / (1.0 + 2.0 * delta);
+      const double alpha = 4.0 / (1.0 + 2.0 * delta);
+      const int xm = wrapi(x - c[0], I.nx), ym = wrapi(y - c[1], I.ny), zm = wrapi(z - c[2], I.nz);
+      const double gq_m = (double)Codec<S>::ld(b[(long long)q * N + cell]);
+      const double gqb = (double)Codec<S>::ld(b[(long long)qb * N + ((long long)zm * I.ny + ym) * I.nx + xm]);
+      val = gtq + k0 * gq_m - k0 * gqb - 3.0 * alpha * w * vc;
+    } else {
+      val = gtq - 6.0 * w * vc;
+    }
+    const S sv = Codec<S>::st((typename CompOf<S>::type)val);
+    b[(long long)qb * N + cell] = sv;
+    if (p >= 0) {
+      const double vs = (double)Codec<S>::ld(sv);
+      double F[3];
+      for (int k = 0; k < 3; ++k) F[k] = (c[k] - v[k]) * gtq + (c[k] + v[k]) * vs;
+      double* o = L.out + 6LL * i;
+      o[0] = F[0];
+      o[1] = F[1];
+      o[2] = F[2];
+      o[3] = arm[1] * F[2] - arm[2] * F[1];
+      o[4] = arm[2] * F[0] - arm[0] * F[2];
+      o[5] = arm[0] * F[1] - arm[1] * F[0];
+    }
+  }
+}
+
+hipError_t launch_links_bc(int prec, int n_wall, const int* count, int cap, LinkDev links, const double* wall_v,
+                           const InstDev* insts, PartDev parts, void* buf, hipStream_t st) {
+  LBM_DISPATCH(prec, hipLaunchKernelGGL(links_bc_kernel<S>, dim3(512), dim3(256), 0, st, n_wall, count, cap, links,
+                                        wall_v, insts, parts, (S*)buf));
+  return hipGetLastError();
+}
+
+}  // namespace lbm

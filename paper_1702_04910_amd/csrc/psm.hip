@@ -1,0 +1,478 @@
+// Partially saturated cells coupling (Sec. 2.3): supersampled solid volume
+// fractions (Sec. 2.3.2), the (cell, particle) overlap list, and the PSM
+// collision of the overlapped cells (Eqs. PSM, PSM_B1/B2, PSM_M1..M3,
+// LBM_Collide_PSM) with the per-pair force and torque terms of
+// Eqs. PSM_TotForce/TotTorque.
+//
+// Geometry conventions: cell centres at index + 1/2, minimum-image
+// displacements, a sample point is inside when ((dx*dx + dy*dy) + dz*dz) <= R^2
+// evaluated without fused multiply-add, sample points at the centres of an
+// n^3 sub-cell grid.  The recursive count classifies octree blocks of sample
+// points by their farthest and nearest sample point; both counts are exact
+// integers and equal.
+#include <climits>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace lbm {
+
+constexpr int KMAX = 8;  // particles sharing one cell
+
+__device__ __forceinline__ double sq3(double x, double y, double z) {
+  return __dadd_rn(__dadd_rn(__dmul_rn(x, x), __dmul_rn(y, y)), __dmul_rn(z, z));
+}
+
+__device__ __forceinline__ double sample_off(int a, int n) { return __dadd_rn(__ddiv_rn((double)a + 0.5, (double)n), -0.5); }
+
+// Whole-block classification: 1 all inside, -1 all outside, 0 mixed.
+__device__ __forceinline__ int classify(const double (&lo)[3], const double (&hi)[3], double R2) {
+  double f[3], nr[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double a = fabs(lo[k]), b = fabs(hi[k]);
+    f[k] = a > b ? a : b;
+    nr[k] = (lo[k] <= 0.0 && 0.0 <= hi[k]) ? 0.0 : (a < b ? a : b);
+  }
+  if (sq3(f[0], f[1], f[2]) <= R2) return 1;
+  if (sq3(nr[0], nr[1], nr[2]) > R2) return -1;
+  return 0;
+}
+
+__device__ int count_flat(const double dc[3], double R2, int n) {
+  int cnt = 0;
+  for (int c = 0; c < n; ++c) {
+    const double pz = __dadd_rn(dc[2], sample_off(c, n));
+    for (int b = 0; b < n; ++b) {
+      const double py = __dadd_rn(dc[1], sample_off(b, n));
+      for (int a = 0; a < n; ++a) {
+        const double px = __dadd_rn(dc[0], sample_off(a, n));
+        cnt += sq3(px, py, pz) <= R2 ? 1 : 0;
+      }
+    }
+  }
+  return cnt;
+}
+
+__device__ int count_recursive(const double dc[3], double R2, int n) {
+  // explicit stack of blocks (a0, b0, c0, m); depth <= log2(n) <= 6
+  int st_a[64], st_b[64], st_c[64], st_m[64];
+  int sp = 0, cnt = 0;
+  st_a[0] = 0; st_b[0] = 0; st_c[0] = 0; st_m[0] = n; sp = 1;
+  while (sp > 0) {
+    --sp;
+    const int a0 = st_a[sp], b0 = st_b[sp], c0 = st_c[sp], m = st_m[sp];
+    double lo[3], hi[3];
+    lo[0] = __dadd_rn(dc[0], sample_off(a0, n)); hi[0] = __dadd_rn(dc[0], sample_off(a0 + m - 1, n));
+    lo[1] = __dadd_rn(dc[1], sample_off(b0, n)); hi[1] = __dadd_rn(dc[1], sample_off(b0 + m - 1, n));
+    lo[2] = __dadd_rn(dc[2], sample_off(c0, n)); hi[2] = __dadd_rn(dc[2], sample_off(c0 + m - 1, n));
+    const int cl = classify(lo, hi, R2);
+    if (cl == 1) { cnt += m * m * m; continue; }
+    if (cl == -1) continue;
+    if (m == 1) { cnt += sq3(lo[0], lo[1], lo[2]) <= R2 ? 1 : 0; continue; }
+    const int h = m / 2;
+    for (int k = 0; k < 8; ++k) {
+      st_a[sp] = a0 + ((k & 1) ? h : 0);
+      st_b[sp] = b0 + ((k & 2) ? h : 0);
+      st_c[sp] = c0 + ((k & 4) ? h : 0);
+      st_m[sp] = h;
+      ++sp;
+    }
+  }
+  return cnt;
+}
+
+// Bounding box of particle p: `side` cells per axis starting at floor(X - R - 2).
+__device__ __forceinline__ void bbox_lo(const PartDev& P, int p, int (&lo)[3]) {
+  const double R = 0.5 * P.D[p];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) lo[k] = (int)floor(P.X[3 * p + k] - R - 2.0);
+}
+
+__device__ __forceinline__ void centre_disp(const InstDev& I, const PartDev& P, int p, int i, int j, int k,
+                                            double (&d)[3]) {
+  d[0] = min_image(((double)i + 0.5) - P.X[3 * p + 0], (double)I.nx);
+  d[1] = min_image(((double)j + 0.5) - P.X[3 * p + 1], (double)I.ny);
+  d[2] = min_image(((double)k + 0.5) - P.X[3 * p + 2], (double)I.nz);
+}
+
+// Block-wide exclusive scan of one int per thread (256 threads).
+__device__ __forceinline__ int block_excl_scan(int v, int* sh, int* total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int a = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += a;
+    __syncthreads();
+  }
+  const int incl = sh[t];
+  *total = sh[255];
+  __syncthreads();
+  return incl - v;
+}
+
+// Grid (side, nlist): workgroup (z, j) handles slab z of the bounding box of particle list[j].
+__global__ __launch_bounds__(256) void psm_count_kernel(const int* __restrict__ list, int side,
+                                                        const InstDev* __restrict__ insts, PartDev P,
+                                                        const float* __restrict__ mlp_w, int* __restrict__ slots,
+                                                        int* __restrict__ totals) {
+  const int j = blockIdx.y, z = blockIdx.x;
+  const int p = list[j];
+  const InstDev& I = insts[P.inst[p]];
+  int lo[3];
+  bbox_lo(P, p, lo);
+  const double R = 0.5 * P.D[p];
+  const double R2 = __dmul_rn(R, R);
+  const int n = I.eps_n;
+  const int ncs = side * side;
+  const int chunk = (ncs + 255) / 256;
+  const int a = min(ncs, (int)threadIdx.x * chunk), b = min(ncs, a + chunk);
+  int* slot = slots + ((long long)j * side + z) * ncs;
+  int local = 0;
+  for (int c = a; c < b; ++c) {
+    const int dy = c / side, dx = c - dy * side;
+    const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny), k = wrapi(lo[2] + z, I.nz);
+    double dc[3];
+    centre_disp(I, P, p, i, jj, k, dc);
+    // the whole cell: farthest / nearest sample point
+    double blo[3], bhi[3];
+    const double o0 = sample_off(0, n), o1 = sample_off(n - 1, n);
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      blo[q] = __dadd_rn(dc[q], o0);
+      bhi[q] = __dadd_rn(dc[q], o1);
+    }
+    const int cl = classify(blo, bhi, R2);
+    int v;
+    if (cl == 1) v = n * n * n;
+    else if (cl == -1) v = 0;
+    else v = (I.eps_mode == EPS_RECURSIVE) ? count_recursive(dc, R2, n) : count_flat(dc, R2, n);
+    slot[c] = v;
+    local += v > 0 ? 1 : 0;
+  }
+  __shared__ int sh[256];
+  int total;
+  block_excl_scan(local, sh, &total);
+  if (threadIdx.x == 0) totals[j * side + z] = total;
+}
+
+hipError_t launch_psm_count(const int* list, int nlist, int side, const InstDev* insts, PartDev parts,
+                            const float* mlp_w, int* slots, int* totals, hipStream_t st) {
+  if (nlist <= 0) return hipSuccess;
+  hipLaunchKernelGGL(psm_count_kernel, dim3(side, nlist), dim3(256), 0, st, list, side, insts, parts, mlp_w, slots,
+                     totals);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void psm_fill_kernel(const int* __restrict__ list, int side,
+                                                       const InstDev* __restrict__ insts, PartDev P,
+                                                       const int* __restrict__ slots, const int* __restrict__ offsets,
+                                                       int cap, PairDev pairs) {
+  const int j = blockIdx.y, z = blockIdx.x;
+  const int p = list[j];
+  const InstDev& I = insts[P.inst[p]];
+  int lo[3];
+  bbox_lo(P, p, lo);
+  const int n = I.eps_n;
+  const double nn = (double)n * (double)n * (double)n;
+  const double t = I.tau - 0.5;
+  const int ncs = side * side;
+  const int chunk = (ncs + 255) / 256;
+  const int a = min(ncs, (int)threadIdx.x * chunk), b = min(ncs, a + chunk);
+  const int* slot = slots + ((long long)j * side + z) * ncs;
+  int local = 0;
+  for (int c = a; c < b; ++c) local += slot[c] > 0 ? 1 : 0;
+  __shared__ int sh[256];
+  int total;
+  int pos = offsets[j * side + z] + block_excl_scan(local, sh, &total);
+  for (int c = a; c < b; ++c) {
+    const int v = slot[c];
+    if (v <= 0) continue;
+    if (pos < cap) {
+      const int dy = c / side, dx = c - dy * side;
+      const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny), k = wrapi(lo[2] + z, I.nz);
+      const double eps = (double)v / nn;
+      pairs.cell[pos] = (k * I.ny + jj) * I.nx + i;
+      pairs.p[pos] = p;
+      pairs.eps[pos] = eps;
+      pairs.B[pos] = I.psm_b == 1 ? eps : eps * t / ((1.0 - eps) + t);
+      pairs.next[pos] = -1;
+    }
+    ++pos;
+  }
+}
+
+hipError_t launch_psm_fill(const int* list, int nlist, int side, const InstDev* insts, PartDev parts,
+                           const int* slots, const int* offsets, int cap, PairDev pairs, hipStream_t st) {
+  if (nlist <= 0) return hipSuccess;
+  hipLaunchKernelGGL(psm_fill_kernel, dim3(side, nlist), dim3(256), 0, st, list, side, insts, parts, slots, offsets,
+                     cap, pairs);
+  return hipGetLastError();
+}
+
+// stage 0: reset the cell map entries of the listed pairs; stage 1: each cell's
+// leader is its smallest pair index; stage 2: the other pairs of a cell are
+// chained behind the leader (order fixed later by sorting).
+__global__ void psm_cellmap_kernel(int stage, const int* __restrict__ count, int cap,
+                                   const InstDev* __restrict__ insts, PartDev P, PairDev pairs,
+                                   int* __restrict__ cellmap) {
+  const int n = min(*count, cap);
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const int p = pairs.p[i];
+    int* cm = cellmap + insts[P.inst[p]].cellmap_off;
+    const int c = pairs.cell[i];
+    if (stage == 0) {
+      cm[c] = INT_MAX;
+    } else if (stage == 1) {
+      atomicMin(&cm[c], i);
+    } else {
+      const int L = cm[c];
+      if (L != i) pairs.next[i] = atomicExch(&pairs.next[L], i);
+    }
+  }
+}
+
+hipError_t launch_psm_cellmap(int stage, const int* count, int cap, const InstDev* insts, PartDev parts,
+                              PairDev pairs, int* cellmap, hipStream_t st) {
+  hipLaunchKernelGGL(psm_cellmap_kernel, dim3(1024), dim3(256), 0, st, stage, count, cap, insts, parts, pairs,
+                     cellmap);
+  return hipGetLastError();
+}
+
+// Members of the cell led by pair L, in increasing pair order.
+__device__ __forceinline__ int gather_members(const PairDev& pairs, int L, int (&mem)[KMAX]) {
+  int k = 0;
+  mem[k++] = L;
+  int nx = pairs.next[L];
+  while (nx >= 0 && k < KMAX) {
+    mem[k++] = nx;
+    nx = pairs.next[nx];
+  }
+  for (int a = 1; a < k; ++a) {
+    const int v = mem[a];
+    int b = a - 1;
+    while (b >= 0 && mem[b] > v) {
+      mem[b + 1] = mem[b];
+      --b;
+    }
+    mem[b + 1] = v;
+  }
+  return k;
+}
+
+// Equilibrium deviation, Eq. LBM_EQ minus w_q, for all q.
+template <typename R>
+__device__ __forceinline__ void geq_all(R drho, R ux, R uy, R uz, R (&e)[Q]) {
+  const R base = drho - (R)1.5 * (ux * ux + uy * uy + uz * uz);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const R cu = (R)cx(q) * ux + (R)cy(q) * uy + (R)cz(q) * uz;
+    e[q] = (R)wq(q) * (base + cu * ((R)3 + (R)4.5 * cu));
+  }
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void psm_collide_kernel(const int* __restrict__ count, int cap,
+                                                          const InstDev* __restrict__ insts, PartDev P,
+                                                          PairDev pairs, const int* __restrict__ cellmap,
+                                                          const S* __restrict__ src, S* __restrict__ dst) {
+  using R = typename CompOf<S>::type;
+  const int npairs = min(*count, cap);
+  for (int L = blockIdx.x * blockDim.x + threadIdx.x; L < npairs; L += gridDim.x * blockDim.x) {
+    const int p0 = pairs.p[L];
+    const InstDev& I = insts[P.inst[p0]];
+    const int c = pairs.cell[L];
+    if (cellmap[I.cellmap_off + c] != L) continue;  // not the cell's leader
+    int mem[KMAX];
+    const int k = gather_members(pairs, L, mem);
+    const long long N = I.ncell;
+    const S* s = src + I.pdf_off;
+    S* d = dst + I.pdf_off;
+    R g[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) g[q] = Codec<S>::ld(s[(long long)q * N + c]);
+    R drho = 0, ux = 0, uy = 0, uz = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      drho += g[q];
+      ux += (R)cx(q) * g[q];
+      uy += (R)cy(q) * g[q];
+      uz += (R)cz(q) * g[q];
+    }
+    R eU[Q];
+    geq_all<R>(drho, ux, uy, uz, eU);
+    const R lp = (R)I.lam_p, lm = (R)I.lam_m;
+    const R fx = (R)I.fext[0], fy = (R)I.fext[1], fz = (R)I.fext[2];
+    const R fu = ux * fx + uy * fy + uz * fz;
+    // weights, normalised where several particles share the cell and sum above 1
+    double Bs[KMAX];
+    double Bsum = 0.0;
+    for (int m = 0; m < k; ++m) {
+      Bs[m] = pairs.B[mem[m]];
+      Bsum += Bs[m];
+    }
+    if (Bsum > 1.0) {
+      for (int m = 0; m < k; ++m) Bs[m] = Bs[m] * (1.0 / Bsum);
+      Bsum = 0.0;
+      for (int m = 0; m < k; ++m) Bsum += Bs[m];
+    }
+    R acc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) acc[q] = 0;
+    const int x = c % I.nx, yz = c / I.nx, y = yz % I.ny, z = yz / I.ny;
+    const R inv_tau = (R)(1.0 / I.tau);
+    for (int m = 0; m < k; ++m) {
+      const int pm = pairs.p[mem[m]];
+      double r[3];
+      r[0] = min_image(((double)x + 0.5) - P.X[3 * pm + 0], (double)I.nx);
+      r[1] = min_image(((double)y + 0.5) - P.X[3 * pm + 1], (double)I.ny);
+      r[2] = min_image(((double)z + 0.5) - P.X[3 * pm + 2], (double)I.nz);
+      const double* Up = P.U + 3 * pm;
+      const double* Wp = P.Om + 3 * pm;
+      const double v0 = Up[0] + (Wp[1] * r[2] - Wp[2] * r[1]);
+      const double v1 = Up[1] + (Wp[2] * r[0] - Wp[0] * r[2]);
+      const double v2 = Up[2] + (Wp[0] * r[1] - Wp[1] * r[0]);
+      R eV[Q];
+      geq_all<R>(drho, (R)v0, (R)v1, (R)v2, eV);
+      const R B = (R)Bs[m];
+      R mx = 0, my = 0, mz = 0;
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const int qb = opp(q);
+        R om;
+        if (I.psm_m == 1) om = (g[qb] - eU[qb]) - (g[q] - eV[q]);
+        else if (I.psm_m == 2) om = (eV[q] - g[q]) + ((R)1 - inv_tau) * (g[q] - eU[q]);
+        else om = (g[qb] - eV[qb]) - (g[q] - eV[q]);
+        acc[q] += B * om;
+        mx -= (R)cx(q) * om;
+        my -= (R)cy(q) * om;
+        mz -= (R)cz(q) * om;
+      }
+      // F_s = B_s sum_q Omega_q c_qbar, T_s = (x_s - X_p) x F_s
+      const double Fx = Bs[m] * (double)mx, Fy = Bs[m] * (double)my, Fz = Bs[m] * (double)mz;
+      double* o = pairs.out + 6LL * mem[m];
+      o[0] = Fx;
+      o[1] = Fy;
+      o[2] = Fz;
+      o[3] = r[1] * Fz - r[2] * Fy;
+      o[4] = r[2] * Fx - r[0] * Fz;
+      o[5] = r[0] * Fy - r[1] * Fx;
+    }
+    const R omB = (R)(1.0 - Bsum);
+    // fluid operator and forcing, then Eq. LBM_Collide_PSM
+    R out[Q];
+    {
+      const R base = drho - (R)1.5 * (ux * ux + uy * uy + uz * uz);
+      const R C0 = lp * (g[0] - (R)wq(0) * base);
+      const R F0 = -(R)wq(0) * (R)3 * fu;
+      out[0] = g[0] + omB * C0 + acc[0] + omB * F0;
+#pragma unroll
+      for (int qa = 1; qa < Q; qa += 2) {
+        const int qb = qa + 1;
+        const R w = (R)wq(qa);
+        const R cu = (R)cx(qa) * ux + (R)cy(qa) * uy + (R)cz(qa) * uz;
+        const R cf = (R)cx(qa) * fx + (R)cy(qa) * fy + (R)cz(qa) * fz;
+        const R gp = (R)0.5 * (g[qa] + g[qb]), gm = (R)0.5 * (g[qa] - g[qb]);
+        const R ep = (R)0.5 * (eU[qa] + eU[qb]), em = (R)0.5 * (eU[qa] - eU[qb]);
+        const R cp = lp * (gp - ep), cm = lm * (gm - em);
+        const R Fp = w * ((R)9 * cu * cf - (R)3 * fu), Fm = w * ((R)3 * cf);
+        out[qa] = g[qa] + omB * (cp + cm) + acc[qa] + omB * (Fp + Fm);
+        out[qb] = g[qb] + omB * (cp - cm) + acc[qb] + omB * (Fp - Fm);
+      }
+    }
+    const int nx = I.nx, ny = I.ny, nz = I.nz;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int xa = wrapi(x + cx(q), nx), ya = wrapi(y + cy(q), ny), za = wrapi(z + cz(q), nz);
+      d[(long long)q * N + ((long long)za * ny + ya) * nx + xa] = Codec<S>::st(out[q]);
+    }
+  }
+}
+
+#define LBM_DISPATCH(prec, CALL)                          \
+  switch (prec) {                                         \
+    case PREC_FP64: { using S = double; CALL; } break;    \
+    case PREC_FP32: { using S = float; CALL; } break;     \
+    case PREC_FP16: { using S = _Float16; CALL; } break;  \
+    case PREC_BF16: { using S = __bf16; CALL; } break;    \
+    default: return hipErrorInvalidValue;                 \
+  }
+
+hipError_t launch_psm_collide(int prec, const int* count, int cap, const InstDev* insts, PartDev parts,
+                              PairDev pairs, const int* cellmap, const void* src, void* dst, hipStream_t st) {
+  const int grid = 2048;
+  LBM_DISPATCH(prec, hipLaunchKernelGGL(psm_collide_kernel<S>, dim3(grid), dim3(256), 0, st, count, cap, insts, parts,
+                                        pairs, cellmap, (const S*)src, (S*)dst));
+  return hipGetLastError();
+}
+
+// Eq. MacVel_PSM for the overlapped cells of instance `inst` within [c0, c0 + n):
+// u = (1 - B)(U + f_ext/2) + sum_s B_s v_s, written over the fluid velocity in out.
+template <typename S>
+__global__ void psm_fields_kernel(const int* __restrict__ count, int cap, const InstDev* __restrict__ insts,
+                                  PartDev P, PairDev pairs, const int* __restrict__ cellmap,
+                                  const S* __restrict__ buf, int inst, long long c0, long long n,
+                                  double* __restrict__ out) {
+  const int npairs = min(*count, cap);
+  for (int L = blockIdx.x * blockDim.x + threadIdx.x; L < npairs; L += gridDim.x * blockDim.x) {
+    const int p0 = pairs.p[L];
+    if (P.inst[p0] != inst) continue;
+    const InstDev& I = insts[inst];
+    const int c = pairs.cell[L];
+    if (c < c0 || c >= c0 + n) continue;
+    if (cellmap[I.cellmap_off + c] != L) continue;
+    int mem[KMAX];
+    const int k = gather_members(pairs, L, mem);
+    const long long N = I.ncell;
+    const S* s = buf + I.pdf_off;
+    double jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+      const double gq = (double)Codec<S>::ld(s[(long long)q * N + c]);
+      jx += cx(q) * gq;
+      jy += cy(q) * gq;
+      jz += cz(q) * gq;
+    }
+    double Bs[KMAX], Bsum = 0;
+    for (int m = 0; m < k; ++m) {
+      Bs[m] = pairs.B[mem[m]];
+      Bsum += Bs[m];
+    }
+    if (Bsum > 1.0) {
+      for (int m = 0; m < k; ++m) Bs[m] = Bs[m] * (1.0 / Bsum);
+      Bsum = 0.0;
+      for (int m = 0; m < k; ++m) Bsum += Bs[m];
+    }
+    const int x = c % I.nx, yz = c / I.nx, y = yz % I.ny, z = yz / I.ny;
+    double u[3] = {(1.0 - Bsum) * (jx + 0.5 * I.fext[0]), (1.0 - Bsum) * (jy + 0.5 * I.fext[1]),
+                   (1.0 - Bsum) * (jz + 0.5 * I.fext[2])};
+    for (int m = 0; m < k; ++m) {
+      const int pm = pairs.p[mem[m]];
+      double r[3];
+      r[0] = min_image(((double)x + 0.5) - P.X[3 * pm + 0], (double)I.nx);
+      r[1] = min_image(((double)y + 0.5) - P.X[3 * pm + 1], (double)I.ny);
+      r[2] = min_image(((double)z + 0.5) - P.X[3 * pm + 2], (double)I.nz);
+      const double* Up = P.U + 3 * pm;
+      const double* Wp = P.Om + 3 * pm;
+      u[0] += Bs[m] * (Up[0] + (Wp[1] * r[2] - Wp[2] * r[1]));
+      u[1] += Bs[m] * (Up[1] + (Wp[2] * r[0] - Wp[0] * r[2]));
+      u[2] += Bs[m] * (Up[2] + (Wp[0] * r[1] - Wp[1] * r[0]));
+    }
+    const long long i = c - c0;
+    out[n + i] = u[0];
+    out[2 * n + i] = u[1];
+    out[3 * n + i] = u[2];
+  }
+}
+
+hipError_t launch_psm_fields(int prec, const int* count, int cap, const InstDev* insts, PartDev parts, PairDev pairs,
+                             const int* cellmap, const void* buf, int inst, long long c0, long long n, double* out,
+                             hipStream_t st) {
+  LBM_DISPATCH(prec, hipLaunchKernelGGL(psm_fields_kernel<S>, dim3(512), dim3(256), 0, st, count, cap, insts, parts,
+                                        pairs, cellmap, (const S*)buf, inst, c0, n, out));
+  return hipGetLastError();
+}
+
+}  // namespace lbm

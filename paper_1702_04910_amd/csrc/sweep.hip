@@ -1,0 +1,246 @@
+// Fused D3Q19 collide-and-push sweep (Sec. 2.1, Eqs. LBM_Collide, LBM_Stream,
+// LBM_EQ, LBM_SRT, MEM_TRT, Forcing) and the field/PDF conversion kernels.
+//
+// One sweep reads the canonical PDFs f(x, t) of every cell from buffer `src`
+// (aligned, coalesced along x), collides them with BGK or TRT plus the body
+// force, and pushes f~_q(x, t) to x + c_q in buffer `dst` (periodic wrap).
+// The sweep knows nothing about particles: coupling is applied afterwards by
+// the link kernel (MEM) and the overlap kernel (PSM), which overwrite the few
+// affected values.  Each workgroup owns whole x-rows, so every cache line of
+// `dst` is written by a single workgroup (row pitch * element size is a
+// multiple of the line size for the supported sizes).
+#include "common.h"
+#include "kernels.h"
+
+namespace lbm {
+
+// c.v for a lattice velocity with components (a, b, c) in {-1, 0, 1}, without
+// multiplications or additions of zero terms.
+template <typename R, int k>
+__device__ __forceinline__ R term(R v) {
+  return k == 1 ? v : -v;
+}
+template <typename R, int a, int b, int c>
+__device__ __forceinline__ R dot3(R x, R y, R z) {
+  if constexpr (a != 0 && b != 0) return term<R, a>(x) + term<R, b>(y);
+  else if constexpr (a != 0 && c != 0) return term<R, a>(x) + term<R, c>(z);
+  else if constexpr (b != 0 && c != 0) return term<R, b>(y) + term<R, c>(z);
+  else if constexpr (a != 0) return term<R, a>(x);
+  else if constexpr (b != 0) return term<R, b>(y);
+  else if constexpr (c != 0) return term<R, c>(z);
+  else return (R)0;
+}
+
+// TRT collision of the pair (QA, QA + 1) in deviation variables; see the
+// collision operator of Eq. MEM_TRT with f^+- = (f_q +- f_qbar)/2 and the
+// forcing of Eq. Forcing split into its symmetric and antisymmetric parts.
+template <typename R, int QA>
+__device__ __forceinline__ void trt_pair(const R (&g)[Q], R (&o)[Q], R base, R ux, R uy, R uz, R fx, R fy, R fz,
+                                         R fu, R lp, R lm) {
+  constexpr int QB = QA + 1;
+  const R w = (R)wq(QA);
+  const R cu = dot3<R, cx(QA), cy(QA), cz(QA)>(ux, uy, uz);
+  const R cf = dot3<R, cx(QA), cy(QA), cz(QA)>(fx, fy, fz);
+  const R eqp = w * (base + (R)4.5 * cu * cu);
+  const R eqm = w * ((R)3 * cu);
+  const R Fp = w * ((R)9 * cu * cf - (R)3 * fu);
+  const R Fm = w * ((R)3 * cf);
+  const R gp = (R)0.5 * (g[QA] + g[QB]);
+  const R gm = (R)0.5 * (g[QA] - g[QB]);
+  const R cp = lp * (gp - eqp) + Fp;
+  const R cm = lm * (gm - eqm) + Fm;
+  o[QA] = g[QA] + cp + cm;
+  o[QB] = g[QB] + cp - cm;
+}
+
+template <typename R>
+__device__ __forceinline__ void collide_cell(const R (&g)[Q], R (&o)[Q], R lp, R lm, R fx, R fy, R fz) {
+  R drho = g[0];
+#pragma unroll
+  for (int q = 1; q < Q; ++q) drho += g[q];
+  const R ux = (g[1] - g[2]) + (g[7] - g[8]) + (g[9] - g[10]) + (g[11] - g[12]) + (g[13] - g[14]);
+  const R uy = (g[3] - g[4]) + (g[7] - g[8]) + (g[10] - g[9]) + (g[15] - g[16]) + (g[17] - g[18]);
+  const R uz = (g[5] - g[6]) + (g[11] - g[12]) + (g[14] - g[13]) + (g[15] - g[16]) + (g[18] - g[17]);
+  const R uu = ux * ux + uy * uy + uz * uz;
+  const R fu = ux * fx + uy * fy + uz * fz;
+  const R base = drho - (R)1.5 * uu;
+  o[0] = g[0] + lp * (g[0] - (R)wq(0) * base) - (R)wq(0) * (R)3 * fu;
+  trt_pair<R, 1>(g, o, base, ux, uy, uz, fx, fy, fz, fu, lp, lm);
+  trt_pair<R, 3>(g, o, base, ux, uy, uz, fx, fy, fz, fu, lp, lm);
+  trt_pair<R, 5>(g, o, base, ux, uy, uz, fx, fy, fz, fu, lp, lm);
+  trt_pair<R, 7>(g, o, base, ux, uy, uz, fx, fy, fz, fu, lp, lm);
+  trt_pair<R, 9>(g, o, base, ux, uy, uz, fx, fy, fz, fu, lp, lm);
+  trt_pair<R, 11>(g, o, base, ux, uy, uz, fx, fy, fz, fu, lp, lm);
+  trt_pair<R, 13>(g, o, base, ux, uy, uz, fx, fy, fz, fu, lp, lm);
+  trt_pair<R, 15>(g, o, base, ux, uy, uz, fx, fy, fz, fu, lp, lm);
+  trt_pair<R, 17>(g, o, base, ux, uy, uz, fx, fy, fz, fu, lp, lm);
+}
+
+template <int q>
+__device__ __forceinline__ int pick(int m, int c, int p) {
+  return q < 0 ? m : (q > 0 ? p : c);
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void sweep_kernel(const InstDev* __restrict__ insts, const int4* __restrict__ tiles,
+                                                    int ntiles, const S* __restrict__ src, S* __restrict__ dst) {
+  using R = typename CompOf<S>::type;
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int4 tl = tiles[t];
+    const InstDev& I = insts[tl.x];
+    const int nx = I.nx, ny = I.ny, nz = I.nz;
+    const long long N = I.ncell;
+    const S* __restrict__ s = src + I.pdf_off;
+    S* __restrict__ d = dst + I.pdf_off;
+    const R lp = (R)I.lam_p, lm = (R)I.lam_m;
+    const R fx = (R)I.fext[0], fy = (R)I.fext[1], fz = (R)I.fext[2];
+    const int ncells = tl.z * nx;
+    for (int i = threadIdx.x; i < ncells; i += blockDim.x) {
+      const int r = i / nx;
+      const int x = i - r * nx;
+      const int row = tl.y + r;
+      const int z = row / ny;
+      const int y = row - z * ny;
+      const int idx = row * nx + x;
+      R g[Q], o[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) g[q] = Codec<S>::ld(s[(long long)q * N + idx]);
+      collide_cell<R>(g, o, lp, lm, fx, fy, fz);
+      const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+      const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+      const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+#define LBM_PUSH(qq)                                                                                   \
+  {                                                                                                    \
+    const int xa = pick<cx(qq)>(xm, x, xp), ya = pick<cy(qq)>(ym, y, yp), za = pick<cz(qq)>(zm, z, zp); \
+    d[(long long)(qq) * N + (za * ny + ya) * nx + xa] = Codec<S>::st(o[qq]);                          \
+  }
+      LBM_PUSH(0) LBM_PUSH(1) LBM_PUSH(2) LBM_PUSH(3) LBM_PUSH(4) LBM_PUSH(5) LBM_PUSH(6)
+      LBM_PUSH(7) LBM_PUSH(8) LBM_PUSH(9) LBM_PUSH(10) LBM_PUSH(11) LBM_PUSH(12) LBM_PUSH(13)
+      LBM_PUSH(14) LBM_PUSH(15) LBM_PUSH(16) LBM_PUSH(17) LBM_PUSH(18)
+#undef LBM_PUSH
+    }
+  }
+}
+
+// Uniform equilibrium initial state, Eq. LBM_EQ: g_q = w_q (rho - 1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u).
+template <typename S>
+__global__ void init_eq_kernel(S* __restrict__ buf, long long N, double rho, double ux, double uy, double uz) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const double uu = ux * ux + uy * uy + uz * uz;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const double cu = cx(q) * ux + cy(q) * uy + cz(q) * uz;
+    const double v = wq(q) * ((rho - 1.0) + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+    buf[(long long)q * N + i] = Codec<S>::st((typename CompOf<S>::type)v);
+  }
+}
+
+template <typename S>
+__global__ void to_f64_kernel(const S* __restrict__ a, double* __restrict__ b, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (double)Codec<S>::ld(a[i]);
+}
+
+template <typename S>
+__global__ void from_f64_kernel(const double* __restrict__ a, S* __restrict__ b, long long n) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = Codec<S>::st((typename CompOf<S>::type)a[i]);
+}
+
+// Density and macroscopic velocity (Eq. MacVel) of cells [c0, c0 + n); solid
+// cells of the owner field report rho = 1, u = 0.  Output: out[0..n) rho,
+// out[n..4n) u_x, u_y, u_z.
+template <typename S>
+__global__ void fields_kernel(const S* __restrict__ buf, long long N, long long c0, long long n,
+                              const int* __restrict__ owner, double fx, double fy, double fz,
+                              double* __restrict__ out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const long long c = c0 + i;
+  double rho = 1.0, ux = 0.0, uy = 0.0, uz = 0.0;
+  const bool solid = owner != nullptr && !own_is_fluid(owner[c]);
+  if (!solid) {
+    double g[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) g[q] = (double)Codec<S>::ld(buf[(long long)q * N + c]);
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) s += g[q];
+    rho = 1.0 + s;
+    double jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+      jx += cx(q) * g[q];
+      jy += cy(q) * g[q];
+      jz += cz(q) * g[q];
+    }
+    ux = jx + 0.5 * fx;
+    uy = jy + 0.5 * fy;
+    uz = jz + 0.5 * fz;
+  }
+  out[i] = rho;
+  out[n + i] = ux;
+  out[2 * n + i] = uy;
+  out[3 * n + i] = uz;
+}
+
+// ------------------------------------------------------------------------ launchers
+template <typename S>
+hipError_t launch_sweep_t(const InstDev* insts, const int4* tiles, int ntiles, int grid, int block, const void* src,
+                          void* dst, hipStream_t st) {
+  hipLaunchKernelGGL(sweep_kernel<S>, dim3(grid), dim3(block), 0, st, insts, tiles, ntiles, (const S*)src, (S*)dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep(int prec, const InstDev* insts, const int4* tiles, int ntiles, int grid, int block,
+                        const void* src, void* dst, hipStream_t st) {
+  switch (prec) {
+    case PREC_FP64: return launch_sweep_t<double>(insts, tiles, ntiles, grid, block, src, dst, st);
+    case PREC_FP32: return launch_sweep_t<float>(insts, tiles, ntiles, grid, block, src, dst, st);
+    case PREC_FP16: return launch_sweep_t<_Float16>(insts, tiles, ntiles, grid, block, src, dst, st);
+    case PREC_BF16: return launch_sweep_t<__bf16>(insts, tiles, ntiles, grid, block, src, dst, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+#define LBM_DISPATCH(prec, CALL)                  \
+  switch (prec) {                                 \
+    case PREC_FP64: { using S = double; CALL; } break;   \
+    case PREC_FP32: { using S = float; CALL; } break;    \
+    case PREC_FP16: { using S = _Float16; CALL; } break; \
+    case PREC_BF16: { using S = __bf16; CALL; } break;   \
+    default: return hipErrorInvalidValue;          \
+  }
+
+hipError_t launch_init_eq(int prec, void* buf, long long N, double rho, const double u[3], hipStream_t st) {
+  const int b = 256;
+  const unsigned g = (unsigned)((N + b - 1) / b);
+  LBM_DISPATCH(prec, hipLaunchKernelGGL(init_eq_kernel<S>, dim3(g), dim3(b), 0, st, (S*)buf, N, rho, u[0], u[1], u[2]));
+  return hipGetLastError();
+}
+
+hipError_t launch_to_f64(int prec, const void* a, double* b, long long n, hipStream_t st) {
+  const int bl = 256;
+  const unsigned g = (unsigned)((n + bl - 1) / bl);
+  LBM_DISPATCH(prec, hipLaunchKernelGGL(to_f64_kernel<S>, dim3(g), dim3(bl), 0, st, (const S*)a, b, n));
+  return hipGetLastError();
+}
+
+hipError_t launch_from_f64(int prec, const double* a, void* b, long long n, hipStream_t st) {
+  const int bl = 256;
+  const unsigned g = (unsigned)((n + bl - 1) / bl);
+  LBM_DISPATCH(prec, hipLaunchKernelGGL(from_f64_kernel<S>, dim3(g), dim3(bl), 0, st, a, (S*)b, n));
+  return hipGetLastError();
+}
+
+hipError_t launch_fields(int prec, const void* buf, long long N, long long c0, long long n, const int* owner,
+                         const double f[3], double* out, hipStream_t st) {
+  const int bl = 256;
+  const unsigned g = (unsigned)((n + bl - 1) / bl);
+  LBM_DISPATCH(prec, hipLaunchKernelGGL(fields_kernel<S>, dim3(g), dim3(bl), 0, st, (const S*)buf, N, c0, n, owner,
+                                        f[0], f[1], f[2], out));
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,131 @@
+"""Seeded synthetic workloads (numpy only; no lattice Boltzmann arithmetic).
+
+Shapes and parameters follow the paper's two experiments: the simple-cubic
+sphere array of Sec. 3 and the settling sphere of Sec. 4.1 (sphere resolution
+8-48 cells per diameter, density ratio around 1.5, viscosity 0.01, particle
+Reynolds numbers 185-365).  The benchmark's own reference data are not used;
+these inputs stand in for its configurations.
+
+Every generator takes a seed and returns plain Python/numpy values.
+"""
+import math
+
+import numpy as np
+
+# (Re, Ga) pairs of the four regimes (reference rows of Tabs. 1-4 and the Ga of
+# Sec. 4.2-4.5): Re = Ga |u_pV / u_ref|
+RE_GA = [(185.0, 144.0), (242.0, 178.46), (261.4, 190.0), (365.1, 250.0)]
+
+
+def ga_for_re(re):
+    """Piecewise-linear Ga for a target particle Reynolds number (clamped)."""
+    res = [r for r, _ in RE_GA]
+    gas = [g for _, g in RE_GA]
+    return float(np.interp(re, res, gas))
+
+
+def gravity_for(ga, nu, D, rho_ratio):
+    """|g| from Eq. Galileo: Ga = sqrt(|rho_p/rho_f - 1| g D^3) / nu."""
+    return (ga * nu) ** 2 / (abs(rho_ratio - 1.0) * D ** 3)
+
+
+def c1_plain(seed=0):
+    """32x32x64 periodic box, one fixed sphere D = 8 at the box centre with a
+    seeded offset uniform in +-1/2 cell, body force 1e-6 along x."""
+    rng = np.random.default_rng(seed)
+    off = rng.uniform(-0.5, 0.5, 3)
+    return dict(nx=32, ny=32, nz=64, D=8.0, X=np.array([16.0, 16.0, 32.0]) + off, f_ext=(1e-6, 0.0, 0.0),
+                nus=(0.01, 1.0 / 30.0, 0.1), steps=100, eps_n=8)
+
+
+def settling_sphere(seed, D, box, height_frac=0.75, nu=None, re=None, rho_ratio=None):
+    """One settling sphere: density ratio uniform in [1.1, 1.5], target Re uniform
+    in [185, 365], Ga from the (Re, Ga) pairs, g along -z, centred in x, y at
+    `height_frac` of the box height plus a seeded offset uniform in +-1/2 cell."""
+    rng = np.random.default_rng(seed)
+    if rho_ratio is None:
+        rho_ratio = float(rng.uniform(1.1, 1.5))
+    if re is None:
+        re = float(rng.uniform(185.0, 365.0))
+    if nu is None:
+        nu = 0.01
+    ga = ga_for_re(re)
+    g = gravity_for(ga, nu, D, rho_ratio)
+    nx, ny, nz = box
+    X = np.array([nx / 2.0, ny / 2.0, nz * height_frac]) + rng.uniform(-0.5, 0.5, 3)
+    # uniform fluid body force balancing the particle's net weight (periodic box)
+    V = math.pi * D ** 3 / 6.0
+    fz = (rho_ratio - 1.0) * V * g / (nx * ny * nz)
+    return dict(nx=nx, ny=ny, nz=nz, D=float(D), X=X, rho=rho_ratio, re=re, ga=ga, nu=nu,
+                gravity=(0.0, 0.0, -g), f_ext=(0.0, 0.0, fz))
+
+
+def c2_scale(seed=0):
+    return settling_sphere(seed, 24.0, (192, 192, 384))
+
+
+def c3_precision(seed=0):
+    return settling_sphere(seed, 48.0, (512, 512, 1024), re=300.0, rho_ratio=1.5)
+
+
+def c4_batch(seed=0, n=48):
+    """48 settling-sphere instances: D from {8, 12, 16, 24}, box 6D x 6D x 12D,
+    density ratio in [1.1, 1.5], nu = 0.1 D / Re for terminal speed ~0.1,
+    coupling alternating MEM-CLI / PSM (M2B2 or M3B2) by the seed."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        D = float(rng.choice([8, 12, 16, 24]))
+        rho = float(rng.uniform(1.1, 1.5))
+        re = float(rng.uniform(185.0, 365.0))
+        nu = 0.1 * D / re
+        box = (int(6 * D), int(6 * D), int(12 * D))
+        inst = settling_sphere(int(rng.integers(1 << 30)), D, box, nu=nu, re=re, rho_ratio=rho)
+        kind = rng.integers(0, 3)
+        inst["coupling"] = "mem_cli" if kind == 0 else "psm"
+        inst["psm_m"], inst["psm_b"] = (2, 2) if kind == 1 else (3, 2)
+        out.append(inst)
+    return out
+
+
+def c5_many(seed=0, n=2000, L=512, dmin=12.0, dmax=20.0, gap=2.0):
+    """n spheres, D uniform in [dmin, dmax], random sequential addition in an
+    L^3 periodic box with surface gap >= `gap` cells (seeded)."""
+    rng = np.random.default_rng(seed)
+    Xs, Ds = [], []
+    cell = 32.0
+    grid = {}
+    tries = 0
+    while len(Xs) < n and tries < 200 * n:
+        tries += 1
+        D = float(rng.uniform(dmin, dmax))
+        X = rng.uniform(0.0, L, 3)
+        key = tuple((X // cell).astype(int))
+        ok = True
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    k2 = ((key[0] + dx) % int(L // cell), (key[1] + dy) % int(L // cell), (key[2] + dz) % int(L // cell))
+                    for j in grid.get(k2, []):
+                        d = X - Xs[j]
+                        d -= L * np.round(d / L)
+                        if np.sqrt((d * d).sum()) < 0.5 * (D + Ds[j]) + gap:
+                            ok = False
+                            break
+                    if not ok:
+                        break
+                if not ok:
+                    break
+            if not ok:
+                break
+        if ok:
+            grid.setdefault(key, []).append(len(Xs))
+            Xs.append(X)
+            Ds.append(D)
+    return dict(L=L, X=np.array(Xs), D=np.array(Ds))
+
+
+def random_pdfs(shape, scale, seed):
+    """Seeded random PDF deviations g[19, z, y, x]."""
+    rng = np.random.default_rng(seed)
+    return scale * rng.standard_normal((19,) + tuple(shape))

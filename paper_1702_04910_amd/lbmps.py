@@ -1,0 +1,281 @@
+"""Python binding of the lbmps C-ABI (include/lbmps.h): argument marshalling only.
+
+Every computation runs in the HIP library ``liblbmps.so`` built in this
+package directory; torch supplies the device workspace and the stream.  If the
+library is missing, importing it raises -- there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbmps.so")
+
+BGK, TRT = 0, 1
+NONE, MEM_BB, MEM_CLI, PSM = 0, 1, 2, 3
+FP64, FP32, FP16_DEV, BF16_DEV = 0, 1, 2, 3
+EPS_FLAT, EPS_RECURSIVE = 0, 1
+COUPLING = {"none": NONE, "mem_bb": MEM_BB, "mem_cli": MEM_CLI, "psm": PSM}
+PRECISION = {"fp64": FP64, "fp32": FP32, "fp16": FP16_DEV, "bf16": BF16_DEV}
+STORAGE_BYTES = {FP64: 8, FP32: 4, FP16_DEV: 2, BF16_DEV: 2}
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("collision", ctypes.c_int32), ("coupling", ctypes.c_int32),
+        ("psm_m", ctypes.c_int32), ("psm_b", ctypes.c_int32), ("n_sub", ctypes.c_int32),
+        ("eps_n", ctypes.c_int32), ("eps_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("max_particles", ctypes.c_int32), ("tile_rows", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+        ("grid_blocks", ctypes.c_int32), ("wall_link_cap", ctypes.c_int32),
+        ("max_diameter", ctypes.c_double), ("nu", ctypes.c_double), ("magic", ctypes.c_double),
+        ("f_ext", ctypes.c_double * 3), ("gravity", ctypes.c_double * 3),
+    ]
+
+
+class Particle(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_double * 3), ("U", ctypes.c_double * 3), ("Omega", ctypes.c_double * 3),
+                ("D", ctypes.c_double), ("rho_p", ctypes.c_double), ("fixed", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
+
+
+class ParticleState(ctypes.Structure):
+    _fields_ = [("F", ctypes.c_double * 3), ("T", ctypes.c_double * 3), ("U", ctypes.c_double * 3),
+                ("Omega", ctypes.c_double * 3), ("X", ctypes.c_double * 3)]
+
+
+class LbmpsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("lbmps status %d: %s" % (status, msg))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("liblbmps.so is not built: run `python -m paper_1702_04910_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, D, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+        L.lbmps_workspace_bytes.restype = SZ
+        L.lbmps_workspace_bytes.argtypes = [P]
+        L.lbmps_batch_workspace_bytes.restype = SZ
+        L.lbmps_batch_workspace_bytes.argtypes = [I32, P]
+        L.lbmps_batch_create.restype = I32
+        L.lbmps_batch_create.argtypes = [I32, P, P, SZ, P, ctypes.POINTER(P)]
+        L.lbmps_create.restype = I32
+        L.lbmps_create.argtypes = [P, P, SZ, P, ctypes.POINTER(P)]
+        L.lbmps_destroy.restype = None
+        L.lbmps_destroy.argtypes = [P]
+        L.lbmps_init_equilibrium.restype = I32
+        L.lbmps_init_equilibrium.argtypes = [P, I32, D, P]
+        L.lbmps_set_static_solid.restype = I32
+        L.lbmps_set_static_solid.argtypes = [P, I32, P, P]
+        L.lbmps_set_particles.restype = I32
+        L.lbmps_set_particles.argtypes = [P, I32, I32, P]
+        L.lbmps_step.restype = I32
+        L.lbmps_step.argtypes = [P, I32]
+        L.lbmps_sync.restype = I32
+        L.lbmps_sync.argtypes = [P]
+        L.lbmps_get_particles.restype = I32
+        L.lbmps_get_particles.argtypes = [P, I32, I32, P]
+        L.lbmps_get_fields.restype = I32
+        L.lbmps_get_fields.argtypes = [P, I32, P, P]
+        L.lbmps_get_pdfs.restype = I32
+        L.lbmps_get_pdfs.argtypes = [P, I32, P]
+        L.lbmps_set_pdfs.restype = I32
+        L.lbmps_set_pdfs.argtypes = [P, I32, P]
+        L.lbmps_get_links.restype = I32
+        L.lbmps_get_links.argtypes = [P, I64, P, P, P, P, ctypes.POINTER(I64)]
+        L.lbmps_get_overlaps.restype = I32
+        L.lbmps_get_overlaps.argtypes = [P, I64, P, P, P, ctypes.POINTER(I64)]
+        L.lbmps_particle_base.restype = I32
+        L.lbmps_particle_base.argtypes = [P, I32]
+        L.lbmps_status_string.restype = ctypes.c_char_p
+        L.lbmps_status_string.argtypes = [I32]
+        L.lbmps_last_error.restype = ctypes.c_char_p
+        L.lbmps_last_error.argtypes = [P]
+        L.lbmps_set_timing.restype = I32
+        L.lbmps_set_timing.argtypes = [P, I32]
+        L.lbmps_get_timing.restype = I32
+        L.lbmps_get_timing.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(I64)]
+        L.lbmps_velocities.restype = None
+        L.lbmps_velocities.argtypes = [P]
+        _lib = L
+    return _lib
+
+
+def velocities():
+    c = np.zeros((19, 3), dtype=np.int32)
+    lib().lbmps_velocities(c.ctypes.data)
+    return c
+
+
+def make_config(nx, ny, nz, nu, collision="trt", coupling="none", psm_m=1, psm_b=1, n_sub=0, eps_n=8,
+                eps_mode=EPS_FLAT, precision="fp64", max_particles=0, max_diameter=0.0, magic=3.0 / 16.0,
+                f_ext=(0.0, 0.0, 0.0), gravity=(0.0, 0.0, 0.0), tile_rows=0, block_threads=0, grid_blocks=0,
+                wall_link_cap=0):
+    c = Config()
+    c.nx, c.ny, c.nz = nx, ny, nz
+    c.collision = TRT if collision == "trt" else BGK
+    c.coupling = COUPLING[coupling] if isinstance(coupling, str) else coupling
+    c.psm_m, c.psm_b, c.n_sub = psm_m, psm_b, n_sub
+    c.eps_n, c.eps_mode = eps_n, eps_mode
+    c.precision = PRECISION[precision] if isinstance(precision, str) else precision
+    c.max_particles = max_particles
+    c.tile_rows, c.block_threads, c.grid_blocks, c.wall_link_cap = tile_rows, block_threads, grid_blocks, wall_link_cap
+    c.max_diameter, c.nu, c.magic = max_diameter, nu, magic
+    for k in range(3):
+        c.f_ext[k] = f_ext[k]
+        c.gravity[k] = gravity[k]
+    return c
+
+
+def workspace_bytes(cfgs):
+    if isinstance(cfgs, Config):
+        cfgs = [cfgs]
+    arr = (Config * len(cfgs))(*cfgs)
+    return int(lib().lbmps_batch_workspace_bytes(len(cfgs), ctypes.addressof(arr)))
+
+
+class Sim:
+    """A context of one or more lattice instances (batched when len(cfgs) > 1)."""
+
+    def __init__(self, cfgs, device="cuda", stream=None):
+        import torch
+
+        if isinstance(cfgs, Config):
+            cfgs = [cfgs]
+        self.cfgs = list(cfgs)
+        self._arr = (Config * len(cfgs))(*cfgs)
+        nbytes = int(lib().lbmps_batch_workspace_bytes(len(cfgs), ctypes.addressof(self._arr)))
+        if nbytes == 0:
+            raise LbmpsError(-1, "invalid configuration")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._ctx = ctypes.c_void_p()
+        st = lib().lbmps_batch_create(len(cfgs), ctypes.addressof(self._arr), self.workspace.data_ptr(), nbytes,
+                                      self.stream.cuda_stream, ctypes.byref(self._ctx))
+        if st != 0:
+            msg = lib().lbmps_last_error(self._ctx).decode() if self._ctx.value else ""
+            raise LbmpsError(st, msg)
+        self.n_particles = [0] * len(cfgs)
+
+    # -- helpers
+    def _chk(self, st):
+        if st != 0:
+            raise LbmpsError(st, lib().lbmps_last_error(self._ctx).decode())
+
+    def close(self):
+        if self._ctx.value:
+            lib().lbmps_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def ncell(self, inst=0):
+        c = self.cfgs[inst]
+        return c.nx * c.ny * c.nz
+
+    # -- API
+    def init_equilibrium(self, rho=1.0, u=(0.0, 0.0, 0.0), inst=0):
+        uu = (ctypes.c_double * 3)(*u)
+        self._chk(lib().lbmps_init_equilibrium(self._ctx, inst, float(rho), ctypes.addressof(uu)))
+
+    def set_static_solid(self, mask, v_wall=(0.0, 0.0, 0.0), inst=0):
+        m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8).reshape(-1))
+        assert m.size == self.ncell(inst)
+        v = (ctypes.c_double * 3)(*v_wall)
+        self._chk(lib().lbmps_set_static_solid(self._ctx, inst, m.ctypes.data, ctypes.addressof(v)))
+
+    def set_particles(self, X, U, Om, D, rho_p, fixed, inst=0):
+        n = len(D)
+        arr = (Particle * max(n, 1))()
+        for i in range(n):
+            for k in range(3):
+                arr[i].X[k] = float(X[i][k])
+                arr[i].U[k] = float(U[i][k])
+                arr[i].Omega[k] = float(Om[i][k])
+            arr[i].D = float(D[i])
+            arr[i].rho_p = float(rho_p[i])
+            arr[i].fixed = 1 if fixed[i] else 0
+        self._chk(lib().lbmps_set_particles(self._ctx, inst, n, ctypes.addressof(arr)))
+        self.n_particles[inst] = n
+
+    def step(self, n):
+        self._chk(lib().lbmps_step(self._ctx, int(n)))
+
+    def sync(self):
+        self._chk(lib().lbmps_sync(self._ctx))
+
+    def particles(self, inst=0):
+        n = self.n_particles[inst]
+        arr = (ParticleState * max(n, 1))()
+        self._chk(lib().lbmps_get_particles(self._ctx, inst, n, ctypes.addressof(arr)))
+        out = {k: np.array([[getattr(arr[i], k)[j] for j in range(3)] for i in range(n)]).reshape(-1, 3)
+               for k in ("F", "T", "U", "Omega", "X")}
+        return out
+
+    def fields(self, inst=0):
+        N = self.ncell(inst)
+        c = self.cfgs[inst]
+        rho = np.empty(N)
+        u = np.empty(3 * N)
+        self._chk(lib().lbmps_get_fields(self._ctx, inst, rho.ctypes.data, u.ctypes.data))
+        return rho.reshape(c.nz, c.ny, c.nx), u.reshape(3, c.nz, c.ny, c.nx)
+
+    def get_pdfs(self, inst=0):
+        c = self.cfgs[inst]
+        g = np.empty(19 * self.ncell(inst))
+        self._chk(lib().lbmps_get_pdfs(self._ctx, inst, g.ctypes.data))
+        return g.reshape(19, c.nz, c.ny, c.nx)
+
+    def set_pdfs(self, g, inst=0):
+        g = np.ascontiguousarray(np.asarray(g, dtype=np.float64).reshape(-1))
+        assert g.size == 19 * self.ncell(inst)
+        self._chk(lib().lbmps_set_pdfs(self._ctx, inst, g.ctypes.data))
+
+    def links(self):
+        n = ctypes.c_int64()
+        self._chk(lib().lbmps_get_links(self._ctx, 0, None, None, None, None, ctypes.byref(n)))
+        cnt = n.value
+        cell = np.empty(cnt, np.int32)
+        q = np.empty(cnt, np.int32)
+        p = np.empty(cnt, np.int32)
+        d = np.empty(cnt, np.float64)
+        self._chk(lib().lbmps_get_links(self._ctx, cnt, cell.ctypes.data, q.ctypes.data, p.ctypes.data,
+                                        d.ctypes.data, ctypes.byref(n)))
+        return dict(cell=cell, q=q, p=p, delta=d)
+
+    def overlaps(self):
+        n = ctypes.c_int64()
+        self._chk(lib().lbmps_get_overlaps(self._ctx, 0, None, None, None, ctypes.byref(n)))
+        cnt = n.value
+        cell = np.empty(cnt, np.int32)
+        p = np.empty(cnt, np.int32)
+        e = np.empty(cnt, np.float64)
+        self._chk(lib().lbmps_get_overlaps(self._ctx, cnt, cell.ctypes.data, p.ctypes.data, e.ctypes.data,
+                                           ctypes.byref(n)))
+        return dict(cell=cell, p=p, eps=e)
+
+    def set_timing(self, enable):
+        self._chk(lib().lbmps_set_timing(self._ctx, 1 if enable else 0))
+
+    def timing(self):
+        """(summed sweep-kernel milliseconds, number of sweep launches) since set_timing."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self._chk(lib().lbmps_get_timing(self._ctx, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def particle_base(self, inst):
+        return int(lib().lbmps_particle_base(self._ctx, inst))
