@@ -4,7 +4,8 @@
 Workload (default): one settling sphere, D = 24 cells, in a 192x192x384
 periodic box (14.16 M cells), density ratio and Galileo number from seed 0,
 nu = 0.01, TRT (Lambda = 3/16), momentum exchange with CLI links and refill,
-two LBM sweeps per rigid-body step, PDFs stored as FP32 deviations.  A bench
+two LBM sweeps per rigid-body step with averaged forces, PDFs stored as FP32
+deviations.  A bench
 "step" is one rigid-body step: two fused collide-push sweeps over the box, the
 link rule and link forces, the force/torque reduction, the rigid-body update,
 the remap with refill and the rebuild of the link list.
@@ -34,8 +35,9 @@ def log(*a):
 
 
 def build_sim(lbmps, inp, coupling, precision, psm=(3, 2), eps_n=8, **launch):
+    # two LBM sweeps per rigid-body step with averaged forces, for MEM and PSM (Sec. 4.1)
     cfg = lbmps.make_config(inp["nx"], inp["ny"], inp["nz"], inp["nu"], collision="trt", coupling=coupling,
-                            psm_m=psm[0], psm_b=psm[1], eps_n=eps_n, eps_mode=lbmps.EPS_RECURSIVE,
+                            psm_m=psm[0], psm_b=psm[1], n_sub=2, eps_n=eps_n, eps_mode=lbmps.EPS_RECURSIVE,
                             precision=precision, max_particles=1, max_diameter=inp["D"], f_ext=inp["f_ext"],
                             gravity=inp["gravity"], **launch)
     sim = lbmps.Sim(cfg)
@@ -152,9 +154,9 @@ def main():
                                      ("fp64_psm_m3b2", "psm", "fp64"), ("fp16_psm_m3b2", "psm", "fp16")]:
             log("form", name)
             s = build_sim(lbmps, inp, coupling, prec)
-            ns = n_sub if coupling.startswith("mem") else 1
-            steps = args.steps * n_sub // ns
-            w, ms_f, l_f = timed_run(torch, s, steps, args.warmup * n_sub // ns, ns)
+            ns = n_sub
+            steps = args.steps
+            w, ms_f, l_f = timed_run(torch, s, steps, args.warmup, ns)
             pf = s.particles()
             s.close()
             del s

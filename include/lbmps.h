@@ -73,7 +73,8 @@ typedef struct lbmps_config {
   int32_t coupling;    /* LBMPS_NONE, LBMPS_MEM_BB, LBMPS_MEM_CLI, LBMPS_PSM */
   int32_t psm_m;       /* 1, 2, 3: solid operator, Eqs. PSM_M1..M3 */
   int32_t psm_b;       /* 1, 2: weighting, Eqs. PSM_B1, PSM_B2 */
-  int32_t n_sub;       /* LBM sweeps per rigid-body step; 0 = 2 for MEM (Sec. 2.2.4), 1 otherwise */
+  int32_t n_sub;       /* LBM sweeps per rigid-body step, forces averaged over them (Sec. 2.2.4, Sec. 4.1);
+                          0 = 2 for MEM, 1 for PSM (Alg. 2) */
   int32_t eps_n;       /* supersampling points per axis (default 8) */
   int32_t eps_mode;    /* LBMPS_EPS_FLAT or LBMPS_EPS_RECURSIVE */
   int32_t precision;   /* LBMPS_FP64 .. LBMPS_BF16_DEV */
@@ -117,7 +118,8 @@ size_t lbmps_batch_workspace_bytes(int32_t n, const lbmps_config* cfgs);
 
 /* Create a context for one instance (lbmps_create) or for n independent
  * instances advanced together by every lbmps_step (lbmps_batch_create; all
- * instances share the storage precision; MEM instances share n_sub).
+ * instances share the storage precision; MEM instances share n_sub, and so
+ * do PSM instances).
  * dev_workspace: caller-owned device memory of `bytes` >= the size above.
  * hip_stream: a hipStream_t (may be NULL for the default stream).
  * Errors: EINVAL (config), ENOMEM (workspace too small), EDEVICE. */
@@ -145,8 +147,8 @@ lbmps_status lbmps_set_static_solid(lbmps_ctx* ctx, int32_t inst, const uint8_t*
  * D + 6 > min(nx, ny, nz), rho_p <= 0 or any value is non-finite. */
 lbmps_status lbmps_set_particles(lbmps_ctx* ctx, int32_t inst, int32_t n, const lbmps_particle* host);
 
-/* Advance every instance by n_steps LBM time steps (Alg. 1 / Alg. 2); for MEM
- * instances n_steps must be a multiple of n_sub.  Asynchronous. */
+/* Advance every instance by n_steps LBM time steps (Alg. 1 / Alg. 2);
+ * n_steps must be a multiple of every n_sub in the context.  Asynchronous. */
 lbmps_status lbmps_step(lbmps_ctx* ctx, int32_t n_steps);
 
 /* Block until the stream is idle; report device-side errors. */

@@ -11,7 +11,13 @@ One call of ``step(n)`` advances n LBM time steps:
   forces are averaged over the n_sub sweeps, the rigid bodies advance with
   dt = n_sub, and the particle mapping is updated with refill of uncovered cells.
 * PSM: every sweep = solid fractions from the current positions -> PSM collide
-  -> stream -> force/torque -> rigid body with dt = 1.
+  -> stream -> force/torque; every n_sub sweeps (default 1, Alg. 2) the forces
+  are averaged, the rigid bodies advance with dt = n_sub and the solid
+  fractions are recomputed.  (Sec. 4.1 obtains the sphere forces of the
+  settling benchmark from two averaged subcycles; with M3, whose force is
+  2 sum B (U - v), a single sweep per rigid-body step makes the fluid inside
+  fully covered cells and the sphere exchange an alternating momentum that
+  grows by (1 + 2 rho_f/rho_p) per step, so moving M3 runs use n_sub = 2.)
 * none: collide -> stream.
 Static walls (half-way bounce-back with a wall velocity) are applied after the
 stream in every mode.
@@ -188,10 +194,17 @@ class OracleSim:
                 if self._rigid(float(self.n_sub)):
                     self._remap()
             return
-        for _ in range(n):
-            self.F, self.T = self._sweep_psm()
-            self.time += 1
-            if self._rigid(1.0):
+        assert n % self.n_sub == 0, "PSM steps must be a multiple of n_sub"
+        for _ in range(n // self.n_sub):
+            P = len(self.parts)
+            Fs, Ts = np.zeros((P, 3)), np.zeros((P, 3))
+            for _s in range(self.n_sub):
+                F, T = self._sweep_psm()
+                Fs += F
+                Ts += T
+                self.time += 1
+            self.F, self.T = Fs / self.n_sub, Ts / self.n_sub
+            if self._rigid(float(self.n_sub)):
                 self._remap()
 
     # --- outputs ------------------------------------------------------------

@@ -38,7 +38,7 @@ size_t storage_size(int prec) {
 struct Layout {
   bool ok = false;
   std::string err;
-  int n = 0, prec = 0, side = 0, ptotal = 0, mem_nsub = 0;
+  int n = 0, prec = 0, side = 0, ptotal = 0, mem_nsub = 0, psm_nsub = 0;
   size_t ssz = 0;
   std::vector<long long> pdf_off, owner_off, cellmap_off, ncell;
   std::vector<int> part_begin;
@@ -74,13 +74,12 @@ bool valid_cfg(const lbmps_config& c, std::string& err) {
   if (c.eps_mode < 0 || c.eps_mode > 1) { err = "unknown eps_mode"; return false; }
   if (c.block_threads < 0 || c.block_threads > 256 || (c.block_threads % 64)) { err = "block_threads must be a multiple of 64, <= 256"; return false; }
   if (c.n_sub < 0) { err = "n_sub must be >= 0"; return false; }
-  if (c.coupling == LBMPS_PSM && c.n_sub > 1) { err = "PSM uses one sweep per rigid-body step (n_sub = 1)"; return false; }
   return true;
 }
 
 int eff_nsub(const lbmps_config& c) {
   if (c.coupling == LBMPS_MEM_BB || c.coupling == LBMPS_MEM_CLI) return c.n_sub ? c.n_sub : 2;
-  return 1;
+  return c.n_sub ? c.n_sub : 1;
 }
 
 int eff_tile_rows(const lbmps_config& c) {
@@ -101,6 +100,10 @@ Layout make_layout(int n, const lbmps_config* cfgs) {
     if (mem) {
       if (L.mem_nsub && L.mem_nsub != eff_nsub(cfgs[i])) { L.err = "MEM instances of a batch must share n_sub"; return L; }
       L.mem_nsub = eff_nsub(cfgs[i]);
+    }
+    if (cfgs[i].coupling == LBMPS_PSM) {
+      if (L.psm_nsub && L.psm_nsub != eff_nsub(cfgs[i])) { L.err = "PSM instances of a batch must share n_sub"; return L; }
+      L.psm_nsub = eff_nsub(cfgs[i]);
     }
     if (cfgs[i].max_particles > 0) dmax = std::max(dmax, cfgs[i].max_diameter);
   }
@@ -675,6 +678,7 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
   if (n < 0) return fail(c, LBMPS_EINVAL, "negative step count");
   const Layout& L = c->L;
   if (L.mem_nsub && (n % L.mem_nsub)) return fail(c, LBMPS_EINVAL, "MEM steps must be a multiple of n_sub");
+  if (L.psm_nsub && (n % L.psm_nsub)) return fail(c, LBMPS_EINVAL, "PSM steps must be a multiple of n_sub");
   unsigned* err = err_word(c);
   for (int s = 0; s < n; ++s) {
     void* src = c->buf[c->cur];
@@ -709,7 +713,7 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
     }
     c->cur = 1 - c->cur;
     c->sweeps++;
-    if (c->n_psm) {
+    if (c->n_psm && (c->sweeps % L.psm_nsub) == 0) {
       HIPCHK(c, launch_rigid(psm_list(c), c->n_psm, c->inst_d, c->parts, err, c->st));
       if (c->psm_moving) {
         lbmps_status r = rebuild_psm(c);

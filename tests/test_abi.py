@@ -48,7 +48,7 @@ def test_workspace_bytes_valid_and_invalid():
         lbmps.make_config(32, 32, 64, 0.1, max_particles=1, max_diameter=30.0),
         lbmps.make_config(32, 32, 64, 0.1, eps_n=6, eps_mode=lbmps.EPS_RECURSIVE),
         lbmps.make_config(32, 32, 64, 0.1, block_threads=100),
-        lbmps.make_config(32, 32, 64, 0.1, coupling="psm", n_sub=2),
+        lbmps.make_config(32, 32, 64, 0.1, coupling="psm", n_sub=-1),
     ]
     for b in bad:
         assert lbmps.workspace_bytes(b) == 0

@@ -111,15 +111,15 @@ def test_c1_box_mem_fixed_sphere(precision, coupling):
 def test_moving_mem_sphere_with_refill(coupling):
     # a sphere pushed through the box: cells are uncovered (refill) and covered
     say("moving MEM", coupling)
-    parts = dict(X=[[16.3, 15.8, 20.2]], U=[[0.02, -0.01, 0.03]], Om=[[0.0, 0.002, -0.001]], D=[7.0], rho=[1.2],
+    parts = dict(X=[[16.3, 15.8, 20.2]], U=[[0.01, -0.005, 0.0]], Om=[[0.0, 0.001, 0.0]], D=[7.0], rho=[1.5],
                  fixed=[False])
     ora, sim = make_pair(32, 32, 40, 0.05, coupling=coupling, collision="trt", f_ext=(0, 0, 1e-6),
-                         gravity=(0, 0, -2e-4), parts=parts)
+                         gravity=(0, 0, -1e-3), parts=parts)
     for k in range(5):
         ora.step(40)
         sim.step(40)
-        (eF, eT, nF), po, pg = force_errors(ora, sim)
-        eF, eT, nF = eF
+        errs, po, pg = force_errors(ora, sim)
+        eF, eT, nF = errs[0]
         e, _ = pdf_error(ora, sim)
         eX = np.abs(pg["X"] - po["X"]).max()
         say("  t=%d refilled=%d e_f=%.3e e_F=%.3e e_T=%.3e eX=%.3e" % (ora.time, ora.refilled, e, eF, eT, eX))
@@ -127,18 +127,18 @@ def test_moving_mem_sphere_with_refill(coupling):
     assert ora.refilled > 20
 
 
-@pytest.mark.parametrize("m,b", [(1, 1), (3, 2)])
-def test_moving_psm_sphere(m, b):
-    say("moving PSM", m, b)
-    parts = dict(X=[[16.3, 15.8, 20.2]], U=[[0.02, -0.01, 0.03]], Om=[[0.0, 0.002, -0.001]], D=[7.0], rho=[1.2],
+@pytest.mark.parametrize("m,b,n_sub", [(1, 1, 1), (2, 2, 1), (3, 2, 2)])
+def test_moving_psm_sphere(m, b, n_sub):
+    say("moving PSM", m, b, n_sub)
+    parts = dict(X=[[16.3, 15.8, 20.2]], U=[[0.01, -0.005, 0.0]], Om=[[0.0, 0.001, 0.0]], D=[7.0], rho=[1.5],
                  fixed=[False])
     ora, sim = make_pair(32, 32, 40, 0.05, coupling="psm", collision="bgk", psm_m=m, psm_b=b, f_ext=(0, 0, 1e-6),
-                         gravity=(0, 0, -2e-4), parts=parts, eps_n=4)
+                         gravity=(0, 0, -1e-3), parts=parts, eps_n=4, n_sub=n_sub)
     for k in range(4):
-        ora.step(25)
-        sim.step(25)
-        (eF, eT, nF), po, pg = force_errors(ora, sim)
-        eF, eT, nF = eF
+        ora.step(26)
+        sim.step(26)
+        errs, po, pg = force_errors(ora, sim)
+        eF, eT, nF = errs[0]
         e, _ = pdf_error(ora, sim)
         say("  t=%d e_f=%.3e e_F=%.3e e_T=%.3e" % (ora.time, e, eF, eT))
         assert e < 1e-11 and eF < 1e-11 and eT < 1e-11
