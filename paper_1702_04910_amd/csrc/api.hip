@@ -51,6 +51,7 @@ struct Layout {
   size_t o_bufA, o_bufB, o_owner, o_cellmap, o_inst, o_parts, o_plists, o_slots, o_totals, o_offsets, o_ranges,
       o_counts, o_links, o_wallv, o_pairs, o_refill, o_scratch, o_tiles, total;
   int ntiles = 0;
+  int max_tile_cells = 0;
 };
 
 bool valid_cfg(const lbmps_config& c, std::string& err) {
@@ -74,6 +75,9 @@ bool valid_cfg(const lbmps_config& c, std::string& err) {
   if (c.eps_mode < 0 || c.eps_mode > 1) { err = "unknown eps_mode"; return false; }
   if (c.block_threads < 0 || c.block_threads > 256 || (c.block_threads % 64)) { err = "block_threads must be a multiple of 64, <= 256"; return false; }
   if (c.n_sub < 0) { err = "n_sub must be >= 0"; return false; }
+  if (10LL * (long long)storage_size(c.precision) * c.nx > SWEEP_LDS_LIMIT) {
+    err = "nx too large for the LDS-staged sweep (10 * nx * element size must be <= 64 KiB)"; return false;
+  }
   return true;
 }
 
@@ -82,9 +86,13 @@ int eff_nsub(const lbmps_config& c) {
   return c.n_sub ? c.n_sub : 1;
 }
 
+// Rows per sweep tile: by default about 40 KB of LDS staging (10 shifted planes).
 int eff_tile_rows(const lbmps_config& c) {
-  if (c.tile_rows > 0) return c.tile_rows;
-  return std::max(1, 1024 / c.nx);
+  const int s = (int)storage_size(c.precision);
+  const int max_rows = std::max(1, SWEEP_LDS_LIMIT / (10 * s * c.nx));
+  if (c.tile_rows > 0) return std::min(c.tile_rows, max_rows);
+  const int target_cells = 40960 / (10 * s);
+  return std::max(1, std::min(max_rows, target_cells / c.nx));
 }
 
 Layout make_layout(int n, const lbmps_config* cfgs) {
@@ -137,6 +145,7 @@ Layout make_layout(int n, const lbmps_config* cfgs) {
                                  : 10LL * ((long long)c.nx * c.ny + (long long)c.ny * c.nz + (long long)c.nz * c.nx);
     cmax = std::max(cmax, N);
     L.ntiles += (c.ny * c.nz + eff_tile_rows(c) - 1) / eff_tile_rows(c);
+    L.max_tile_cells = std::max(L.max_tile_cells, eff_tile_rows(c) * c.nx);
   }
   if (links + walls >= (1LL << 31) || pairs >= (1LL << 31)) { L.err = "list capacities exceed 2^31"; return L; }
   L.pdf_elems = pdf;
@@ -695,7 +704,8 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
       }
       HIPCHK(c, hipEventRecord(c->ev[c->ev_used], c->st));
     }
-    HIPCHK(c, launch_sweep(L.prec, c->inst_d, c->tiles_d, c->ntiles, c->grid, c->block, src, dst, c->st));
+    HIPCHK(c, launch_sweep(L.prec, c->inst_d, c->tiles_d, c->ntiles, c->grid, c->block, L.max_tile_cells, src, dst,
+                           c->st));
     if (c->timing) {
       HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->st));
       c->ev_used += 2;

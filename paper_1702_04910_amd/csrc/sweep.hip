@@ -6,9 +6,8 @@
 // force, and pushes f~_q(x, t) to x + c_q in buffer `dst` (periodic wrap).
 // The sweep knows nothing about particles: coupling is applied afterwards by
 // the link kernel (MEM) and the overlap kernel (PSM), which overwrite the few
-// affected values.  Each workgroup owns whole x-rows, so every cache line of
-// `dst` is written by a single workgroup (row pitch * element size is a
-// multiple of the line size for the supported sizes).
+// affected values.  Each workgroup owns whole x-rows and realigns the +-x
+// shifted values through LDS, so all stores are aligned row segments.
 #include "common.h"
 #include "kernels.h"
 
@@ -81,10 +80,36 @@ __device__ __forceinline__ int pick(int m, int c, int p) {
   return q < 0 ? m : (q > 0 ? p : c);
 }
 
+// Streaming stores that bypass the cache hierarchy's write-allocate path.
+template <typename S>
+__device__ __forceinline__ void st_nt(S* p, S v) {
+  __builtin_nontemporal_store(v, p);
+}
+template <>
+__device__ __forceinline__ void st_nt<__bf16>(__bf16* p, __bf16 v) {
+  __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, v), (unsigned short*)p);
+}
+
+// Directions with c_x != 0 and their slot in the LDS staging area.
+__host__ __device__ constexpr int xslot(int q) {
+  return q == 1 ? 0 : q == 2 ? 1 : q == 7 ? 2 : q == 8 ? 3 : q == 9 ? 4 : q == 10 ? 5 : q == 11 ? 6
+       : q == 12 ? 7 : q == 13 ? 8 : q == 14 ? 9 : -1;
+}
+constexpr int NXSHIFT = 10;
+
+// One tile = `tl.z` whole x-rows of one instance.  Phase 1: every cell is
+// loaded (19 coalesced loads), collided, and its 9 post-collision values with
+// c_x = 0 are pushed straight to the neighbouring rows (aligned).  The 10
+// values with c_x = +-1 land in the same local row shifted by one cell, so they
+// are staged in LDS at their shifted position.  Phase 2: the staged rows are
+// written out aligned.  Every global store therefore covers whole, aligned row
+// segments.
 template <typename S>
 __global__ __launch_bounds__(256) void sweep_kernel(const InstDev* __restrict__ insts, const int4* __restrict__ tiles,
                                                     int ntiles, const S* __restrict__ src, S* __restrict__ dst) {
   using R = typename CompOf<S>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  S* sh = reinterpret_cast<S*>(smem_raw);
   for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int4 tl = tiles[t];
     const InstDev& I = insts[tl.x];
@@ -106,19 +131,41 @@ __global__ __launch_bounds__(256) void sweep_kernel(const InstDev* __restrict__ 
 #pragma unroll
       for (int q = 0; q < Q; ++q) g[q] = Codec<S>::ld(s[(long long)q * N + idx]);
       collide_cell<R>(g, o, lp, lm, fx, fy, fz);
-      const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
       const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
       const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
-#define LBM_PUSH(qq)                                                                                   \
-  {                                                                                                    \
-    const int xa = pick<cx(qq)>(xm, x, xp), ya = pick<cy(qq)>(ym, y, yp), za = pick<cz(qq)>(zm, z, zp); \
-    d[(long long)(qq) * N + (za * ny + ya) * nx + xa] = Codec<S>::st(o[qq]);                          \
+      const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+      const int lrow = r * nx;
+#define LBM_PUSH(qq)                                                                        \
+  if constexpr (cx(qq) == 0) {                                                              \
+    const int ya = pick<cy(qq)>(ym, y, yp), za = pick<cz(qq)>(zm, z, zp);                   \
+    st_nt(&d[(long long)(qq) * N + (za * ny + ya) * nx + x], Codec<S>::st(o[qq]));         \
+  } else {                                                                                  \
+    sh[xslot(qq) * ncells + lrow + pick<cx(qq)>(xm, x, xp)] = Codec<S>::st(o[qq]);          \
   }
       LBM_PUSH(0) LBM_PUSH(1) LBM_PUSH(2) LBM_PUSH(3) LBM_PUSH(4) LBM_PUSH(5) LBM_PUSH(6)
       LBM_PUSH(7) LBM_PUSH(8) LBM_PUSH(9) LBM_PUSH(10) LBM_PUSH(11) LBM_PUSH(12) LBM_PUSH(13)
       LBM_PUSH(14) LBM_PUSH(15) LBM_PUSH(16) LBM_PUSH(17) LBM_PUSH(18)
 #undef LBM_PUSH
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ncells; i += blockDim.x) {
+      const int r = i / nx;
+      const int x = i - r * nx;
+      const int row = tl.y + r;
+      const int z = row / ny;
+      const int y = row - z * ny;
+      const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+      const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+#define LBM_FLUSH(qq)                                                                       \
+  {                                                                                         \
+    const int ya = pick<cy(qq)>(ym, y, yp), za = pick<cz(qq)>(zm, z, zp);                   \
+    st_nt(&d[(long long)(qq) * N + (za * ny + ya) * nx + x], sh[xslot(qq) * ncells + i]);   \
+  }
+      LBM_FLUSH(1) LBM_FLUSH(2) LBM_FLUSH(7) LBM_FLUSH(8) LBM_FLUSH(9) LBM_FLUSH(10) LBM_FLUSH(11)
+      LBM_FLUSH(12) LBM_FLUSH(13) LBM_FLUSH(14)
+#undef LBM_FLUSH
+    }
+    __syncthreads();
   }
 }
 
@@ -187,19 +234,20 @@ __global__ void fields_kernel(const S* __restrict__ buf, long long N, long long 
 
 // ------------------------------------------------------------------------ launchers
 template <typename S>
-hipError_t launch_sweep_t(const InstDev* insts, const int4* tiles, int ntiles, int grid, int block, const void* src,
-                          void* dst, hipStream_t st) {
-  hipLaunchKernelGGL(sweep_kernel<S>, dim3(grid), dim3(block), 0, st, insts, tiles, ntiles, (const S*)src, (S*)dst);
+hipError_t launch_sweep_t(const InstDev* insts, const int4* tiles, int ntiles, int grid, int block, int max_tile_cells,
+                          const void* src, void* dst, hipStream_t st) {
+  const size_t lds = (size_t)NXSHIFT * max_tile_cells * sizeof(S);
+  hipLaunchKernelGGL(sweep_kernel<S>, dim3(grid), dim3(block), lds, st, insts, tiles, ntiles, (const S*)src, (S*)dst);
   return hipGetLastError();
 }
 
 hipError_t launch_sweep(int prec, const InstDev* insts, const int4* tiles, int ntiles, int grid, int block,
-                        const void* src, void* dst, hipStream_t st) {
+                        int max_tile_cells, const void* src, void* dst, hipStream_t st) {
   switch (prec) {
-    case PREC_FP64: return launch_sweep_t<double>(insts, tiles, ntiles, grid, block, src, dst, st);
-    case PREC_FP32: return launch_sweep_t<float>(insts, tiles, ntiles, grid, block, src, dst, st);
-    case PREC_FP16: return launch_sweep_t<_Float16>(insts, tiles, ntiles, grid, block, src, dst, st);
-    case PREC_BF16: return launch_sweep_t<__bf16>(insts, tiles, ntiles, grid, block, src, dst, st);
+    case PREC_FP64: return launch_sweep_t<double>(insts, tiles, ntiles, grid, block, max_tile_cells, src, dst, st);
+    case PREC_FP32: return launch_sweep_t<float>(insts, tiles, ntiles, grid, block, max_tile_cells, src, dst, st);
+    case PREC_FP16: return launch_sweep_t<_Float16>(insts, tiles, ntiles, grid, block, max_tile_cells, src, dst, st);
+    case PREC_BF16: return launch_sweep_t<__bf16>(insts, tiles, ntiles, grid, block, max_tile_cells, src, dst, st);
   }
   return hipErrorInvalidValue;
 }
