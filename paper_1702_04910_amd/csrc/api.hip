@@ -45,7 +45,7 @@ struct Layout {
   long long pdf_elems = 0, owner_elems = 0, cellmap_elems = 0;
   int link_cap = 0, wall_cap = 0, pair_cap = 0, refill_cap = 0;
   long long slot_elems = 0;
-  int box_total = 0;  // ptotal * side
+  int box_total = 0;  // ptotal * side * side: work units at the finest split
   long long chunk = 0;
   // byte offsets
   size_t o_bufA, o_bufB, o_owner, o_cellmap, o_inst, o_parts, o_plists, o_slots, o_totals, o_offsets, o_ranges,
@@ -66,6 +66,9 @@ bool valid_cfg(const lbmps_config& c, std::string& err) {
   if (!(c.nu > 0.0) || !std::isfinite(c.nu)) { err = "nu must be positive"; return false; }
   if (c.max_particles < 0) { err = "max_particles must be >= 0"; return false; }
   if (c.max_particles > 0 && !(c.max_diameter > 0.0)) { err = "max_diameter must be positive"; return false; }
+  if (c.max_particles > 0 && std::ceil(c.max_diameter) + 6 > 64) {
+    err = "max_diameter must be <= 58 cells (bounding boxes of at most 64 cells per axis)"; return false;
+  }
   if (c.max_particles > 0 && c.max_diameter + 6 > std::min(c.nx, std::min(c.ny, c.nz))) {
     err = "max_diameter + 6 exceeds the smallest box dimension"; return false;
   }
@@ -156,7 +159,7 @@ Layout make_layout(int n, const lbmps_config* cfgs) {
   L.pair_cap = (int)pairs;
   L.refill_cap = (int)refill;
   L.slot_elems = (long long)L.ptotal * L.side * L.side * L.side;
-  L.box_total = L.ptotal * L.side;
+  L.box_total = L.ptotal * L.side * L.side;
   L.chunk = std::min<long long>(cmax, 1LL << 22);
   size_t o = 0;
   auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
@@ -256,6 +259,13 @@ lbmps_status check_device_errors(lbmps_ctx* c) {
   return LBMPS_OK;
 }
 
+// Row ranges per bounding-box slab: enough work units (>= ~2048) to fill the GPU.
+int nsplit_for(int nlist, int side) {
+  if (nlist <= 0) return 1;
+  const int want = (2048 + nlist * side - 1) / (nlist * side);
+  return std::max(1, std::min(side, want));
+}
+
 int* mem_list(lbmps_ctx* c) { return c->plist_d; }
 int* psm_list(lbmps_ctx* c) { return c->plist_d + c->n_mem; }
 
@@ -264,27 +274,32 @@ lbmps_status rebuild_mem(lbmps_ctx* c, bool refill) {
   const Layout& L = c->L;
   if (c->n_mem == 0) return LBMPS_OK;
   unsigned* err = err_word(c);
+  const int ns = nsplit_for(c->n_mem, L.side);
+  const int units = L.side * ns;
   if (refill) {
-    HIPCHK(c, launch_mem_count(1, mem_list(c), c->n_mem, L.side, c->inst_d, c->parts, c->owner, c->slots, c->totals, c->st));
-    HIPCHK(c, launch_scan(c->totals, c->offsets, c->n_mem * L.side, L.side, c->n_mem, c->rbeg, c->rend, c->counts + 2,
+    HIPCHK(c, launch_mem_count(1, mem_list(c), c->n_mem, L.side, ns, c->inst_d, c->parts, c->owner, c->slots,
+                               c->totals, c->st));
+    HIPCHK(c, launch_scan(c->totals, c->offsets, c->n_mem * units, units, c->n_mem, c->rbeg, c->rend, c->counts + 2,
                           L.refill_cap, err, ERR_REFILL_CAP, c->st));
-    HIPCHK(c, launch_mem_fill_refill(mem_list(c), c->n_mem, L.side, c->inst_d, c->parts, c->owner, c->slots, c->offsets,
-                                     L.refill_cap, c->rcell, c->rpart, c->st));
+    HIPCHK(c, launch_mem_fill_refill(mem_list(c), c->n_mem, L.side, ns, c->inst_d, c->parts, c->owner, c->slots,
+                                     c->offsets, L.refill_cap, c->rcell, c->rpart, c->st));
     HIPCHK(c, launch_mem_refill(L.prec, c->counts + 2, L.refill_cap, c->rcell, c->rpart, c->inst_d, c->parts, c->owner,
                                 c->buf[c->cur], c->st));
   }
-  HIPCHK(c, launch_mem_count(0, mem_list(c), c->n_mem, L.side, c->inst_d, c->parts, c->owner, c->slots, c->totals, c->st));
-  HIPCHK(c, launch_scan(c->totals, c->offsets, c->n_mem * L.side, L.side, c->n_mem, c->lbeg, c->lend, c->counts + 0,
+  HIPCHK(c, launch_mem_count(0, mem_list(c), c->n_mem, L.side, ns, c->inst_d, c->parts, c->owner, c->slots, c->totals,
+                             c->st));
+  HIPCHK(c, launch_scan(c->totals, c->offsets, c->n_mem * units, units, c->n_mem, c->lbeg, c->lend, c->counts + 0,
                         L.link_cap, err, ERR_LINK_CAP, c->st));
-  HIPCHK(c, launch_mem_fill_links(mem_list(c), c->n_mem, L.side, c->inst_d, c->parts, c->owner, c->slots, c->offsets,
-                                  c->n_wall, L.link_cap, c->links, c->st));
-  HIPCHK(c, launch_mem_clear_was(mem_list(c), c->n_mem, L.side, c->inst_d, c->parts, c->owner, c->st));
+  HIPCHK(c, launch_mem_fill_links(mem_list(c), c->n_mem, L.side, ns, c->inst_d, c->parts, c->owner, c->slots,
+                                  c->offsets, c->n_wall, L.link_cap, c->links, c->st));
+  HIPCHK(c, launch_mem_clear_was(mem_list(c), c->n_mem, L.side, ns, c->inst_d, c->parts, c->owner, c->st));
   return LBMPS_OK;
 }
 
 lbmps_status remap_mem(lbmps_ctx* c) {
-  HIPCHK(c, launch_mem_unmap(mem_list(c), c->n_mem, c->L.side, c->inst_d, c->parts, c->owner, c->st));
-  HIPCHK(c, launch_mem_map(mem_list(c), c->n_mem, c->L.side, c->inst_d, c->parts, c->owner, c->st));
+  const int ns = nsplit_for(c->n_mem, c->L.side);
+  HIPCHK(c, launch_mem_unmap(mem_list(c), c->n_mem, c->L.side, ns, c->inst_d, c->parts, c->owner, c->st));
+  HIPCHK(c, launch_mem_map(mem_list(c), c->n_mem, c->L.side, ns, c->inst_d, c->parts, c->owner, c->st));
   return rebuild_mem(c, true);
 }
 
@@ -292,11 +307,14 @@ lbmps_status rebuild_psm(lbmps_ctx* c) {
   const Layout& L = c->L;
   if (c->n_psm == 0) return LBMPS_OK;
   unsigned* err = err_word(c);
+  const int ns = nsplit_for(c->n_psm, L.side);
+  const int units = L.side * ns;
   HIPCHK(c, launch_psm_cellmap(0, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap, c->st));
-  HIPCHK(c, launch_psm_count(psm_list(c), c->n_psm, L.side, c->inst_d, c->parts, nullptr, c->slots, c->totals, c->st));
-  HIPCHK(c, launch_scan(c->totals, c->offsets, c->n_psm * L.side, L.side, c->n_psm, c->pbeg, c->pend, c->counts + 1,
+  HIPCHK(c, launch_psm_count(psm_list(c), c->n_psm, L.side, ns, c->inst_d, c->parts, nullptr, c->slots, c->totals,
+                             c->st));
+  HIPCHK(c, launch_scan(c->totals, c->offsets, c->n_psm * units, units, c->n_psm, c->pbeg, c->pend, c->counts + 1,
                         L.pair_cap, err, ERR_PAIR_CAP, c->st));
-  HIPCHK(c, launch_psm_fill(psm_list(c), c->n_psm, L.side, c->inst_d, c->parts, c->slots, c->offsets, L.pair_cap,
+  HIPCHK(c, launch_psm_fill(psm_list(c), c->n_psm, L.side, ns, c->inst_d, c->parts, c->slots, c->offsets, L.pair_cap,
                             c->pairs, c->st));
   HIPCHK(c, launch_psm_cellmap(1, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap, c->st));
   HIPCHK(c, launch_psm_cellmap(2, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap, c->st));
@@ -672,7 +690,8 @@ lbmps_status lbmps_set_particles(lbmps_ctx* c, int32_t inst, int32_t n, const lb
     hipLaunchKernelGGL(reset_owner_kernel, dim3((unsigned)((c->L.ncell[inst] + 255) / 256)), dim3(256), 0, c->st,
                        c->owner + c->L.owner_off[inst], c->L.ncell[inst]);
     HIPCHK(c, hipGetLastError());
-    HIPCHK(c, launch_mem_map(mem_list(c), c->n_mem, c->L.side, c->inst_d, c->parts, c->owner, c->st));
+    HIPCHK(c, launch_mem_map(mem_list(c), c->n_mem, c->L.side, nsplit_for(c->n_mem, c->L.side), c->inst_d, c->parts,
+                             c->owner, c->st));
     s = rebuild_mem(c, false);
     if (s) return s;
   } else if (cf.coupling == LBMPS_PSM) {

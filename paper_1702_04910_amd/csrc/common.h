@@ -126,4 +126,41 @@ __device__ inline int wrapi(int i, int n) {
   return i < 0 ? i + n : i;
 }
 
+// Work units over the bounding boxes of listed particles: box side `side`,
+// slab z split into `nsplit` row ranges.  Unit u of a box covers slab
+// z = u / nsplit, rows [y0, y1).  Record lists are compacted unit by unit,
+// so their order is fixed by the geometry alone.
+struct Unit {
+  int z, y0, y1;
+};
+__device__ inline Unit unit_of(int u, int side, int nsplit) {
+  Unit r;
+  r.z = u / nsplit;
+  const int s = u - r.z * nsplit;
+  r.y0 = s * side / nsplit;
+  r.y1 = (s + 1) * side / nsplit;
+  return r;
+}
+// Index of bbox cell (z, y, x) of list entry j in the per-cell slot array.
+__device__ inline long long slot_index(int j, int side, int z, int y, int x) {
+  return (((long long)j * side + z) * side + y) * side + x;
+}
+
+// Block-wide exclusive scan of one int per thread (blockDim.x == 256).
+__device__ inline int block_excl_scan256(int v, int* sh, int* total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int a = t >= off ? sh[t - off] : 0;
+    __syncthreads();
+    sh[t] += a;
+    __syncthreads();
+  }
+  const int incl = sh[t];
+  *total = sh[255];
+  __syncthreads();
+  return incl - v;
+}
+
 }  // namespace lbm

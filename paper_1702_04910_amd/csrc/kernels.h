@@ -30,30 +30,30 @@ hipError_t launch_rigid(const int* list, int nlist, const InstDev* insts, PartDe
                         hipStream_t st);
 
 // ---- mem.hip
-hipError_t launch_mem_unmap(const int* list, int nlist, int side, const InstDev* insts, PartDev parts, int* owner,
-                            hipStream_t st);
-hipError_t launch_mem_map(const int* list, int nlist, int side, const InstDev* insts, PartDev parts, int* owner,
-                          hipStream_t st);
+hipError_t launch_mem_unmap(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
+                            int* owner, hipStream_t st);
+hipError_t launch_mem_map(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
+                          int* owner, hipStream_t st);
 // kind 0: links, kind 1: uncovered cells (refill list)
-hipError_t launch_mem_count(int kind, const int* list, int nlist, int side, const InstDev* insts, PartDev parts,
-                            const int* owner, int* slots, int* totals, hipStream_t st);
-hipError_t launch_mem_fill_links(const int* list, int nlist, int side, const InstDev* insts, PartDev parts,
-                                 int* owner, const int* slots, const int* offsets, int base, int cap, LinkDev links,
-                                 hipStream_t st);
-hipError_t launch_mem_fill_refill(const int* list, int nlist, int side, const InstDev* insts, PartDev parts,
-                                  int* owner, const int* slots, const int* offsets, int cap, int* rcell, int* rpart,
-                                  hipStream_t st);
+hipError_t launch_mem_count(int kind, const int* list, int nlist, int side, int nsplit, const InstDev* insts,
+                            PartDev parts, const int* owner, int* slots, int* totals, hipStream_t st);
+hipError_t launch_mem_fill_links(const int* list, int nlist, int side, int nsplit, const InstDev* insts,
+                                 PartDev parts, int* owner, const int* slots, const int* offsets, int base, int cap,
+                                 LinkDev links, hipStream_t st);
+hipError_t launch_mem_fill_refill(const int* list, int nlist, int side, int nsplit, const InstDev* insts,
+                                  PartDev parts, int* owner, const int* slots, const int* offsets, int cap, int* rcell,
+                                  int* rpart, hipStream_t st);
 hipError_t launch_mem_refill(int prec, const int* count, int cap, const int* rcell, const int* rpart,
                              const InstDev* insts, PartDev parts, const int* owner, void* buf, hipStream_t st);
-hipError_t launch_mem_clear_was(const int* list, int nlist, int side, const InstDev* insts, PartDev parts, int* owner,
-                                hipStream_t st);
+hipError_t launch_mem_clear_was(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
+                                int* owner, hipStream_t st);
 hipError_t launch_links_bc(int prec, int n_wall, const int* count, int cap, LinkDev links, const double* wall_v,
                            const InstDev* insts, PartDev parts, void* buf, hipStream_t st);
 
 // ---- psm.hip
-hipError_t launch_psm_count(const int* list, int nlist, int side, const InstDev* insts, PartDev parts,
+hipError_t launch_psm_count(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
                             const float* mlp_w, int* slots, int* totals, hipStream_t st);
-hipError_t launch_psm_fill(const int* list, int nlist, int side, const InstDev* insts, PartDev parts,
+hipError_t launch_psm_fill(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
                            const int* slots, const int* offsets, int cap, PairDev pairs, hipStream_t st);
 hipError_t launch_psm_cellmap(int stage, const int* count, int cap, const InstDev* insts, PartDev parts,
                               PairDev pairs, int* cellmap, hipStream_t st);

@@ -32,27 +32,30 @@ __device__ __forceinline__ void disp(const InstDev& I, const PartDev& P, int p, 
   d[2] = min_image(((double)k + 0.5) - P.X[3 * p + 2], (double)I.nz);
 }
 
-// Iterate the bounding-box cells of (list[blockIdx.y], slab blockIdx.x) in
-// contiguous per-thread chunks: body(c, i, j, k, linear cell index).
+// Each workgroup handles one work unit (a row range of one slab) of the
+// bounding box of particle list[blockIdx.y], in contiguous per-thread chunks.
 #define MEM_BBOX_PROLOGUE                                                              \
-  const int jl = blockIdx.y, zs = blockIdx.x;                                          \
+  const int jl = blockIdx.y;                                                           \
+  const Unit U_ = unit_of(blockIdx.x, side, nsplit);                                   \
   const int p = list[jl];                                                              \
   const InstDev& I = insts[P.inst[p]];                                                 \
   int lo[3];                                                                           \
   mem_bbox_lo(P, p, lo);                                                               \
-  const int ncs = side * side;                                                         \
+  const int ncs = (U_.y1 - U_.y0) * side;                                              \
   const int chunk = (ncs + 255) / 256;                                                 \
   const int ca = min(ncs, (int)threadIdx.x * chunk), cb = min(ncs, ca + chunk);        \
   int* own = owner + I.owner_off;                                                      \
   (void)own;
 
-#define MEM_CELL_COORDS(c)                                             \
-  const int dy_ = (c) / side, dx_ = (c) - dy_ * side;                  \
-  const int ci = wrapi(lo[0] + dx_, I.nx), cj = wrapi(lo[1] + dy_, I.ny), \
-            ck = wrapi(lo[2] + zs, I.nz);                              \
-  const int cell = (ck * I.ny + cj) * I.nx + ci;
+#define MEM_CELL_COORDS(c)                                                 \
+  const int dy_ = U_.y0 + (c) / side, dx_ = (c) % side;                    \
+  const int ci = wrapi(lo[0] + dx_, I.nx), cj = wrapi(lo[1] + dy_, I.ny),  \
+            ck = wrapi(lo[2] + U_.z, I.nz);                                \
+  const int cell = (ck * I.ny + cj) * I.nx + ci;                           \
+  const long long sidx = slot_index(jl, side, U_.z, dy_, dx_);             \
+  (void)sidx;
 
-__global__ __launch_bounds__(256) void mem_unmap_kernel(const int* __restrict__ list, int side,
+__global__ __launch_bounds__(256) void mem_unmap_kernel(const int* __restrict__ list, int side, int nsplit,
                                                         const InstDev* __restrict__ insts, PartDev P,
                                                         int* __restrict__ owner) {
   MEM_BBOX_PROLOGUE
@@ -62,7 +65,7 @@ __global__ __launch_bounds__(256) void mem_unmap_kernel(const int* __restrict__ 
   }
 }
 
-__global__ __launch_bounds__(256) void mem_map_kernel(const int* __restrict__ list, int side,
+__global__ __launch_bounds__(256) void mem_map_kernel(const int* __restrict__ list, int side, int nsplit,
                                                       const InstDev* __restrict__ insts, PartDev P,
                                                       int* __restrict__ owner) {
   MEM_BBOX_PROLOGUE
@@ -76,44 +79,29 @@ __global__ __launch_bounds__(256) void mem_map_kernel(const int* __restrict__ li
   }
 }
 
-hipError_t launch_mem_unmap(const int* list, int nlist, int side, const InstDev* insts, PartDev parts, int* owner,
-                            hipStream_t st) {
+hipError_t launch_mem_unmap(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
+                            int* owner, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(mem_unmap_kernel, dim3(side, nlist), dim3(256), 0, st, list, side, insts, parts, owner);
+  hipLaunchKernelGGL(mem_unmap_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts, parts,
+                     owner);
   return hipGetLastError();
 }
 
-hipError_t launch_mem_map(const int* list, int nlist, int side, const InstDev* insts, PartDev parts, int* owner,
-                          hipStream_t st) {
+hipError_t launch_mem_map(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
+                          int* owner, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(mem_map_kernel, dim3(side, nlist), dim3(256), 0, st, list, side, insts, parts, owner);
+  hipLaunchKernelGGL(mem_map_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts, parts,
+                     owner);
   return hipGetLastError();
-}
-
-__device__ __forceinline__ int mem_block_scan(int v, int* sh, int* total) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    const int a = t >= off ? sh[t - off] : 0;
-    __syncthreads();
-    sh[t] += a;
-    __syncthreads();
-  }
-  const int incl = sh[t];
-  *total = sh[255];
-  __syncthreads();
-  return incl - v;
 }
 
 // kind 0: per fluid cell the mask of directions q whose neighbour x + c_q is a
 // solid cell of p (one link each); kind 1: 1 for a cell uncovered by p.
-__global__ __launch_bounds__(256) void mem_count_kernel(int kind, const int* __restrict__ list, int side,
+__global__ __launch_bounds__(256) void mem_count_kernel(int kind, const int* __restrict__ list, int side, int nsplit,
                                                         const InstDev* __restrict__ insts, PartDev P,
                                                         int* __restrict__ owner, int* __restrict__ slots,
                                                         int* __restrict__ totals) {
   MEM_BBOX_PROLOGUE
-  int* slot = slots + ((long long)jl * side + zs) * ncs;
   int local = 0;
   for (int c = ca; c < cb; ++c) {
     MEM_CELL_COORDS(c)
@@ -131,19 +119,19 @@ __global__ __launch_bounds__(256) void mem_count_kernel(int kind, const int* __r
       v = own[cell] == (WAS_BIT | p) ? 1 : 0;
       local += v;
     }
-    slot[c] = v;
+    slots[sidx] = v;
   }
   __shared__ int sh[256];
   int total;
-  mem_block_scan(local, sh, &total);
-  if (threadIdx.x == 0) totals[jl * side + zs] = total;
+  block_excl_scan256(local, sh, &total);
+  if (threadIdx.x == 0) totals[jl * (side * nsplit) + blockIdx.x] = total;
 }
 
-hipError_t launch_mem_count(int kind, const int* list, int nlist, int side, const InstDev* insts, PartDev parts,
-                            const int* owner, int* slots, int* totals, hipStream_t st) {
+hipError_t launch_mem_count(int kind, const int* list, int nlist, int side, int nsplit, const InstDev* insts,
+                            PartDev parts, const int* owner, int* slots, int* totals, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(mem_count_kernel, dim3(side, nlist), dim3(256), 0, st, kind, list, side, insts, parts,
-                     (int*)owner, slots, totals);
+  hipLaunchKernelGGL(mem_count_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, kind, list, side, nsplit, insts,
+                     parts, (int*)owner, slots, totals);
   return hipGetLastError();
 }
 
@@ -151,23 +139,25 @@ hipError_t launch_mem_count(int kind, const int* list, int nlist, int side, cons
 // smallest root in (0, 1] of |d + delta c|^2 = R^2 computed as e/(-b + sqrt(b^2 - a e))
 // (a = c.c, b = d.c, e = |d|^2 - R^2), and whether x - c_q is fluid (needed by
 // CLI).  Clears the "was solid" marks of the cells it visits afterwards.
-__global__ __launch_bounds__(256) void mem_fill_links_kernel(const int* __restrict__ list, int side,
+__global__ __launch_bounds__(256) void mem_fill_links_kernel(const int* __restrict__ list, int side, int nsplit,
                                                              const InstDev* __restrict__ insts, PartDev P,
                                                              int* __restrict__ owner, const int* __restrict__ slots,
                                                              const int* __restrict__ offsets, int base, int cap,
                                                              LinkDev L) {
   MEM_BBOX_PROLOGUE
-  const int* slot = slots + ((long long)jl * side + zs) * ncs;
   int local = 0;
-  for (int c = ca; c < cb; ++c) local += __popc(slot[c]);
+  for (int c = ca; c < cb; ++c) {
+    MEM_CELL_COORDS(c)
+    local += __popc(slots[sidx]);
+  }
   __shared__ int sh[256];
   int total;
-  int pos = base + offsets[jl * side + zs] + mem_block_scan(local, sh, &total);
+  int pos = base + offsets[jl * (side * nsplit) + blockIdx.x] + block_excl_scan256(local, sh, &total);
   const double R = 0.5 * P.D[p];
   for (int c = ca; c < cb; ++c) {
-    const int m = slot[c];
-    if (m == 0) continue;
     MEM_CELL_COORDS(c)
+    const int m = slots[sidx];
+    if (m == 0) continue;
     double d[3];
     disp(I, P, p, ci, cj, ck, d);
     const double e = sq3m(d[0], d[1], d[2]) - R * R;
@@ -190,16 +180,16 @@ __global__ __launch_bounds__(256) void mem_fill_links_kernel(const int* __restri
   }
 }
 
-hipError_t launch_mem_fill_links(const int* list, int nlist, int side, const InstDev* insts, PartDev parts,
-                                 int* owner, const int* slots, const int* offsets, int base, int cap, LinkDev links,
-                                 hipStream_t st) {
+hipError_t launch_mem_fill_links(const int* list, int nlist, int side, int nsplit, const InstDev* insts,
+                                 PartDev parts, int* owner, const int* slots, const int* offsets, int base, int cap,
+                                 LinkDev links, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(mem_fill_links_kernel, dim3(side, nlist), dim3(256), 0, st, list, side, insts, parts, owner,
-                     slots, offsets, base, cap, links);
+  hipLaunchKernelGGL(mem_fill_links_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts,
+                     parts, owner, slots, offsets, base, cap, links);
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void mem_clear_was_kernel(const int* __restrict__ list, int side,
+__global__ __launch_bounds__(256) void mem_clear_was_kernel(const int* __restrict__ list, int side, int nsplit,
                                                             const InstDev* __restrict__ insts, PartDev P,
                                                             int* __restrict__ owner) {
   MEM_BBOX_PROLOGUE
@@ -209,28 +199,31 @@ __global__ __launch_bounds__(256) void mem_clear_was_kernel(const int* __restric
   }
 }
 
-hipError_t launch_mem_clear_was(const int* list, int nlist, int side, const InstDev* insts, PartDev parts, int* owner,
-                                hipStream_t st) {
+hipError_t launch_mem_clear_was(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
+                                int* owner, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(mem_clear_was_kernel, dim3(side, nlist), dim3(256), 0, st, list, side, insts, parts, owner);
+  hipLaunchKernelGGL(mem_clear_was_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts,
+                     parts, owner);
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void mem_fill_refill_kernel(const int* __restrict__ list, int side,
+__global__ __launch_bounds__(256) void mem_fill_refill_kernel(const int* __restrict__ list, int side, int nsplit,
                                                               const InstDev* __restrict__ insts, PartDev P,
                                                               int* __restrict__ owner, const int* __restrict__ slots,
                                                               const int* __restrict__ offsets, int cap,
                                                               int* __restrict__ rcell, int* __restrict__ rpart) {
   MEM_BBOX_PROLOGUE
-  const int* slot = slots + ((long long)jl * side + zs) * ncs;
   int local = 0;
-  for (int c = ca; c < cb; ++c) local += slot[c];
+  for (int c = ca; c < cb; ++c) {
+    MEM_CELL_COORDS(c)
+    local += slots[sidx];
+  }
   __shared__ int sh[256];
   int total;
-  int pos = offsets[jl * side + zs] + mem_block_scan(local, sh, &total);
+  int pos = offsets[jl * (side * nsplit) + blockIdx.x] + block_excl_scan256(local, sh, &total);
   for (int c = ca; c < cb; ++c) {
-    if (!slot[c]) continue;
     MEM_CELL_COORDS(c)
+    if (!slots[sidx]) continue;
     if (pos < cap) {
       rcell[pos] = cell;
       rpart[pos] = p;
@@ -239,28 +232,38 @@ __global__ __launch_bounds__(256) void mem_fill_refill_kernel(const int* __restr
   }
 }
 
-hipError_t launch_mem_fill_refill(const int* list, int nlist, int side, const InstDev* insts, PartDev parts,
-                                  int* owner, const int* slots, const int* offsets, int cap, int* rcell, int* rpart,
-                                  hipStream_t st) {
+hipError_t launch_mem_fill_refill(const int* list, int nlist, int side, int nsplit, const InstDev* insts,
+                                  PartDev parts, int* owner, const int* slots, const int* offsets, int cap, int* rcell,
+                                  int* rpart, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(mem_fill_refill_kernel, dim3(side, nlist), dim3(256), 0, st, list, side, insts, parts, owner,
-                     slots, offsets, cap, rcell, rpart);
+  hipLaunchKernelGGL(mem_fill_refill_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts,
+                     parts, owner, slots, offsets, cap, rcell, rpart);
   return hipGetLastError();
 }
 
-// Refill of one uncovered cell x (Sec. 2.2.3):
+// Refill of one uncovered cell x (Sec. 2.2.3), one wave per cell, lane q
+// handling direction q:
 //  * q_n maximises n.c_q/|c_q| with n along x - X_p (ties: largest (cx, cy, cz)
 //    lexicographically);
 //  * sources x + k c_qn, k = 1..3, must be fluid cells that were fluid before the
 //    remap; quadratic 3 f1 - 3 f2 + f3, else linear 2 f1 - f2, else constant f1,
-//    else f^eq(rho_bar, v(x)) with rho_bar the mean density of such neighbours;
+//    else f^eq(rho0 + drho_bar, v(x)) with drho_bar the mean density fluctuation
+//    of the old-fluid neighbours (0 if there are none);
 //  * velocity constraint: f_q += c_q.(j* - j)/10 with j* = v(x) - f_ext/2.
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
 template <typename S>
-__global__ void mem_refill_kernel(const int* __restrict__ count, int cap, const int* __restrict__ rcell,
-                                  const int* __restrict__ rpart, const InstDev* __restrict__ insts, PartDev P,
-                                  const int* __restrict__ owner, S* __restrict__ buf) {
+__global__ __launch_bounds__(256) void mem_refill_kernel(const int* __restrict__ count, int cap,
+                                                         const int* __restrict__ rcell, const int* __restrict__ rpart,
+                                                         const InstDev* __restrict__ insts, PartDev P,
+                                                         const int* __restrict__ owner, S* __restrict__ buf) {
   const int n = min(*count, cap);
-  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+  const int lane = threadIdx.x & 63;
+  const int nw = (gridDim.x * blockDim.x) >> 6;
+  for (int r = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; r < n; r += nw) {
     const int cell = rcell[r], p = rpart[r];
     const InstDev& I = insts[P.inst[p]];
     const int* own = owner + I.owner_off;
@@ -285,56 +288,56 @@ __global__ void mem_refill_kernel(const int* __restrict__ count, int cap, const 
         bz = cz(q);
       }
     }
-    double src[3][Q];
+    // source cells along c_qn that are old fluid (consecutive from k = 1)
+    int src_cell[3];
     int ns = 0;
     for (int k = 1; k <= 3; ++k) {
       const int xi = wrapi(x + k * cx(qn), I.nx), yi = wrapi(y + k * cy(qn), I.ny), zi = wrapi(z + k * cz(qn), I.nz);
-      const int c2 = (zi * I.ny + yi) * I.nx + xi;
-      if (own[c2] != OWN_FLUID) break;
-      for (int q = 0; q < Q; ++q) src[k - 1][q] = (double)Codec<S>::ld(b[(long long)q * N + c2]);
+      src_cell[k - 1] = (zi * I.ny + yi) * I.nx + xi;
+    }
+    for (int k = 0; k < 3; ++k) {
+      if (own[src_cell[k]] != OWN_FLUID) break;
       ++ns;
     }
     const double* Up = P.U + 3 * p;
     const double* Wp = P.Om + 3 * p;
     const double v[3] = {Up[0] + (Wp[1] * d[2] - Wp[2] * d[1]), Up[1] + (Wp[2] * d[0] - Wp[0] * d[2]),
                          Up[2] + (Wp[0] * d[1] - Wp[1] * d[0])};
-    double o[Q];
-    if (ns == 3) {
-      for (int q = 0; q < Q; ++q) o[q] = 3.0 * src[0][q] - 3.0 * src[1][q] + src[2][q];
-    } else if (ns == 2) {
-      for (int q = 0; q < Q; ++q) o[q] = 2.0 * src[0][q] - src[1][q];
-    } else if (ns == 1) {
-      for (int q = 0; q < Q; ++q) o[q] = src[0][q];
+    const int q = lane < Q ? lane : 0;
+    double o = 0.0;
+    if (ns > 0) {
+      double f[3] = {0, 0, 0};
+      for (int k = 0; k < ns; ++k) f[k] = (double)Codec<S>::ld(b[(long long)q * N + src_cell[k]]);
+      o = ns == 3 ? 3.0 * f[0] - 3.0 * f[1] + f[2] : (ns == 2 ? 2.0 * f[0] - f[1] : f[0]);
     } else {
-      // mean density fluctuation of the old-fluid neighbours (0 when there are none)
-      double rs = 0.0;
-      int nr = 0;
-      for (int q = 1; q < Q; ++q) {
-        const int xi = wrapi(x + cx(q), I.nx), yi = wrapi(y + cy(q), I.ny), zi = wrapi(z + cz(q), I.nz);
+      // lane q' < 18 inspects neighbour q' + 1; fluctuation sum over its 19 PDFs
+      double s = 0.0, cntv = 0.0;
+      if (lane < 18) {
+        const int qq = lane + 1;
+        const int xi = wrapi(x + cx(qq), I.nx), yi = wrapi(y + cy(qq), I.ny), zi = wrapi(z + cz(qq), I.nz);
         const int c2 = (zi * I.ny + yi) * I.nx + xi;
-        if (own[c2] != OWN_FLUID) continue;
-        double s = 0.0;
-        for (int qq = 0; qq < Q; ++qq) s += (double)Codec<S>::ld(b[(long long)qq * N + c2]);
-        rs += s;
-        ++nr;
+        if (own[c2] == OWN_FLUID) {
+          for (int k = 0; k < Q; ++k) s += (double)Codec<S>::ld(b[(long long)k * N + c2]);
+          cntv = 1.0;
+        }
       }
-      const double drho = nr ? rs / nr : 0.0;
+      // fixed-order sum over the 18 neighbours (lane order)
+      __shared__ double red[4][64];
+      const int w = (threadIdx.x >> 6);
+      red[w][lane] = s;
+      double nr = wave_sum(cntv);
+      double rs = 0.0;
+      for (int k = 0; k < 18; ++k) rs += red[w][k];
+      const double drho = nr > 0.0 ? rs / nr : 0.0;
       const double uu = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
-      for (int q = 0; q < Q; ++q) {
-        const double cu = cx(q) * v[0] + cy(q) * v[1] + cz(q) * v[2];
-        o[q] = wq(q) * ((drho - 1.5 * uu) + cu * (3.0 + 4.5 * cu));
-      }
+      const double cu = cx(q) * v[0] + cy(q) * v[1] + cz(q) * v[2];
+      o = wq(q) * ((drho - 1.5 * uu) + cu * (3.0 + 4.5 * cu));
     }
-    double j[3] = {0, 0, 0};
-    for (int q = 1; q < Q; ++q) {
-      j[0] += cx(q) * o[q];
-      j[1] += cy(q) * o[q];
-      j[2] += cz(q) * o[q];
-    }
-    const double dj[3] = {(v[0] - 0.5 * I.fext[0]) - j[0], (v[1] - 0.5 * I.fext[1]) - j[1],
-                          (v[2] - 0.5 * I.fext[2]) - j[2]};
-    for (int q = 0; q < Q; ++q) {
-      const double val = o[q] + (cx(q) * dj[0] + cy(q) * dj[1] + cz(q) * dj[2]) / 10.0;
+    const double om = lane < Q ? o : 0.0;
+    const double jx = wave_sum(cx(q) * om), jy = wave_sum(cy(q) * om), jz = wave_sum(cz(q) * om);
+    const double dj[3] = {(v[0] - 0.5 * I.fext[0]) - jx, (v[1] - 0.5 * I.fext[1]) - jy, (v[2] - 0.5 * I.fext[2]) - jz};
+    if (lane < Q) {
+      const double val = o + (cx(q) * dj[0] + cy(q) * dj[1] + cz(q) * dj[2]) / 10.0;
       b[(long long)q * N + cell] = Codec<S>::st((typename CompOf<S>::type)val);
     }
   }
@@ -351,7 +354,7 @@ __global__ void mem_refill_kernel(const int* __restrict__ count, int cap, const 
 
 hipError_t launch_mem_refill(int prec, const int* count, int cap, const int* rcell, const int* rpart,
                              const InstDev* insts, PartDev parts, const int* owner, void* buf, hipStream_t st) {
-  LBM_DISPATCH(prec, hipLaunchKernelGGL(mem_refill_kernel<S>, dim3(64), dim3(128), 0, st, count, cap, rcell, rpart,
+  LBM_DISPATCH(prec, hipLaunchKernelGGL(mem_refill_kernel<S>, dim3(64), dim3(256), 0, st, count, cap, rcell, rpart,
                                         insts, parts, owner, (S*)buf));
   return hipGetLastError();
 }

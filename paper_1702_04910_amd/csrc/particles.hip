@@ -59,8 +59,9 @@ hipError_t launch_scan(const int* totals, int* offsets, int m, int side, int nli
 // ------------------------------------------------------------------------ reduction
 // Workgroup j sums the 6-double records [base + begin[j], base + end[j]) in a
 // fixed order: strided per-thread partial sums, a butterfly over the 64 lanes of
-// each wave, then the four waves in order.  The result is added to Facc/Tacc.
-__global__ __launch_bounds__(256) void reduce_kernel(const int* __restrict__ list, const int* __restrict__ begin,
+// each wave, then the waves in order.  The result is added to Facc/Tacc.
+constexpr int RED_THREADS = 1024;
+__global__ __launch_bounds__(RED_THREADS) void reduce_kernel(const int* __restrict__ list, const int* __restrict__ begin,
                                                      const int* __restrict__ end, int base,
                                                      const double* __restrict__ out, PartDev parts) {
   const int j = blockIdx.x;
@@ -77,7 +78,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(const int* __restrict__ lis
     for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
     acc[k] = v;
   }
-  __shared__ double wsum[4][6];
+  __shared__ double wsum[RED_THREADS / 64][6];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (lane == 0) {
 #pragma unroll
@@ -99,7 +100,7 @@ __global__ __launch_bounds__(256) void reduce_kernel(const int* __restrict__ lis
 hipError_t launch_reduce(const int* list, int nlist, const int* begin, const int* end, int base, const double* out,
                          PartDev parts, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_kernel, dim3(nlist), dim3(256), 0, st, list, begin, end, base, out, parts);
+  hipLaunchKernelGGL(reduce_kernel, dim3(nlist), dim3(RED_THREADS), 0, st, list, begin, end, base, out, parts);
   return hipGetLastError();
 }
 

@@ -39,26 +39,12 @@ __device__ __forceinline__ int classify(const double (&lo)[3], const double (&hi
   return 0;
 }
 
-__device__ int count_flat(const double dc[3], double R2, int n) {
-  int cnt = 0;
-  for (int c = 0; c < n; ++c) {
-    const double pz = __dadd_rn(dc[2], sample_off(c, n));
-    for (int b = 0; b < n; ++b) {
-      const double py = __dadd_rn(dc[1], sample_off(b, n));
-      for (int a = 0; a < n; ++a) {
-        const double px = __dadd_rn(dc[0], sample_off(a, n));
-        cnt += sq3(px, py, pz) <= R2 ? 1 : 0;
-      }
-    }
-  }
-  return cnt;
-}
-
-__device__ int count_recursive(const double dc[3], double R2, int n) {
+// Octree count over the block of m^3 sample points starting at (a0, b0, c0).
+__device__ int count_recursive_block(const double dc[3], double R2, int n, int a0_, int b0_, int c0_, int m0) {
   // explicit stack of blocks (a0, b0, c0, m); depth <= log2(n) <= 6
   int st_a[64], st_b[64], st_c[64], st_m[64];
   int sp = 0, cnt = 0;
-  st_a[0] = 0; st_b[0] = 0; st_c[0] = 0; st_m[0] = n; sp = 1;
+  st_a[0] = a0_; st_b[0] = b0_; st_c[0] = c0_; st_m[0] = m0; sp = 1;
   while (sp > 0) {
     --sp;
     const int a0 = st_a[sp], b0 = st_b[sp], c0 = st_c[sp], m = st_m[sp];
@@ -82,6 +68,30 @@ __device__ int count_recursive(const double dc[3], double R2, int n) {
   return cnt;
 }
 
+// Sample count of one cut cell, computed by a whole wave: the flat estimator
+// splits the n^3 points over the lanes; the recursive one gives each lane one
+// of the 64 octree blocks of (n/4)^3 points (or one point for n = 2).  Both
+// return the exact same integer as a serial evaluation.
+__device__ int wave_count(const double dc[3], double R2, int n, int mode) {
+  const int lane = threadIdx.x & 63;
+  int cnt = 0;
+  if (mode == EPS_RECURSIVE && n >= 4) {
+    const int m = n / 4;
+    cnt = count_recursive_block(dc, R2, n, (lane & 3) * m, ((lane >> 2) & 3) * m, (lane >> 4) * m, m);
+  } else {
+    const int tot = n * n * n;
+    for (int pidx = lane; pidx < tot; pidx += 64) {
+      const int a = pidx % n, b = (pidx / n) % n, c = pidx / (n * n);
+      const double px = __dadd_rn(dc[0], sample_off(a, n));
+      const double py = __dadd_rn(dc[1], sample_off(b, n));
+      const double pz = __dadd_rn(dc[2], sample_off(c, n));
+      cnt += sq3(px, py, pz) <= R2 ? 1 : 0;
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+  return cnt;
+}
+
 // Bounding box of particle p: `side` cells per axis starting at floor(X - R - 2).
 __device__ __forceinline__ void bbox_lo(const PartDev& P, int p, int (&lo)[3]) {
   const double R = 0.5 * P.D[p];
@@ -96,29 +106,22 @@ __device__ __forceinline__ void centre_disp(const InstDev& I, const PartDev& P, 
   d[2] = min_image(((double)k + 0.5) - P.X[3 * p + 2], (double)I.nz);
 }
 
-// Block-wide exclusive scan of one int per thread (256 threads).
-__device__ __forceinline__ int block_excl_scan(int v, int* sh, int* total) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    const int a = t >= off ? sh[t - off] : 0;
-    __syncthreads();
-    sh[t] += a;
-    __syncthreads();
-  }
-  const int incl = sh[t];
-  *total = sh[255];
-  __syncthreads();
-  return incl - v;
-}
+constexpr int MAX_UNIT_CELLS = 64 * 64;  // side <= 64
 
-// Grid (side, nlist): workgroup (z, j) handles slab z of the bounding box of particle list[j].
-__global__ __launch_bounds__(256) void psm_count_kernel(const int* __restrict__ list, int side,
+// Grid (units, nlist): workgroup (u, j) handles work unit u of the bounding box
+// of particle list[j].  Cells entirely inside (outside) the sphere by their
+// farthest (nearest) sample point get n^3 (0) directly; cut cells are counted
+// by one wave each.
+__global__ __launch_bounds__(256) void psm_count_kernel(const int* __restrict__ list, int side, int nsplit,
                                                         const InstDev* __restrict__ insts, PartDev P,
                                                         const float* __restrict__ mlp_w, int* __restrict__ slots,
                                                         int* __restrict__ totals) {
-  const int j = blockIdx.y, z = blockIdx.x;
+  __shared__ int vals[MAX_UNIT_CELLS];
+  __shared__ int cut[MAX_UNIT_CELLS];
+  __shared__ int ncut;
+  __shared__ int sh[256];
+  const int j = blockIdx.y;
+  const Unit U = unit_of(blockIdx.x, side, nsplit);
   const int p = list[j];
   const InstDev& I = insts[P.inst[p]];
   int lo[3];
@@ -126,51 +129,63 @@ __global__ __launch_bounds__(256) void psm_count_kernel(const int* __restrict__ 
   const double R = 0.5 * P.D[p];
   const double R2 = __dmul_rn(R, R);
   const int n = I.eps_n;
-  const int ncs = side * side;
-  const int chunk = (ncs + 255) / 256;
-  const int a = min(ncs, (int)threadIdx.x * chunk), b = min(ncs, a + chunk);
-  int* slot = slots + ((long long)j * side + z) * ncs;
-  int local = 0;
-  for (int c = a; c < b; ++c) {
-    const int dy = c / side, dx = c - dy * side;
-    const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny), k = wrapi(lo[2] + z, I.nz);
+  const int ncu = (U.y1 - U.y0) * side;
+  if (threadIdx.x == 0) ncut = 0;
+  __syncthreads();
+  const double o0 = sample_off(0, n), o1 = sample_off(n - 1, n);
+  for (int c = threadIdx.x; c < ncu; c += blockDim.x) {
+    const int dy = U.y0 + c / side, dx = c % side;
+    const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny), k = wrapi(lo[2] + U.z, I.nz);
     double dc[3];
     centre_disp(I, P, p, i, jj, k, dc);
-    // the whole cell: farthest / nearest sample point
     double blo[3], bhi[3];
-    const double o0 = sample_off(0, n), o1 = sample_off(n - 1, n);
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       blo[q] = __dadd_rn(dc[q], o0);
       bhi[q] = __dadd_rn(dc[q], o1);
     }
     const int cl = classify(blo, bhi, R2);
-    int v;
-    if (cl == 1) v = n * n * n;
-    else if (cl == -1) v = 0;
-    else v = (I.eps_mode == EPS_RECURSIVE) ? count_recursive(dc, R2, n) : count_flat(dc, R2, n);
-    slot[c] = v;
-    local += v > 0 ? 1 : 0;
+    vals[c] = cl == 1 ? n * n * n : 0;
+    if (cl == 0) cut[atomicAdd(&ncut, 1)] = c;
   }
-  __shared__ int sh[256];
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  for (int t = wave; t < ncut; t += nwaves) {
+    const int c = cut[t];
+    const int dy = U.y0 + c / side, dx = c % side;
+    const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny), k = wrapi(lo[2] + U.z, I.nz);
+    double dc[3];
+    centre_disp(I, P, p, i, jj, k, dc);
+    const int cnt = wave_count(dc, R2, n, I.eps_mode);
+    if ((threadIdx.x & 63) == 0) vals[c] = cnt;
+  }
+  __syncthreads();
+  int local = 0;
+  for (int c = threadIdx.x; c < ncu; c += blockDim.x) {
+    const int dy = U.y0 + c / side, dx = c % side;
+    slots[slot_index(j, side, U.z, dy, dx)] = vals[c];
+    local += vals[c] > 0 ? 1 : 0;
+  }
   int total;
-  block_excl_scan(local, sh, &total);
-  if (threadIdx.x == 0) totals[j * side + z] = total;
+  block_excl_scan256(local, sh, &total);
+  if (threadIdx.x == 0) totals[j * (side * nsplit) + blockIdx.x] = total;
 }
 
-hipError_t launch_psm_count(const int* list, int nlist, int side, const InstDev* insts, PartDev parts,
+hipError_t launch_psm_count(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
                             const float* mlp_w, int* slots, int* totals, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(psm_count_kernel, dim3(side, nlist), dim3(256), 0, st, list, side, insts, parts, mlp_w, slots,
-                     totals);
+  hipLaunchKernelGGL(psm_count_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts, parts,
+                     mlp_w, slots, totals);
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void psm_fill_kernel(const int* __restrict__ list, int side,
+// Writes the overlap pairs of each unit in cell order (per-thread contiguous chunks).
+__global__ __launch_bounds__(256) void psm_fill_kernel(const int* __restrict__ list, int side, int nsplit,
                                                        const InstDev* __restrict__ insts, PartDev P,
                                                        const int* __restrict__ slots, const int* __restrict__ offsets,
                                                        int cap, PairDev pairs) {
-  const int j = blockIdx.y, z = blockIdx.x;
+  const int j = blockIdx.y;
+  const Unit U = unit_of(blockIdx.x, side, nsplit);
   const int p = list[j];
   const InstDev& I = insts[P.inst[p]];
   int lo[3];
@@ -178,21 +193,20 @@ __global__ __launch_bounds__(256) void psm_fill_kernel(const int* __restrict__ l
   const int n = I.eps_n;
   const double nn = (double)n * (double)n * (double)n;
   const double t = I.tau - 0.5;
-  const int ncs = side * side;
-  const int chunk = (ncs + 255) / 256;
-  const int a = min(ncs, (int)threadIdx.x * chunk), b = min(ncs, a + chunk);
-  const int* slot = slots + ((long long)j * side + z) * ncs;
+  const int ncu = (U.y1 - U.y0) * side;
+  const int chunk = (ncu + 255) / 256;
+  const int a = min(ncu, (int)threadIdx.x * chunk), b = min(ncu, a + chunk);
   int local = 0;
-  for (int c = a; c < b; ++c) local += slot[c] > 0 ? 1 : 0;
+  for (int c = a; c < b; ++c) local += slots[slot_index(j, side, U.z, U.y0 + c / side, c % side)] > 0 ? 1 : 0;
   __shared__ int sh[256];
   int total;
-  int pos = offsets[j * side + z] + block_excl_scan(local, sh, &total);
+  int pos = offsets[j * (side * nsplit) + blockIdx.x] + block_excl_scan256(local, sh, &total);
   for (int c = a; c < b; ++c) {
-    const int v = slot[c];
+    const int dy = U.y0 + c / side, dx = c % side;
+    const int v = slots[slot_index(j, side, U.z, dy, dx)];
     if (v <= 0) continue;
     if (pos < cap) {
-      const int dy = c / side, dx = c - dy * side;
-      const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny), k = wrapi(lo[2] + z, I.nz);
+      const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny), k = wrapi(lo[2] + U.z, I.nz);
       const double eps = (double)v / nn;
       pairs.cell[pos] = (k * I.ny + jj) * I.nx + i;
       pairs.p[pos] = p;
@@ -204,11 +218,11 @@ __global__ __launch_bounds__(256) void psm_fill_kernel(const int* __restrict__ l
   }
 }
 
-hipError_t launch_psm_fill(const int* list, int nlist, int side, const InstDev* insts, PartDev parts,
+hipError_t launch_psm_fill(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
                            const int* slots, const int* offsets, int cap, PairDev pairs, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(psm_fill_kernel, dim3(side, nlist), dim3(256), 0, st, list, side, insts, parts, slots, offsets,
-                     cap, pairs);
+  hipLaunchKernelGGL(psm_fill_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts, parts,
+                     slots, offsets, cap, pairs);
   return hipGetLastError();
 }
 
