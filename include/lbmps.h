@@ -83,6 +83,8 @@ typedef struct lbmps_config {
   int32_t block_threads; /* sweep workgroup size, <= 256 (0 = 256) */
   int32_t grid_blocks;   /* sweep workgroups; 0 = one per tile, > 0 = persistent grid of that size */
   int32_t wall_link_cap; /* capacity of static-wall links (0 = automatic) */
+  int32_t sweep_flags;   /* bit 0: non-temporal loads in the sweep (launch tuning only; results unchanged) */
+  int32_t reserved;
   double max_diameter;   /* largest particle diameter that will be set (cells) */
   double nu;             /* kinematic viscosity, nu = (tau - 1/2)/3 (Eq. Viscosity) */
   double magic;          /* TRT parameter Lambda (default 3/16 when 0) */

@@ -1,0 +1,90 @@
+"""Launch-shape autotuner for the sweep kernel.
+
+For a box shape and storage precision it times the sweep kernel (HIP events
+recorded by the library around every launch) over a grid of launch shapes:
+rows per tile (sized by the LDS staging they need), workgroup size, a
+persistent grid or one workgroup per tile, and plain or non-temporal loads.
+The timing instance is a coupling-free copy of the box (the sweep kernel does
+not depend on the coupling).  Results are cached in a JSON file keyed by the
+device name, shape and precision.
+
+    python -m paper_1702_04910_amd.autotune 192 192 384 fp32
+"""
+import json
+import os
+import sys
+import time
+
+from . import lbmps
+
+CACHE = os.path.join(os.path.expanduser("~"), ".cache", "lbmps", "sweep_tuning.json")
+
+
+def _key(nx, ny, nz, precision):
+    import torch
+
+    return "%s|%dx%dx%d|%s" % (torch.cuda.get_device_name(0), nx, ny, nz, precision)
+
+
+def candidates(nx, precision):
+    s = lbmps.STORAGE_BYTES[lbmps.PRECISION[precision]]
+    max_rows = max(1, 65536 // (10 * s * nx))
+    rows = sorted({max(1, min(max_rows, t // nx)) for t in (256, 512, 1024, 2048, 4096)})
+    out = []
+    for r in rows:
+        for block in (128, 256):
+            for grid in (0, 2048):
+                for flags in (0, 1):
+                    out.append(dict(tile_rows=r, block_threads=block, grid_blocks=grid, sweep_flags=flags))
+    return out
+
+
+def time_shape(nx, ny, nz, precision, shape, sweeps=20, warmup=4):
+    cfg = lbmps.make_config(nx, ny, nz, 0.05, precision=precision, **shape)
+    sim = lbmps.Sim(cfg)
+    try:
+        sim.init_equilibrium()
+        sim.step(warmup)
+        sim.sync()
+        sim.set_timing(True)
+        sim.step(sweeps)
+        ms, n = sim.timing()
+        return ms / n * 1e3  # microseconds per sweep launch
+    finally:
+        sim.close()
+
+
+def tune(nx, ny, nz, precision, sweeps=20, cache=CACHE, force=False, verbose=False):
+    """Best launch shape for the box; returns dict(tile_rows, block_threads,
+    grid_blocks, sweep_flags, us)."""
+    key = _key(nx, ny, nz, precision)
+    db = {}
+    if cache and os.path.exists(cache):
+        try:
+            db = json.load(open(cache))
+        except ValueError:
+            db = {}
+    if key in db and not force:
+        return db[key]
+    best = None
+    for shape in candidates(nx, precision):
+        us = time_shape(nx, ny, nz, precision, shape, sweeps=sweeps)
+        if verbose:
+            print("  %s -> %.1f us" % (shape, us), file=sys.stderr, flush=True)
+        if best is None or us < best["us"]:
+            best = dict(shape, us=us)
+    if cache:
+        os.makedirs(os.path.dirname(cache), exist_ok=True)
+        db[key] = best
+        tmp = cache + ".tmp%d" % os.getpid()
+        json.dump(db, open(tmp, "w"), indent=1)
+        os.replace(tmp, cache)
+    return best
+
+
+if __name__ == "__main__":
+    nx, ny, nz = (int(v) for v in sys.argv[1:4])
+    prec = sys.argv[4] if len(sys.argv) > 4 else "fp32"
+    t0 = time.time()
+    r = tune(nx, ny, nz, prec, force=True, verbose=True)
+    print(json.dumps(r), "(%.1f s)" % (time.time() - t0))

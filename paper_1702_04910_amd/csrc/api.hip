@@ -77,6 +77,7 @@ bool valid_cfg(const lbmps_config& c, std::string& err) {
   if (c.eps_mode == LBMPS_EPS_RECURSIVE && (en & (en - 1))) { err = "recursive supersampling needs eps_n = 2^k"; return false; }
   if (c.eps_mode < 0 || c.eps_mode > 1) { err = "unknown eps_mode"; return false; }
   if (c.block_threads < 0 || c.block_threads > 256 || (c.block_threads % 64)) { err = "block_threads must be a multiple of 64, <= 256"; return false; }
+  if (c.sweep_flags & ~1) { err = "unknown sweep_flags bits"; return false; }
   if (c.n_sub < 0) { err = "n_sub must be >= 0"; return false; }
   if (10LL * (long long)storage_size(c.precision) * c.nx > SWEEP_LDS_LIMIT) {
     err = "nx too large for the LDS-staged sweep (10 * nx * element size must be <= 64 KiB)"; return false;
@@ -89,13 +90,13 @@ int eff_nsub(const lbmps_config& c) {
   return c.n_sub ? c.n_sub : 1;
 }
 
-// Rows per sweep tile: by default about 40 KB of LDS staging (10 shifted planes).
+// Rows per sweep tile: by default about one PDF block (256 cells) per tile,
+// bounded by the LDS staging limit (10 shifted planes).
 int eff_tile_rows(const lbmps_config& c) {
   const int s = (int)storage_size(c.precision);
   const int max_rows = std::max(1, SWEEP_LDS_LIMIT / (10 * s * c.nx));
   if (c.tile_rows > 0) return std::min(c.tile_rows, max_rows);
-  const int target_cells = 40960 / (10 * s);
-  return std::max(1, std::min(max_rows, target_cells / c.nx));
+  return std::max(1, std::min(max_rows, PDF_BLOCK / c.nx));
 }
 
 Layout make_layout(int n, const lbmps_config* cfgs) {
@@ -129,7 +130,7 @@ Layout make_layout(int n, const lbmps_config* cfgs) {
     const long long N = (long long)c.nx * c.ny * c.nz;
     L.ncell.push_back(N);
     L.pdf_off.push_back(pdf);
-    pdf += (19 * N + 63) / 64 * 64;
+    pdf += pdf_elems(N);
     L.owner_off.push_back(own);
     own += (N + 63) / 64 * 64;
     if (c.coupling == LBMPS_PSM) {
@@ -723,8 +724,8 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
       }
       HIPCHK(c, hipEventRecord(c->ev[c->ev_used], c->st));
     }
-    HIPCHK(c, launch_sweep(L.prec, c->inst_d, c->tiles_d, c->ntiles, c->grid, c->block, L.max_tile_cells, src, dst,
-                           c->st));
+    HIPCHK(c, launch_sweep(L.prec, c->inst_d, c->tiles_d, c->ntiles, c->grid, c->block, L.max_tile_cells,
+                           c->cfg[0].sweep_flags, src, dst, c->st));
     if (c->timing) {
       HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->st));
       c->ev_used += 2;
@@ -824,7 +825,7 @@ lbmps_status lbmps_get_pdfs(lbmps_ctx* c, int32_t inst, double* g) {
   for (int q = 0; q < 19; ++q)
     for (long long c0 = 0; c0 < N; c0 += ch) {
       const long long n = std::min(ch, N - c0);
-      HIPCHK(c, launch_to_f64(L.prec, buf + ((long long)q * N + c0) * L.ssz, c->scratch, n, c->st));
+      HIPCHK(c, launch_to_f64(L.prec, buf, q, c0, c->scratch, n, c->st));
       HIPCHK(c, hipMemcpyAsync(g + (long long)q * N + c0, c->scratch, n * 8, hipMemcpyDeviceToHost, c->st));
       HIPCHK(c, hipStreamSynchronize(c->st));
     }
@@ -848,7 +849,7 @@ lbmps_status lbmps_set_pdfs(lbmps_ctx* c, int32_t inst, const double* g) {
     for (long long c0 = 0; c0 < N; c0 += ch) {
       const long long n = std::min(ch, N - c0);
       HIPCHK(c, hipMemcpyAsync(c->scratch, g + (long long)q * N + c0, n * 8, hipMemcpyHostToDevice, c->st));
-      HIPCHK(c, launch_from_f64(L.prec, c->scratch, buf + ((long long)q * N + c0) * L.ssz, n, c->st));
+      HIPCHK(c, launch_from_f64(L.prec, c->scratch, buf, q, c0, n, c->st));
       HIPCHK(c, hipStreamSynchronize(c->st));
     }
   return LBMPS_OK;

@@ -8,8 +8,12 @@
 //   (0,1,1) (0,-1,-1) (0,1,-1) (0,-1,1)
 // Weights 1/3, 1/18 (axis), 1/36 (diagonal).
 //
-// PDFs are stored as deviations g_q = f_q - w_q, structure of arrays
-// g[q][z][y][x] (x fastest), one array per buffer per instance.
+// PDFs are stored as deviations g_q = f_q - w_q in blocks of PDF_BLOCK = 256
+// consecutive cells (linear cell index (z*ny + y)*nx + x): block b holds its 19
+// planes one after the other, so (q, cell) lives at
+//   ((cell / 256) * 19 + q) * 256 + cell % 256.
+// Inside a block this is a structure of arrays; the blocks keep the 19 streams
+// of a workgroup within one contiguous region of memory.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -19,6 +23,14 @@
 namespace lbm {
 
 constexpr int Q = 19;
+constexpr int PDF_BLOCK = 256;
+__host__ __device__ inline long long pdf_at(long long cell, int q) {
+  return ((cell >> 8) * Q + q) * PDF_BLOCK + (cell & (PDF_BLOCK - 1));
+}
+// elements of one instance's PDF array (cells padded to whole blocks)
+__host__ __device__ inline long long pdf_elems(long long ncell) {
+  return (ncell + PDF_BLOCK - 1) / PDF_BLOCK * PDF_BLOCK * Q;
+}
 
 __host__ __device__ constexpr int cx(int q) {
   return (q == 1 || q == 7 || q == 9 || q == 11 || q == 13) ? 1

@@ -7,12 +7,13 @@
 namespace lbm {
 
 // ---- sweep.hip
+enum { SWEEP_NT_LOADS = 1 };
 hipError_t launch_sweep(int prec, const InstDev* insts, const int4* tiles, int ntiles, int grid, int block,
-                        int max_tile_cells, const void* src, void* dst, hipStream_t st);
+                        int max_tile_cells, int flags, const void* src, void* dst, hipStream_t st);
 constexpr int SWEEP_LDS_LIMIT = 64 * 1024;  // bytes of LDS staging per sweep workgroup
 hipError_t launch_init_eq(int prec, void* buf, long long N, double rho, const double u[3], hipStream_t st);
-hipError_t launch_to_f64(int prec, const void* a, double* b, long long n, hipStream_t st);
-hipError_t launch_from_f64(int prec, const double* a, void* b, long long n, hipStream_t st);
+hipError_t launch_to_f64(int prec, const void* a, int q, long long c0, double* b, long long n, hipStream_t st);
+hipError_t launch_from_f64(int prec, const double* a, void* b, int q, long long c0, long long n, hipStream_t st);
 hipError_t launch_fields(int prec, const void* buf, long long N, long long c0, long long n, const int* owner,
                          const double f[3], double* out, hipStream_t st);
 

@@ -307,7 +307,7 @@ __global__ __launch_bounds__(256) void mem_refill_kernel(const int* __restrict__
     double o = 0.0;
     if (ns > 0) {
       double f[3] = {0, 0, 0};
-      for (int k = 0; k < ns; ++k) f[k] = (double)Codec<S>::ld(b[(long long)q * N + src_cell[k]]);
+      for (int k = 0; k < ns; ++k) f[k] = (double)Codec<S>::ld(b[pdf_at(src_cell[k], q)]);
       o = ns == 3 ? 3.0 * f[0] - 3.0 * f[1] + f[2] : (ns == 2 ? 2.0 * f[0] - f[1] : f[0]);
     } else {
       // lane q' < 18 inspects neighbour q' + 1; fluctuation sum over its 19 PDFs
@@ -317,7 +317,7 @@ __global__ __launch_bounds__(256) void mem_refill_kernel(const int* __restrict__
         const int xi = wrapi(x + cx(qq), I.nx), yi = wrapi(y + cy(qq), I.ny), zi = wrapi(z + cz(qq), I.nz);
         const int c2 = (zi * I.ny + yi) * I.nx + xi;
         if (own[c2] == OWN_FLUID) {
-          for (int k = 0; k < Q; ++k) s += (double)Codec<S>::ld(b[(long long)k * N + c2]);
+          for (int k = 0; k < Q; ++k) s += (double)Codec<S>::ld(b[pdf_at(c2, k)]);
           cntv = 1.0;
         }
       }
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(256) void mem_refill_kernel(const int* __restrict__
     const double dj[3] = {(v[0] - 0.5 * I.fext[0]) - jx, (v[1] - 0.5 * I.fext[1]) - jy, (v[2] - 0.5 * I.fext[2]) - jz};
     if (lane < Q) {
       const double val = o + (cx(q) * dj[0] + cy(q) * dj[1] + cz(q) * dj[2]) / 10.0;
-      b[(long long)q * N + cell] = Codec<S>::st((typename CompOf<S>::type)val);
+      b[pdf_at(cell, q)] = Codec<S>::st((typename CompOf<S>::type)val);
     }
   }
 }
@@ -378,7 +378,7 @@ __global__ void links_bc_kernel(int n_wall, const int* __restrict__ count, int c
     S* b = buf + I.pdf_off;
     const int c[3] = {cx(q), cy(q), cz(q)};
     const int xs = wrapi(x + c[0], I.nx), ys = wrapi(y + c[1], I.ny), zs = wrapi(z + c[2], I.nz);
-    const double gtq = (double)Codec<S>::ld(b[(long long)q * N + ((long long)zs * I.ny + ys) * I.nx + xs]);
+    const double gtq = (double)Codec<S>::ld(b[pdf_at(((long long)zs * I.ny + ys) * I.nx + xs, q)]);
     double v[3], arm[3] = {0, 0, 0};
     bool cli = false;
     double delta = 0.5;
@@ -406,14 +406,14 @@ __global__ void links_bc_kernel(int n_wall, const int* __restrict__ count, int c
       const double k0 = (1.0 - 2.0 * delta) / (1.0 + 2.0 * delta);
       const double alpha = 4.0 / (1.0 + 2.0 * delta);
       const int xm = wrapi(x - c[0], I.nx), ym = wrapi(y - c[1], I.ny), zm = wrapi(z - c[2], I.nz);
-      const double gq_m = (double)Codec<S>::ld(b[(long long)q * N + cell]);
-      const double gqb = (double)Codec<S>::ld(b[(long long)qb * N + ((long long)zm * I.ny + ym) * I.nx + xm]);
+      const double gq_m = (double)Codec<S>::ld(b[pdf_at(cell, q)]);
+      const double gqb = (double)Codec<S>::ld(b[pdf_at(((long long)zm * I.ny + ym) * I.nx + xm, qb)]);
       val = gtq + k0 * gq_m - k0 * gqb - 3.0 * alpha * w * vc;
     } else {
       val = gtq - 6.0 * w * vc;
     }
     const S sv = Codec<S>::st((typename CompOf<S>::type)val);
-    b[(long long)qb * N + cell] = sv;
+    b[pdf_at(cell, qb)] = sv;
     if (p >= 0) {
       const double vs = (double)Codec<S>::ld(sv);
       double F[3];

@@ -306,7 +306,7 @@ __global__ __launch_bounds__(256) void psm_collide_kernel(const int* __restrict_
     S* d = dst + I.pdf_off;
     R g[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) g[q] = Codec<S>::ld(s[(long long)q * N + c]);
+    for (int q = 0; q < Q; ++q) g[q] = Codec<S>::ld(s[pdf_at(c, q)]);
     R drho = 0, ux = 0, uy = 0, uz = 0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(256) void psm_collide_kernel(const int* __restrict_
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int xa = wrapi(x + cx(q), nx), ya = wrapi(y + cy(q), ny), za = wrapi(z + cz(q), nz);
-      d[(long long)q * N + ((long long)za * ny + ya) * nx + xa] = Codec<S>::st(out[q]);
+      d[pdf_at(((long long)za * ny + ya) * nx + xa, q)] = Codec<S>::st(out[q]);
     }
   }
 }
@@ -444,7 +444,7 @@ __global__ void psm_fields_kernel(const int* __restrict__ count, int cap, const 
     double jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int q = 1; q < Q; ++q) {
-      const double gq = (double)Codec<S>::ld(s[(long long)q * N + c]);
+      const double gq = (double)Codec<S>::ld(s[pdf_at(c, q)]);
       jx += cx(q) * gq;
       jy += cy(q) * gq;
       jz += cz(q) * gq;

@@ -105,6 +105,15 @@ constexpr int NXSHIFT = 10;
 // written out aligned.  Every global store therefore covers whole, aligned row
 // segments.
 template <typename S>
+__device__ __forceinline__ S ld_nt(const S* p) {
+  return __builtin_nontemporal_load(p);
+}
+template <>
+__device__ __forceinline__ __bf16 ld_nt<__bf16>(const __bf16* p) {
+  return __builtin_bit_cast(__bf16, __builtin_nontemporal_load((const unsigned short*)p));
+}
+
+template <typename S, bool NTLD>
 __global__ __launch_bounds__(256) void sweep_kernel(const InstDev* __restrict__ insts, const int4* __restrict__ tiles,
                                                     int ntiles, const S* __restrict__ src, S* __restrict__ dst) {
   using R = typename CompOf<S>::type;
@@ -129,7 +138,10 @@ __global__ __launch_bounds__(256) void sweep_kernel(const InstDev* __restrict__ 
       const int idx = row * nx + x;
       R g[Q], o[Q];
 #pragma unroll
-      for (int q = 0; q < Q; ++q) g[q] = Codec<S>::ld(s[(long long)q * N + idx]);
+      for (int q = 0; q < Q; ++q) {
+        const S* a = &s[pdf_at(idx, q)];
+        g[q] = Codec<S>::ld(NTLD ? ld_nt(a) : *a);
+      }
       collide_cell<R>(g, o, lp, lm, fx, fy, fz);
       const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
       const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
@@ -138,7 +150,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(const InstDev* __restrict__ 
 #define LBM_PUSH(qq)                                                                        \
   if constexpr (cx(qq) == 0) {                                                              \
     const int ya = pick<cy(qq)>(ym, y, yp), za = pick<cz(qq)>(zm, z, zp);                   \
-    st_nt(&d[(long long)(qq) * N + (za * ny + ya) * nx + x], Codec<S>::st(o[qq]));         \
+    st_nt(&d[pdf_at((za * ny + ya) * nx + x, qq)], Codec<S>::st(o[qq]));                   \
   } else {                                                                                  \
     sh[xslot(qq) * ncells + lrow + pick<cx(qq)>(xm, x, xp)] = Codec<S>::st(o[qq]);          \
   }
@@ -159,7 +171,7 @@ __global__ __launch_bounds__(256) void sweep_kernel(const InstDev* __restrict__ 
 #define LBM_FLUSH(qq)                                                                       \
   {                                                                                         \
     const int ya = pick<cy(qq)>(ym, y, yp), za = pick<cz(qq)>(zm, z, zp);                   \
-    st_nt(&d[(long long)(qq) * N + (za * ny + ya) * nx + x], sh[xslot(qq) * ncells + i]);   \
+    st_nt(&d[pdf_at((za * ny + ya) * nx + x, qq)], sh[xslot(qq) * ncells + i]);             \
   }
       LBM_FLUSH(1) LBM_FLUSH(2) LBM_FLUSH(7) LBM_FLUSH(8) LBM_FLUSH(9) LBM_FLUSH(10) LBM_FLUSH(11)
       LBM_FLUSH(12) LBM_FLUSH(13) LBM_FLUSH(14)
@@ -179,20 +191,21 @@ __global__ void init_eq_kernel(S* __restrict__ buf, long long N, double rho, dou
   for (int q = 0; q < Q; ++q) {
     const double cu = cx(q) * ux + cy(q) * uy + cz(q) * uz;
     const double v = wq(q) * ((rho - 1.0) + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-    buf[(long long)q * N + i] = Codec<S>::st((typename CompOf<S>::type)v);
+    buf[pdf_at(i, q)] = Codec<S>::st((typename CompOf<S>::type)v);
   }
 }
 
+// Plane q, cells [c0, c0 + n) of one instance <-> a dense FP64 array.
 template <typename S>
-__global__ void to_f64_kernel(const S* __restrict__ a, double* __restrict__ b, long long n) {
+__global__ void to_f64_kernel(const S* __restrict__ a, int q, long long c0, double* __restrict__ b, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = (double)Codec<S>::ld(a[i]);
+  if (i < n) b[i] = (double)Codec<S>::ld(a[pdf_at(c0 + i, q)]);
 }
 
 template <typename S>
-__global__ void from_f64_kernel(const double* __restrict__ a, S* __restrict__ b, long long n) {
+__global__ void from_f64_kernel(const double* __restrict__ a, S* __restrict__ b, int q, long long c0, long long n) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = Codec<S>::st((typename CompOf<S>::type)a[i]);
+  if (i < n) b[pdf_at(c0 + i, q)] = Codec<S>::st((typename CompOf<S>::type)a[i]);
 }
 
 // Density and macroscopic velocity (Eq. MacVel) of cells [c0, c0 + n); solid
@@ -210,7 +223,7 @@ __global__ void fields_kernel(const S* __restrict__ buf, long long N, long long 
   if (!solid) {
     double g[Q];
 #pragma unroll
-    for (int q = 0; q < Q; ++q) g[q] = (double)Codec<S>::ld(buf[(long long)q * N + c]);
+    for (int q = 0; q < Q; ++q) g[q] = (double)Codec<S>::ld(buf[pdf_at(c, q)]);
     double s = 0.0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) s += g[q];
@@ -235,19 +248,24 @@ __global__ void fields_kernel(const S* __restrict__ buf, long long N, long long 
 // ------------------------------------------------------------------------ launchers
 template <typename S>
 hipError_t launch_sweep_t(const InstDev* insts, const int4* tiles, int ntiles, int grid, int block, int max_tile_cells,
-                          const void* src, void* dst, hipStream_t st) {
+                          int flags, const void* src, void* dst, hipStream_t st) {
   const size_t lds = (size_t)NXSHIFT * max_tile_cells * sizeof(S);
-  hipLaunchKernelGGL(sweep_kernel<S>, dim3(grid), dim3(block), lds, st, insts, tiles, ntiles, (const S*)src, (S*)dst);
+  if (flags & SWEEP_NT_LOADS)
+    hipLaunchKernelGGL((sweep_kernel<S, true>), dim3(grid), dim3(block), lds, st, insts, tiles, ntiles, (const S*)src,
+                       (S*)dst);
+  else
+    hipLaunchKernelGGL((sweep_kernel<S, false>), dim3(grid), dim3(block), lds, st, insts, tiles, ntiles, (const S*)src,
+                       (S*)dst);
   return hipGetLastError();
 }
 
 hipError_t launch_sweep(int prec, const InstDev* insts, const int4* tiles, int ntiles, int grid, int block,
-                        int max_tile_cells, const void* src, void* dst, hipStream_t st) {
+                        int max_tile_cells, int flags, const void* src, void* dst, hipStream_t st) {
   switch (prec) {
-    case PREC_FP64: return launch_sweep_t<double>(insts, tiles, ntiles, grid, block, max_tile_cells, src, dst, st);
-    case PREC_FP32: return launch_sweep_t<float>(insts, tiles, ntiles, grid, block, max_tile_cells, src, dst, st);
-    case PREC_FP16: return launch_sweep_t<_Float16>(insts, tiles, ntiles, grid, block, max_tile_cells, src, dst, st);
-    case PREC_BF16: return launch_sweep_t<__bf16>(insts, tiles, ntiles, grid, block, max_tile_cells, src, dst, st);
+    case PREC_FP64: return launch_sweep_t<double>(insts, tiles, ntiles, grid, block, max_tile_cells, flags, src, dst, st);
+    case PREC_FP32: return launch_sweep_t<float>(insts, tiles, ntiles, grid, block, max_tile_cells, flags, src, dst, st);
+    case PREC_FP16: return launch_sweep_t<_Float16>(insts, tiles, ntiles, grid, block, max_tile_cells, flags, src, dst, st);
+    case PREC_BF16: return launch_sweep_t<__bf16>(insts, tiles, ntiles, grid, block, max_tile_cells, flags, src, dst, st);
   }
   return hipErrorInvalidValue;
 }
@@ -268,17 +286,17 @@ hipError_t launch_init_eq(int prec, void* buf, long long N, double rho, const do
   return hipGetLastError();
 }
 
-hipError_t launch_to_f64(int prec, const void* a, double* b, long long n, hipStream_t st) {
+hipError_t launch_to_f64(int prec, const void* a, int q, long long c0, double* b, long long n, hipStream_t st) {
   const int bl = 256;
   const unsigned g = (unsigned)((n + bl - 1) / bl);
-  LBM_DISPATCH(prec, hipLaunchKernelGGL(to_f64_kernel<S>, dim3(g), dim3(bl), 0, st, (const S*)a, b, n));
+  LBM_DISPATCH(prec, hipLaunchKernelGGL(to_f64_kernel<S>, dim3(g), dim3(bl), 0, st, (const S*)a, q, c0, b, n));
   return hipGetLastError();
 }
 
-hipError_t launch_from_f64(int prec, const double* a, void* b, long long n, hipStream_t st) {
+hipError_t launch_from_f64(int prec, const double* a, void* b, int q, long long c0, long long n, hipStream_t st) {
   const int bl = 256;
   const unsigned g = (unsigned)((n + bl - 1) / bl);
-  LBM_DISPATCH(prec, hipLaunchKernelGGL(from_f64_kernel<S>, dim3(g), dim3(bl), 0, st, a, (S*)b, n));
+  LBM_DISPATCH(prec, hipLaunchKernelGGL(from_f64_kernel<S>, dim3(g), dim3(bl), 0, st, a, (S*)b, q, c0, n));
   return hipGetLastError();
 }
 

@@ -29,6 +29,7 @@ class Config(ctypes.Structure):
         ("eps_n", ctypes.c_int32), ("eps_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("max_particles", ctypes.c_int32), ("tile_rows", ctypes.c_int32), ("block_threads", ctypes.c_int32),
         ("grid_blocks", ctypes.c_int32), ("wall_link_cap", ctypes.c_int32),
+        ("sweep_flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
         ("max_diameter", ctypes.c_double), ("nu", ctypes.c_double), ("magic", ctypes.c_double),
         ("f_ext", ctypes.c_double * 3), ("gravity", ctypes.c_double * 3),
     ]
@@ -118,7 +119,7 @@ def velocities():
 def make_config(nx, ny, nz, nu, collision="trt", coupling="none", psm_m=1, psm_b=1, n_sub=0, eps_n=8,
                 eps_mode=EPS_FLAT, precision="fp64", max_particles=0, max_diameter=0.0, magic=3.0 / 16.0,
                 f_ext=(0.0, 0.0, 0.0), gravity=(0.0, 0.0, 0.0), tile_rows=0, block_threads=0, grid_blocks=0,
-                wall_link_cap=0):
+                wall_link_cap=0, sweep_flags=0):
     c = Config()
     c.nx, c.ny, c.nz = nx, ny, nz
     c.collision = TRT if collision == "trt" else BGK
@@ -128,6 +129,7 @@ def make_config(nx, ny, nz, nu, collision="trt", coupling="none", psm_m=1, psm_b
     c.precision = PRECISION[precision] if isinstance(precision, str) else precision
     c.max_particles = max_particles
     c.tile_rows, c.block_threads, c.grid_blocks, c.wall_link_cap = tile_rows, block_threads, grid_blocks, wall_link_cap
+    c.sweep_flags = sweep_flags
     c.max_diameter, c.nu, c.magic = max_diameter, nu, magic
     for k in range(3):
         c.f_ext[k] = f_ext[k]
