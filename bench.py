@@ -34,7 +34,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def tuned_shape(inp, precision):
+    """Sweep launch shape from the autotuner (timed on this GPU, cached)."""
+    from paper_1702_04910_amd import autotune
+
+    best = autotune.tune(inp["nx"], inp["ny"], inp["nz"], precision)
+    return {k: best[k] for k in ("tile_rows", "block_threads", "grid_blocks", "sweep_flags")}
+
+
 def build_sim(lbmps, inp, coupling, precision, psm=(3, 2), eps_n=8, **launch):
+    if not launch:
+        launch = tuned_shape(inp, precision)
     # two LBM sweeps per rigid-body step with averaged forces, for MEM and PSM (Sec. 4.1)
     cfg = lbmps.make_config(inp["nx"], inp["ny"], inp["nz"], inp["nu"], collision="trt", coupling=coupling,
                             psm_m=psm[0], psm_b=psm[1], n_sub=2, eps_n=eps_n, eps_mode=lbmps.EPS_RECURSIVE,
@@ -141,7 +151,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "sweep_kernel<float>", "alg_bytes_per_launch": alg_bytes,
-                     "avg_launch_us": round(sweep_s * 1e6, 2), "launches": launches},
+                     "avg_launch_us": round(sweep_s * 1e6, 2), "launches": launches,
+                     "launch_shape": tuned_shape(inp, "fp32")},
     }
 
     # ---- storage forms and couplings against the FP64 run

@@ -90,13 +90,15 @@ int eff_nsub(const lbmps_config& c) {
   return c.n_sub ? c.n_sub : 1;
 }
 
-// Rows per sweep tile: by default about one PDF block (256 cells) per tile,
+// Rows per sweep tile: by default about one PDF block (256 cells) per tile for
+// 4- and 8-byte storage and two blocks for 2-byte storage (measured optima),
 // bounded by the LDS staging limit (10 shifted planes).
 int eff_tile_rows(const lbmps_config& c) {
   const int s = (int)storage_size(c.precision);
   const int max_rows = std::max(1, SWEEP_LDS_LIMIT / (10 * s * c.nx));
   if (c.tile_rows > 0) return std::min(c.tile_rows, max_rows);
-  return std::max(1, std::min(max_rows, PDF_BLOCK / c.nx));
+  const int target = s == 2 ? 2 * PDF_BLOCK : PDF_BLOCK;
+  return std::max(1, std::min(max_rows, target / c.nx));
 }
 
 Layout make_layout(int n, const lbmps_config* cfgs) {
