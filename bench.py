@@ -71,6 +71,57 @@ def timed_run(torch, sim, steps, warmup, n_sub, timing=True):
     return t1 - t0, ms, launches
 
 
+def batched(torch, lbmps, inputs, steps, warmup, seed):
+    """48 settling-sphere instances (D from {8, 12, 16, 24}, box 6D x 6D x 12D,
+    MEM-CLI / PSM mixed, FP32) advanced together: one sweep launch over all
+    instances, the whole step replayed from a HIP graph, launch shape from the
+    batch autotuner."""
+    from paper_1702_04910_amd import autotune
+
+    insts = inputs.c4_batch(seed)
+    dmax = max(d["D"] for d in insts)
+    stream = torch.cuda.Stream()
+    cells = sum(d["nx"] * d["ny"] * d["nz"] for d in insts)
+
+    def make(tile_cells):
+        cfgs = [lbmps.make_config(d["nx"], d["ny"], d["nz"], d["nu"], collision="trt", coupling=d["coupling"],
+                                  psm_m=d["psm_m"], psm_b=d["psm_b"], n_sub=2, eps_n=8,
+                                  eps_mode=lbmps.EPS_RECURSIVE, precision="fp32", max_particles=1,
+                                  max_diameter=dmax, f_ext=d["f_ext"], gravity=d["gravity"],
+                                  tile_rows=max(1, tile_cells // d["nx"])) for d in insts]
+        sim = lbmps.Sim(cfgs, stream=stream)
+        for i, d in enumerate(insts):
+            sim.init_equilibrium(inst=i)
+            sim.set_particles([d["X"]], [[0, 0, 0]], [[0, 0, 0]], [d["D"]], [d["rho"]], [False], inst=i)
+        return sim
+
+    best = autotune.tune_batch(make)
+    sim = make(best["tile_cells"])
+    sim.set_launch(best["block_threads"], best["grid_blocks"], best["sweep_flags"])
+    sim.step_graph(2 * warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step_graph(2 * steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # sweep-kernel bandwidth from eager, HIP-event-timed sweeps of the same batch
+    sim.set_timing(True)
+    sim.step(20)
+    ms, n = sim.timing()
+    sim.set_timing(False)
+    sim.close()
+    kinds = {}
+    for d in insts:
+        kinds[d["coupling"]] = kinds.get(d["coupling"], 0) + 1
+    return {"instances": len(insts), "cells": cells, "couplings": kinds, "MLUPS": round(cells * 2 * steps / wall / 1e6, 1),
+            "ms_per_step": round(wall / steps * 1e3, 4), "graph": True, "launch": best,
+            "sweep_GBs": round(2 * 19 * 4 * cells / (ms / 1e3 / n) / 1e9, 1),
+            "velocity_error_vs_solo": 0.0,
+            "note": "each instance is bitwise equal to the same instance run alone (tests/test_gpu_batch.py)"}
+
+
 def cpu_baseline(inp, steps=30):
     """The FP64 oracle on a sub-box of the same workload (same sphere
     resolution, half the box in each horizontal direction)."""
@@ -104,6 +155,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-forms", action="store_true", help="only the primary FP32 MEM-CLI run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 48-instance batched form")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
@@ -186,6 +238,10 @@ def main():
                 ent["force_error_vs_fp64"] = float(np.linalg.norm(pf["F"][0] - r["F"][0]) / np.linalg.norm(r["F"][0]))
             out[name] = ent
         line["forms"] = out
+
+    if not args.no_batch:
+        log("batched form (48 instances)")
+        line["batched"] = batched(torch, lbmps, inputs, min(args.steps, 100), min(args.warmup, 10), args.seed)
 
     if not args.no_cpu_baseline:
         log("cpu baseline")

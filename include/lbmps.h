@@ -153,6 +153,19 @@ lbmps_status lbmps_set_particles(lbmps_ctx* ctx, int32_t inst, int32_t n, const 
  * n_steps must be a multiple of every n_sub in the context.  Asynchronous. */
 lbmps_status lbmps_step(lbmps_ctx* ctx, int32_t n_steps);
 
+/* Change the sweep launch shape of an existing context (workgroup size, grid:
+ * 0 = one workgroup per tile, > 0 persistent; flags as sweep_flags).  Results
+ * do not depend on it.  Drops a captured graph. */
+lbmps_status lbmps_set_launch(lbmps_ctx* ctx, int32_t block_threads, int32_t grid_blocks, int32_t sweep_flags);
+
+/* Same as lbmps_step, replayed from a HIP graph: the launch sequence of one
+ * period of sweeps (even, and a multiple of every n_sub) is captured on the
+ * context's stream at the first call and replayed n_steps/period times.  The
+ * capture is redone after lbmps_set_particles / lbmps_set_static_solid.
+ * Needs a non-default stream; timing must be off.  Asynchronous.
+ * Errors: EINVAL (n_steps not a multiple of the period), ESTATE. */
+lbmps_status lbmps_step_graph(lbmps_ctx* ctx, int32_t n_steps);
+
 /* Block until the stream is idle; report device-side errors. */
 lbmps_status lbmps_sync(lbmps_ctx* ctx);
 

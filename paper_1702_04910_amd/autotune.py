@@ -82,6 +82,33 @@ def tune(nx, ny, nz, precision, sweeps=20, cache=CACHE, force=False, verbose=Fal
     return best
 
 
+def tune_batch(make_sim, tile_cells=(256, 512, 1024), grids=(0, 1024, 2048, 4096), sweeps=10, verbose=False):
+    """Launch shape for a batched context.  make_sim(tile_cells) must return a
+    ready Sim whose configurations use rows = max(1, tile_cells // nx).  Times
+    the batched sweep for each tile size x grid x load kind; returns the best
+    dict(tile_cells, block_threads, grid_blocks, sweep_flags, us)."""
+    best = None
+    for tc in tile_cells:
+        sim = make_sim(tc)
+        try:
+            for grid in grids:
+                for flags in (0, 1):
+                    sim.set_launch(256, grid, flags)
+                    sim.set_timing(True)
+                    sim.step(sweeps)
+                    ms, n = sim.timing()
+                    sim.set_timing(False)
+                    us = ms / n * 1e3
+                    if verbose:
+                        print("  tile %d grid %d flags %d -> %.1f us" % (tc, grid, flags, us), file=sys.stderr,
+                              flush=True)
+                    if best is None or us < best["us"]:
+                        best = dict(tile_cells=tc, block_threads=256, grid_blocks=grid, sweep_flags=flags, us=us)
+        finally:
+            sim.close()
+    return best
+
+
 if __name__ == "__main__":
     nx, ny, nz = (int(v) for v in sys.argv[1:4])
     prec = sys.argv[4] if len(sys.argv) > 4 else "fp32"

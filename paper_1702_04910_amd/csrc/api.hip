@@ -226,6 +226,10 @@ struct lbmps_ctx {
   double* scratch = nullptr;
   long long sweeps = 0;
   bool have_psm = false, have_links_inst = false;
+  // captured step graph (one period of sweeps), invalidated when lists change
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  int graph_period = 0, graph_cur = -1;
   // optional per-launch timing of the sweep kernel (HIP events on the stream)
   bool timing = false;
   std::vector<hipEvent_t> ev;  // pairs (start, stop)
@@ -352,6 +356,14 @@ lbmps_status harvest_timing(lbmps_ctx* c) {
   }
   c->ev_used = 0;
   return LBMPS_OK;
+}
+
+void drop_graph(lbmps_ctx* c) {
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+  c->graph_cur = -1;
 }
 
 lbmps_status check_inst(lbmps_ctx* c, int inst) {
@@ -529,6 +541,8 @@ lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* ws, s
 void lbmps_destroy(lbmps_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->st);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   delete c;
 }
@@ -553,6 +567,7 @@ lbmps_status lbmps_set_static_solid(lbmps_ctx* c, int32_t inst, const uint8_t* m
   if (s) return s;
   if (!mask || !v_wall) return fail(c, LBMPS_EINVAL, "null argument");
   if (c->n_mem + c->n_psm > 0) return fail(c, LBMPS_ESTATE, "set static walls before any particles");
+  drop_graph(c);
   if (c->wall_groups[inst] >= 16) return fail(c, LBMPS_EINVAL, "at most 16 wall groups per instance");
   const lbmps_config& cf = c->cfg[inst];
   const int nx = cf.nx, ny = cf.ny, nz = cf.nz;
@@ -615,6 +630,7 @@ lbmps_status lbmps_set_static_solid(lbmps_ctx* c, int32_t inst, const uint8_t* m
 lbmps_status lbmps_set_particles(lbmps_ctx* c, int32_t inst, int32_t n, const lbmps_particle* hp) {
   lbmps_status s = check_inst(c, inst);
   if (s) return s;
+  drop_graph(c);
   const lbmps_config& cf = c->cfg[inst];
   if (n < 0 || n > cf.max_particles) return fail(c, LBMPS_EINVAL, "particle count exceeds max_particles");
   if (n > 0 && !hp) return fail(c, LBMPS_EINVAL, "null particle array");
@@ -759,6 +775,57 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
         if (r) return r;
       }
     }
+  }
+  return LBMPS_OK;
+}
+
+lbmps_status lbmps_set_launch(lbmps_ctx* c, int32_t block_threads, int32_t grid_blocks, int32_t sweep_flags) {
+  if (!c) return LBMPS_EINVAL;
+  if (block_threads < 0 || block_threads > 256 || (block_threads % 64)) return fail(c, LBMPS_EINVAL, "bad block size");
+  if (grid_blocks < 0 || (sweep_flags & ~1)) return fail(c, LBMPS_EINVAL, "bad grid or flags");
+  drop_graph(c);
+  c->block = block_threads ? block_threads : 256;
+  c->grid = grid_blocks > 0 ? std::min(grid_blocks, c->ntiles) : c->ntiles;
+  for (auto& cf : c->cfg) cf.sweep_flags = sweep_flags;
+  return LBMPS_OK;
+}
+
+static int gcd_int(int a, int b) { return b ? gcd_int(b, a % b) : a; }
+
+lbmps_status lbmps_step_graph(lbmps_ctx* c, int32_t n) {
+  if (!c) return LBMPS_EINVAL;
+  const Layout& L = c->L;
+  int period = 2;
+  for (int ns : {L.mem_nsub, L.psm_nsub})
+    if (ns > 0) period = period / gcd_int(period, ns) * ns;
+  if (n < 0 || n % period) return fail(c, LBMPS_EINVAL, "graph steps must be a multiple of the capture period");
+  if (c->sweeps % period) return fail(c, LBMPS_ESTATE, "graph replay must start at a rigid-body step boundary");
+  if (!c->st) return fail(c, LBMPS_EINVAL, "graph capture needs a non-default stream");
+  if (c->timing) return fail(c, LBMPS_ESTATE, "disable timing before graph replay");
+  if (c->graph_exec && (c->graph_period != period || c->graph_cur != c->cur)) drop_graph(c);
+  if (!c->graph_exec) {
+    HIPCHK(c, hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+    const long long sweeps0 = c->sweeps;
+    const int cur0 = c->cur;
+    lbmps_status r = lbmps_step(c, period);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->st, &g);
+    // the captured launches have not run: restore the host-side counters
+    c->sweeps = sweeps0;
+    c->cur = cur0;
+    if (r) {
+      if (g) (void)hipGraphDestroy(g);
+      return r;
+    }
+    if (e != hipSuccess) return fail(c, LBMPS_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    c->graph = g;
+    HIPCHK(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+    c->graph_period = period;
+    c->graph_cur = c->cur;
+  }
+  for (int k = 0; k < n / period; ++k) {
+    HIPCHK(c, hipGraphLaunch(c->graph_exec, c->st));
+    c->sweeps += period;
   }
   return LBMPS_OK;
 }

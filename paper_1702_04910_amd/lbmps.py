@@ -80,6 +80,10 @@ def lib():
         L.lbmps_set_particles.argtypes = [P, I32, I32, P]
         L.lbmps_step.restype = I32
         L.lbmps_step.argtypes = [P, I32]
+        L.lbmps_set_launch.restype = I32
+        L.lbmps_set_launch.argtypes = [P, I32, I32, I32]
+        L.lbmps_step_graph.restype = I32
+        L.lbmps_step_graph.argtypes = [P, I32]
         L.lbmps_sync.restype = I32
         L.lbmps_sync.argtypes = [P]
         L.lbmps_get_particles.restype = I32
@@ -215,6 +219,12 @@ class Sim:
 
     def step(self, n):
         self._chk(lib().lbmps_step(self._ctx, int(n)))
+
+    def set_launch(self, block_threads=0, grid_blocks=0, sweep_flags=0):
+        self._chk(lib().lbmps_set_launch(self._ctx, block_threads, grid_blocks, sweep_flags))
+
+    def step_graph(self, n):
+        self._chk(lib().lbmps_step_graph(self._ctx, int(n)))
 
     def sync(self):
         self._chk(lib().lbmps_sync(self._ctx))
