@@ -66,6 +66,8 @@ typedef int32_t lbmps_status;
 /* solid-fraction estimator (Sec. 2.3.2) */
 #define LBMPS_EPS_FLAT 0      /* eps_n^3 sub-cell sample points, every point tested */
 #define LBMPS_EPS_RECURSIVE 1 /* same points, octree blocks classified at once (eps_n power of 2) */
+#define LBMPS_EPS_LEARNED 2   /* cells cut by the surface: the network of lbmps_set_eps_model inside its
+                                 radius range, flat eps_n^3 supersampling outside it */
 
 typedef struct lbmps_config {
   int32_t nx, ny, nz;  /* periodic box (cells) */
@@ -76,7 +78,7 @@ typedef struct lbmps_config {
   int32_t n_sub;       /* LBM sweeps per rigid-body step, forces averaged over them (Sec. 2.2.4, Sec. 4.1);
                           0 = 2 for MEM, 1 for PSM (Alg. 2) */
   int32_t eps_n;       /* supersampling points per axis (default 8) */
-  int32_t eps_mode;    /* LBMPS_EPS_FLAT or LBMPS_EPS_RECURSIVE */
+  int32_t eps_mode;    /* LBMPS_EPS_FLAT, LBMPS_EPS_RECURSIVE or LBMPS_EPS_LEARNED */
   int32_t precision;   /* LBMPS_FP64 .. LBMPS_BF16_DEV */
   int32_t max_particles;
   int32_t tile_rows;     /* x-rows per sweep workgroup (0 = automatic) */
@@ -197,6 +199,81 @@ lbmps_status lbmps_get_overlaps(lbmps_ctx* ctx, int64_t cap, int32_t* cell, int3
  * and the number of launches timed. */
 lbmps_status lbmps_set_timing(lbmps_ctx* ctx, int32_t enable);
 lbmps_status lbmps_get_timing(lbmps_ctx* ctx, double* sweep_ms, int64_t* launches);
+
+/* ---------------------------------------------------------------------------
+ * Learned solid fraction.  Supersampling (Sec. 2.3.2) costs eps_n^3 point
+ * tests per cell cut by a sphere surface and is redone after every
+ * rigid-body step of moving particles (the cost Sec. 2.3.4 discusses).  A
+ * multilayer perceptron 8 -> 64 -> 64 -> 1 (ReLU hidden layers) replaces it
+ * for cut cells; cells entirely inside or outside a sphere stay exact.
+ * Inputs of a cell with centre displacement d from a sphere of radius R:
+ * |d_x|/R, |d_y|/R, |d_z|/R sorted descending, then 8/R, then four zeros.
+ * Products run in bfloat16 (round to nearest even) on the matrix cores with
+ * FP32 accumulation; parameters are FP32.  Parameter blob
+ * (LBMPS_MLP_NPARAM floats): W1[64][8], b1[64], W2[64][64], b2[64], W3[64], b3.
+ * Prediction y = W3 . relu(W2 relu(W1 x + b1) + b2) + b3; as eps_s it is
+ * clamped to [0, 1] and rounded to the nearest multiple of 1/eps_n^3 (so
+ * that every estimator yields sample counts). */
+#define LBMPS_MLP_NPARAM 4801
+#define LBMPS_MLP_MAX_BATCH 65536
+
+/* Install the network used by LBMPS_EPS_LEARNED instances for particles with
+ * r_min <= R <= r_max (host_params: LBMPS_MLP_NPARAM floats, copied).  Other
+ * radii fall back to flat supersampling.  Required before lbmps_set_particles
+ * on such instances; remaps current PSM particles.  Synchronising.
+ * Errors: EINVAL (null, non-finite, r_min > r_max), EDEVICE. */
+lbmps_status lbmps_set_eps_model(lbmps_ctx* ctx, const float* host_params, double r_min, double r_max);
+
+/* Recompute solid fractions and overlap lists of every PSM particle at the
+ * current positions (what each rigid-body step of moving particles does).
+ * Asynchronous; for timing the estimator. */
+lbmps_status lbmps_rebuild_overlaps(lbmps_ctx* ctx);
+
+/* Judge of the learned estimator: every `stride`-th cut cell that the network
+ * evaluated in the last rebuild is recounted by flat eps_n^3 supersampling.
+ * out[0] = mean |eps_net - eps_exact|, out[1] = max, out[2] = cells judged.
+ * Synchronising.  Errors: EINVAL (stride < 1). */
+lbmps_status lbmps_eps_judge(lbmps_ctx* ctx, int32_t stride, double out[3]);
+
+/* Trainer of the network (independent of any lattice context).  Training
+ * samples are cells (R, d); targets are exact flat supersampling counts.
+ * Device memory: one caller-owned workspace of lbmps_mlp_workspace_bytes()
+ * for up to max_samples samples. */
+typedef struct lbmps_mlp lbmps_mlp;
+size_t lbmps_mlp_workspace_bytes(int64_t max_samples);
+lbmps_status lbmps_mlp_create(int64_t max_samples, void* dev_workspace, size_t bytes, void* hip_stream,
+                              lbmps_mlp** out);
+void lbmps_mlp_destroy(lbmps_mlp* m);
+/* Parameters in and out (host, LBMPS_MLP_NPARAM floats); set resets the
+ * optimiser state.  Synchronising. */
+lbmps_status lbmps_mlp_set_params(lbmps_mlp* m, const float* host);
+lbmps_status lbmps_mlp_get_params(lbmps_mlp* m, float* host);
+/* Training set: n rows (R, d_x, d_y, d_z), FP64, host.  Features are formed
+ * on the device.  Clears the targets.  Errors: EINVAL (n out of range, R <= 0). */
+lbmps_status lbmps_mlp_set_samples(lbmps_mlp* m, int64_t n, const double* host_rd);
+/* Targets: eps_s of every sample by flat supersampling with eps_n^3 points
+ * (count / eps_n^3, rounded to FP32). */
+lbmps_status lbmps_mlp_label(lbmps_mlp* m, int32_t eps_n);
+lbmps_status lbmps_mlp_set_targets(lbmps_mlp* m, const float* host);
+lbmps_status lbmps_mlp_get_targets(lbmps_mlp* m, float* host);
+/* Clamped network output for every sample (host, n floats). */
+lbmps_status lbmps_mlp_predict(lbmps_mlp* m, float* host_y);
+/* Gradient of the batch loss L = (1/B) sum_k (y(s_k) - t(s_k))^2 (unclamped y)
+ * with respect to every parameter, over the samples
+ * s_k = (((b0 + k) mod n) * mult + add) mod n, k < B = batch; mult must be
+ * coprime to n, 0 <= add < n, 1 <= batch <= LBMPS_MLP_MAX_BATCH. */
+lbmps_status lbmps_mlp_gradient(lbmps_mlp* m, int64_t b0, int32_t batch, int64_t mult, int64_t add,
+                                float* host_grad);
+typedef struct lbmps_mlp_train_cfg {
+  int32_t epochs;        /* passes over the training set */
+  int32_t batch;         /* samples per Adam step, <= LBMPS_MLP_MAX_BATCH */
+  float lr, beta1, beta2, adam_eps;
+  const int64_t* mult;   /* per epoch: sample order s -> (s*mult + add) mod n (the caller's random draw) */
+  const int64_t* add;
+} lbmps_mlp_train_cfg;
+/* Adam on the batch loss above, ceil(n / batch) steps per epoch.  Asynchronous. */
+lbmps_status lbmps_mlp_train(lbmps_mlp* m, const lbmps_mlp_train_cfg* cfg);
+const char* lbmps_mlp_last_error(const lbmps_mlp* m);
 
 /* Global index of particle 0 of instance `inst`. */
 int32_t lbmps_particle_base(const lbmps_ctx* ctx, int32_t inst);

@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblbmps.so")
-SOURCES = ["sweep.hip", "psm.hip", "mem.hip", "particles.hip", "api.hip"]
+SOURCES = ["sweep.hip", "psm.hip", "mem.hip", "particles.hip", "mlp.hip", "api.hip"]
 ARCH = os.environ.get("LBMPS_ARCH", "gfx950")
 
 CFLAGS = [

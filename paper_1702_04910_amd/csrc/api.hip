@@ -43,13 +43,14 @@ struct Layout {
   std::vector<long long> pdf_off, owner_off, cellmap_off, ncell;
   std::vector<int> part_begin;
   long long pdf_elems = 0, owner_elems = 0, cellmap_elems = 0;
-  int link_cap = 0, wall_cap = 0, pair_cap = 0, refill_cap = 0;
+  int link_cap = 0, wall_cap = 0, pair_cap = 0, refill_cap = 0, cut_cap = 0;
+  bool learned = false;  // some instance estimates eps_s with the network
   long long slot_elems = 0;
   int box_total = 0;  // ptotal * side * side: work units at the finest split
   long long chunk = 0;
   // byte offsets
   size_t o_bufA, o_bufB, o_owner, o_cellmap, o_inst, o_parts, o_plists, o_slots, o_totals, o_offsets, o_ranges,
-      o_counts, o_links, o_wallv, o_pairs, o_refill, o_scratch, o_tiles, total;
+      o_counts, o_links, o_wallv, o_pairs, o_refill, o_scratch, o_tiles, o_cuts, o_cutx, o_mlp, total;
   int ntiles = 0;
   int max_tile_cells = 0;
 };
@@ -75,7 +76,7 @@ bool valid_cfg(const lbmps_config& c, std::string& err) {
   const int en = c.eps_n ? c.eps_n : 8;
   if (en < 1 || en > 64) { err = "eps_n must be 1..64"; return false; }
   if (c.eps_mode == LBMPS_EPS_RECURSIVE && (en & (en - 1))) { err = "recursive supersampling needs eps_n = 2^k"; return false; }
-  if (c.eps_mode < 0 || c.eps_mode > 1) { err = "unknown eps_mode"; return false; }
+  if (c.eps_mode < 0 || c.eps_mode > 2) { err = "unknown eps_mode"; return false; }
   if (c.block_threads < 0 || c.block_threads > 256 || (c.block_threads % 64)) { err = "block_threads must be a multiple of 64, <= 256"; return false; }
   if (c.sweep_flags & ~1) { err = "unknown sweep_flags bits"; return false; }
   if (c.n_sub < 0) { err = "n_sub must be >= 0"; return false; }
@@ -125,7 +126,7 @@ Layout make_layout(int n, const lbmps_config* cfgs) {
   L.side = (int)std::ceil(dmax) + 6;
   long long pdf = 0, own = 0, cm = 0;
   double rmax = 0.5 * dmax;
-  long long pairs = 0, links = 0, refill = 0, walls = 0;
+  long long pairs = 0, links = 0, refill = 0, walls = 0, cuts = 0;
   long long cmax = 0;
   for (int i = 0; i < n; ++i) {
     const lbmps_config& c = cfgs[i];
@@ -146,6 +147,12 @@ Layout make_layout(int n, const lbmps_config* cfgs) {
     const long long sd = L.side;
     links += (long long)c.max_particles * 40 * sd * sd;
     pairs += (long long)c.max_particles * (long long)std::ceil(4.2 * std::pow(rmax + 1.8, 3));
+    if (c.coupling == LBMPS_PSM) {
+      // cells cut by a sphere surface lie within sqrt(3)/2 of it: a shell of
+      // volume below 8 pi (R + 1)^2
+      cuts += (long long)c.max_particles * (long long)std::ceil(8.0 * M_PI * (rmax + 1.0) * (rmax + 1.0));
+      if (c.eps_mode == LBMPS_EPS_LEARNED) L.learned = true;
+    }
     refill += (long long)c.max_particles * 6 * sd * sd;
     walls += c.wall_link_cap > 0 ? c.wall_link_cap
                                  : 10LL * ((long long)c.nx * c.ny + (long long)c.ny * c.nz + (long long)c.nz * c.nx);
@@ -153,7 +160,9 @@ Layout make_layout(int n, const lbmps_config* cfgs) {
     L.ntiles += (c.ny * c.nz + eff_tile_rows(c) - 1) / eff_tile_rows(c);
     L.max_tile_cells = std::max(L.max_tile_cells, eff_tile_rows(c) * c.nx);
   }
-  if (links + walls >= (1LL << 31) || pairs >= (1LL << 31)) { L.err = "list capacities exceed 2^31"; return L; }
+  if (links + walls >= (1LL << 31) || pairs >= (1LL << 31) || cuts >= (1LL << 31)) {
+    L.err = "list capacities exceed 2^31"; return L;
+  }
   L.pdf_elems = pdf;
   L.owner_elems = own;
   L.cellmap_elems = cm;
@@ -161,6 +170,7 @@ Layout make_layout(int n, const lbmps_config* cfgs) {
   L.wall_cap = (int)walls;
   L.pair_cap = (int)pairs;
   L.refill_cap = (int)refill;
+  L.cut_cap = (int)cuts;
   L.slot_elems = (long long)L.ptotal * L.side * L.side * L.side;
   L.box_total = L.ptotal * L.side * L.side;
   L.chunk = std::min<long long>(cmax, 1LL << 22);
@@ -184,6 +194,9 @@ Layout make_layout(int n, const lbmps_config* cfgs) {
   L.o_refill = take((size_t)L.refill_cap * 2 * 4);
   L.o_scratch = take((size_t)L.chunk * 4 * 8);
   L.o_tiles = take((size_t)L.ntiles * sizeof(int4));
+  L.o_cuts = take((size_t)L.cut_cap * (8 + 4 + 4 + 24) + 4 * ALIGN);
+  L.o_cutx = take(L.learned ? (size_t)L.cut_cap * (8 + 1) * 4 : 0);
+  L.o_mlp = take((size_t)mlp_nparam() * 4 + 4 * 8);
   L.total = o;
   L.ok = true;
   return L;
@@ -223,6 +236,12 @@ struct lbmps_ctx {
   PairDev pairs{};
   int* rcell = nullptr;
   int* rpart = nullptr;
+  CutDev cuts{};
+  float* cut_x = nullptr;  // features [cut_cap][8], then outputs [cut_cap]
+  float* mlp_p = nullptr;  // network parameters (learned eps_s)
+  double* judge = nullptr; // error statistics of lbmps_eps_judge
+  bool mlp_set = false;
+  double mlp_rmin = 0.0, mlp_rmax = -1.0;
   double* scratch = nullptr;
   long long sweeps = 0;
   bool have_psm = false, have_links_inst = false;
@@ -263,6 +282,7 @@ lbmps_status check_device_errors(lbmps_ctx* c) {
   if (e & ERR_LINK_CAP) return fail(c, LBMPS_ENOMEM, "boundary-link capacity exceeded");
   if (e & ERR_PAIR_CAP) return fail(c, LBMPS_ENOMEM, "overlap-pair capacity exceeded");
   if (e & ERR_REFILL_CAP) return fail(c, LBMPS_ENOMEM, "refill-list capacity exceeded");
+  if (e & ERR_CUT_CAP) return fail(c, LBMPS_ENOMEM, "cut-cell list capacity exceeded");
   return LBMPS_OK;
 }
 
@@ -310,6 +330,12 @@ lbmps_status remap_mem(lbmps_ctx* c) {
   return rebuild_mem(c, true);
 }
 
+__global__ void fill_int_kernel(int* a, long long n, int v);
+
+// Solid fractions and overlap lists of every PSM particle (Sec. 2.3.2):
+// classify bounding-box cells, evaluate the cut ones (supersampling, or the
+// network inside its radius range), count per work unit, scan, fill, and link
+// the pairs of shared cells.  Kernel launches only (graph capturable).
 lbmps_status rebuild_psm(lbmps_ctx* c) {
   const Layout& L = c->L;
   if (c->n_psm == 0) return LBMPS_OK;
@@ -317,8 +343,19 @@ lbmps_status rebuild_psm(lbmps_ctx* c) {
   const int ns = nsplit_for(c->n_psm, L.side);
   const int units = L.side * ns;
   HIPCHK(c, launch_psm_cellmap(0, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap, c->st));
-  HIPCHK(c, launch_psm_count(psm_list(c), c->n_psm, L.side, ns, c->inst_d, c->parts, nullptr, c->slots, c->totals,
-                             c->st));
+  hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, c->st, c->cuts.count, 1LL, 0);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, launch_psm_classify(psm_list(c), c->n_psm, L.side, ns, c->inst_d, c->parts, c->slots, c->cuts, L.cut_cap,
+                                c->st));
+  const double rmin = c->mlp_set ? c->mlp_rmin : 0.0, rmax = c->mlp_set ? c->mlp_rmax : -1.0;
+  if (L.learned && c->mlp_set) {
+    float* y = c->cut_x + (size_t)L.cut_cap * 8;
+    HIPCHK(c, launch_psm_cut_features(c->inst_d, c->parts, c->cuts, L.cut_cap, rmin, rmax, c->cut_x, c->st));
+    HIPCHK(c, launch_mlp_infer_count(c->mlp_p, c->cut_x, c->cuts.count, L.cut_cap, y, c->st));
+    HIPCHK(c, launch_psm_cut_scatter(c->inst_d, c->parts, c->cuts, L.cut_cap, y, c->slots, c->st));
+  }
+  HIPCHK(c, launch_psm_cut_exact(c->inst_d, c->parts, c->slots, c->cuts, L.cut_cap, rmin, rmax, c->st));
+  HIPCHK(c, launch_psm_unit_totals(c->n_psm, L.side, ns, c->slots, c->totals, c->st));
   HIPCHK(c, launch_scan(c->totals, c->offsets, c->n_psm * units, units, c->n_psm, c->pbeg, c->pend, c->counts + 1,
                         L.pair_cap, err, ERR_PAIR_CAP, c->st));
   HIPCHK(c, launch_psm_fill(psm_list(c), c->n_psm, L.side, ns, c->inst_d, c->parts, c->slots, c->offsets, L.pair_cap,
@@ -470,6 +507,19 @@ lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* ws, s
   c->rcell = (int*)(w + L.o_refill);
   c->rpart = c->rcell + L.refill_cap;
   c->scratch = (double*)(w + L.o_scratch);
+  {
+    const size_t nc = L.cut_cap;
+    char* b = w + L.o_cuts;
+    c->cuts.slot = (long long*)b; b += align_up(nc * 8);
+    c->cuts.d = (double*)b; b += align_up(nc * 24);
+    c->cuts.p = (int*)b; b += align_up(nc * 4);
+    c->cuts.use = (int*)b;
+    c->cuts.count = c->counts + 3;
+    c->cuts.err = err_word(c);
+    c->cut_x = L.learned ? (float*)(w + L.o_cutx) : nullptr;
+    c->mlp_p = (float*)(w + L.o_mlp);
+    c->judge = (double*)(w + L.o_mlp + (size_t)mlp_nparam() * 4);
+  }
 
   // instance table and sweep tiles
   std::vector<int4> tiles;
@@ -634,6 +684,8 @@ lbmps_status lbmps_set_particles(lbmps_ctx* c, int32_t inst, int32_t n, const lb
   const lbmps_config& cf = c->cfg[inst];
   if (n < 0 || n > cf.max_particles) return fail(c, LBMPS_EINVAL, "particle count exceeds max_particles");
   if (n > 0 && !hp) return fail(c, LBMPS_EINVAL, "null particle array");
+  if (n > 0 && cf.coupling == LBMPS_PSM && cf.eps_mode == LBMPS_EPS_LEARNED && !c->mlp_set)
+    return fail(c, LBMPS_ESTATE, "learned eps_s: call lbmps_set_eps_model before setting particles");
   const int mind = std::min(cf.nx, std::min(cf.ny, cf.nz));
   const double L3[3] = {(double)cf.nx, (double)cf.ny, (double)cf.nz};
   const int P = c->L.ptotal;
@@ -980,6 +1032,260 @@ lbmps_status lbmps_get_timing(lbmps_ctx* c, double* sweep_ms, int64_t* launches)
   *launches = c->sweep_launches;
   return LBMPS_OK;
 }
+
+lbmps_status lbmps_set_eps_model(lbmps_ctx* c, const float* hp, double r_min, double r_max) {
+  if (!c) return LBMPS_EINVAL;
+  if (!hp) return fail(c, LBMPS_EINVAL, "null parameters");
+  if (!std::isfinite(r_min) || !std::isfinite(r_max) || r_min > r_max) return fail(c, LBMPS_EINVAL, "bad radius range");
+  const int np = mlp_nparam();
+  for (int k = 0; k < np; ++k)
+    if (!std::isfinite(hp[k])) return fail(c, LBMPS_EINVAL, "non-finite parameter");
+  drop_graph(c);
+  HIPCHK(c, hipMemcpyAsync(c->mlp_p, hp, (size_t)np * 4, hipMemcpyHostToDevice, c->st));
+  c->mlp_set = true;
+  c->mlp_rmin = r_min;
+  c->mlp_rmax = r_max;
+  lbmps_status s = rebuild_psm(c);
+  if (s) return s;
+  return check_device_errors(c);
+}
+
+lbmps_status lbmps_rebuild_overlaps(lbmps_ctx* c) {
+  if (!c) return LBMPS_EINVAL;
+  return rebuild_psm(c);
+}
+
+lbmps_status lbmps_eps_judge(lbmps_ctx* c, int32_t stride, double out[3]) {
+  if (!c || !out) return LBMPS_EINVAL;
+  if (stride < 1) return fail(c, LBMPS_EINVAL, "stride must be >= 1");
+  out[0] = out[1] = out[2] = 0.0;
+  if (!c->L.learned || c->n_psm == 0) return check_device_errors(c);
+  HIPCHK(c, hipMemsetAsync(c->judge, 0, 3 * 8, c->st));
+  HIPCHK(c, launch_psm_judge(c->inst_d, c->parts, c->slots, c->cuts, c->L.cut_cap, stride, c->judge, c->st));
+  double h[3];
+  HIPCHK(c, hipMemcpyAsync(h, c->judge, 3 * 8, hipMemcpyDeviceToHost, c->st));
+  lbmps_status s = check_device_errors(c);
+  if (s) return s;
+  out[0] = h[2] > 0 ? h[0] / h[2] : 0.0;
+  out[1] = h[1];
+  out[2] = h[2];
+  return LBMPS_OK;
+}
+
+}  // extern "C"
+
+// ----------------------------------------------------------------------------- trainer
+struct lbmps_mlp {
+  hipStream_t st = nullptr;
+  long long cap = 0, n = 0;
+  float *P = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr, *X = nullptr, *T = nullptr, *y = nullptr,
+        *partial = nullptr;
+  double* rd = nullptr;
+  int step = 0;
+  bool labelled = false;
+  std::string last;
+};
+
+namespace {
+
+constexpr long long MLP_MAX_BATCH = LBMPS_MLP_MAX_BATCH;
+
+struct MlpLayout {
+  size_t P, m, v, grad, partial, rd, X, T, y, total;
+};
+
+MlpLayout mlp_layout(long long cap) {
+  MlpLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+  const size_t np = (size_t)mlp_nparam();
+  L.P = take(np * 4);
+  L.m = take(np * 4);
+  L.v = take(np * 4);
+  L.grad = take(np * 4);
+  L.partial = take((size_t)(MLP_MAX_BATCH / 32) * np * 4);
+  L.rd = take((size_t)cap * 4 * 8);
+  L.X = take((size_t)cap * 8 * 4);
+  L.T = take((size_t)cap * 4);
+  L.y = take((size_t)cap * 4);
+  L.total = o;
+  return L;
+}
+
+lbmps_status mfail(lbmps_mlp* m, lbmps_status s, const std::string& msg) {
+  if (m) m->last = msg;
+  return s;
+}
+
+#define MHIPCHK(m, expr)                                                                        \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess)                                                                       \
+      return mfail(m, LBMPS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+long long gcd_ll(long long a, long long b) { return b ? gcd_ll(b, a % b) : a; }
+
+lbmps_status check_order(lbmps_mlp* m, long long mult, long long add) {
+  if (mult < 1 || mult >= std::max(m->n, 2LL) || gcd_ll(mult, m->n) != 1 || add < 0 || add >= m->n)
+    return mfail(m, LBMPS_EINVAL, "sample order needs 1 <= mult < n coprime to n and 0 <= add < n");
+  return LBMPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbmps_mlp_workspace_bytes(int64_t max_samples) {
+  if (max_samples < 1 || max_samples >= (1LL << 31)) return 0;
+  return mlp_layout(max_samples).total;
+}
+
+lbmps_status lbmps_mlp_create(int64_t cap, void* ws, size_t bytes, void* stream, lbmps_mlp** out) {
+  if (!out) return LBMPS_EINVAL;
+  *out = nullptr;
+  if (cap < 1 || cap >= (1LL << 31)) return LBMPS_EINVAL;
+  const MlpLayout L = mlp_layout(cap);
+  if (!ws || bytes < L.total) return LBMPS_ENOMEM;
+  lbmps_mlp* m = new lbmps_mlp();
+  char* w = (char*)ws;
+  m->st = (hipStream_t)stream;
+  m->cap = cap;
+  m->P = (float*)(w + L.P);
+  m->m = (float*)(w + L.m);
+  m->v = (float*)(w + L.v);
+  m->grad = (float*)(w + L.grad);
+  m->partial = (float*)(w + L.partial);
+  m->rd = (double*)(w + L.rd);
+  m->X = (float*)(w + L.X);
+  m->T = (float*)(w + L.T);
+  m->y = (float*)(w + L.y);
+  *out = m;
+  MHIPCHK(m, hipMemsetAsync(w, 0, L.partial, m->st));
+  MHIPCHK(m, hipStreamSynchronize(m->st));
+  return LBMPS_OK;
+}
+
+void lbmps_mlp_destroy(lbmps_mlp* m) {
+  if (!m) return;
+  (void)hipStreamSynchronize(m->st);
+  delete m;
+}
+
+lbmps_status lbmps_mlp_set_params(lbmps_mlp* m, const float* hp) {
+  if (!m) return LBMPS_EINVAL;
+  if (!hp) return mfail(m, LBMPS_EINVAL, "null parameters");
+  const size_t np = (size_t)mlp_nparam();
+  MHIPCHK(m, hipMemcpyAsync(m->P, hp, np * 4, hipMemcpyHostToDevice, m->st));
+  MHIPCHK(m, hipMemsetAsync(m->m, 0, np * 4, m->st));
+  MHIPCHK(m, hipMemsetAsync(m->v, 0, np * 4, m->st));
+  MHIPCHK(m, hipStreamSynchronize(m->st));
+  m->step = 0;
+  return LBMPS_OK;
+}
+
+lbmps_status lbmps_mlp_get_params(lbmps_mlp* m, float* hp) {
+  if (!m) return LBMPS_EINVAL;
+  if (!hp) return mfail(m, LBMPS_EINVAL, "null output");
+  MHIPCHK(m, hipMemcpyAsync(hp, m->P, (size_t)mlp_nparam() * 4, hipMemcpyDeviceToHost, m->st));
+  MHIPCHK(m, hipStreamSynchronize(m->st));
+  return LBMPS_OK;
+}
+
+lbmps_status lbmps_mlp_set_samples(lbmps_mlp* m, int64_t n, const double* rd) {
+  if (!m) return LBMPS_EINVAL;
+  if (n < 1 || n > m->cap) return mfail(m, LBMPS_EINVAL, "sample count out of range");
+  if (!rd) return mfail(m, LBMPS_EINVAL, "null samples");
+  for (long long s = 0; s < n; ++s) {
+    bool ok = rd[4 * s] > 0;
+    for (int k = 0; k < 4; ++k) ok = ok && std::isfinite(rd[4 * s + k]);
+    if (!ok) return mfail(m, LBMPS_EINVAL, "samples need finite values and R > 0");
+  }
+  MHIPCHK(m, hipMemcpyAsync(m->rd, rd, (size_t)n * 32, hipMemcpyHostToDevice, m->st));
+  MHIPCHK(m, launch_mlp_features(m->rd, n, m->X, m->st));
+  MHIPCHK(m, hipStreamSynchronize(m->st));
+  m->n = n;
+  m->labelled = false;
+  return LBMPS_OK;
+}
+
+lbmps_status lbmps_mlp_label(lbmps_mlp* m, int32_t eps_n) {
+  if (!m) return LBMPS_EINVAL;
+  if (m->n < 1) return mfail(m, LBMPS_ESTATE, "set samples first");
+  if (eps_n < 1 || eps_n > 64) return mfail(m, LBMPS_EINVAL, "eps_n must be 1..64");
+  MHIPCHK(m, launch_psm_label(m->rd, m->n, eps_n, m->T, m->st));
+  m->labelled = true;
+  return LBMPS_OK;
+}
+
+lbmps_status lbmps_mlp_set_targets(lbmps_mlp* m, const float* h) {
+  if (!m) return LBMPS_EINVAL;
+  if (m->n < 1) return mfail(m, LBMPS_ESTATE, "set samples first");
+  if (!h) return mfail(m, LBMPS_EINVAL, "null targets");
+  MHIPCHK(m, hipMemcpyAsync(m->T, h, (size_t)m->n * 4, hipMemcpyHostToDevice, m->st));
+  MHIPCHK(m, hipStreamSynchronize(m->st));
+  m->labelled = true;
+  return LBMPS_OK;
+}
+
+lbmps_status lbmps_mlp_get_targets(lbmps_mlp* m, float* h) {
+  if (!m) return LBMPS_EINVAL;
+  if (!m->labelled) return mfail(m, LBMPS_ESTATE, "no targets");
+  if (!h) return mfail(m, LBMPS_EINVAL, "null output");
+  MHIPCHK(m, hipMemcpyAsync(h, m->T, (size_t)m->n * 4, hipMemcpyDeviceToHost, m->st));
+  MHIPCHK(m, hipStreamSynchronize(m->st));
+  return LBMPS_OK;
+}
+
+lbmps_status lbmps_mlp_predict(lbmps_mlp* m, float* h) {
+  if (!m) return LBMPS_EINVAL;
+  if (m->n < 1) return mfail(m, LBMPS_ESTATE, "set samples first");
+  if (!h) return mfail(m, LBMPS_EINVAL, "null output");
+  MHIPCHK(m, launch_mlp_infer(m->P, m->X, m->n, m->y, m->st));
+  MHIPCHK(m, hipMemcpyAsync(h, m->y, (size_t)m->n * 4, hipMemcpyDeviceToHost, m->st));
+  MHIPCHK(m, hipStreamSynchronize(m->st));
+  return LBMPS_OK;
+}
+
+lbmps_status lbmps_mlp_gradient(lbmps_mlp* m, int64_t b0, int32_t batch, int64_t mult, int64_t add, float* h) {
+  if (!m) return LBMPS_EINVAL;
+  if (!m->labelled) return mfail(m, LBMPS_ESTATE, "set samples and targets first");
+  if (!h) return mfail(m, LBMPS_EINVAL, "null output");
+  if (batch < 1 || batch > MLP_MAX_BATCH || b0 < 0) return mfail(m, LBMPS_EINVAL, "batch out of range");
+  lbmps_status s = check_order(m, mult, add);
+  if (s) return s;
+  const int ntiles = (batch + 31) / 32;
+  MHIPCHK(m, launch_mlp_grad(m->P, m->X, m->T, m->n, b0 % m->n, mult, add, batch, m->partial, m->st));
+  MHIPCHK(m, launch_mlp_reduce_adam(m->P, m->partial, ntiles, m->grad, m->m, m->v, 0, 0.f, 0.f, 0.f, 0.f, 0, m->st));
+  MHIPCHK(m, hipMemcpyAsync(h, m->grad, (size_t)mlp_nparam() * 4, hipMemcpyDeviceToHost, m->st));
+  MHIPCHK(m, hipStreamSynchronize(m->st));
+  return LBMPS_OK;
+}
+
+lbmps_status lbmps_mlp_train(lbmps_mlp* m, const lbmps_mlp_train_cfg* cfg) {
+  if (!m) return LBMPS_EINVAL;
+  if (!cfg || !cfg->mult || !cfg->add) return mfail(m, LBMPS_EINVAL, "null configuration");
+  if (!m->labelled) return mfail(m, LBMPS_ESTATE, "set samples and targets first");
+  if (cfg->epochs < 0 || cfg->batch < 1 || cfg->batch > MLP_MAX_BATCH) return mfail(m, LBMPS_EINVAL, "bad epochs or batch");
+  if (!(cfg->lr > 0) || !(cfg->beta1 >= 0 && cfg->beta1 < 1) || !(cfg->beta2 >= 0 && cfg->beta2 < 1) ||
+      !(cfg->adam_eps > 0))
+    return mfail(m, LBMPS_EINVAL, "bad optimiser constants");
+  for (int e = 0; e < cfg->epochs; ++e) {
+    lbmps_status s = check_order(m, cfg->mult[e], cfg->add[e]);
+    if (s) return s;
+  }
+  for (int e = 0; e < cfg->epochs; ++e)
+    for (long long b0 = 0; b0 < m->n; b0 += cfg->batch) {
+      const int B = (int)std::min<long long>(cfg->batch, m->n - b0);
+      m->step++;
+      MHIPCHK(m, launch_mlp_grad(m->P, m->X, m->T, m->n, b0, cfg->mult[e], cfg->add[e], B, m->partial, m->st));
+      MHIPCHK(m, launch_mlp_reduce_adam(m->P, m->partial, (B + 31) / 32, m->grad, m->m, m->v, 1, cfg->lr, cfg->beta1,
+                                        cfg->beta2, cfg->adam_eps, m->step, m->st));
+    }
+  return LBMPS_OK;
+}
+
+const char* lbmps_mlp_last_error(const lbmps_mlp* m) { return m ? m->last.c_str() : "null trainer"; }
 
 const char* lbmps_status_string(lbmps_status s) {
   switch (s) {

@@ -54,7 +54,7 @@ __host__ __device__ constexpr double wq(int q) {
 enum { COUP_NONE = 0, COUP_MEM_BB = 1, COUP_MEM_CLI = 2, COUP_PSM = 3 };
 enum { COLL_BGK = 0, COLL_TRT = 1 };
 enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP16 = 2, PREC_BF16 = 3 };
-enum { EPS_FLAT = 0, EPS_RECURSIVE = 1, EPS_MLP = 2 };
+enum { EPS_FLAT = 0, EPS_RECURSIVE = 1, EPS_LEARNED = 2 };
 
 // Owner field values (MEM): -1 fluid, <= -2 static wall group (-2 - k),
 // 0 <= p < WAS_BIT solid cell of particle p, WAS_BIT | p: was solid of p before
@@ -64,7 +64,7 @@ constexpr int WAS_BIT = 1 << 30;
 __host__ __device__ inline bool own_is_fluid(int o) { return o == OWN_FLUID || (o >= WAS_BIT); }
 
 // Error flags (bit mask in the device status word).
-enum { ERR_LINK_CAP = 1, ERR_PAIR_CAP = 2, ERR_REFILL_CAP = 4, ERR_UNSTABLE = 8, ERR_CONTACT = 16 };
+enum { ERR_LINK_CAP = 1, ERR_PAIR_CAP = 2, ERR_REFILL_CAP = 4, ERR_UNSTABLE = 8, ERR_CONTACT = 16, ERR_CUT_CAP = 32 };
 
 // Per-instance parameters, read by every kernel.
 struct InstDev {
@@ -101,6 +101,15 @@ struct PairDev {
   int *cell, *p, *next;
   double *eps, *B;
   double *out;  // 6 per pair
+};
+
+// Cells cut by a sphere surface, collected while classifying bounding boxes.
+struct CutDev {
+  int* count;       // number of entries (may exceed the capacity: then truncated)
+  long long* slot;  // slot index of the cell
+  int *p, *use;     // particle; 1 when the learned estimator evaluates it
+  double* d;        // 3 per entry: centre displacement from the sphere centre
+  unsigned* err;    // error word (ERR_CUT_CAP on overflow)
 };
 
 // -------------------------------------------------------------------------- storage codecs

@@ -52,8 +52,18 @@ hipError_t launch_links_bc(int prec, int n_wall, const int* count, int cap, Link
                            const InstDev* insts, PartDev parts, void* buf, hipStream_t st);
 
 // ---- psm.hip
-hipError_t launch_psm_count(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
-                            const float* mlp_w, int* slots, int* totals, hipStream_t st);
+hipError_t launch_psm_classify(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
+                               int* slots, CutDev cuts, int cap, hipStream_t st);
+hipError_t launch_psm_cut_exact(const InstDev* insts, PartDev parts, int* slots, CutDev cuts, int cap, double rmin,
+                                double rmax, hipStream_t st);
+hipError_t launch_psm_cut_features(const InstDev* insts, PartDev parts, CutDev cuts, int cap, double rmin,
+                                   double rmax, float* X, hipStream_t st);
+hipError_t launch_psm_cut_scatter(const InstDev* insts, PartDev parts, CutDev cuts, int cap, const float* y,
+                                  int* slots, hipStream_t st);
+hipError_t launch_psm_unit_totals(int nlist, int side, int nsplit, const int* slots, int* totals, hipStream_t st);
+hipError_t launch_psm_label(const double* rd, long long ns, int n, float* eps, hipStream_t st);
+hipError_t launch_psm_judge(const InstDev* insts, PartDev parts, const int* slots, CutDev cuts, int cap, int stride,
+                            double* stats, hipStream_t st);
 hipError_t launch_psm_fill(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
                            const int* slots, const int* offsets, int cap, PairDev pairs, hipStream_t st);
 hipError_t launch_psm_cellmap(int stage, const int* count, int cap, const InstDev* insts, PartDev parts,
@@ -63,5 +73,16 @@ hipError_t launch_psm_collide(int prec, const int* count, int cap, const InstDev
 hipError_t launch_psm_fields(int prec, const int* count, int cap, const InstDev* insts, PartDev parts, PairDev pairs,
                              const int* cellmap, const void* buf, int inst, long long c0, long long n, double* out,
                              hipStream_t st);
+
+// ---- mlp.hip
+int mlp_nparam();
+hipError_t launch_mlp_features(const double* rd, long long n, float* X, hipStream_t st);
+hipError_t launch_mlp_infer(const float* P, const float* X, long long n, float* y, hipStream_t st);
+hipError_t launch_mlp_infer_count(const float* P, const float* X, const int* count, long long cap, float* y,
+                                  hipStream_t st);
+hipError_t launch_mlp_grad(const float* P, const float* X, const float* T, long long n, long long b0, long long mult,
+                           long long add, int batch, float* partial, hipStream_t st);
+hipError_t launch_mlp_reduce_adam(float* P, const float* partial, int ntiles, float* grad, float* m, float* v,
+                                  int do_adam, float lr, float b1, float b2, float eps, int step, hipStream_t st);
 
 }  // namespace lbm

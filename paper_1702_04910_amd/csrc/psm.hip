@@ -10,6 +10,7 @@
 // n^3 sub-cell grid.  The recursive count classifies octree blocks of sample
 // points by their farthest and nearest sample point; both counts are exact
 // integers and equal.
+#include <algorithm>
 #include <climits>
 
 #include "common.h"
@@ -106,20 +107,15 @@ __device__ __forceinline__ void centre_disp(const InstDev& I, const PartDev& P, 
   d[2] = min_image(((double)k + 0.5) - P.X[3 * p + 2], (double)I.nz);
 }
 
-constexpr int MAX_UNIT_CELLS = 64 * 64;  // side <= 64
-
-// Grid (units, nlist): workgroup (u, j) handles work unit u of the bounding box
-// of particle list[j].  Cells entirely inside (outside) the sphere by their
-// farthest (nearest) sample point get n^3 (0) directly; cut cells are counted
-// by one wave each.
-__global__ __launch_bounds__(256) void psm_count_kernel(const int* __restrict__ list, int side, int nsplit,
-                                                        const InstDev* __restrict__ insts, PartDev P,
-                                                        const float* __restrict__ mlp_w, int* __restrict__ slots,
-                                                        int* __restrict__ totals) {
-  __shared__ int vals[MAX_UNIT_CELLS];
-  __shared__ int cut[MAX_UNIT_CELLS];
-  __shared__ int ncut;
-  __shared__ int sh[256];
+// Stage 1 of the solid fractions, grid (units, nlist): every bounding-box cell
+// of the unit is classified by its farthest and nearest sample point.  Cells
+// entirely inside get the full count n^3, entirely outside 0; cut cells are
+// appended to the cut list (their slot index, particle and centre
+// displacement) and evaluated by stage 2.  Slots hold sample counts out of
+// n^3 for every estimator (the learned one rounds its prediction to a count).
+__global__ __launch_bounds__(256) void psm_classify_kernel(const int* __restrict__ list, int side, int nsplit,
+                                                           const InstDev* __restrict__ insts, PartDev P,
+                                                           int* __restrict__ slots, CutDev cuts, int cap) {
   const int j = blockIdx.y;
   const Unit U = unit_of(blockIdx.x, side, nsplit);
   const int p = list[j];
@@ -130,52 +126,200 @@ __global__ __launch_bounds__(256) void psm_count_kernel(const int* __restrict__ 
   const double R2 = __dmul_rn(R, R);
   const int n = I.eps_n;
   const int ncu = (U.y1 - U.y0) * side;
-  if (threadIdx.x == 0) ncut = 0;
-  __syncthreads();
   const double o0 = sample_off(0, n), o1 = sample_off(n - 1, n);
-  for (int c = threadIdx.x; c < ncu; c += blockDim.x) {
-    const int dy = U.y0 + c / side, dx = c % side;
-    const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny), k = wrapi(lo[2] + U.z, I.nz);
-    double dc[3];
-    centre_disp(I, P, p, i, jj, k, dc);
-    double blo[3], bhi[3];
+  const int lane = threadIdx.x & 63;
+  // wave-uniform trip count: the cut cells of a wave take one atomic together
+  for (int c0 = 0; c0 < ncu; c0 += blockDim.x) {
+    const int c = c0 + threadIdx.x;
+    int cl = -1;
+    long long si = 0;
+    double dc[3] = {0.0, 0.0, 0.0};
+    if (c < ncu) {
+      const int dy = U.y0 + c / side, dx = c % side;
+      const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny), k = wrapi(lo[2] + U.z, I.nz);
+      centre_disp(I, P, p, i, jj, k, dc);
+      double blo[3], bhi[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      blo[q] = __dadd_rn(dc[q], o0);
-      bhi[q] = __dadd_rn(dc[q], o1);
+      for (int q = 0; q < 3; ++q) {
+        blo[q] = __dadd_rn(dc[q], o0);
+        bhi[q] = __dadd_rn(dc[q], o1);
+      }
+      cl = classify(blo, bhi, R2);
+      si = slot_index(j, side, U.z, dy, dx);
+      slots[si] = cl == 1 ? n * n * n : 0;
     }
-    const int cl = classify(blo, bhi, R2);
-    vals[c] = cl == 1 ? n * n * n : 0;
-    if (cl == 0) cut[atomicAdd(&ncut, 1)] = c;
+    const unsigned long long cut = __ballot(cl == 0);
+    if (cut) {
+      const int leader = __ffsll((long long)cut) - 1;
+      int base = 0;
+      if (lane == leader) base = atomicAdd(cuts.count, __popcll(cut));
+      base = __shfl(base, leader, 64);
+      const int t = base + __popcll(cut & ((1ull << lane) - 1ull));
+      if (cl == 0 && t < cap) {
+        cuts.slot[t] = si;
+        cuts.p[t] = p;
+        cuts.d[3 * t] = dc[0];
+        cuts.d[3 * t + 1] = dc[1];
+        cuts.d[3 * t + 2] = dc[2];
+      }
+    }
   }
-  __syncthreads();
-  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-  for (int t = wave; t < ncut; t += nwaves) {
-    const int c = cut[t];
-    const int dy = U.y0 + c / side, dx = c % side;
-    const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny), k = wrapi(lo[2] + U.z, I.nz);
-    double dc[3];
-    centre_disp(I, P, p, i, jj, k, dc);
-    const int cnt = wave_count(dc, R2, n, I.eps_mode);
-    if ((threadIdx.x & 63) == 0) vals[c] = cnt;
+}
+
+// Stage 2 (supersampling): one wave per cut cell.  With the learned estimator
+// only cells whose radius lies outside the trained range are evaluated here
+// (fallback, flat sampling).
+__global__ __launch_bounds__(256) void psm_cut_exact_kernel(const InstDev* __restrict__ insts, PartDev P,
+                                                            int* __restrict__ slots, CutDev cuts, int cap,
+                                                            double rmin, double rmax) {
+  const int n_cut = min(*cuts.count, cap);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && *cuts.count > cap) atomicOr(cuts.err, (unsigned)ERR_CUT_CAP);
+  const int nw = (gridDim.x * blockDim.x) >> 6;
+  for (int t = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < n_cut; t += nw) {
+    const int p = cuts.p[t];
+    const InstDev& I = insts[P.inst[p]];
+    const double R = 0.5 * P.D[p];
+    const bool learned = I.eps_mode == EPS_LEARNED;
+    if (learned && R >= rmin && R <= rmax) continue;
+    const double dc[3] = {cuts.d[3 * t], cuts.d[3 * t + 1], cuts.d[3 * t + 2]};
+    const int n = I.eps_n;
+    const int cnt = wave_count(dc, __dmul_rn(R, R), n, learned ? EPS_FLAT : I.eps_mode);
+    if ((threadIdx.x & 63) == 0) slots[cuts.slot[t]] = cnt;
   }
-  __syncthreads();
+}
+
+// Stage 2 (learned): features of every cut cell; `use` flags the cells of
+// learned-estimator instances whose radius is inside the trained range.
+__global__ void psm_cut_features_kernel(const InstDev* __restrict__ insts, PartDev P, CutDev cuts, int cap,
+                                        double rmin, double rmax, float* __restrict__ X) {
+  const int n_cut = min(*cuts.count, cap);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_cut) return;
+  const int p = cuts.p[t];
+  const InstDev& I = insts[P.inst[p]];
+  const double R = 0.5 * P.D[p];
+  const bool use = I.eps_mode == EPS_LEARNED && R >= rmin && R <= rmax;
+  cuts.use[t] = use ? 1 : 0;
+  double a = fabs(cuts.d[3 * t]), b = fabs(cuts.d[3 * t + 1]), c = fabs(cuts.d[3 * t + 2]), tmp;
+  if (a < b) { tmp = a; a = b; b = tmp; }
+  if (b < c) { tmp = b; b = c; c = tmp; }
+  if (a < b) { tmp = a; a = b; b = tmp; }
+  float* x = X + 8LL * t;
+  x[0] = (float)(a / R);
+  x[1] = (float)(b / R);
+  x[2] = (float)(c / R);
+  x[3] = (float)(8.0 / R);
+  x[4] = x[5] = x[6] = x[7] = 0.f;
+}
+
+// The network's eps (clamped to [0, 1]) as the nearest count out of n^3.
+__global__ void psm_cut_scatter_kernel(const InstDev* __restrict__ insts, PartDev P, CutDev cuts, int cap,
+                                       const float* __restrict__ y, int* __restrict__ slots) {
+  const int n_cut = min(*cuts.count, cap);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_cut || !cuts.use[t]) return;
+  const int n = insts[P.inst[cuts.p[t]]].eps_n;
+  slots[cuts.slot[t]] = (int)rintf(y[t] * (float)(n * n * n));
+}
+
+// Stage 3: number of cells with eps > 0 (count > 0) per work unit.
+__global__ __launch_bounds__(256) void psm_unit_totals_kernel(int side, int nsplit, const int* __restrict__ slots,
+                                                              int* __restrict__ totals) {
+  __shared__ int sh[256];
+  const int j = blockIdx.y;
+  const Unit U = unit_of(blockIdx.x, side, nsplit);
+  const int ncu = (U.y1 - U.y0) * side;
   int local = 0;
-  for (int c = threadIdx.x; c < ncu; c += blockDim.x) {
-    const int dy = U.y0 + c / side, dx = c % side;
-    slots[slot_index(j, side, U.z, dy, dx)] = vals[c];
-    local += vals[c] > 0 ? 1 : 0;
-  }
+  for (int c = threadIdx.x; c < ncu; c += blockDim.x)
+    local += slots[slot_index(j, side, U.z, U.y0 + c / side, c % side)] > 0 ? 1 : 0;
   int total;
   block_excl_scan256(local, sh, &total);
   if (threadIdx.x == 0) totals[j * (side * nsplit) + blockIdx.x] = total;
 }
 
-hipError_t launch_psm_count(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
-                            const float* mlp_w, int* slots, int* totals, hipStream_t st) {
+// Labels for training samples (R, dx, dy, dz): exact eps by flat n^3
+// supersampling, one wave per sample.
+__global__ __launch_bounds__(256) void psm_label_kernel(const double* __restrict__ rd, long long ns, int n,
+                                                        float* __restrict__ eps) {
+  const long long nw = ((long long)gridDim.x * blockDim.x) >> 6;
+  for (long long t = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < ns; t += nw) {
+    const double R = rd[4 * t];
+    const double dc[3] = {rd[4 * t + 1], rd[4 * t + 2], rd[4 * t + 3]};
+    const int cnt = wave_count(dc, __dmul_rn(R, R), n, EPS_FLAT);
+    if ((threadIdx.x & 63) == 0) eps[t] = (float)((double)cnt / ((double)n * n * n));
+  }
+}
+
+// Error judge of the learned estimator: every `stride`-th cut cell that used
+// the network is recounted exactly; stats[0] += |error|, stats[1] = max |error|
+// (ordered as bits of a non-negative double), stats[2] += 1.
+__global__ __launch_bounds__(256) void psm_judge_kernel(const InstDev* __restrict__ insts, PartDev P,
+                                                        const int* __restrict__ slots, CutDev cuts, int cap,
+                                                        int stride, double* __restrict__ stats) {
+  const int n_cut = min(*cuts.count, cap);
+  const int nw = (gridDim.x * blockDim.x) >> 6;
+  for (int k = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; (long long)k * stride < n_cut; k += nw) {
+    const int t = k * stride;
+    if (!cuts.use[t]) continue;
+    const int p = cuts.p[t];
+    const InstDev& I = insts[P.inst[p]];
+    const double R = 0.5 * P.D[p];
+    const double dc[3] = {cuts.d[3 * t], cuts.d[3 * t + 1], cuts.d[3 * t + 2]};
+    const int n = I.eps_n;
+    const int cnt = wave_count(dc, __dmul_rn(R, R), n, EPS_FLAT);
+    if ((threadIdx.x & 63) == 0) {
+      const double e = fabs((double)(slots[cuts.slot[t]] - cnt) / ((double)n * n * n));
+      atomicAdd(&stats[0], e);
+      atomicMax((unsigned long long*)&stats[1], (unsigned long long)__double_as_longlong(e));
+      atomicAdd(&stats[2], 1.0);
+    }
+  }
+}
+
+hipError_t launch_psm_classify(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
+                               int* slots, CutDev cuts, int cap, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(psm_count_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts, parts,
-                     mlp_w, slots, totals);
+  hipLaunchKernelGGL(psm_classify_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts,
+                     parts, slots, cuts, cap);
+  return hipGetLastError();
+}
+
+hipError_t launch_psm_cut_exact(const InstDev* insts, PartDev parts, int* slots, CutDev cuts, int cap, double rmin,
+                                double rmax, hipStream_t st) {
+  hipLaunchKernelGGL(psm_cut_exact_kernel, dim3(2048), dim3(256), 0, st, insts, parts, slots, cuts, cap, rmin, rmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_psm_cut_features(const InstDev* insts, PartDev parts, CutDev cuts, int cap, double rmin,
+                                   double rmax, float* X, hipStream_t st) {
+  hipLaunchKernelGGL(psm_cut_features_kernel, dim3((cap + 255) / 256), dim3(256), 0, st, insts, parts, cuts, cap,
+                     rmin, rmax, X);
+  return hipGetLastError();
+}
+
+hipError_t launch_psm_cut_scatter(const InstDev* insts, PartDev parts, CutDev cuts, int cap, const float* y,
+                                  int* slots, hipStream_t st) {
+  hipLaunchKernelGGL(psm_cut_scatter_kernel, dim3((cap + 255) / 256), dim3(256), 0, st, insts, parts, cuts, cap, y,
+                     slots);
+  return hipGetLastError();
+}
+
+hipError_t launch_psm_unit_totals(int nlist, int side, int nsplit, const int* slots, int* totals, hipStream_t st) {
+  if (nlist <= 0) return hipSuccess;
+  hipLaunchKernelGGL(psm_unit_totals_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, side, nsplit, slots, totals);
+  return hipGetLastError();
+}
+
+hipError_t launch_psm_label(const double* rd, long long ns, int n, float* eps, hipStream_t st) {
+  if (ns <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<long long>((ns + 3) / 4, 65536);
+  hipLaunchKernelGGL(psm_label_kernel, dim3(grid), dim3(256), 0, st, rd, ns, n, eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_psm_judge(const InstDev* insts, PartDev parts, const int* slots, CutDev cuts, int cap, int stride,
+                            double* stats, hipStream_t st) {
+  hipLaunchKernelGGL(psm_judge_kernel, dim3(1024), dim3(256), 0, st, insts, parts, slots, cuts, cap, stride, stats);
   return hipGetLastError();
 }
 

@@ -136,6 +136,50 @@ def c5_many(seed=0, n=2000, L=512, dmin=12.0, dmax=20.0, gap=2.0):
     return dict(L=L, X=np.array(Xs), D=np.array(Ds))
 
 
+def eps_training_cells(seed, n, r_min=5.5, r_max=10.5):
+    """n cells near a sphere surface as rows (R, dx, dy, dz): R uniform in
+    [r_min, r_max], the direction of d uniform on the unit sphere, |d| uniform
+    in R +- sqrt(3)/2 (the band that holds every cut cell)."""
+    rng = np.random.default_rng(seed)
+    R = rng.uniform(r_min, r_max, n)
+    v = rng.standard_normal((n, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    r = R + rng.uniform(-0.5 * math.sqrt(3.0), 0.5 * math.sqrt(3.0), n)
+    out = np.empty((n, 4))
+    out[:, 0] = R
+    out[:, 1:] = v * r[:, None]
+    return out
+
+
+def affine_orders(seed, n, epochs):
+    """Per-epoch sample orders s -> (s * mult + add) mod n with mult coprime to n."""
+    rng = np.random.default_rng(seed)
+    mult, add = [], []
+    for _ in range(epochs):
+        while True:
+            m = int(rng.integers(1, max(n, 2)))
+            if math.gcd(m, n) == 1:
+                break
+        mult.append(m)
+        add.append(int(rng.integers(0, n)))
+    return np.array(mult, np.int64), np.array(add, np.int64)
+
+
+def c5_learned(seed=0, n=2000):
+    """Learned-eps workload: 512^3 periodic box, n spheres with D uniform in
+    [12, 20] placed by random sequential addition (gap >= 2 cells), density
+    ratio 1.5, one gravity for all with Ga = 144 at D = 16, fluid body force
+    balancing the net weight of all spheres."""
+    pl = c5_many(seed, n=n)
+    L = pl["L"]
+    nu = 0.01
+    g = gravity_for(144.0, nu, 16.0, 1.5)
+    V = math.pi * pl["D"] ** 3 / 6.0
+    fz = 0.5 * V.sum() * g / float(L) ** 3
+    return dict(nx=L, ny=L, nz=L, X=pl["X"], D=pl["D"], rho=1.5, nu=nu, gravity=(0.0, 0.0, -g),
+                f_ext=(0.0, 0.0, fz))
+
+
 def random_pdfs(shape, scale, seed):
     """Seeded random PDF deviations g[19, z, y, x]."""
     rng = np.random.default_rng(seed)

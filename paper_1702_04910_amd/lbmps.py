@@ -15,7 +15,9 @@ LIB_PATH = os.path.join(_HERE, "liblbmps.so")
 BGK, TRT = 0, 1
 NONE, MEM_BB, MEM_CLI, PSM = 0, 1, 2, 3
 FP64, FP32, FP16_DEV, BF16_DEV = 0, 1, 2, 3
-EPS_FLAT, EPS_RECURSIVE = 0, 1
+EPS_FLAT, EPS_RECURSIVE, EPS_LEARNED = 0, 1, 2
+MLP_NPARAM = 4801
+MLP_MAX_BATCH = 65536
 COUPLING = {"none": NONE, "mem_bb": MEM_BB, "mem_cli": MEM_CLI, "psm": PSM}
 PRECISION = {"fp64": FP64, "fp32": FP32, "fp16": FP16_DEV, "bf16": BF16_DEV}
 STORAGE_BYTES = {FP64: 8, FP32: 4, FP16_DEV: 2, BF16_DEV: 2}
@@ -44,6 +46,12 @@ class Particle(ctypes.Structure):
 class ParticleState(ctypes.Structure):
     _fields_ = [("F", ctypes.c_double * 3), ("T", ctypes.c_double * 3), ("U", ctypes.c_double * 3),
                 ("Omega", ctypes.c_double * 3), ("X", ctypes.c_double * 3)]
+
+
+class MlpTrainCfg(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("adam_eps", ctypes.c_float),
+                ("mult", ctypes.c_void_p), ("add", ctypes.c_void_p)]
 
 
 class LbmpsError(RuntimeError):
@@ -110,6 +118,32 @@ def lib():
         L.lbmps_get_timing.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(I64)]
         L.lbmps_velocities.restype = None
         L.lbmps_velocities.argtypes = [P]
+        L.lbmps_set_eps_model.restype = I32
+        L.lbmps_set_eps_model.argtypes = [P, P, D, D]
+        L.lbmps_rebuild_overlaps.restype = I32
+        L.lbmps_rebuild_overlaps.argtypes = [P]
+        L.lbmps_eps_judge.restype = I32
+        L.lbmps_eps_judge.argtypes = [P, I32, P]
+        L.lbmps_mlp_workspace_bytes.restype = SZ
+        L.lbmps_mlp_workspace_bytes.argtypes = [I64]
+        L.lbmps_mlp_create.restype = I32
+        L.lbmps_mlp_create.argtypes = [I64, P, SZ, P, ctypes.POINTER(P)]
+        L.lbmps_mlp_destroy.restype = None
+        L.lbmps_mlp_destroy.argtypes = [P]
+        for name in ("set_params", "get_params", "set_targets", "get_targets", "predict"):
+            f = getattr(L, "lbmps_mlp_" + name)
+            f.restype = I32
+            f.argtypes = [P, P]
+        L.lbmps_mlp_set_samples.restype = I32
+        L.lbmps_mlp_set_samples.argtypes = [P, I64, P]
+        L.lbmps_mlp_label.restype = I32
+        L.lbmps_mlp_label.argtypes = [P, I32]
+        L.lbmps_mlp_gradient.restype = I32
+        L.lbmps_mlp_gradient.argtypes = [P, I64, I32, I64, I64, P]
+        L.lbmps_mlp_train.restype = I32
+        L.lbmps_mlp_train.argtypes = [P, P]
+        L.lbmps_mlp_last_error.restype = ctypes.c_char_p
+        L.lbmps_mlp_last_error.argtypes = [P]
         _lib = L
     return _lib
 
@@ -291,3 +325,98 @@ class Sim:
 
     def particle_base(self, inst):
         return int(lib().lbmps_particle_base(self._ctx, inst))
+
+    # -- learned solid fraction
+    def set_eps_model(self, params, r_min, r_max):
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+        assert p.size == MLP_NPARAM
+        self._chk(lib().lbmps_set_eps_model(self._ctx, p.ctypes.data, float(r_min), float(r_max)))
+
+    def rebuild_overlaps(self):
+        self._chk(lib().lbmps_rebuild_overlaps(self._ctx))
+
+    def eps_judge(self, stride=1):
+        """(mean |error|, max |error|, cells judged) of the learned eps_s of the last rebuild."""
+        out = np.zeros(3)
+        self._chk(lib().lbmps_eps_judge(self._ctx, int(stride), out.ctypes.data))
+        return float(out[0]), float(out[1]), int(out[2])
+
+
+class Mlp:
+    """Trainer of the solid-fraction network on the device."""
+
+    def __init__(self, max_samples, device="cuda", stream=None):
+        import torch
+
+        nbytes = int(lib().lbmps_mlp_workspace_bytes(int(max_samples)))
+        if nbytes == 0:
+            raise LbmpsError(-1, "invalid sample capacity")
+        self.device = torch.device(device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._m = ctypes.c_void_p()
+        st = lib().lbmps_mlp_create(int(max_samples), self.workspace.data_ptr(), nbytes, self.stream.cuda_stream,
+                                    ctypes.byref(self._m))
+        if st != 0:
+            raise LbmpsError(st, "lbmps_mlp_create failed")
+        self.n = 0
+
+    def _chk(self, st):
+        if st != 0:
+            raise LbmpsError(st, lib().lbmps_mlp_last_error(self._m).decode())
+
+    def close(self):
+        if self._m.value:
+            lib().lbmps_mlp_destroy(self._m)
+            self._m = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+        assert p.size == MLP_NPARAM
+        self._chk(lib().lbmps_mlp_set_params(self._m, p.ctypes.data))
+
+    def params(self):
+        p = np.empty(MLP_NPARAM, np.float32)
+        self._chk(lib().lbmps_mlp_get_params(self._m, p.ctypes.data))
+        return p
+
+    def set_samples(self, rd):
+        rd = np.ascontiguousarray(np.asarray(rd, dtype=np.float64).reshape(-1, 4))
+        self._chk(lib().lbmps_mlp_set_samples(self._m, len(rd), rd.ctypes.data))
+        self.n = len(rd)
+
+    def label(self, eps_n):
+        self._chk(lib().lbmps_mlp_label(self._m, int(eps_n)))
+
+    def set_targets(self, t):
+        t = np.ascontiguousarray(np.asarray(t, dtype=np.float32).reshape(-1))
+        assert t.size == self.n
+        self._chk(lib().lbmps_mlp_set_targets(self._m, t.ctypes.data))
+
+    def targets(self):
+        t = np.empty(self.n, np.float32)
+        self._chk(lib().lbmps_mlp_get_targets(self._m, t.ctypes.data))
+        return t
+
+    def predict(self):
+        y = np.empty(self.n, np.float32)
+        self._chk(lib().lbmps_mlp_predict(self._m, y.ctypes.data))
+        return y
+
+    def gradient(self, b0, batch, mult, add):
+        g = np.empty(MLP_NPARAM, np.float32)
+        self._chk(lib().lbmps_mlp_gradient(self._m, int(b0), int(batch), int(mult), int(add), g.ctypes.data))
+        return g
+
+    def train(self, mult, add, batch, lr=1e-3, beta1=0.9, beta2=0.999, adam_eps=1e-8):
+        mult = np.ascontiguousarray(np.asarray(mult, dtype=np.int64))
+        add = np.ascontiguousarray(np.asarray(add, dtype=np.int64))
+        assert mult.size == add.size
+        cfg = MlpTrainCfg(len(mult), int(batch), lr, beta1, beta2, adam_eps, mult.ctypes.data, add.ctypes.data)
+        self._chk(lib().lbmps_mlp_train(self._m, ctypes.byref(cfg)))
