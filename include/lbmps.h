@@ -207,7 +207,8 @@ lbmps_status lbmps_get_timing(lbmps_ctx* ctx, double* sweep_ms, int64_t* launche
  * multilayer perceptron 8 -> 64 -> 64 -> 1 (ReLU hidden layers) replaces it
  * for cut cells; cells entirely inside or outside a sphere stay exact.
  * Inputs of a cell with centre displacement d from a sphere of radius R:
- * |d_x|/R, |d_y|/R, |d_z|/R sorted descending, then 8/R, then four zeros.
+ * |d| - R, then |d_x|/|d|, |d_y|/|d|, |d_z|/|d| sorted descending, then 8/R,
+ * then three zeros.
  * Products run in bfloat16 (round to nearest even) on the matrix cores with
  * FP32 accumulation; parameters are FP32.  Parameter blob
  * (LBMPS_MLP_NPARAM floats): W1[64][8], b1[64], W2[64][64], b2[64], W3[64], b3.

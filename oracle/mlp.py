@@ -7,9 +7,10 @@ cells.  Its design is not from the paper (parity unpinned for the design
 choices; the arithmetic is pinned by finite differences):
 
 * features of a cell with centre displacement d = x_c - X_p from a sphere of
-  radius R: the three |d_k| / R sorted descending (the cube symmetry of the
-  cell makes eps_s invariant under axis permutations and reflections), and
-  8 / R (the cell size in units of the radius, scaled to O(1)); padded with
+  radius R: the signed distance |d| - R of the cell centre from the surface,
+  the direction cosines |d_k| / |d| sorted descending (the cube symmetry of
+  the cell makes eps_s invariant under axis permutations and reflections), and
+  8 / R (curvature relative to the cell size, scaled to O(1)); padded with
   zeros to 8 inputs;
 * network 8 -> 64 -> 64 -> 1 with ReLU hidden layers, output clamped to [0, 1]
   only at inference;
@@ -57,10 +58,13 @@ def features(d, R):
     """Inputs for displacements d (n, 3) and radii R (n,): (n, 8)."""
     d = np.asarray(d, dtype=np.float64)
     R = np.asarray(R, dtype=np.float64)
-    a = -np.sort(-np.abs(d), axis=1) / R[:, None]
+    s = -np.sort(-np.abs(d), axis=1)  # |d_k| sorted descending
+    r = np.sqrt((s[:, 0] * s[:, 0] + s[:, 1] * s[:, 1]) + s[:, 2] * s[:, 2])
+    cos = s / np.where(r > 0, r, np.inf)[:, None]
     x = np.zeros((len(R), NIN))
-    x[:, :3] = a
-    x[:, 3] = 8.0 / R
+    x[:, 0] = r - R
+    x[:, 1:4] = cos
+    x[:, 4] = 8.0 / R
     return x
 
 

@@ -103,6 +103,27 @@ struct PairDev {
   double *out;  // 6 per pair
 };
 
+// Inputs of the solid-fraction network for a cell whose centre lies at d from
+// the centre of a sphere of radius R: the signed distance |d| - R of the cell
+// centre from the surface, the direction cosines |d_k| / |d| sorted
+// descending (the cube symmetry of a cell folds every surface orientation
+// into one 48th of the sphere), 8 / R (curvature relative to the cell size),
+// then zeros.
+__device__ __forceinline__ void eps_features(const double (&d)[3], double R, float (&x)[8]) {
+  double a = fabs(d[0]), b = fabs(d[1]), c = fabs(d[2]), t;
+  if (a < b) { t = a; a = b; b = t; }
+  if (b < c) { t = b; b = c; c = t; }
+  if (a < b) { t = a; a = b; b = t; }
+  const double r = sqrt(__dadd_rn(__dadd_rn(__dmul_rn(a, a), __dmul_rn(b, b)), __dmul_rn(c, c)));
+  const double inv = r > 0.0 ? 1.0 / r : 0.0;
+  x[0] = (float)(r - R);
+  x[1] = (float)(a * inv);
+  x[2] = (float)(b * inv);
+  x[3] = (float)(c * inv);
+  x[4] = (float)(8.0 / R);
+  x[5] = x[6] = x[7] = 0.f;
+}
+
 // Cells cut by a sphere surface, collected while classifying bounding boxes.
 struct CutDev {
   int* count;       // number of entries (may exceed the capacity: then truncated)

@@ -1,7 +1,7 @@
 // Learned solid fraction: an 8 -> 64 -> 64 -> 1 MLP (ReLU) that replaces the
-// supersampling (Sec. 2.3.2) of cells cut by a sphere surface.  Inputs: the
-// three |d_k|/R sorted descending and 8/R (d: cell-centre displacement from the
-// sphere centre, R: radius), padded with zeros to 8.
+// supersampling (Sec. 2.3.2) of cells cut by a sphere surface.  Inputs: see
+// eps_features (signed distance from the surface, sorted direction cosines,
+// scaled curvature, zero padding).
 //
 // All GEMMs run on MFMA (v_mfma_f32_32x32x8bf16_1k: bf16 operands, fp32
 // accumulation).  Layers are chained with the weights as the A operand
@@ -43,19 +43,6 @@ __device__ __forceinline__ f16v zero16() {
 #pragma unroll
   for (int e = 0; e < 16; ++e) z[e] = 0.f;
   return z;
-}
-
-// Feature k (0..7) of a cell: sorted |d|/R, then 8/R, then zeros.
-__device__ __forceinline__ void mlp_features(const double d[3], double R, float (&x)[NIN]) {
-  double a = fabs(d[0]), b = fabs(d[1]), c = fabs(d[2]), t;
-  if (a < b) { t = a; a = b; b = t; }
-  if (b < c) { t = b; b = c; c = t; }
-  if (a < b) { t = a; a = b; b = t; }
-  x[0] = (float)(a / R);
-  x[1] = (float)(b / R);
-  x[2] = (float)(c / R);
-  x[3] = (float)(8.0 / R);
-  x[4] = x[5] = x[6] = x[7] = 0.f;
 }
 
 // Forward pass for the 32 samples of one wave.  xin: the 4 inputs of this lane
@@ -323,7 +310,7 @@ __global__ void mlp_features_kernel(const double* __restrict__ rd, long long n, 
   if (s >= n) return;
   const double d[3] = {rd[4 * s + 1], rd[4 * s + 2], rd[4 * s + 3]};
   float x[NIN];
-  mlp_features(d, rd[4 * s], x);
+  eps_features(d, rd[4 * s], x);
 #pragma unroll
   for (int k = 0; k < NIN; ++k) X[s * NIN + k] = x[k];
 }

@@ -200,16 +200,11 @@ __global__ void psm_cut_features_kernel(const InstDev* __restrict__ insts, PartD
   const double R = 0.5 * P.D[p];
   const bool use = I.eps_mode == EPS_LEARNED && R >= rmin && R <= rmax;
   cuts.use[t] = use ? 1 : 0;
-  double a = fabs(cuts.d[3 * t]), b = fabs(cuts.d[3 * t + 1]), c = fabs(cuts.d[3 * t + 2]), tmp;
-  if (a < b) { tmp = a; a = b; b = tmp; }
-  if (b < c) { tmp = b; b = c; c = tmp; }
-  if (a < b) { tmp = a; a = b; b = tmp; }
-  float* x = X + 8LL * t;
-  x[0] = (float)(a / R);
-  x[1] = (float)(b / R);
-  x[2] = (float)(c / R);
-  x[3] = (float)(8.0 / R);
-  x[4] = x[5] = x[6] = x[7] = 0.f;
+  const double d[3] = {cuts.d[3 * t], cuts.d[3 * t + 1], cuts.d[3 * t + 2]};
+  float x[8];
+  eps_features(d, R, x);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) X[8LL * t + k] = x[k];
 }
 
 // The network's eps (clamped to [0, 1]) as the nearest count out of n^3.

@@ -42,9 +42,12 @@ def test_features_are_cube_symmetric_and_sorted():
     R = rng.uniform(3, 12, 200)
     x = mlp.features(d, R)
     assert x.shape == (200, mlp.NIN)
-    assert np.all(x[:, 0] >= x[:, 1]) and np.all(x[:, 1] >= x[:, 2]) and np.all(x[:, 2] >= 0)
-    assert np.array_equal(x[:, 3], 8.0 / R)
-    assert np.all(x[:, 4:] == 0)
+    r = np.linalg.norm(d, axis=1)
+    assert np.allclose(x[:, 0], r - R, rtol=0, atol=1e-14)
+    assert np.all(x[:, 1] >= x[:, 2]) and np.all(x[:, 2] >= x[:, 3]) and np.all(x[:, 3] >= 0)
+    assert np.allclose((x[:, 1:4] ** 2).sum(axis=1), 1.0, rtol=0, atol=1e-14)
+    assert np.array_equal(x[:, 4], 8.0 / R)
+    assert np.all(x[:, 5:] == 0)
     for perm in ([1, 0, 2], [2, 1, 0], [1, 2, 0]):
         for signs in ([1, 1, 1], [-1, 1, 1], [1, -1, -1], [-1, -1, -1]):
             d2 = d[:, perm] * np.array(signs)
