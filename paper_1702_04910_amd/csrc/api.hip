@@ -50,7 +50,7 @@ struct Layout {
   long long chunk = 0;
   // byte offsets
   size_t o_bufA, o_bufB, o_owner, o_cellmap, o_inst, o_parts, o_plists, o_slots, o_totals, o_offsets, o_ranges,
-      o_counts, o_links, o_wallv, o_pairs, o_refill, o_scratch, o_tiles, o_cuts, o_cutx, o_mlp, total;
+      o_counts, o_links, o_wallv, o_pairs, o_refill, o_scratch, o_tiles, o_cuts, o_cutx, o_mlp, o_judge, total;
   int ntiles = 0;
   int max_tile_cells = 0;
 };
@@ -196,7 +196,8 @@ Layout make_layout(int n, const lbmps_config* cfgs) {
   L.o_tiles = take((size_t)L.ntiles * sizeof(int4));
   L.o_cuts = take((size_t)L.cut_cap * (8 + 4 + 4 + 24) + 4 * ALIGN);
   L.o_cutx = take(L.learned ? (size_t)L.cut_cap * (8 + 1) * 4 : 0);
-  L.o_mlp = take((size_t)mlp_nparam() * 4 + 4 * 8);
+  L.o_mlp = take((size_t)mlp_nparam() * 4);
+  L.o_judge = take(4 * 8);  // own aligned block: the judge updates it with 8-byte atomics
   L.total = o;
   L.ok = true;
   return L;
@@ -518,7 +519,7 @@ lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* ws, s
     c->cuts.err = err_word(c);
     c->cut_x = L.learned ? (float*)(w + L.o_cutx) : nullptr;
     c->mlp_p = (float*)(w + L.o_mlp);
-    c->judge = (double*)(w + L.o_mlp + (size_t)mlp_nparam() * 4);
+    c->judge = (double*)(w + L.o_judge);
   }
 
   // instance table and sweep tiles
