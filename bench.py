@@ -122,6 +122,119 @@ def batched(torch, lbmps, inputs, steps, warmup, seed):
             "note": "each instance is bitwise equal to the same instance run alone (tests/test_gpu_batch.py)"}
 
 
+def _overlap_keys(ov):
+    import numpy as np
+
+    key = ov["p"].astype(np.int64) * (1 << 31) + ov["cell"].astype(np.int64)
+    order = np.argsort(key)
+    return key[order], ov["eps"][order]
+
+
+def eps_error(ref, other):
+    """Mean and max |eps - eps_ref| over the cells cut by a surface (0 < eps < 1
+    in either estimate, plus cells present in only one of them)."""
+    import numpy as np
+
+    kr, er = ref
+    ko, eo = other
+    keys = np.union1d(kr, ko)
+    a = np.zeros(len(keys))
+    b = np.zeros(len(keys))
+    a[np.searchsorted(keys, kr)] = er
+    b[np.searchsorted(keys, ko)] = eo
+    cut = ((a > 0) & (a < 1)) | ((b > 0) & (b < 1))
+    d = np.abs(a - b)[cut]
+    return float(d.mean()), float(d.max()), int(cut.sum())
+
+
+def learned(torch, lbmps, inputs, steps, warmup, seed):
+    """Learned solid fraction on 2000 moving spheres (D uniform in 12..20) in a
+    512^3 periodic box, PSM-M3B2, FP32 storage, two sweeps per rigid-body step:
+    the overlap rebuild after every rigid-body step evaluates eps_s of every
+    cut cell.  Estimators: flat 16^3 supersampling (reference), flat 8^3,
+    recursive 16^3, and the network (trained here on 2^22 labelled cells,
+    R uniform in 5.5..10.5, by the library's own MFMA kernels)."""
+    import numpy as np
+
+    wl = inputs.c5_learned(seed)
+    n_p = len(wl["D"])
+    L = wl["nx"]
+    N = L ** 3
+    # training
+    t0 = time.perf_counter()
+    ns = 1 << 22
+    rd = inputs.eps_training_cells(seed + 1, ns)
+    m = lbmps.Mlp(ns)
+    m.set_samples(rd)
+    m.set_params(inputs.mlp_init(seed + 1))
+    m.label(16)
+    mult, add = inputs.affine_orders(seed + 1, ns, 4)
+    m.train(mult[:3], add[:3], batch=1024, lr=2e-3)
+    m.train(mult[3:], add[3:], batch=1024, lr=4e-4)
+    t_pred = m.predict()
+    params = m.params()
+    train_mae = float(np.mean(np.abs(t_pred - m.targets())))
+    m.close()
+    del m
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    log("  trained on %d cells in %.1f s, mean |err| %.4f" % (ns, train_s, train_mae))
+
+    out = {"workload": "512^3 periodic, %d moving spheres D 12..20, PSM-M3B2, FP32" % n_p, "spheres": n_p,
+           "train": {"cells": ns, "epochs": 4, "seconds": round(train_s, 2), "mean_abs_err": round(train_mae, 5)}}
+    variants = [("flat16", lbmps.EPS_FLAT, 16), ("flat8", lbmps.EPS_FLAT, 8),
+                ("recursive16", lbmps.EPS_RECURSIVE, 16), ("learned16", lbmps.EPS_LEARNED, 16)]
+    ref_keys, ref_U = None, None
+    launch = tuned_shape(dict(nx=L, ny=L, nz=L), "fp32")
+    res = {}
+    for name, mode, n in variants:
+        log("  learned-form variant", name)
+        cfg = lbmps.make_config(L, L, L, wl["nu"], collision="trt", coupling="psm", psm_m=3, psm_b=2, n_sub=2,
+                                eps_n=n, eps_mode=mode, precision="fp32", max_particles=n_p, max_diameter=20.0,
+                                f_ext=wl["f_ext"], gravity=wl["gravity"], **launch)
+        sim = lbmps.Sim(cfg)
+        sim.init_equilibrium()
+        if mode == lbmps.EPS_LEARNED:
+            sim.set_eps_model(params, 5.5, 10.5)
+        zeros = [[0.0, 0.0, 0.0]] * n_p
+        sim.set_particles(wl["X"], zeros, zeros, wl["D"], [wl["rho"]] * n_p, [False] * n_p)
+        keys = _overlap_keys(sim.overlaps())
+        ent = {}
+        if mode == lbmps.EPS_LEARNED:
+            jm, jx, jn = sim.eps_judge(1)
+            ent["judge"] = {"mean_abs_err": jm, "max_abs_err": jx, "cells": jn}
+        # cost of one overlap rebuild
+        for _ in range(2):
+            sim.rebuild_overlaps()
+        sim.sync()
+        tr = time.perf_counter()
+        for _ in range(5):
+            sim.rebuild_overlaps()
+        sim.sync()
+        ent["rebuild_ms"] = round((time.perf_counter() - tr) / 5 * 1e3, 3)
+        w, _, _ = timed_run(torch, sim, steps, warmup, 2, timing=False)
+        U = sim.particles()["U"]
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        ent["MLUPS"] = round(N * 2 * steps / w / 1e6, 1)
+        ent["ms_per_step"] = round(w / steps * 1e3, 3)
+        if ref_keys is None:
+            ref_keys, ref_U = keys, U
+        else:
+            em, ex, ec = eps_error(ref_keys, keys)
+            ent["eps_error_vs_flat16"] = {"mean_abs": em, "max_abs": ex, "cut_cells": ec}
+            ent["velocity_error_vs_flat16"] = float(np.linalg.norm(U - ref_U) / np.linalg.norm(ref_U))
+        res[name] = ent
+    out["variants"] = res
+    out["steps"] = steps
+    best_exact = min(("flat16", "recursive16"), key=lambda k: res[k]["rebuild_ms"])
+    out["gain_vs_best_exact_16"] = {"best_exact": best_exact,
+                                    "rebuild_speedup": round(res[best_exact]["rebuild_ms"] / res["learned16"]["rebuild_ms"], 2),
+                                    "MLUPS_ratio": round(res["learned16"]["MLUPS"] / res[best_exact]["MLUPS"], 3)}
+    return out
+
+
 def cpu_baseline(inp, steps=30):
     """The FP64 oracle on a sub-box of the same workload (same sphere
     resolution, half the box in each horizontal direction)."""
@@ -156,6 +269,7 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="only the primary FP32 MEM-CLI run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 48-instance batched form")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned solid-fraction form")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
@@ -242,6 +356,10 @@ def main():
     if not args.no_batch:
         log("batched form (48 instances)")
         line["batched"] = batched(torch, lbmps, inputs, min(args.steps, 100), min(args.warmup, 10), args.seed)
+
+    if not args.no_learned:
+        log("learned solid fraction (512^3, 2000 spheres)")
+        line["learned"] = learned(torch, lbmps, inputs, min(args.steps, 40), min(args.warmup, 5), args.seed)
 
     if not args.no_cpu_baseline:
         log("cpu baseline")

@@ -104,11 +104,3 @@ def backward(p, X, t, emulate_bf16=False):
     g["W1"] = r(dZ1).T @ c["Xb"]
     g["b1"] = dZ1.sum(axis=0)
     return g
-
-
-def init_params(seed):
-    """He-style initialisation (seeded) of a fresh network."""
-    rng = np.random.default_rng(seed)
-    return dict(W1=rng.standard_normal((NH, NIN)) * np.sqrt(2.0 / 4.0), b1=np.zeros(NH),
-                W2=rng.standard_normal((NH, NH)) * np.sqrt(2.0 / NH), b2=np.zeros(NH),
-                W3=rng.standard_normal(NH) * np.sqrt(1.0 / NH), b3=np.array([0.5]))

@@ -165,6 +165,17 @@ def affine_orders(seed, n, epochs):
     return np.array(mult, np.int64), np.array(add, np.int64)
 
 
+def mlp_init(seed):
+    """Seeded initial parameters of the solid-fraction network as the float32
+    blob W1[64][8], b1[64], W2[64][64], b2[64], W3[64], b3: He-scaled normal
+    weights (five non-zero inputs), zero hidden biases, output bias 1/2."""
+    rng = np.random.default_rng(seed)
+    W1 = rng.standard_normal((64, 8)) * math.sqrt(2.0 / 5.0)
+    W2 = rng.standard_normal((64, 64)) * math.sqrt(2.0 / 64.0)
+    W3 = rng.standard_normal(64) * math.sqrt(1.0 / 64.0)
+    return np.concatenate([W1.ravel(), np.zeros(64), W2.ravel(), np.zeros(64), W3, [0.5]]).astype(np.float32)
+
+
 def c5_learned(seed=0, n=2000):
     """Learned-eps workload: 512^3 periodic box, n spheres with D uniform in
     [12, 20] placed by random sequential addition (gap >= 2 cells), density

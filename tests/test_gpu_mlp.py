@@ -25,7 +25,7 @@ def _exact_eps(rd, n):
 
 
 def _params(seed):
-    p = om.init_params(seed)
+    p = om.unpack(inputs.mlp_init(seed).astype(np.float64))
     rng = np.random.default_rng(seed + 7)
     p["b1"] = rng.standard_normal(om.NH) * 0.1
     p["b2"] = rng.standard_normal(om.NH) * 0.1
@@ -98,7 +98,7 @@ def _train(n=65536, seed=8):
     rd = inputs.eps_training_cells(seed, n)
     m = lbmps.Mlp(n)
     m.set_samples(rd)
-    m.set_params(om.pack(om.init_params(seed)).astype(np.float32))
+    m.set_params(inputs.mlp_init(seed))
     m.label(16)
     t = m.targets()
     y0 = m.predict()

@@ -7,6 +7,7 @@ import pytest
 
 from oracle import geometry as geo
 from oracle import mlp
+from paper_1702_04910_amd import inputs
 
 
 # ----------------------------------------------------------------------- bfloat16
@@ -63,7 +64,7 @@ def test_features_are_cube_symmetric_and_sorted():
 # ----------------------------------------------------------------------- backward
 def _problem(seed, m=48):
     rng = np.random.default_rng(seed)
-    p = mlp.init_params(seed)
+    p = mlp.unpack(inputs.mlp_init(seed).astype(np.float64))
     p["b1"] = rng.standard_normal(mlp.NH) * 0.1
     p["b2"] = rng.standard_normal(mlp.NH) * 0.1
     R = rng.uniform(4, 10, m)
@@ -120,7 +121,7 @@ def test_bf16_emulation_stays_close_to_fp64():
 
 
 def test_pack_roundtrip_and_size():
-    p = mlp.init_params(0)
+    p = mlp.unpack(inputs.mlp_init(0).astype(np.float64))
     blob = mlp.pack(p)
     assert blob.size == mlp.NPARAM == 4801
     q = mlp.unpack(blob)
