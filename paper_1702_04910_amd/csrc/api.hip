@@ -186,7 +186,7 @@ Layout make_layout(int n, const lbmps_config* cfgs) {
   L.o_slots = take((size_t)L.slot_elems * 4);
   L.o_totals = take((size_t)L.box_total * 4);
   L.o_offsets = take((size_t)L.box_total * 4);
-  L.o_ranges = take((size_t)L.ptotal * 6 * 4);
+  L.o_ranges = take((size_t)L.ptotal * 8 * 4);
   L.o_counts = take(16 * 4);
   L.o_links = take((size_t)(L.link_cap + L.wall_cap) * (5 * 4 + 8 + 6 * 8) + 2 * ALIGN);
   L.o_wallv = take((size_t)n * 16 * 3 * 8);
@@ -228,7 +228,8 @@ struct lbmps_ctx {
   int* slots = nullptr;
   int* totals = nullptr;
   int* offsets = nullptr;
-  int *lbeg = nullptr, *lend = nullptr, *pbeg = nullptr, *pend = nullptr, *rbeg = nullptr, *rend = nullptr;
+  int *lbeg = nullptr, *lend = nullptr, *pbeg = nullptr, *pend = nullptr, *rbeg = nullptr, *rend = nullptr,
+      *cbeg = nullptr, *cend = nullptr;
   int* counts = nullptr;  // [0] links, [1] pairs, [2] refill, [4] error bits (unsigned)
   LinkDev links{};
   int n_wall = 0;
@@ -243,6 +244,8 @@ struct lbmps_ctx {
   double* judge = nullptr; // error statistics of lbmps_eps_judge
   bool mlp_set = false;
   double mlp_rmin = 0.0, mlp_rmax = -1.0;
+  bool psm_exact = true;           // some PSM cut cell needs supersampling
+  std::vector<double> diam_h;      // per global particle
   double* scratch = nullptr;
   long long sweeps = 0;
   bool have_psm = false, have_links_inst = false;
@@ -295,6 +298,21 @@ int nsplit_for(int nlist, int side) {
 }
 
 int* mem_list(lbmps_ctx* c) { return c->plist_d; }
+
+// Whether any current PSM particle needs supersampled cut cells (an exact
+// estimator, or the learned one outside its radius range).
+void update_psm_exact(lbmps_ctx* c) {
+  c->psm_exact = false;
+  for (int k = 0; k < c->L.n; ++k) {
+    if (c->cfg[k].coupling != LBMPS_PSM) continue;
+    const int b = c->L.part_begin[k];
+    for (int i = 0; i < c->n_active[k]; ++i) {
+      const double R = 0.5 * c->diam_h[b + i];
+      if (c->cfg[k].eps_mode != LBMPS_EPS_LEARNED || !c->mlp_set || R < c->mlp_rmin || R > c->mlp_rmax)
+        c->psm_exact = true;
+    }
+  }
+}
 int* psm_list(lbmps_ctx* c) { return c->plist_d + c->n_mem; }
 
 // Rebuild links of every MEM particle (after mapping); refill first when `refill`.
@@ -344,10 +362,11 @@ lbmps_status rebuild_psm(lbmps_ctx* c) {
   const int ns = nsplit_for(c->n_psm, L.side);
   const int units = L.side * ns;
   HIPCHK(c, launch_psm_cellmap(0, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap, c->st));
-  hipLaunchKernelGGL(fill_int_kernel, dim3(1), dim3(64), 0, c->st, c->cuts.count, 1LL, 0);
-  HIPCHK(c, hipGetLastError());
-  HIPCHK(c, launch_psm_classify(psm_list(c), c->n_psm, L.side, ns, c->inst_d, c->parts, c->slots, c->cuts, L.cut_cap,
-                                c->st));
+  HIPCHK(c, launch_psm_classify(psm_list(c), c->n_psm, L.side, ns, c->inst_d, c->parts, c->slots, c->totals, c->st));
+  HIPCHK(c, launch_scan(c->totals, c->offsets, c->n_psm * units, units, c->n_psm, c->cbeg, c->cend, c->cuts.count,
+                        L.cut_cap, err, ERR_CUT_CAP, c->st));
+  HIPCHK(c, launch_psm_cut_fill(psm_list(c), c->n_psm, L.side, ns, c->inst_d, c->parts, c->slots, c->offsets,
+                                c->cuts, L.cut_cap, c->st));
   const double rmin = c->mlp_set ? c->mlp_rmin : 0.0, rmax = c->mlp_set ? c->mlp_rmax : -1.0;
   if (L.learned && c->mlp_set) {
     float* y = c->cut_x + (size_t)L.cut_cap * 8;
@@ -355,7 +374,8 @@ lbmps_status rebuild_psm(lbmps_ctx* c) {
     HIPCHK(c, launch_mlp_infer_count(c->mlp_p, c->cut_x, c->cuts.count, L.cut_cap, y, c->st));
     HIPCHK(c, launch_psm_cut_scatter(c->inst_d, c->parts, c->cuts, L.cut_cap, y, c->slots, c->st));
   }
-  HIPCHK(c, launch_psm_cut_exact(c->inst_d, c->parts, c->slots, c->cuts, L.cut_cap, rmin, rmax, c->st));
+  if (c->psm_exact)
+    HIPCHK(c, launch_psm_cut_exact(c->inst_d, c->parts, c->slots, c->cuts, L.cut_cap, rmin, rmax, c->st));
   HIPCHK(c, launch_psm_unit_totals(c->n_psm, L.side, ns, c->slots, c->totals, c->st));
   HIPCHK(c, launch_scan(c->totals, c->offsets, c->n_psm * units, units, c->n_psm, c->pbeg, c->pend, c->counts + 1,
                         L.pair_cap, err, ERR_PAIR_CAP, c->st));
@@ -479,6 +499,7 @@ lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* ws, s
     int* r = (int*)(w + L.o_ranges);
     const int P = L.ptotal;
     c->lbeg = r; c->lend = r + P; c->pbeg = r + 2 * P; c->pend = r + 3 * P; c->rbeg = r + 4 * P; c->rend = r + 5 * P;
+    c->cbeg = r + 6 * P; c->cend = r + 7 * P;
   }
   c->counts = (int*)(w + L.o_counts);
   {
@@ -562,6 +583,7 @@ lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* ws, s
   c->n_active.assign(n, 0);
   c->wall_groups.assign(n, 0);
   c->fixed_h.assign(L.ptotal, 1);
+  c->diam_h.assign(L.ptotal, 0.0);
   c->coupling_of_part.assign(L.ptotal, 0);
   lbmps_status s = LBMPS_OK;
   auto bail = [&](hipError_t e, const char* what) {
@@ -732,6 +754,7 @@ lbmps_status lbmps_set_particles(lbmps_ctx* c, int32_t inst, int32_t n, const lb
   c->n_active[inst] = n;
   for (int i = 0; i < n; ++i) {
     c->fixed_h[base + i] = fixed[i];
+    c->diam_h[base + i] = D[i];
     c->coupling_of_part[base + i] = cf.coupling;
   }
   c->inst_h[inst].part_count = n;
@@ -754,6 +777,7 @@ lbmps_status lbmps_set_particles(lbmps_ctx* c, int32_t inst, int32_t n, const lb
   }
   c->n_mem = (int)lm.size();
   c->n_psm = (int)lps.size();
+  update_psm_exact(c);
   std::vector<int> all(lm);
   all.insert(all.end(), lps.begin(), lps.end());
   if (!all.empty()) HIPCHK(c, hipMemcpy(c->plist_d, all.data(), 4 * all.size(), hipMemcpyHostToDevice));
@@ -1046,6 +1070,7 @@ lbmps_status lbmps_set_eps_model(lbmps_ctx* c, const float* hp, double r_min, do
   c->mlp_set = true;
   c->mlp_rmin = r_min;
   c->mlp_rmax = r_max;
+  update_psm_exact(c);
   lbmps_status s = rebuild_psm(c);
   if (s) return s;
   return check_device_errors(c);

@@ -53,7 +53,9 @@ hipError_t launch_links_bc(int prec, int n_wall, const int* count, int cap, Link
 
 // ---- psm.hip
 hipError_t launch_psm_classify(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
-                               int* slots, CutDev cuts, int cap, hipStream_t st);
+                               int* slots, int* totals, hipStream_t st);
+hipError_t launch_psm_cut_fill(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
+                               const int* slots, const int* offsets, CutDev cuts, int cap, hipStream_t st);
 hipError_t launch_psm_cut_exact(const InstDev* insts, PartDev parts, int* slots, CutDev cuts, int cap, double rmin,
                                 double rmax, hipStream_t st);
 hipError_t launch_psm_cut_features(const InstDev* insts, PartDev parts, CutDev cuts, int cap, double rmin,

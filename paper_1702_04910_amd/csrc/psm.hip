@@ -40,8 +40,37 @@ __device__ __forceinline__ int classify(const double (&lo)[3], const double (&hi
   return 0;
 }
 
+// Per-wave LDS table for the cell being counted: the sample offsets along one
+// axis and the squared sample coordinates (d_k + o_a)^2 along each axis.
+struct WaveTab {
+  double off[64];
+  double sq[3][64];
+};
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Fill the table for centre displacement dc (lane a < n writes entry a).
+__device__ __forceinline__ void wave_table(const double dc[3], int n, WaveTab& T) {
+  const int lane = threadIdx.x & 63;
+  wave_sync_lds();  // previous readers are done
+  if (lane < n) {
+    const double o = sample_off(lane, n);
+    T.off[lane] = o;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double x = __dadd_rn(dc[k], o);
+      T.sq[k][lane] = __dmul_rn(x, x);
+    }
+  }
+  wave_sync_lds();
+}
+
 // Octree count over the block of m^3 sample points starting at (a0, b0, c0).
-__device__ int count_recursive_block(const double dc[3], double R2, int n, int a0_, int b0_, int c0_, int m0) {
+__device__ int count_recursive_block(const double dc[3], double R2, const WaveTab& T, int a0_, int b0_, int c0_,
+                                     int m0) {
   // explicit stack of blocks (a0, b0, c0, m); depth <= log2(n) <= 6
   int st_a[64], st_b[64], st_c[64], st_m[64];
   int sp = 0, cnt = 0;
@@ -49,14 +78,17 @@ __device__ int count_recursive_block(const double dc[3], double R2, int n, int a
   while (sp > 0) {
     --sp;
     const int a0 = st_a[sp], b0 = st_b[sp], c0 = st_c[sp], m = st_m[sp];
+    if (m == 1) {
+      cnt += __dadd_rn(__dadd_rn(T.sq[0][a0], T.sq[1][b0]), T.sq[2][c0]) <= R2 ? 1 : 0;
+      continue;
+    }
     double lo[3], hi[3];
-    lo[0] = __dadd_rn(dc[0], sample_off(a0, n)); hi[0] = __dadd_rn(dc[0], sample_off(a0 + m - 1, n));
-    lo[1] = __dadd_rn(dc[1], sample_off(b0, n)); hi[1] = __dadd_rn(dc[1], sample_off(b0 + m - 1, n));
-    lo[2] = __dadd_rn(dc[2], sample_off(c0, n)); hi[2] = __dadd_rn(dc[2], sample_off(c0 + m - 1, n));
+    lo[0] = __dadd_rn(dc[0], T.off[a0]); hi[0] = __dadd_rn(dc[0], T.off[a0 + m - 1]);
+    lo[1] = __dadd_rn(dc[1], T.off[b0]); hi[1] = __dadd_rn(dc[1], T.off[b0 + m - 1]);
+    lo[2] = __dadd_rn(dc[2], T.off[c0]); hi[2] = __dadd_rn(dc[2], T.off[c0 + m - 1]);
     const int cl = classify(lo, hi, R2);
     if (cl == 1) { cnt += m * m * m; continue; }
     if (cl == -1) continue;
-    if (m == 1) { cnt += sq3(lo[0], lo[1], lo[2]) <= R2 ? 1 : 0; continue; }
     const int h = m / 2;
     for (int k = 0; k < 8; ++k) {
       st_a[sp] = a0 + ((k & 1) ? h : 0);
@@ -70,23 +102,22 @@ __device__ int count_recursive_block(const double dc[3], double R2, int n, int a
 }
 
 // Sample count of one cut cell, computed by a whole wave: the flat estimator
-// splits the n^3 points over the lanes; the recursive one gives each lane one
-// of the 64 octree blocks of (n/4)^3 points (or one point for n = 2).  Both
-// return the exact same integer as a serial evaluation.
-__device__ int wave_count(const double dc[3], double R2, int n, int mode) {
+// gives each lane (a, b) columns of n points along z; the recursive one gives
+// each lane one of the 64 octree blocks of (n/4)^3 points (or the flat loop
+// for n < 4).  Squared coordinates come from the wave's table, so every point
+// test is ((x^2 + y^2) + z^2 <= R^2) with the same roundings as a direct
+// evaluation, and both return the exact serial count.
+__device__ int wave_count(const double dc[3], double R2, int n, int mode, WaveTab& T) {
   const int lane = threadIdx.x & 63;
+  wave_table(dc, n, T);
   int cnt = 0;
   if (mode == EPS_RECURSIVE && n >= 4) {
     const int m = n / 4;
-    cnt = count_recursive_block(dc, R2, n, (lane & 3) * m, ((lane >> 2) & 3) * m, (lane >> 4) * m, m);
+    cnt = count_recursive_block(dc, R2, T, (lane & 3) * m, ((lane >> 2) & 3) * m, (lane >> 4) * m, m);
   } else {
-    const int tot = n * n * n;
-    for (int pidx = lane; pidx < tot; pidx += 64) {
-      const int a = pidx % n, b = (pidx / n) % n, c = pidx / (n * n);
-      const double px = __dadd_rn(dc[0], sample_off(a, n));
-      const double py = __dadd_rn(dc[1], sample_off(b, n));
-      const double pz = __dadd_rn(dc[2], sample_off(c, n));
-      cnt += sq3(px, py, pz) <= R2 ? 1 : 0;
+    for (int ab = lane; ab < n * n; ab += 64) {
+      const double sab = __dadd_rn(T.sq[0][ab % n], T.sq[1][ab / n]);
+      for (int c = 0; c < n; ++c) cnt += __dadd_rn(sab, T.sq[2][c]) <= R2 ? 1 : 0;
     }
   }
   for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
@@ -109,13 +140,14 @@ __device__ __forceinline__ void centre_disp(const InstDev& I, const PartDev& P, 
 
 // Stage 1 of the solid fractions, grid (units, nlist): every bounding-box cell
 // of the unit is classified by its farthest and nearest sample point.  Cells
-// entirely inside get the full count n^3, entirely outside 0; cut cells are
-// appended to the cut list (their slot index, particle and centre
-// displacement) and evaluated by stage 2.  Slots hold sample counts out of
-// n^3 for every estimator (the learned one rounds its prediction to a count).
+// entirely inside get the full count n^3, entirely outside 0, cut cells the
+// marker -1; totals[unit] receives the number of cut cells.  Slots end up
+// holding sample counts out of n^3 for every estimator (the learned one
+// rounds its prediction to a count).
 __global__ __launch_bounds__(256) void psm_classify_kernel(const int* __restrict__ list, int side, int nsplit,
                                                            const InstDev* __restrict__ insts, PartDev P,
-                                                           int* __restrict__ slots, CutDev cuts, int cap) {
+                                                           int* __restrict__ slots, int* __restrict__ totals) {
+  __shared__ int sh[256];
   const int j = blockIdx.y;
   const Unit U = unit_of(blockIdx.x, side, nsplit);
   const int p = list[j];
@@ -127,42 +159,65 @@ __global__ __launch_bounds__(256) void psm_classify_kernel(const int* __restrict
   const int n = I.eps_n;
   const int ncu = (U.y1 - U.y0) * side;
   const double o0 = sample_off(0, n), o1 = sample_off(n - 1, n);
-  const int lane = threadIdx.x & 63;
-  // wave-uniform trip count: the cut cells of a wave take one atomic together
-  for (int c0 = 0; c0 < ncu; c0 += blockDim.x) {
-    const int c = c0 + threadIdx.x;
-    int cl = -1;
-    long long si = 0;
-    double dc[3] = {0.0, 0.0, 0.0};
-    if (c < ncu) {
-      const int dy = U.y0 + c / side, dx = c % side;
-      const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny), k = wrapi(lo[2] + U.z, I.nz);
-      centre_disp(I, P, p, i, jj, k, dc);
-      double blo[3], bhi[3];
+  const int k = wrapi(lo[2] + U.z, I.nz);
+  const double dz = min_image(((double)k + 0.5) - P.X[3 * p + 2], (double)I.nz);
+  int ncut = 0;
+  for (int c = threadIdx.x; c < ncu; c += blockDim.x) {
+    const int dy = U.y0 + c / side, dx = c % side;
+    const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny);
+    const double dc[3] = {min_image(((double)i + 0.5) - P.X[3 * p + 0], (double)I.nx),
+                          min_image(((double)jj + 0.5) - P.X[3 * p + 1], (double)I.ny), dz};
+    double blo[3], bhi[3];
 #pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        blo[q] = __dadd_rn(dc[q], o0);
-        bhi[q] = __dadd_rn(dc[q], o1);
-      }
-      cl = classify(blo, bhi, R2);
-      si = slot_index(j, side, U.z, dy, dx);
-      slots[si] = cl == 1 ? n * n * n : 0;
+    for (int q = 0; q < 3; ++q) {
+      blo[q] = __dadd_rn(dc[q], o0);
+      bhi[q] = __dadd_rn(dc[q], o1);
     }
-    const unsigned long long cut = __ballot(cl == 0);
-    if (cut) {
-      const int leader = __ffsll((long long)cut) - 1;
-      int base = 0;
-      if (lane == leader) base = atomicAdd(cuts.count, __popcll(cut));
-      base = __shfl(base, leader, 64);
-      const int t = base + __popcll(cut & ((1ull << lane) - 1ull));
-      if (cl == 0 && t < cap) {
-        cuts.slot[t] = si;
-        cuts.p[t] = p;
-        cuts.d[3 * t] = dc[0];
-        cuts.d[3 * t + 1] = dc[1];
-        cuts.d[3 * t + 2] = dc[2];
-      }
+    const int cl = classify(blo, bhi, R2);
+    slots[slot_index(j, side, U.z, dy, dx)] = cl == 1 ? n * n * n : (cl == 0 ? -1 : 0);
+    ncut += cl == 0 ? 1 : 0;
+  }
+  int total;
+  block_excl_scan256(ncut, sh, &total);
+  if (threadIdx.x == 0) totals[j * (side * nsplit) + blockIdx.x] = total;
+}
+
+// Stage 1b: the cut cells of each unit, in cell order, at the unit's scanned
+// offset: slot index, particle and centre displacement.
+__global__ __launch_bounds__(256) void psm_cut_fill_kernel(const int* __restrict__ list, int side, int nsplit,
+                                                           const InstDev* __restrict__ insts, PartDev P,
+                                                           const int* __restrict__ slots,
+                                                           const int* __restrict__ offsets, CutDev cuts, int cap) {
+  __shared__ int sh[256];
+  const int j = blockIdx.y;
+  const Unit U = unit_of(blockIdx.x, side, nsplit);
+  const int p = list[j];
+  const InstDev& I = insts[P.inst[p]];
+  int lo[3];
+  bbox_lo(P, p, lo);
+  const int ncu = (U.y1 - U.y0) * side;
+  const int chunk = (ncu + 255) / 256;
+  const int a = min(ncu, (int)threadIdx.x * chunk), b = min(ncu, a + chunk);
+  int local = 0;
+  for (int c = a; c < b; ++c) local += slots[slot_index(j, side, U.z, U.y0 + c / side, c % side)] < 0 ? 1 : 0;
+  int total;
+  int pos = offsets[j * (side * nsplit) + blockIdx.x] + block_excl_scan256(local, sh, &total);
+  for (int c = a; c < b; ++c) {
+    const int dy = U.y0 + c / side, dx = c % side;
+    const long long si = slot_index(j, side, U.z, dy, dx);
+    if (slots[si] >= 0) continue;
+    if (pos < cap) {
+      const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny), k = wrapi(lo[2] + U.z, I.nz);
+      double dc[3];
+      centre_disp(I, P, p, i, jj, k, dc);
+      cuts.slot[pos] = si;
+      cuts.p[pos] = p;
+      cuts.use[pos] = 0;
+      cuts.d[3 * pos] = dc[0];
+      cuts.d[3 * pos + 1] = dc[1];
+      cuts.d[3 * pos + 2] = dc[2];
     }
+    ++pos;
   }
 }
 
@@ -172,8 +227,8 @@ __global__ __launch_bounds__(256) void psm_classify_kernel(const int* __restrict
 __global__ __launch_bounds__(256) void psm_cut_exact_kernel(const InstDev* __restrict__ insts, PartDev P,
                                                             int* __restrict__ slots, CutDev cuts, int cap,
                                                             double rmin, double rmax) {
+  __shared__ WaveTab tab[4];
   const int n_cut = min(*cuts.count, cap);
-  if (blockIdx.x == 0 && threadIdx.x == 0 && *cuts.count > cap) atomicOr(cuts.err, (unsigned)ERR_CUT_CAP);
   const int nw = (gridDim.x * blockDim.x) >> 6;
   for (int t = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < n_cut; t += nw) {
     const int p = cuts.p[t];
@@ -183,7 +238,7 @@ __global__ __launch_bounds__(256) void psm_cut_exact_kernel(const InstDev* __res
     if (learned && R >= rmin && R <= rmax) continue;
     const double dc[3] = {cuts.d[3 * t], cuts.d[3 * t + 1], cuts.d[3 * t + 2]};
     const int n = I.eps_n;
-    const int cnt = wave_count(dc, __dmul_rn(R, R), n, learned ? EPS_FLAT : I.eps_mode);
+    const int cnt = wave_count(dc, __dmul_rn(R, R), n, learned ? EPS_FLAT : I.eps_mode, tab[threadIdx.x >> 6]);
     if ((threadIdx.x & 63) == 0) slots[cuts.slot[t]] = cnt;
   }
 }
@@ -236,11 +291,12 @@ __global__ __launch_bounds__(256) void psm_unit_totals_kernel(int side, int nspl
 // supersampling, one wave per sample.
 __global__ __launch_bounds__(256) void psm_label_kernel(const double* __restrict__ rd, long long ns, int n,
                                                         float* __restrict__ eps) {
+  __shared__ WaveTab tab[4];
   const long long nw = ((long long)gridDim.x * blockDim.x) >> 6;
   for (long long t = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6; t < ns; t += nw) {
     const double R = rd[4 * t];
     const double dc[3] = {rd[4 * t + 1], rd[4 * t + 2], rd[4 * t + 3]};
-    const int cnt = wave_count(dc, __dmul_rn(R, R), n, EPS_FLAT);
+    const int cnt = wave_count(dc, __dmul_rn(R, R), n, EPS_FLAT, tab[threadIdx.x >> 6]);
     if ((threadIdx.x & 63) == 0) eps[t] = (float)((double)cnt / ((double)n * n * n));
   }
 }
@@ -251,6 +307,7 @@ __global__ __launch_bounds__(256) void psm_label_kernel(const double* __restrict
 __global__ __launch_bounds__(256) void psm_judge_kernel(const InstDev* __restrict__ insts, PartDev P,
                                                         const int* __restrict__ slots, CutDev cuts, int cap,
                                                         int stride, double* __restrict__ stats) {
+  __shared__ WaveTab tab[4];
   const int n_cut = min(*cuts.count, cap);
   const int nw = (gridDim.x * blockDim.x) >> 6;
   for (int k = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; (long long)k * stride < n_cut; k += nw) {
@@ -261,7 +318,7 @@ __global__ __launch_bounds__(256) void psm_judge_kernel(const InstDev* __restric
     const double R = 0.5 * P.D[p];
     const double dc[3] = {cuts.d[3 * t], cuts.d[3 * t + 1], cuts.d[3 * t + 2]};
     const int n = I.eps_n;
-    const int cnt = wave_count(dc, __dmul_rn(R, R), n, EPS_FLAT);
+    const int cnt = wave_count(dc, __dmul_rn(R, R), n, EPS_FLAT, tab[threadIdx.x >> 6]);
     if ((threadIdx.x & 63) == 0) {
       const double e = fabs((double)(slots[cuts.slot[t]] - cnt) / ((double)n * n * n));
       atomicAdd(&stats[0], e);
@@ -272,10 +329,18 @@ __global__ __launch_bounds__(256) void psm_judge_kernel(const InstDev* __restric
 }
 
 hipError_t launch_psm_classify(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
-                               int* slots, CutDev cuts, int cap, hipStream_t st) {
+                               int* slots, int* totals, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
   hipLaunchKernelGGL(psm_classify_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts,
-                     parts, slots, cuts, cap);
+                     parts, slots, totals);
+  return hipGetLastError();
+}
+
+hipError_t launch_psm_cut_fill(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
+                               const int* slots, const int* offsets, CutDev cuts, int cap, hipStream_t st) {
+  if (nlist <= 0) return hipSuccess;
+  hipLaunchKernelGGL(psm_cut_fill_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts,
+                     parts, slots, offsets, cuts, cap);
   return hipGetLastError();
 }
 
