@@ -68,34 +68,42 @@ __device__ __forceinline__ void wave_table(const double dc[3], int n, WaveTab& T
   wave_sync_lds();
 }
 
-// Octree count over the block of m^3 sample points starting at (a0, b0, c0).
-__device__ int count_recursive_block(const double dc[3], double R2, const WaveTab& T, int a0_, int b0_, int c0_,
-                                     int m0) {
-  // explicit stack of blocks (a0, b0, c0, m); depth <= log2(n) <= 6
-  int st_a[64], st_b[64], st_c[64], st_m[64];
-  int sp = 0, cnt = 0;
-  st_a[0] = a0_; st_b[0] = b0_; st_c[0] = c0_; st_m[0] = m0; sp = 1;
-  while (sp > 0) {
-    --sp;
-    const int a0 = st_a[sp], b0 = st_b[sp], c0 = st_c[sp], m = st_m[sp];
-    if (m == 1) {
-      cnt += __dadd_rn(__dadd_rn(T.sq[0][a0], T.sq[1][b0]), T.sq[2][c0]) <= R2 ? 1 : 0;
-      continue;
+// Octree count over the block of m^3 sample points (m = 2^L) starting at
+// (a0, b0, c0), without a stack: the points are walked in Morton order
+// (bit 3i of the code -> a, 3i+1 -> b, 3i+2 -> c), and at each position the
+// largest aligned sub-block that starts there is classified by its farthest
+// and nearest point; a decided sub-block is counted whole and skipped, an
+// undecided one is split by retrying one level lower.
+__device__ int count_recursive_block(const double dc[3], double R2, const WaveTab& T, int a0, int b0, int c0, int L) {
+  const int total = 1 << (3 * L);
+  int cnt = 0;
+  int i = 0;
+  while (i < total) {
+    int l = i == 0 ? L : min(L, __builtin_ctz(i) / 3);
+    int a = a0, b = b0, c = c0;
+    for (int bit = 0; bit < L; ++bit) {
+      a += ((i >> (3 * bit)) & 1) << bit;
+      b += ((i >> (3 * bit + 1)) & 1) << bit;
+      c += ((i >> (3 * bit + 2)) & 1) << bit;
     }
-    double lo[3], hi[3];
-    lo[0] = __dadd_rn(dc[0], T.off[a0]); hi[0] = __dadd_rn(dc[0], T.off[a0 + m - 1]);
-    lo[1] = __dadd_rn(dc[1], T.off[b0]); hi[1] = __dadd_rn(dc[1], T.off[b0 + m - 1]);
-    lo[2] = __dadd_rn(dc[2], T.off[c0]); hi[2] = __dadd_rn(dc[2], T.off[c0 + m - 1]);
-    const int cl = classify(lo, hi, R2);
-    if (cl == 1) { cnt += m * m * m; continue; }
-    if (cl == -1) continue;
-    const int h = m / 2;
-    for (int k = 0; k < 8; ++k) {
-      st_a[sp] = a0 + ((k & 1) ? h : 0);
-      st_b[sp] = b0 + ((k & 2) ? h : 0);
-      st_c[sp] = c0 + ((k & 4) ? h : 0);
-      st_m[sp] = h;
-      ++sp;
+    for (;;) {
+      if (l == 0) {
+        cnt += __dadd_rn(__dadd_rn(T.sq[0][a], T.sq[1][b]), T.sq[2][c]) <= R2 ? 1 : 0;
+        i += 1;
+        break;
+      }
+      const int h = 1 << l;
+      double lo[3], hi[3];
+      lo[0] = __dadd_rn(dc[0], T.off[a]); hi[0] = __dadd_rn(dc[0], T.off[a + h - 1]);
+      lo[1] = __dadd_rn(dc[1], T.off[b]); hi[1] = __dadd_rn(dc[1], T.off[b + h - 1]);
+      lo[2] = __dadd_rn(dc[2], T.off[c]); hi[2] = __dadd_rn(dc[2], T.off[c + h - 1]);
+      const int cl = classify(lo, hi, R2);
+      if (cl != 0) {
+        if (cl == 1) cnt += h * h * h;
+        i += 1 << (3 * l);
+        break;
+      }
+      --l;
     }
   }
   return cnt;
@@ -112,8 +120,8 @@ __device__ int wave_count(const double dc[3], double R2, int n, int mode, WaveTa
   wave_table(dc, n, T);
   int cnt = 0;
   if (mode == EPS_RECURSIVE && n >= 4) {
-    const int m = n / 4;
-    cnt = count_recursive_block(dc, R2, T, (lane & 3) * m, ((lane >> 2) & 3) * m, (lane >> 4) * m, m);
+    const int m = n / 4, L = __builtin_ctz(m);
+    cnt = count_recursive_block(dc, R2, T, (lane & 3) * m, ((lane >> 2) & 3) * m, (lane >> 4) * m, L);
   } else {
     for (int ab = lane; ab < n * n; ab += 64) {
       const double sab = __dadd_rn(T.sq[0][ab % n], T.sq[1][ab / n]);
