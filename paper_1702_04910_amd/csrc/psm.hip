@@ -123,9 +123,40 @@ __device__ int wave_count(const double dc[3], double R2, int n, int mode, WaveTa
     const int m = n / 4, L = __builtin_ctz(m);
     cnt = count_recursive_block(dc, R2, T, (lane & 3) * m, ((lane >> 2) & 3) * m, (lane >> 4) * m, L);
   } else {
+    // Along z the coordinates dz + o_c increase with c, so their squares fall
+    // on [0, k0) (negative coordinates) and rise on [k0, n), and a column's
+    // inside points form a suffix of the first range and a prefix of the
+    // second: two bisections count them with the exact point tests.
+    const int k0 = __popcll(__ballot(lane < n && __dadd_rn(dc[2], T.off[lane]) < 0.0));
     for (int ab = lane; ab < n * n; ab += 64) {
       const double sab = __dadd_rn(T.sq[0][ab % n], T.sq[1][ab / n]);
-      for (int c = 0; c < n; ++c) cnt += __dadd_rn(sab, T.sq[2][c]) <= R2 ? 1 : 0;
+      int first = k0;  // first inside point of [0, k0)
+      if (k0 > 0 && __dadd_rn(sab, T.sq[2][k0 - 1]) <= R2) {
+        if (__dadd_rn(sab, T.sq[2][0]) <= R2) {
+          first = 0;
+        } else {
+          int l = 0, h = k0 - 1;  // l outside, h inside
+          while (h - l > 1) {
+            const int mid = (l + h) >> 1;
+            if (__dadd_rn(sab, T.sq[2][mid]) <= R2) h = mid; else l = mid;
+          }
+          first = h;
+        }
+      }
+      int last = k0;  // one past the last inside point of [k0, n)
+      if (k0 < n && __dadd_rn(sab, T.sq[2][k0]) <= R2) {
+        if (__dadd_rn(sab, T.sq[2][n - 1]) <= R2) {
+          last = n;
+        } else {
+          int l = k0, h = n - 1;  // l inside, h outside
+          while (h - l > 1) {
+            const int mid = (l + h) >> 1;
+            if (__dadd_rn(sab, T.sq[2][mid]) <= R2) l = mid; else h = mid;
+          }
+          last = l + 1;
+        }
+      }
+      cnt += (k0 - first) + (last - k0);
     }
   }
   for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
