@@ -122,6 +122,44 @@ def batched(torch, lbmps, inputs, steps, warmup, seed):
             "note": "each instance is bitwise equal to the same instance run alone (tests/test_gpu_batch.py)"}
 
 
+def precision_c3(torch, lbmps, inputs, steps, warmup, seed):
+    """Storage precision at full size: one settling sphere D = 48 in a
+    512x512x1024 periodic box (268 M cells), density ratio 1.5, Re 300,
+    MEM-CLI and PSM-M3B2, PDFs stored as FP64, FP32, FP16 or BF16 deviations;
+    sphere velocity and force error of each form against the FP64 run after
+    the same number of sweeps."""
+    import numpy as np
+
+    inp = inputs.c3_precision(seed)
+    N = inp["nx"] * inp["ny"] * inp["nz"]
+    out = {"workload": "settling sphere, 512x512x1024 periodic, D=48, rho_p 1.5, Re 300, n_sub 2",
+           "cells": N, "sweeps": 2 * steps}
+    for coupling in ("mem_cli", "psm"):
+        ref = None
+        for prec in ("fp64", "fp32", "fp16", "bf16"):
+            name = "%s_%s" % (prec, "mem_cli" if coupling == "mem_cli" else "psm_m3b2")
+            log("  c3", name)
+            sim = build_sim(lbmps, inp, coupling, prec)
+            w, ms, n = timed_run(torch, sim, steps, warmup, 2)
+            pf = sim.particles()
+            sim.close()
+            del sim
+            torch.cuda.empty_cache()
+            sb = lbmps.STORAGE_BYTES[lbmps.PRECISION[prec]]
+            ent = {"MLUPS": round(N * 2 * steps / w / 1e6, 1),
+                   "sweep_GBs": round(2 * 19 * sb * N / (ms / 1e3 / n) / 1e9, 1),
+                   "U_p": [float(v) for v in pf["U"][0]]}
+            if ref is None:
+                ref = pf
+            else:
+                ent["velocity_error_vs_fp64"] = float(np.linalg.norm(pf["U"][0] - ref["U"][0]) /
+                                                      np.linalg.norm(ref["U"][0]))
+                ent["force_error_vs_fp64"] = float(np.linalg.norm(pf["F"][0] - ref["F"][0]) /
+                                                   np.linalg.norm(ref["F"][0]))
+            out[name] = ent
+    return out
+
+
 def _overlap_keys(ov):
     import numpy as np
 
@@ -270,6 +308,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 48-instance batched form")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned solid-fraction form")
+    ap.add_argument("--no-c3", action="store_true", help="skip the full-size storage-precision runs")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
@@ -356,6 +395,11 @@ def main():
     if not args.no_batch:
         log("batched form (48 instances)")
         line["batched"] = batched(torch, lbmps, inputs, min(args.steps, 100), min(args.warmup, 10), args.seed)
+
+    if not args.no_c3:
+        log("storage precision at 512x512x1024")
+        line["precision_c3"] = precision_c3(torch, lbmps, inputs, min(args.steps, 200), min(args.warmup, 5),
+                                            args.seed)
 
     if not args.no_learned:
         log("learned solid fraction (512^3, 2000 spheres)")
