@@ -42,6 +42,27 @@ def tuned_shape(inp, precision):
     return {k: best[k] for k in ("tile_rows", "block_threads", "grid_blocks", "sweep_flags")}
 
 
+COUNTERS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "sweep_kernel_c2_fp32_hbm_counters.txt")
+
+
+def measured_traffic(shape):
+    """HBM bytes per sweep launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes (copy-calibrated), or None when the sweep sources or the
+    launch shape differ from the ones the counters were taken on."""
+    from paper_1702_04910_amd.counters import sweep_source_hash
+
+    try:
+        with open(COUNTERS) as f:
+            line = [l for l in f if l.startswith("counters: ")][-1]
+    except (OSError, IndexError):
+        return None
+    c = json.loads(line[len("counters: "):])
+    want = [shape["tile_rows"], shape["block_threads"], shape["grid_blocks"], shape["sweep_flags"]]
+    if c.get("sweep_source") != sweep_source_hash() or c.get("launch_shape") != want:
+        return None
+    return c["traffic_bytes"]
+
+
 def build_sim(lbmps, inp, coupling, precision, psm=(3, 2), eps_n=8, **launch):
     if not launch:
         launch = tuned_shape(inp, precision)
@@ -354,7 +375,7 @@ def main():
                    "cells": N, "sweeps_per_step": n_sub, "rho_p": round(inp["rho"], 4), "Re_target": round(inp["re"], 2),
                    "Ga": round(inp["ga"], 3), "nu": inp["nu"], "seed": args.seed},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(tuned_shape(inp, "fp32")),
                      "kernel": "sweep_kernel<float>", "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_us": round(sweep_s * 1e6, 2), "launches": launches,
                      "launch_shape": tuned_shape(inp, "fp32")},
