@@ -1,0 +1,99 @@
+"""16-bit storage forms (FP16 / BF16 deviations g = f - w_q, collision in
+FP32) against the FP64 oracle.
+
+Tolerance, derived from the arithmetic: starting from a state the storage
+holds exactly, one sweep computes in FP32 (relative error ~1e-7) and rounds
+once to nearest even on store.  So every stored value equals the oracle's
+FP64 result rounded once to the storage type, except where the FP32 and FP64
+values straddle a rounding midpoint: there the two differ by one unit in the
+last place.  Forces come from the same FP32 arithmetic on exact inputs: FP32
+accuracy.  Over k sweeps each store adds at most half a unit, u = 2^-11
+(FP16) or 2^-8 (BF16) of the value; collision damps the non-equilibrium part
+and conserves the rest, so the error stays below 4 k u of the largest
+deviation."""
+import numpy as np
+import pytest
+
+from oracle import mlp as om
+from paper_1702_04910_amd import inputs
+from gpu_util import make_pair, gpu_to_oracle, force_errors, say
+
+pytestmark = pytest.mark.gpu
+
+KINDS = ["fp16", "bf16"]
+UNIT = {"fp16": 2.0 ** -11, "bf16": 2.0 ** -8}
+
+
+def round_store(x, kind):
+    if kind == "fp16":
+        return np.asarray(x, dtype=np.float64).astype(np.float16).astype(np.float64)
+    return om.bf16(x)
+
+
+def ulp_store(x, kind):
+    """Spacing of the storage type at the rounded magnitude of x."""
+    r = np.abs(round_store(x, kind))
+    if kind == "fp16":
+        return np.spacing(r.astype(np.float16)).astype(np.float64)
+    b = r.astype(np.float32).view(np.uint32)
+    nxt = (((b >> 16) + 1) << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+    return nxt - r
+
+
+def _check_rounded_once(go, gg, mask, kind):
+    ref = round_store(go[:, mask], kind)
+    got = gg[:, mask]
+    diff = np.abs(got - ref)
+    ulp = ulp_store(go[:, mask], kind)
+    exact = float(np.mean(got == ref))
+    say("  exact fraction %.5f, max diff / ulp %.2f" % (exact, float((diff / ulp).max())))
+    assert np.all(diff <= ulp)
+    assert exact >= 0.99
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_fluid_sweep_rounds_once(kind):
+    nx, ny, nz = 37, 23, 19
+    g0 = round_store(inputs.random_pdfs((nz, ny, nx), 1e-3, seed=15), kind)
+    say("fluid one sweep", kind)
+    ora, sim = make_pair(nx, ny, nz, 0.07, collision="trt", f_ext=(1e-5, -2e-5, 3e-5), precision=kind, g0=g0)
+    assert np.array_equal(gpu_to_oracle(sim.get_pdfs()), g0)  # the storage holds the start exactly
+    ora.step(1)
+    sim.step(1)
+    _check_rounded_once(ora.get_pdfs(), gpu_to_oracle(sim.get_pdfs()), ora.owner == -1, kind)
+    sim.close()
+
+
+@pytest.mark.parametrize("kind", KINDS)
+@pytest.mark.parametrize("coupling,m,b", [("mem_cli", 1, 1), ("mem_bb", 1, 1), ("psm", 3, 2), ("psm", 1, 1)])
+def test_coupled_sweep_rounds_once(kind, coupling, m, b):
+    c = inputs.c1_plain(1)
+    parts = dict(X=[c["X"]], U=[[1e-3, -2e-3, 5e-4]], Om=[[1e-4, 0, -2e-4]], D=[c["D"]], rho=[1.5], fixed=[True])
+    shape = (c["nz"], c["ny"], c["nx"])
+    g0 = round_store(inputs.random_pdfs(shape, 1e-4, seed=16), kind)
+    say("coupled one sweep", kind, coupling, m, b)
+    ora, sim = make_pair(c["nx"], c["ny"], c["nz"], 0.05, coupling=coupling, collision="trt", psm_m=m, psm_b=b,
+                         f_ext=c["f_ext"], precision=kind, eps_n=8, parts=parts, g0=g0, n_sub=1)
+    ora.step(1)
+    sim.step(1)
+    _check_rounded_once(ora.get_pdfs(), gpu_to_oracle(sim.get_pdfs()), ora.owner == -1, kind)
+    (eF, eT, nF), = force_errors(ora, sim)[0]
+    say("  e_F %.2e e_T %.2e" % (eF, eT))
+    assert eF < 1e-5 and eT < 1e-5
+    sim.close()
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_error_growth_bounded_over_sweeps(kind):
+    nx, ny, nz = 40, 24, 20
+    k = 20
+    g0 = round_store(inputs.random_pdfs((nz, ny, nx), 1e-3, seed=17), kind)
+    ora, sim = make_pair(nx, ny, nz, 0.05, collision="trt", f_ext=(2e-5, 0, 0), precision=kind, g0=g0)
+    ora.step(k)
+    sim.step(k)
+    go = ora.get_pdfs()
+    gg = gpu_to_oracle(sim.get_pdfs())
+    e = np.abs(gg - go).max() / np.abs(go).max()
+    say("  %s after %d sweeps: e_f = %.3e (bound %.3e)" % (kind, k, e, 4 * k * UNIT[kind]))
+    assert e <= 4 * k * UNIT[kind]
+    sim.close()
