@@ -6,7 +6,10 @@ holds exactly, one sweep computes in FP32 (relative error ~1e-7) and rounds
 once to nearest even on store.  So every stored value equals the oracle's
 FP64 result rounded once to the storage type, except where the FP32 and FP64
 values straddle a rounding midpoint: there the two differ by one unit in the
-last place.  Forces come from the same FP32 arithmetic on exact inputs: FP32
+last place (plus the FP32 absolute error, ~2^-20 of the largest deviation,
+where cancellation leaves a result far below its inputs: BF16 resolves such
+tiny values, FP16 flushes them into its subnormal spacing).  Forces come from
+the same FP32 arithmetic on exact inputs: FP32
 accuracy.  Over k sweeps each store adds at most half a unit, u = 2^-11
 (FP16) or 2^-8 (BF16) of the value; collision damps the non-equilibrium part
 and conserves the rest, so the error stays below 4 k u of the largest
@@ -44,10 +47,10 @@ def _check_rounded_once(go, gg, mask, kind):
     ref = round_store(go[:, mask], kind)
     got = gg[:, mask]
     diff = np.abs(got - ref)
-    ulp = ulp_store(go[:, mask], kind)
+    tol = ulp_store(go[:, mask], kind) + 2.0 ** -20 * np.abs(go[:, mask]).max()
     exact = float(np.mean(got == ref))
-    say("  exact fraction %.5f, max diff / ulp %.2f" % (exact, float((diff / ulp).max())))
-    assert np.all(diff <= ulp)
+    say("  exact fraction %.5f, max diff / tolerance %.2f" % (exact, float((diff / tol).max())))
+    assert np.all(diff <= tol)
     assert exact >= 0.99
 
 
