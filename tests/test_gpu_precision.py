@@ -10,7 +10,10 @@ last place (plus the FP32 absolute error, ~2^-20 of the largest deviation,
 where cancellation leaves a result far below its inputs: BF16 resolves such
 tiny values, FP16 flushes them into its subnormal spacing).  Forces come from
 the same FP32 arithmetic on exact inputs: FP32
-accuracy.  Over k sweeps each store adds at most half a unit, u = 2^-11
+accuracy for PSM.  MEM link forces use post-collision values that the push
+sweep has already stored, i.e. rounded: each link term may carry up to
+4 u |g| (the CLI rule combines three stored values), so the bound adds
+4 sqrt(2) u n_links max|g| / |F| to the FP32 tolerance.  Over k sweeps each store adds at most half a unit, u = 2^-11
 (FP16) or 2^-8 (BF16) of the value; collision damps the non-equilibrium part
 and conserves the rest, so the error stays below 4 k u of the largest
 deviation."""
@@ -81,8 +84,12 @@ def test_coupled_sweep_rounds_once(kind, coupling, m, b):
     sim.step(1)
     _check_rounded_once(ora.get_pdfs(), gpu_to_oracle(sim.get_pdfs()), ora.owner == -1, kind)
     (eF, eT, nF), = force_errors(ora, sim)[0]
-    say("  e_F %.2e e_T %.2e" % (eF, eT))
-    assert eF < 1e-5 and eT < 1e-5
+    bound = 1e-5
+    if coupling.startswith("mem"):
+        gmax = max(np.abs(g0).max(), np.abs(ora.get_pdfs()).max())
+        bound += 4 * np.sqrt(2.0) * UNIT[kind] * len(ora.links["q"]) * gmax / nF
+    say("  e_F %.2e e_T %.2e (bound %.2e)" % (eF, eT, bound))
+    assert eF < bound and eT < 1.5 * bound
     sim.close()
 
 
