@@ -56,7 +56,11 @@ def main(argv=None):
 
     ap = argparse.ArgumentParser()
     ap.add_argument("--shape", default=None, help="tile_rows,block_threads,grid_blocks,sweep_flags")
+    ap.add_argument("--workload", default="primary", choices=("primary", "spheres"),
+                    help="spheres: 2000 moving spheres in 512^3, PSM-M3B2, flat 8^3 solid fractions")
     args = ap.parse_args(argv)
+    if args.workload == "spheres":
+        return spheres(args)
     inp = inputs.c2_scale(0)
     keys = ("tile_rows", "block_threads", "grid_blocks", "sweep_flags")
     if args.shape:
@@ -76,6 +80,31 @@ def main(argv=None):
     sim.close()
     print("counters workload done: copy %d B x5, %d sweeps of %dx%dx%d, shape %s, sweep source %s"
           % (COPY_BYTES, SWEEPS, inp["nx"], inp["ny"], inp["nz"], shape, sweep_source_hash()), flush=True)
+    return 0
+
+
+def spheres(args):
+    """The learned-solid-fraction workload with exact (flat 8^3) solid
+    fractions: 4 sweeps after 2 warm-up sweeps (PSM collide, overlap rebuilds)."""
+    from . import inputs, lbmps
+
+    wl = inputs.c5_learned(0)
+    L, n = wl["nx"], len(wl["D"])
+    keys = ("tile_rows", "block_threads", "grid_blocks", "sweep_flags")
+    shape = dict(zip(keys, (int(v) for v in (args.shape or "1,256,0,1").split(","))))
+    cfg = lbmps.make_config(L, L, L, wl["nu"], collision="trt", coupling="psm", psm_m=3, psm_b=2, n_sub=2, eps_n=8,
+                            eps_mode=lbmps.EPS_FLAT, precision="fp32", max_particles=n, max_diameter=20.0,
+                            f_ext=wl["f_ext"], gravity=wl["gravity"], **shape)
+    sim = lbmps.Sim(cfg)
+    sim.init_equilibrium()
+    z = [[0.0, 0.0, 0.0]] * n
+    sim.set_particles(wl["X"], z, z, wl["D"], [wl["rho"]] * n, [False] * n)
+    sim.step(2)
+    sim.step(4)
+    sim.sync()
+    sim.close()
+    print("counters workload done: %d spheres in %d^3, PSM-M3B2 flat 8^3, 6 sweeps, shape %s" % (n, L, shape),
+          flush=True)
     return 0
 
 

@@ -8,34 +8,62 @@
 namespace lbm {
 
 // ------------------------------------------------------------------------ scan
-// One workgroup of 1024 threads; thread t scans a contiguous chunk, so the
-// result is independent of scheduling.
+// One workgroup of 1024 threads walks the array in tiles of 8192 entries:
+// a coalesced load into LDS, a scan of 8 consecutive entries per thread, a
+// wave-shuffle scan of the thread sums and a 16-entry scan of the wave sums,
+// then a coalesced store.  Integer sums: the result is exact and independent
+// of scheduling.
+constexpr int SCAN_TILE = 8192;
+
 __global__ __launch_bounds__(1024) void scan_kernel(const int* __restrict__ totals, int* __restrict__ offsets, int m,
                                                     int side, int nlist, int* __restrict__ begin,
                                                     int* __restrict__ end, int* __restrict__ count, int cap,
                                                     unsigned* err, unsigned err_bit) {
-  __shared__ long long part[1024];
-  const int t = threadIdx.x;
-  const int chunk = (m + 1023) / 1024;
-  const int a = min(m, t * chunk), b = min(m, a + chunk);
-  long long s = 0;
-  for (int i = a; i < b; ++i) s += totals[i];
-  part[t] = s;
-  __syncthreads();
-  // Hillis-Steele inclusive scan of the 1024 chunk sums
-  for (int off = 1; off < 1024; off <<= 1) {
-    long long v = t >= off ? part[t - off] : 0;
+  __shared__ int tile[SCAN_TILE];
+  __shared__ long long wsum[16];
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  long long carry = 0;
+  for (int base = 0; base < m; base += SCAN_TILE) {
+    const int n = min(SCAN_TILE, m - base);
+    for (int i = t; i < SCAN_TILE; i += 1024) tile[i] = i < n ? totals[base + i] : 0;
     __syncthreads();
-    part[t] += v;
+    int v[8];
+    long long s = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      v[k] = tile[8 * t + k];
+      s += v[k];
+    }
+    long long x = s;  // inclusive scan over the wave
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const long long y = __shfl_up(x, off, 64);
+      if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    if (w == 0) {
+      long long z = lane < 16 ? wsum[lane] : 0;
+#pragma unroll
+      for (int off = 1; off < 16; off <<= 1) {
+        const long long y = __shfl_up(z, off, 64);
+        if (lane >= off) z += y;
+      }
+      if (lane < 16) wsum[lane] = z;
+    }
+    __syncthreads();
+    long long run = carry + (x - s) + (w > 0 ? wsum[w - 1] : 0);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      tile[8 * t + k] = (int)run;
+      run += v[k];
+    }
+    carry += wsum[15];
+    __syncthreads();
+    for (int i = t; i < n; i += 1024) offsets[base + i] = tile[i];
     __syncthreads();
   }
-  long long run = part[t] - s;
-  for (int i = a; i < b; ++i) {
-    offsets[i] = (int)run;
-    run += totals[i];
-  }
-  __syncthreads();
-  const long long total = part[1023];
+  const long long total = carry;
   if (t == 0) {
     *count = (int)(total < cap ? total : cap);
     if (total > cap) atomicOr(err, err_bit);
@@ -60,7 +88,7 @@ hipError_t launch_scan(const int* totals, int* offsets, int m, int side, int nli
 // Workgroup j sums the 6-double records [base + begin[j], base + end[j]) in a
 // fixed order: strided per-thread partial sums, a butterfly over the 64 lanes of
 // each wave, then the waves in order.  The result is added to Facc/Tacc.
-constexpr int RED_THREADS = 1024;
+constexpr int RED_THREADS = 256;  // fixed: the summation order must not depend on the particle count
 __global__ __launch_bounds__(RED_THREADS) void reduce_kernel(const int* __restrict__ list, const int* __restrict__ begin,
                                                      const int* __restrict__ end, int base,
                                                      const double* __restrict__ out, PartDev parts) {
