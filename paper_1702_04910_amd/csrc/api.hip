@@ -513,6 +513,7 @@ lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* ws, s
     b = w + L.o_links + align_up(nl * 20);
     c->links.delta = (double*)b; b += nl * 8;
     c->links.out = (double*)b;
+    c->links.ostride = (long long)nl;
   }
   c->wall_v = (double*)(w + L.o_wallv);
   {
@@ -525,6 +526,7 @@ lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* ws, s
     c->pairs.eps = (double*)b; b += np * 8;
     c->pairs.B = (double*)b; b += np * 8;
     c->pairs.out = (double*)b;
+    c->pairs.ostride = (long long)np;
   }
   c->rcell = (int*)(w + L.o_refill);
   c->rpart = c->rcell + L.refill_cap;
@@ -828,13 +830,15 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
     if (c->n_psm) {
       HIPCHK(c, launch_psm_collide(L.prec, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap, src,
                                    dst, c->st));
-      HIPCHK(c, launch_reduce(psm_list(c), c->n_psm, c->pbeg, c->pend, 0, c->pairs.out, c->parts, c->st));
+      HIPCHK(c, launch_reduce(psm_list(c), c->n_psm, c->pbeg, c->pend, 0, c->pairs.out, c->pairs.ostride, c->parts,
+                              c->st));
     }
     if (c->n_mem || c->n_wall) {
       HIPCHK(c, launch_links_bc(L.prec, c->n_wall, c->counts + 0, L.link_cap, c->links, c->wall_v, c->inst_d, c->parts,
                                 dst, c->st));
       if (c->n_mem)
-        HIPCHK(c, launch_reduce(mem_list(c), c->n_mem, c->lbeg, c->lend, c->n_wall, c->links.out, c->parts, c->st));
+        HIPCHK(c, launch_reduce(mem_list(c), c->n_mem, c->lbeg, c->lend, c->n_wall, c->links.out, c->links.ostride,
+                                c->parts, c->st));
     }
     c->cur = 1 - c->cur;
     c->sweeps++;

@@ -93,14 +93,17 @@ struct PartDev {
 struct LinkDev {
   int *cell, *q, *p, *inst, *cli_ok;  // p >= 0 particle, p <= -2 wall group
   double *delta;
-  double *out;                         // 6 per link: F^q (dev. part), (x_b - X_p) x F^q
+  double *out;                         // 6 components per link, component k at out[k * ostride + link]:
+                                       // F^q (deviation part), (x_b - X_p) x F^q
+  long long ostride;
 };
 
 // PSM (cell, particle) overlap pairs.
 struct PairDev {
   int *cell, *p, *next;
   double *eps, *B;
-  double *out;  // 6 per pair
+  double *out;  // 6 components per pair, component k at out[k * ostride + pair]
+  long long ostride;
 };
 
 // Inputs of the solid-fraction network for a cell whose centre lies at d from

@@ -25,7 +25,7 @@ hipError_t launch_scan(const int* totals, int* offsets, int m, int side, int nli
                        int cap, unsigned* err, unsigned err_bit, hipStream_t st);
 // Per-particle sum of 6-double records [begin[j], end[j]) (+ base) into Facc/Tacc of particle list[j].
 hipError_t launch_reduce(const int* list, int nlist, const int* begin, const int* end, int base, const double* out,
-                         PartDev parts, hipStream_t st);
+                         long long ostride, PartDev parts, hipStream_t st);
 // Explicit Euler rigid-body step of the listed particles (averaging Facc over n_sub sweeps).
 hipError_t launch_rigid(const int* list, int nlist, const InstDev* insts, PartDev parts, unsigned* err,
                         hipStream_t st);

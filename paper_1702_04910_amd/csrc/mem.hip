@@ -418,13 +418,14 @@ __global__ void links_bc_kernel(int n_wall, const int* __restrict__ count, int c
       const double vs = (double)Codec<S>::ld(sv);
       double F[3];
       for (int k = 0; k < 3; ++k) F[k] = (c[k] - v[k]) * gtq + (c[k] + v[k]) * vs;
-      double* o = L.out + 6LL * i;
+      double* o = L.out + i;
+      const long long s = L.ostride;
       o[0] = F[0];
-      o[1] = F[1];
-      o[2] = F[2];
-      o[3] = arm[1] * F[2] - arm[2] * F[1];
-      o[4] = arm[2] * F[0] - arm[0] * F[2];
-      o[5] = arm[0] * F[1] - arm[1] * F[0];
+      o[s] = F[1];
+      o[2 * s] = F[2];
+      o[3 * s] = arm[1] * F[2] - arm[2] * F[1];
+      o[4 * s] = arm[2] * F[0] - arm[0] * F[2];
+      o[5 * s] = arm[0] * F[1] - arm[1] * F[0];
     }
   }
 }

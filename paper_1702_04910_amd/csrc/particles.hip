@@ -85,20 +85,23 @@ hipError_t launch_scan(const int* totals, int* offsets, int m, int side, int nli
 }
 
 // ------------------------------------------------------------------------ reduction
-// Workgroup j sums the 6-double records [base + begin[j], base + end[j]) in a
+// Workgroup j sums the records [base + begin[j], base + end[j]) (6 components,
+// component k of record i at out[k * ostride + i]) in a
 // fixed order: strided per-thread partial sums, a butterfly over the 64 lanes of
 // each wave, then the waves in order.  The result is added to Facc/Tacc.
 constexpr int RED_THREADS = 256;  // fixed: the summation order must not depend on the particle count
 __global__ __launch_bounds__(RED_THREADS) void reduce_kernel(const int* __restrict__ list, const int* __restrict__ begin,
                                                      const int* __restrict__ end, int base,
-                                                     const double* __restrict__ out, PartDev parts) {
+                                                     const double* __restrict__ out, long long ostride,
+                                                     PartDev parts) {
   const int j = blockIdx.x;
   const int p = list[j];
   const int b = base + begin[j], e = base + end[j];
   double acc[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll 4
   for (int i = b + (int)threadIdx.x; i < e; i += blockDim.x) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) acc[k] += out[6LL * i + k];
+    for (int k = 0; k < 6; ++k) acc[k] += out[k * ostride + i];
   }
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
@@ -126,9 +129,10 @@ __global__ __launch_bounds__(RED_THREADS) void reduce_kernel(const int* __restri
 }
 
 hipError_t launch_reduce(const int* list, int nlist, const int* begin, const int* end, int base, const double* out,
-                         PartDev parts, hipStream_t st) {
+                         long long ostride, PartDev parts, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_kernel, dim3(nlist), dim3(RED_THREADS), 0, st, list, begin, end, base, out, parts);
+  hipLaunchKernelGGL(reduce_kernel, dim3(nlist), dim3(RED_THREADS), 0, st, list, begin, end, base, out, ostride,
+                     parts);
   return hipGetLastError();
 }
 

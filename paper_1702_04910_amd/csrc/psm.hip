@@ -609,13 +609,14 @@ __global__ __launch_bounds__(256) void psm_collide_kernel(const int* __restrict_
       }
       // F_s = B_s sum_q Omega_q c_qbar, T_s = (x_s - X_p) x F_s
       const double Fx = Bs[m] * (double)mx, Fy = Bs[m] * (double)my, Fz = Bs[m] * (double)mz;
-      double* o = pairs.out + 6LL * mem[m];
+      double* o = pairs.out + mem[m];
+      const long long s = pairs.ostride;
       o[0] = Fx;
-      o[1] = Fy;
-      o[2] = Fz;
-      o[3] = r[1] * Fz - r[2] * Fy;
-      o[4] = r[2] * Fx - r[0] * Fz;
-      o[5] = r[0] * Fy - r[1] * Fx;
+      o[s] = Fy;
+      o[2 * s] = Fz;
+      o[3 * s] = r[1] * Fz - r[2] * Fy;
+      o[4 * s] = r[2] * Fx - r[0] * Fz;
+      o[5 * s] = r[0] * Fy - r[1] * Fx;
     }
     const R omB = (R)(1.0 - Bsum);
     // fluid operator and forcing, then Eq. LBM_Collide_PSM
