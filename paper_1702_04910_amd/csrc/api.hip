@@ -78,7 +78,10 @@ bool valid_cfg(const lbmps_config& c, std::string& err) {
   if (c.eps_mode == LBMPS_EPS_RECURSIVE && (en & (en - 1))) { err = "recursive supersampling needs eps_n = 2^k"; return false; }
   if (c.eps_mode < 0 || c.eps_mode > 2) { err = "unknown eps_mode"; return false; }
   if (c.block_threads < 0 || c.block_threads > 256 || (c.block_threads % 64)) { err = "block_threads must be a multiple of 64, <= 256"; return false; }
-  if (c.sweep_flags & ~1) { err = "unknown sweep_flags bits"; return false; }
+  if (c.sweep_flags & ~SWEEP_FLAGS_ALL) { err = "unknown sweep_flags bits"; return false; }
+  if ((c.sweep_flags & SWEEP_PSM_FUSED) && (c.sweep_flags & SWEEP_PSM_SEPARATE)) {
+    err = "sweep_flags: PSM fused and separate are exclusive"; return false;
+  }
   if (c.n_sub < 0) { err = "n_sub must be >= 0"; return false; }
   if (10LL * (long long)storage_size(c.precision) * c.nx > SWEEP_LDS_LIMIT) {
     err = "nx too large for the LDS-staged sweep (10 * nx * element size must be <= 64 KiB)"; return false;
@@ -245,6 +248,7 @@ struct lbmps_ctx {
   bool mlp_set = false;
   double mlp_rmin = 0.0, mlp_rmax = -1.0;
   bool psm_exact = true;           // some PSM cut cell needs supersampling
+  bool psm_fused = false;          // PSM cells collided inside the sweep
   std::vector<double> diam_h;      // per global particle
   double* scratch = nullptr;
   long long sweeps = 0;
@@ -300,19 +304,29 @@ int nsplit_for(int nlist, int side) {
 int* mem_list(lbmps_ctx* c) { return c->plist_d; }
 
 // Whether any current PSM particle needs supersampled cut cells (an exact
-// estimator, or the learned one outside its radius range).
+// estimator, or the learned one outside its radius range), and whether PSM
+// cells are collided inside the sweep: forced by sweep_flags, else when the
+// spheres' volumes (radius + 1) exceed 2 % of the PSM instances' cells (the
+// separate kernel reads sparse rows at several times their useful bytes; the
+// inline variant reads one cell-map entry per cell and holds more registers).
 void update_psm_exact(lbmps_ctx* c) {
   c->psm_exact = false;
+  double vol = 0.0, cells = 0.0;
   for (int k = 0; k < c->L.n; ++k) {
     if (c->cfg[k].coupling != LBMPS_PSM) continue;
+    cells += (double)c->L.ncell[k];
     const int b = c->L.part_begin[k];
     for (int i = 0; i < c->n_active[k]; ++i) {
       const double R = 0.5 * c->diam_h[b + i];
+      vol += 4.0 / 3.0 * M_PI * (R + 1.0) * (R + 1.0) * (R + 1.0);
       if (c->cfg[k].eps_mode != LBMPS_EPS_LEARNED || !c->mlp_set || R < c->mlp_rmin || R > c->mlp_rmax)
         c->psm_exact = true;
     }
   }
+  const int fl = c->cfg[0].sweep_flags;
+  c->psm_fused = (fl & SWEEP_PSM_FUSED) ? true : (fl & SWEEP_PSM_SEPARATE) ? false : (cells > 0 && vol > 0.02 * cells);
 }
+
 int* psm_list(lbmps_ctx* c) { return c->plist_d + c->n_mem; }
 
 // Rebuild links of every MEM particle (after mapping); refill first when `refill`.
@@ -821,15 +835,17 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
       }
       HIPCHK(c, hipEventRecord(c->ev[c->ev_used], c->st));
     }
+    const bool fused = c->n_psm && c->psm_fused;
     HIPCHK(c, launch_sweep(L.prec, c->inst_d, c->tiles_d, c->ntiles, c->grid, c->block, L.max_tile_cells,
-                           c->cfg[0].sweep_flags, src, dst, c->st));
+                           c->cfg[0].sweep_flags, src, dst, fused ? c->cellmap : nullptr, c->pairs, c->parts, c->st));
     if (c->timing) {
       HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->st));
       c->ev_used += 2;
     }
     if (c->n_psm) {
-      HIPCHK(c, launch_psm_collide(L.prec, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap, src,
-                                   dst, c->st));
+      if (!fused)
+        HIPCHK(c, launch_psm_collide(L.prec, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap,
+                                     src, dst, c->st));
       HIPCHK(c, launch_reduce(psm_list(c), c->n_psm, c->pbeg, c->pend, 0, c->pairs.out, c->pairs.ostride, c->parts,
                               c->st));
     }
@@ -863,11 +879,14 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
 lbmps_status lbmps_set_launch(lbmps_ctx* c, int32_t block_threads, int32_t grid_blocks, int32_t sweep_flags) {
   if (!c) return LBMPS_EINVAL;
   if (block_threads < 0 || block_threads > 256 || (block_threads % 64)) return fail(c, LBMPS_EINVAL, "bad block size");
-  if (grid_blocks < 0 || (sweep_flags & ~1)) return fail(c, LBMPS_EINVAL, "bad grid or flags");
+  if (grid_blocks < 0 || (sweep_flags & ~SWEEP_FLAGS_ALL) ||
+      ((sweep_flags & SWEEP_PSM_FUSED) && (sweep_flags & SWEEP_PSM_SEPARATE)))
+    return fail(c, LBMPS_EINVAL, "bad grid or flags");
   drop_graph(c);
   c->block = block_threads ? block_threads : 256;
   c->grid = grid_blocks > 0 ? std::min(grid_blocks, c->ntiles) : c->ntiles;
   for (auto& cf : c->cfg) cf.sweep_flags = sweep_flags;
+  update_psm_exact(c);
   return LBMPS_OK;
 }
 

@@ -7,9 +7,13 @@
 namespace lbm {
 
 // ---- sweep.hip
-enum { SWEEP_NT_LOADS = 1 };
+// sweep_flags: bit 0 non-temporal loads; bit 1 collide PSM cells inside the
+// sweep; bit 2 collide them in the separate overlap kernel (neither: chosen
+// from the overlapped share of the cells).  Results never depend on them.
+enum { SWEEP_NT_LOADS = 1, SWEEP_PSM_FUSED = 2, SWEEP_PSM_SEPARATE = 4, SWEEP_FLAGS_ALL = 7 };
 hipError_t launch_sweep(int prec, const InstDev* insts, const int4* tiles, int ntiles, int grid, int block,
-                        int max_tile_cells, int flags, const void* src, void* dst, hipStream_t st);
+                        int max_tile_cells, int flags, const void* src, void* dst, const int* cellmap, PairDev pairs,
+                        PartDev parts, hipStream_t st);
 constexpr int SWEEP_LDS_LIMIT = 64 * 1024;  // bytes of LDS staging per sweep workgroup
 hipError_t launch_init_eq(int prec, void* buf, long long N, double rho, const double u[3], hipStream_t st);
 hipError_t launch_to_f64(int prec, const void* a, int q, long long c0, double* b, long long n, hipStream_t st);

@@ -4,12 +4,17 @@
 // One sweep reads the canonical PDFs f(x, t) of every cell from buffer `src`
 // (aligned, coalesced along x), collides them with BGK or TRT plus the body
 // force, and pushes f~_q(x, t) to x + c_q in buffer `dst` (periodic wrap).
-// The sweep knows nothing about particles: coupling is applied afterwards by
-// the link kernel (MEM) and the overlap kernel (PSM), which overwrite the few
-// affected values.  Each workgroup owns whole x-rows and realigns the +-x
+// MEM coupling is applied afterwards by the link kernel, which overwrites the
+// few affected values.  PSM cells are either collided here (the variant that
+// reads the cell map and applies the partially saturated collision to
+// overlapped cells inline) or re-collided afterwards by the overlap kernel;
+// both use the same per-cell function.  Each workgroup owns whole x-rows and realigns the +-x
 // shifted values through LDS, so all stores are aligned row segments.
+#include <climits>
+
 #include "common.h"
 #include "kernels.h"
+#include "psm_cell.h"
 
 namespace lbm {
 
@@ -113,9 +118,10 @@ __device__ __forceinline__ __bf16 ld_nt<__bf16>(const __bf16* p) {
   return __builtin_bit_cast(__bf16, __builtin_nontemporal_load((const unsigned short*)p));
 }
 
-template <typename S, bool NTLD>
+template <typename S, bool NTLD, bool PSM>
 __global__ __launch_bounds__(256) void sweep_kernel(const InstDev* __restrict__ insts, const int4* __restrict__ tiles,
-                                                    int ntiles, const S* __restrict__ src, S* __restrict__ dst) {
+                                                    int ntiles, const S* __restrict__ src, S* __restrict__ dst,
+                                                    const int* __restrict__ cellmap, PairDev pairs, PartDev P) {
   using R = typename CompOf<S>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   S* sh = reinterpret_cast<S*>(smem_raw);
@@ -142,7 +148,13 @@ __global__ __launch_bounds__(256) void sweep_kernel(const InstDev* __restrict__ 
         const S* a = &s[pdf_at(idx, q)];
         g[q] = Codec<S>::ld(NTLD ? ld_nt(a) : *a);
       }
-      collide_cell<R>(g, o, lp, lm, fx, fy, fz);
+      if constexpr (PSM) {
+        const int L = I.cellmap_off >= 0 ? cellmap[I.cellmap_off + idx] : INT_MAX;
+        if (L != INT_MAX) psm_cell_collide<R>(g, o, I, P, pairs, L, idx);
+        else collide_cell<R>(g, o, lp, lm, fx, fy, fz);
+      } else {
+        collide_cell<R>(g, o, lp, lm, fx, fy, fz);
+      }
       const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
       const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
       const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
@@ -246,26 +258,45 @@ __global__ void fields_kernel(const S* __restrict__ buf, long long N, long long 
 }
 
 // ------------------------------------------------------------------------ launchers
-template <typename S>
-hipError_t launch_sweep_t(const InstDev* insts, const int4* tiles, int ntiles, int grid, int block, int max_tile_cells,
-                          int flags, const void* src, void* dst, hipStream_t st) {
-  const size_t lds = (size_t)NXSHIFT * max_tile_cells * sizeof(S);
-  if (flags & SWEEP_NT_LOADS)
-    hipLaunchKernelGGL((sweep_kernel<S, true>), dim3(grid), dim3(block), lds, st, insts, tiles, ntiles, (const S*)src,
-                       (S*)dst);
+template <typename S, bool NTLD>
+hipError_t launch_sweep_n(const InstDev* insts, const int4* tiles, int ntiles, int grid, int block, size_t lds,
+                          const void* src, void* dst, const int* cellmap, PairDev pairs, PartDev parts,
+                          hipStream_t st) {
+  if (cellmap)
+    hipLaunchKernelGGL((sweep_kernel<S, NTLD, true>), dim3(grid), dim3(block), lds, st, insts, tiles, ntiles,
+                       (const S*)src, (S*)dst, cellmap, pairs, parts);
   else
-    hipLaunchKernelGGL((sweep_kernel<S, false>), dim3(grid), dim3(block), lds, st, insts, tiles, ntiles, (const S*)src,
-                       (S*)dst);
+    hipLaunchKernelGGL((sweep_kernel<S, NTLD, false>), dim3(grid), dim3(block), lds, st, insts, tiles, ntiles,
+                       (const S*)src, (S*)dst, cellmap, pairs, parts);
   return hipGetLastError();
 }
 
+template <typename S>
+hipError_t launch_sweep_t(const InstDev* insts, const int4* tiles, int ntiles, int grid, int block, int max_tile_cells,
+                          int flags, const void* src, void* dst, const int* cellmap, PairDev pairs, PartDev parts,
+                          hipStream_t st) {
+  const size_t lds = (size_t)NXSHIFT * max_tile_cells * sizeof(S);
+  if (flags & SWEEP_NT_LOADS)
+    return launch_sweep_n<S, true>(insts, tiles, ntiles, grid, block, lds, src, dst, cellmap, pairs, parts, st);
+  return launch_sweep_n<S, false>(insts, tiles, ntiles, grid, block, lds, src, dst, cellmap, pairs, parts, st);
+}
+
 hipError_t launch_sweep(int prec, const InstDev* insts, const int4* tiles, int ntiles, int grid, int block,
-                        int max_tile_cells, int flags, const void* src, void* dst, hipStream_t st) {
+                        int max_tile_cells, int flags, const void* src, void* dst, const int* cellmap, PairDev pairs,
+                        PartDev parts, hipStream_t st) {
   switch (prec) {
-    case PREC_FP64: return launch_sweep_t<double>(insts, tiles, ntiles, grid, block, max_tile_cells, flags, src, dst, st);
-    case PREC_FP32: return launch_sweep_t<float>(insts, tiles, ntiles, grid, block, max_tile_cells, flags, src, dst, st);
-    case PREC_FP16: return launch_sweep_t<_Float16>(insts, tiles, ntiles, grid, block, max_tile_cells, flags, src, dst, st);
-    case PREC_BF16: return launch_sweep_t<__bf16>(insts, tiles, ntiles, grid, block, max_tile_cells, flags, src, dst, st);
+    case PREC_FP64:
+      return launch_sweep_t<double>(insts, tiles, ntiles, grid, block, max_tile_cells, flags, src, dst, cellmap, pairs,
+                                    parts, st);
+    case PREC_FP32:
+      return launch_sweep_t<float>(insts, tiles, ntiles, grid, block, max_tile_cells, flags, src, dst, cellmap, pairs,
+                                   parts, st);
+    case PREC_FP16:
+      return launch_sweep_t<_Float16>(insts, tiles, ntiles, grid, block, max_tile_cells, flags, src, dst, cellmap,
+                                      pairs, parts, st);
+    case PREC_BF16:
+      return launch_sweep_t<__bf16>(insts, tiles, ntiles, grid, block, max_tile_cells, flags, src, dst, cellmap,
+                                    pairs, parts, st);
   }
   return hipErrorInvalidValue;
 }

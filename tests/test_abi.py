@@ -49,6 +49,9 @@ def test_workspace_bytes_valid_and_invalid():
         lbmps.make_config(32, 32, 64, 0.1, eps_n=6, eps_mode=lbmps.EPS_RECURSIVE),
         lbmps.make_config(32, 32, 64, 0.1, block_threads=100),
         lbmps.make_config(32, 32, 64, 0.1, coupling="psm", n_sub=-1),
+        lbmps.make_config(32, 32, 64, 0.1, sweep_flags=8),
+        lbmps.make_config(32, 32, 64, 0.1, sweep_flags=lbmps.SWEEP_PSM_FUSED | lbmps.SWEEP_PSM_SEPARATE),
+        lbmps.make_config(32, 32, 64, 0.1, eps_mode=3),
     ]
     for b in bad:
         assert lbmps.workspace_bytes(b) == 0
@@ -70,3 +73,21 @@ def test_create_rejects_small_workspace():
     st = L.lbmps_create(ctypes.addressof(cfg), None, 0, None, ctypes.byref(ctx))
     assert st == -2 and not ctx.value
     assert L.lbmps_status_string(-4) == b"numerical instability"
+
+
+def test_trainer_workspace_and_create_checks():
+    L = lbmps.lib()
+    assert L.lbmps_mlp_workspace_bytes(0) == 0
+    n1, n2 = L.lbmps_mlp_workspace_bytes(1000), L.lbmps_mlp_workspace_bytes(2000)
+    assert 0 < n1 < n2
+    m = ctypes.c_void_p()
+    assert L.lbmps_mlp_create(1000, None, 0, None, ctypes.byref(m)) == -2 and not m.value
+    assert L.lbmps_mlp_create(0, None, 0, None, ctypes.byref(m)) == -1
+    assert lbmps.MLP_NPARAM == 8 * 64 + 64 + 64 * 64 + 64 + 64 + 1
+
+
+def test_learned_mode_workspace():
+    base = lbmps.make_config(64, 64, 64, 0.05, coupling="psm", max_particles=10, max_diameter=16.0, eps_n=16)
+    learned = lbmps.make_config(64, 64, 64, 0.05, coupling="psm", max_particles=10, max_diameter=16.0, eps_n=16,
+                                eps_mode=lbmps.EPS_LEARNED)
+    assert lbmps.workspace_bytes(learned) > lbmps.workspace_bytes(base) > 0

@@ -9,11 +9,12 @@ from gpu_util import say
 pytestmark = pytest.mark.gpu
 
 
-def _cfg(d, dmax, tile_cells=256, grid=0, precision="fp32"):
+def _cfg(d, dmax, tile_cells=256, grid=0, precision="fp32", flags=0):
     return lbmps.make_config(d["nx"], d["ny"], d["nz"], d["nu"], collision="trt", coupling=d["coupling"],
                              psm_m=d["psm_m"], psm_b=d["psm_b"], n_sub=2, eps_n=8, eps_mode=lbmps.EPS_RECURSIVE,
                              precision=precision, max_particles=1, max_diameter=dmax, f_ext=d["f_ext"],
-                             gravity=d["gravity"], tile_rows=max(1, tile_cells // d["nx"]), grid_blocks=grid)
+                             gravity=d["gravity"], tile_rows=max(1, tile_cells // d["nx"]), grid_blocks=grid,
+                             sweep_flags=flags)
 
 
 def _setup(sim, i, d):
@@ -32,11 +33,12 @@ def _small_batch(seed=3):
     return out
 
 
-def test_batched_instances_equal_solo_runs_bitwise():
+@pytest.mark.parametrize("flags", [0, lbmps.SWEEP_PSM_FUSED])
+def test_batched_instances_equal_solo_runs_bitwise(flags):
     insts = _small_batch()
     dmax = max(d["D"] for d in insts)
-    say("batch of", len(insts))
-    batch = lbmps.Sim([_cfg(d, dmax, grid=512) for d in insts])
+    say("batch of", len(insts), "flags", flags)
+    batch = lbmps.Sim([_cfg(d, dmax, grid=512, flags=flags) for d in insts])
     for i, d in enumerate(insts):
         _setup(batch, i, d)
     batch.step(40)
