@@ -32,15 +32,14 @@ __device__ __forceinline__ int gather_members(const PairDev& pairs, int L, int (
   return k;
 }
 
-// Equilibrium deviation, Eq. LBM_EQ minus w_q, for all q.
+// Equilibrium deviation of direction q, Eq. LBM_EQ minus w_q, with
+// base = delta rho - 3/2 u.u.  Recomputed where needed instead of kept in 19
+// registers per velocity: the overlap kernel is bound by memory latency and
+// lives on occupancy.
 template <typename R>
-__device__ __forceinline__ void geq_all(R drho, R ux, R uy, R uz, R (&e)[Q]) {
-  const R base = drho - (R)1.5 * (ux * ux + uy * uy + uz * uz);
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const R cu = (R)cx(q) * ux + (R)cy(q) * uy + (R)cz(q) * uz;
-    e[q] = (R)wq(q) * (base + cu * ((R)3 + (R)4.5 * cu));
-  }
+__device__ __forceinline__ R geq1(int q, R base, R ux, R uy, R uz) {
+  const R cu = (R)cx(q) * ux + (R)cy(q) * uy + (R)cz(q) * uz;
+  return (R)wq(q) * (base + cu * ((R)3 + (R)4.5 * cu));
 }
 
 // g: pre-collision deviations of cell c (instance I), L: the cell's leader
@@ -59,8 +58,7 @@ __device__ __forceinline__ void psm_cell_collide(const R (&g)[Q], R (&out)[Q], c
     uy += (R)cy(q) * g[q];
     uz += (R)cz(q) * g[q];
   }
-  R eU[Q];
-  geq_all<R>(drho, ux, uy, uz, eU);
+  const R baseU = drho - (R)1.5 * (ux * ux + uy * uy + uz * uz);
   const R lp = (R)I.lam_p, lm = (R)I.lam_m;
   const R fx = (R)I.fext[0], fy = (R)I.fext[1], fz = (R)I.fext[2];
   const R fu = ux * fx + uy * fy + uz * fz;
@@ -92,17 +90,20 @@ __device__ __forceinline__ void psm_cell_collide(const R (&g)[Q], R (&out)[Q], c
     const double v0 = Up[0] + (Wp[1] * r[2] - Wp[2] * r[1]);
     const double v1 = Up[1] + (Wp[2] * r[0] - Wp[0] * r[2]);
     const double v2 = Up[2] + (Wp[0] * r[1] - Wp[1] * r[0]);
-    R eV[Q];
-    geq_all<R>(drho, (R)v0, (R)v1, (R)v2, eV);
+    const R vx = (R)v0, vy = (R)v1, vz = (R)v2;
+    const R baseV = drho - (R)1.5 * (vx * vx + vy * vy + vz * vz);
     const R B = (R)Bs[m];
     R mx = 0, my = 0, mz = 0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int qb = opp(q);
       R om;
-      if (I.psm_m == 1) om = (g[qb] - eU[qb]) - (g[q] - eV[q]);
-      else if (I.psm_m == 2) om = (eV[q] - g[q]) + ((R)1 - inv_tau) * (g[q] - eU[q]);
-      else om = (g[qb] - eV[qb]) - (g[q] - eV[q]);
+      if (I.psm_m == 1)
+        om = (g[qb] - geq1<R>(qb, baseU, ux, uy, uz)) - (g[q] - geq1<R>(q, baseV, vx, vy, vz));
+      else if (I.psm_m == 2)
+        om = (geq1<R>(q, baseV, vx, vy, vz) - g[q]) + ((R)1 - inv_tau) * (g[q] - geq1<R>(q, baseU, ux, uy, uz));
+      else
+        om = (g[qb] - geq1<R>(qb, baseV, vx, vy, vz)) - (g[q] - geq1<R>(q, baseV, vx, vy, vz));
       acc[q] += B * om;
       mx -= (R)cx(q) * om;
       my -= (R)cy(q) * om;
@@ -122,8 +123,7 @@ __device__ __forceinline__ void psm_cell_collide(const R (&g)[Q], R (&out)[Q], c
   const R omB = (R)(1.0 - Bsum);
   // fluid operator and forcing, then Eq. LBM_Collide_PSM
   {
-    const R base = drho - (R)1.5 * (ux * ux + uy * uy + uz * uz);
-    const R C0 = lp * (g[0] - (R)wq(0) * base);
+    const R C0 = lp * (g[0] - (R)wq(0) * baseU);
     const R F0 = -(R)wq(0) * (R)3 * fu;
     out[0] = g[0] + omB * C0 + acc[0] + omB * F0;
 #pragma unroll
@@ -133,7 +133,8 @@ __device__ __forceinline__ void psm_cell_collide(const R (&g)[Q], R (&out)[Q], c
       const R cu = (R)cx(qa) * ux + (R)cy(qa) * uy + (R)cz(qa) * uz;
       const R cf = (R)cx(qa) * fx + (R)cy(qa) * fy + (R)cz(qa) * fz;
       const R gp = (R)0.5 * (g[qa] + g[qb]), gm = (R)0.5 * (g[qa] - g[qb]);
-      const R ep = (R)0.5 * (eU[qa] + eU[qb]), em = (R)0.5 * (eU[qa] - eU[qb]);
+      const R eUa = geq1<R>(qa, baseU, ux, uy, uz), eUb = geq1<R>(qb, baseU, ux, uy, uz);
+      const R ep = (R)0.5 * (eUa + eUb), em = (R)0.5 * (eUa - eUb);
       const R cp = lp * (gp - ep), cm = lm * (gm - em);
       const R Fp = w * ((R)9 * cu * cf - (R)3 * fu), Fm = w * ((R)3 * cf);
       out[qa] = g[qa] + omB * (cp + cm) + acc[qa] + omB * (Fp + Fm);
