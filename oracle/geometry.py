@@ -18,6 +18,11 @@ Functions:
                           sample points that lie inside the sphere; the recursive
                           form classifies whole octree blocks of sample points at
                           once and returns exactly the same count.
+* ``eps_edge`` / ``eps_distance`` -- the two other estimators Sec. 2.3.2 names:
+                          the covered share of the cell's twelve edges, and a
+                          value from the distance of the cell centre to the
+                          surface (reading: 1/2 - s clamped to [0, 1], s the
+                          signed distance in cells; parity unpinned as a design).
 """
 import math
 
@@ -148,3 +153,40 @@ def overlap_cells(shape, X, R, n, recursive=False):
     keep = counts > 0
     eps = counts[keep].astype(np.float64) / float(n ** 3)
     return gz[keep], gy[keep], gx[keep], eps
+
+
+def eps_edge(d, R):
+    """Edge-intersection estimate of eps_s (Sec. 2.3.2): the length of the
+    cell's twelve edges inside the sphere over their total length 12.  d: the
+    cell-centre displacement from the sphere centre.  Edges are taken axis by
+    axis (x, y, z); for each, the two other coordinates at (-1/2, -1/2),
+    (+1/2, -1/2), (-1/2, +1/2), (+1/2, +1/2) (first of the two varying fastest)."""
+    R2 = R * R
+    total = 0.0
+    for a in range(3):
+        b, c = [k for k in range(3) if k != a]
+        for s2 in (-0.5, 0.5):
+            for s1 in (-0.5, 0.5):
+                yb = d[b] + s1
+                zc = d[c] + s2
+                h2 = R2 - (yb * yb + zc * zc)
+                if h2 > 0.0:
+                    h = math.sqrt(h2)
+                    lo = max(d[a] - 0.5, -h)
+                    hi = min(d[a] + 0.5, h)
+                    total += max(0.0, hi - lo)
+    return min(1.0, total / 12.0)  # hi - lo of a fully covered edge may round above 1
+
+
+def eps_distance(d, R):
+    """Distance estimate of eps_s (Sec. 2.3.2): 1/2 minus the signed distance
+    s = |d| - R of the cell centre from the surface (in cells), clamped to
+    [0, 1] -- 1/2 on the surface, 1 half a cell inside, 0 half a cell outside."""
+    r = math.sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2])
+    return min(1.0, max(0.0, 0.5 - (r - R)))
+
+
+def eps_count(eps, n):
+    """An estimate expressed as a count out of n^3 (nearest, ties to even), the
+    form every estimator of the library stores."""
+    return int(np.rint(eps * float(n) ** 3))
