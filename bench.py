@@ -211,8 +211,9 @@ def learned(torch, lbmps, inputs, steps, warmup, seed):
     512^3 periodic box, PSM-M3B2, FP32 storage, two sweeps per rigid-body step:
     the overlap rebuild after every rigid-body step evaluates eps_s of every
     cut cell.  Estimators: flat 16^3 supersampling (reference), flat 8^3,
-    recursive 16^3, and the network (trained here on 2^22 labelled cells,
-    R uniform in 5.5..10.5, by the library's own MFMA kernels)."""
+    recursive 16^3, the network (trained here on 2^22 labelled cells, R
+    uniform in 5.5..10.5, by the library's own MFMA kernels), and the two
+    closed forms Sec. 2.3.2 names (edge intersection, surface distance)."""
     import numpy as np
 
     wl = inputs.c5_learned(seed)
@@ -242,7 +243,8 @@ def learned(torch, lbmps, inputs, steps, warmup, seed):
     out = {"workload": "512^3 periodic, %d moving spheres D 12..20, PSM-M3B2, FP32" % n_p, "spheres": n_p,
            "train": {"cells": ns, "epochs": 4, "seconds": round(train_s, 2), "mean_abs_err": round(train_mae, 5)}}
     variants = [("flat16", lbmps.EPS_FLAT, 16), ("flat8", lbmps.EPS_FLAT, 8),
-                ("recursive16", lbmps.EPS_RECURSIVE, 16), ("learned16", lbmps.EPS_LEARNED, 16)]
+                ("recursive16", lbmps.EPS_RECURSIVE, 16), ("learned16", lbmps.EPS_LEARNED, 16),
+                ("edge", lbmps.EPS_EDGE, 16), ("distance", lbmps.EPS_DISTANCE, 16)]
     ref_keys, ref_U = None, None
     launch = tuned_shape(dict(nx=L, ny=L, nz=L), "fp32")
     res = {}

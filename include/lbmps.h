@@ -68,6 +68,10 @@ typedef int32_t lbmps_status;
 #define LBMPS_EPS_RECURSIVE 1 /* same points, octree blocks classified at once (eps_n power of 2) */
 #define LBMPS_EPS_LEARNED 2   /* cells cut by the surface: the network of lbmps_set_eps_model inside its
                                  radius range, flat eps_n^3 supersampling outside it */
+#define LBMPS_EPS_EDGE 3      /* covered share of the cell's 12 edges (alternative named in Sec. 2.3.2) */
+#define LBMPS_EPS_DISTANCE 4  /* 1/2 - (|x_c - X| - R) clamped to [0, 1]: surface distance of the cell
+                                 centre (alternative named in Sec. 2.3.2).  Modes 2-4 store eps_s as the
+                                 nearest count out of eps_n^3 (ties to even). */
 
 typedef struct lbmps_config {
   int32_t nx, ny, nz;  /* periodic box (cells) */
@@ -78,7 +82,7 @@ typedef struct lbmps_config {
   int32_t n_sub;       /* LBM sweeps per rigid-body step, forces averaged over them (Sec. 2.2.4, Sec. 4.1);
                           0 = 2 for MEM, 1 for PSM (Alg. 2) */
   int32_t eps_n;       /* supersampling points per axis (default 8) */
-  int32_t eps_mode;    /* LBMPS_EPS_FLAT, LBMPS_EPS_RECURSIVE or LBMPS_EPS_LEARNED */
+  int32_t eps_mode;    /* LBMPS_EPS_FLAT .. LBMPS_EPS_DISTANCE */
   int32_t precision;   /* LBMPS_FP64 .. LBMPS_BF16_DEV */
   int32_t max_particles;
   int32_t tile_rows;     /* x-rows per sweep workgroup (0 = automatic) */

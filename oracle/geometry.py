@@ -133,8 +133,10 @@ def eps_recursive_count(dcx, dcy, dcz, R, n):
     return _count_block(px, py, pz, R * R)
 
 
-def overlap_cells(shape, X, R, n, recursive=False):
-    """All cells with a nonzero supersampled solid fraction for one sphere.
+def overlap_cells(shape, X, R, n, recursive=False, estimator=None):
+    """All cells with a nonzero solid fraction for one sphere: supersampled
+    (flat or recursive), or by ``estimator`` ('edge' / 'distance') as a count
+    out of n^3.
 
     Returns (iz, iy, ix, eps) with eps = count / n^3 > 0."""
     nz, ny, nx = shape
@@ -146,7 +148,11 @@ def overlap_cells(shape, X, R, n, recursive=False):
     dcx = centre_disp(gx, X[0], nx)
     dcy = centre_disp(gy, X[1], ny)
     dcz = centre_disp(gz, X[2], nz)
-    if recursive:
+    if estimator in ("edge", "distance"):
+        f = eps_edge if estimator == "edge" else eps_distance
+        counts = np.array([eps_count(f(np.array([a, b, c]), R), n) for a, b, c in zip(dcx, dcy, dcz)],
+                          dtype=np.int64)
+    elif recursive:
         counts = np.array([eps_recursive_count(a, b, c, R, n) for a, b, c in zip(dcx, dcy, dcz)], dtype=np.int64)
     else:
         counts = eps_flat_counts(dcx, dcy, dcz, R, n)

@@ -34,7 +34,7 @@ from . import rigid as rb
 class OracleSim:
     def __init__(self, nx, ny, nz, nu, collision="trt", magic=3.0 / 16.0, coupling="none",
                  psm_m=1, psm_b=1, fext=(0.0, 0.0, 0.0), gravity=(0.0, 0.0, 0.0), n_sub=None,
-                 eps_n=8, eps_recursive=False):
+                 eps_n=8, eps_recursive=False, eps_estimator=None):
         self.shape = (nz, ny, nx)
         self.box = np.array([nx, ny, nz], dtype=np.float64)
         self.nu = float(nu)
@@ -50,6 +50,7 @@ class OracleSim:
         self.n_sub = n_sub
         self.eps_n = eps_n
         self.eps_recursive = eps_recursive
+        self.eps_estimator = eps_estimator  # None (supersampling), 'edge' or 'distance' 
         self.g = np.zeros((19,) + self.shape)
         self.owner = np.full(self.shape, mm.FLUID, dtype=np.int64)
         self.v_walls = []
@@ -123,7 +124,8 @@ class OracleSim:
                 self.refilled += len(cells)
             self._mask_solid()
         else:
-            self.overlaps = [geo.overlap_cells(self.shape, p["X"], p["D"] / 2.0, self.eps_n, self.eps_recursive)
+            self.overlaps = [geo.overlap_cells(self.shape, p["X"], p["D"] / 2.0, self.eps_n, self.eps_recursive,
+                                              self.eps_estimator)
                              for p in self.parts]
         self.links = mm.build_links(self.owner, self.parts, self._radii(), self.shape, self.v_walls)
         if self.coupling.startswith("mem"):

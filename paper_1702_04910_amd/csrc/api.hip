@@ -76,7 +76,7 @@ bool valid_cfg(const lbmps_config& c, std::string& err) {
   const int en = c.eps_n ? c.eps_n : 8;
   if (en < 1 || en > 64) { err = "eps_n must be 1..64"; return false; }
   if (c.eps_mode == LBMPS_EPS_RECURSIVE && (en & (en - 1))) { err = "recursive supersampling needs eps_n = 2^k"; return false; }
-  if (c.eps_mode < 0 || c.eps_mode > 2) { err = "unknown eps_mode"; return false; }
+  if (c.eps_mode < 0 || c.eps_mode > 4) { err = "unknown eps_mode"; return false; }
   if (c.block_threads < 0 || c.block_threads > 256 || (c.block_threads % 64)) { err = "block_threads must be a multiple of 64, <= 256"; return false; }
   if (c.sweep_flags & ~SWEEP_FLAGS_ALL) { err = "unknown sweep_flags bits"; return false; }
   if ((c.sweep_flags & SWEEP_PSM_FUSED) && (c.sweep_flags & SWEEP_PSM_SEPARATE)) {
@@ -317,7 +317,9 @@ void update_psm_exact(lbmps_ctx* c) {
     const int b = c->L.part_begin[k];
     for (int i = 0; i < c->n_active[k]; ++i) {
       const double R = 0.5 * c->diam_h[b + i];
-      if (c->cfg[k].eps_mode != LBMPS_EPS_LEARNED || !c->mlp_set || R < c->mlp_rmin || R > c->mlp_rmax)
+      const int em = c->cfg[k].eps_mode;
+      if (em == LBMPS_EPS_FLAT || em == LBMPS_EPS_RECURSIVE ||
+          (em == LBMPS_EPS_LEARNED && (!c->mlp_set || R < c->mlp_rmin || R > c->mlp_rmax)))
         c->psm_exact = true;
     }
   }

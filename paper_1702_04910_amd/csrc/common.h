@@ -54,7 +54,7 @@ __host__ __device__ constexpr double wq(int q) {
 enum { COUP_NONE = 0, COUP_MEM_BB = 1, COUP_MEM_CLI = 2, COUP_PSM = 3 };
 enum { COLL_BGK = 0, COLL_TRT = 1 };
 enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP16 = 2, PREC_BF16 = 3 };
-enum { EPS_FLAT = 0, EPS_RECURSIVE = 1, EPS_LEARNED = 2 };
+enum { EPS_FLAT = 0, EPS_RECURSIVE = 1, EPS_LEARNED = 2, EPS_EDGE = 3, EPS_DISTANCE = 4 };
 
 // Owner field values (MEM): -1 fluid, <= -2 static wall group (-2 - k),
 // 0 <= p < WAS_BIT solid cell of particle p, WAS_BIT | p: was solid of p before

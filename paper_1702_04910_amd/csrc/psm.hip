@@ -177,6 +177,36 @@ __device__ __forceinline__ void centre_disp(const InstDev& I, const PartDev& P, 
   d[2] = min_image(((double)k + 0.5) - P.X[3 * p + 2], (double)I.nz);
 }
 
+// Closed-form estimators of Sec. 2.3.2 other than supersampling.  Edge
+// intersection: the covered length of the cell's twelve edges over 12 (axis by
+// axis; the two other coordinates at (-,-), (+,-), (-,+), (+,+) half-cells).
+__device__ double eps_edge(const double (&d)[3], double R2) {
+  double total = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const double yb = __dadd_rn(d[b], (k & 1) ? 0.5 : -0.5);
+      const double zc = __dadd_rn(d[c], (k & 2) ? 0.5 : -0.5);
+      const double h2 = __dadd_rn(R2, -__dadd_rn(__dmul_rn(yb, yb), __dmul_rn(zc, zc)));
+      if (h2 > 0.0) {
+        const double h = sqrt(h2);
+        const double lo = fmax(__dadd_rn(d[a], -0.5), -h);
+        const double hi = fmin(__dadd_rn(d[a], 0.5), h);
+        total = __dadd_rn(total, fmax(0.0, __dadd_rn(hi, -lo)));
+      }
+    }
+  }
+  return fmin(1.0, __ddiv_rn(total, 12.0));
+}
+
+// Surface distance: 1/2 - (|d| - R), clamped to [0, 1].
+__device__ double eps_distance(const double (&d)[3], double R) {
+  const double r = sqrt(sq3(d[0], d[1], d[2]));
+  return fmin(1.0, fmax(0.0, __dadd_rn(0.5, -__dadd_rn(r, -R))));
+}
+
 // Stage 1 of the solid fractions, grid (units, nlist): every bounding-box cell
 // of the unit is classified by its farthest and nearest sample point.  Cells
 // entirely inside get the full count n^3, entirely outside 0, cut cells the
@@ -213,8 +243,13 @@ __global__ __launch_bounds__(256) void psm_classify_kernel(const int* __restrict
       bhi[q] = __dadd_rn(dc[q], o1);
     }
     const int cl = classify(blo, bhi, R2);
-    slots[slot_index(j, side, U.z, dy, dx)] = cl == 1 ? n * n * n : (cl == 0 ? -1 : 0);
-    ncut += cl == 0 ? 1 : 0;
+    int v = cl == 1 ? n * n * n : (cl == 0 ? -1 : 0);
+    if (I.eps_mode >= EPS_EDGE) {  // closed forms: evaluated here, counts out of n^3
+      const double e = I.eps_mode == EPS_EDGE ? eps_edge(dc, R2) : eps_distance(dc, R);
+      v = (int)rint(e * ((double)n * n * n));
+    }
+    slots[slot_index(j, side, U.z, dy, dx)] = v;
+    ncut += v < 0 ? 1 : 0;
   }
   int total;
   block_excl_scan256(ncut, sh, &total);

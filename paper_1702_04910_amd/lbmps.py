@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(_HERE, "liblbmps.so")
 BGK, TRT = 0, 1
 NONE, MEM_BB, MEM_CLI, PSM = 0, 1, 2, 3
 FP64, FP32, FP16_DEV, BF16_DEV = 0, 1, 2, 3
-EPS_FLAT, EPS_RECURSIVE, EPS_LEARNED = 0, 1, 2
+EPS_FLAT, EPS_RECURSIVE, EPS_LEARNED, EPS_EDGE, EPS_DISTANCE = 0, 1, 2, 3, 4
 SWEEP_NT_LOADS, SWEEP_PSM_FUSED, SWEEP_PSM_SEPARATE = 1, 2, 4
 MLP_NPARAM = 4801
 MLP_MAX_BATCH = 65536

@@ -37,7 +37,8 @@ def make_pair(nx, ny, nz, nu, coupling="none", collision="trt", psm_m=1, psm_b=1
               walls=None, tile_rows=0, block_threads=0, grid_blocks=0, sweep_flags=0):
     """parts: dict(X, U, Om, D, rho, fixed) lists; walls: list of (mask, v)."""
     ora = OracleSim(nx, ny, nz, nu, collision=collision, coupling=coupling, psm_m=psm_m, psm_b=psm_b, fext=f_ext,
-                    gravity=gravity, n_sub=(n_sub or None), eps_n=eps_n, eps_recursive=(eps_mode == 1))
+                    gravity=gravity, n_sub=(n_sub or None), eps_n=eps_n, eps_recursive=(eps_mode == 1),
+                    eps_estimator={3: "edge", 4: "distance"}.get(eps_mode))
     np_ = len(parts["D"]) if parts else 0
     dmax = max(parts["D"]) if parts else 0.0
     cfg = lbmps.make_config(nx, ny, nz, nu, collision=collision, coupling=coupling, psm_m=psm_m, psm_b=psm_b,

@@ -51,7 +51,7 @@ def test_workspace_bytes_valid_and_invalid():
         lbmps.make_config(32, 32, 64, 0.1, coupling="psm", n_sub=-1),
         lbmps.make_config(32, 32, 64, 0.1, sweep_flags=8),
         lbmps.make_config(32, 32, 64, 0.1, sweep_flags=lbmps.SWEEP_PSM_FUSED | lbmps.SWEEP_PSM_SEPARATE),
-        lbmps.make_config(32, 32, 64, 0.1, eps_mode=3),
+        lbmps.make_config(32, 32, 64, 0.1, eps_mode=5),
     ]
     for b in bad:
         assert lbmps.workspace_bytes(b) == 0

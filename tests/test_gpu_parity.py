@@ -220,3 +220,25 @@ def test_psm_collision_inside_sweep_equals_separate_pass(m, b):
     pa, pb = a.particles(), b_.particles()
     for k in ("F", "T", "U", "X"):
         assert np.array_equal(pa[k], pb[k])
+
+
+@pytest.mark.parametrize("mode", [3, 4])  # edge intersection, surface distance
+def test_closed_form_estimators(mode):
+    say("estimator", mode)
+    parts = dict(X=[[10.3, 11.2, 10.9]], U=[[0.01, 0, -0.005]], Om=[[0, 0.001, 0]], D=[9.3], rho=[1.5],
+                 fixed=[False])
+    ora, sim = make_pair(24, 22, 26, 0.05, coupling="psm", collision="trt", psm_m=2, psm_b=2, f_ext=(1e-5, 0, 0),
+                         parts=parts, eps_n=16, eps_mode=mode, n_sub=2)
+    ov = sim.overlaps()
+    iz, iy, ix, eps = ora.overlaps[0]
+    cells_o = (iz * 22 + iy) * 24 + ix
+    o1, o2 = np.argsort(cells_o), np.argsort(ov["cell"])
+    assert np.array_equal(cells_o[o1], ov["cell"][o2])
+    assert np.array_equal(eps[o1], ov["eps"][o2])
+    for k in range(2):
+        ora.step(20)
+        sim.step(20)
+        (eF, eT, _), = force_errors(ora, sim)[0]
+        e, _ = pdf_error(ora, sim)
+        say("  t=%d e_f=%.2e e_F=%.2e e_T=%.2e" % (ora.time, e, eF, eT))
+        assert e < 1e-11 and eF < 1e-11 and eT < 1e-11
