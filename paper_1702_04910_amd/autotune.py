@@ -34,7 +34,7 @@ def candidates(nx, precision):
     for r in rows:
         for block in (128, 256):
             for grid in (0, 2048):
-                for flags in (0, 1):
+                for flags in ((0, 1, 8, 9) if s < 8 else (0, 1)):  # + six-wave build (bit 3) for 4/2-byte storage
                     out.append(dict(tile_rows=r, block_threads=block, grid_blocks=grid, sweep_flags=flags))
     return out
 
@@ -92,7 +92,7 @@ def tune_batch(make_sim, tile_cells=(256, 512, 1024), grids=(0, 1024, 2048, 4096
         sim = make_sim(tc)
         try:
             for grid in grids:
-                for flags in (0, 1):
+                for flags in (0, 1, 8, 9):
                     sim.set_launch(256, grid, flags)
                     sim.set_timing(True)
                     sim.step(sweeps)

@@ -8,9 +8,10 @@ namespace lbm {
 
 // ---- sweep.hip
 // sweep_flags: bit 0 non-temporal loads; bit 1 collide PSM cells inside the
-// sweep; bit 2 (or neither) collide them in the separate overlap kernel.
+// sweep; bit 2 (or neither) collide them in the separate overlap kernel;
+// bit 3 the sweep compiled for six waves per SIMD (4- and 2-byte storage).
 // Results never depend on them.
-enum { SWEEP_NT_LOADS = 1, SWEEP_PSM_FUSED = 2, SWEEP_PSM_SEPARATE = 4, SWEEP_FLAGS_ALL = 7 };
+enum { SWEEP_NT_LOADS = 1, SWEEP_PSM_FUSED = 2, SWEEP_PSM_SEPARATE = 4, SWEEP_OCC6 = 8, SWEEP_FLAGS_ALL = 15 };
 hipError_t launch_sweep(int prec, const InstDev* insts, const int4* tiles, int ntiles, int grid, int block,
                         int max_tile_cells, int flags, const void* src, void* dst, const int* cellmap, PairDev pairs,
                         PartDev parts, hipStream_t st);

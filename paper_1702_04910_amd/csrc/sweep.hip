@@ -119,9 +119,9 @@ __device__ __forceinline__ __bf16 ld_nt<__bf16>(const __bf16* p) {
 }
 
 template <typename S, bool NTLD, bool PSM>
-__global__ __launch_bounds__(256) void sweep_kernel(const InstDev* __restrict__ insts, const int4* __restrict__ tiles,
-                                                    int ntiles, const S* __restrict__ src, S* __restrict__ dst,
-                                                    const int* __restrict__ cellmap, PairDev pairs, PartDev P) {
+__device__ __forceinline__ void sweep_body(const InstDev* __restrict__ insts, const int4* __restrict__ tiles,
+                                           int ntiles, const S* __restrict__ src, S* __restrict__ dst,
+                                           const int* __restrict__ cellmap, const PairDev& pairs, const PartDev& P) {
   using R = typename CompOf<S>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   S* sh = reinterpret_cast<S*>(smem_raw);
@@ -193,6 +193,23 @@ __global__ __launch_bounds__(256) void sweep_kernel(const InstDev* __restrict__ 
   }
 }
 
+template <typename S, bool NTLD, bool PSM>
+__global__ __launch_bounds__(256) void sweep_kernel(const InstDev* __restrict__ insts, const int4* __restrict__ tiles,
+                                                    int ntiles, const S* __restrict__ src, S* __restrict__ dst,
+                                                    const int* __restrict__ cellmap, PairDev pairs, PartDev P) {
+  sweep_body<S, NTLD, PSM>(insts, tiles, ntiles, src, dst, cellmap, pairs, P);
+}
+
+// The same sweep compiled for six waves per SIMD (at most 80 registers per
+// lane instead of ~105): more loads in flight per CU.  Chosen by the launch
+// tuner; without spills for 4- and 2-byte storage only.
+template <typename S, bool NTLD>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void sweep_kernel_occ6(
+    const InstDev* __restrict__ insts, const int4* __restrict__ tiles, int ntiles, const S* __restrict__ src,
+    S* __restrict__ dst) {
+  sweep_body<S, NTLD, false>(insts, tiles, ntiles, src, dst, nullptr, PairDev{}, PartDev{});
+}
+
 // Uniform equilibrium initial state, Eq. LBM_EQ: g_q = w_q (rho - 1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u).
 template <typename S>
 __global__ void init_eq_kernel(S* __restrict__ buf, long long N, double rho, double ux, double uy, double uz) {
@@ -260,8 +277,15 @@ __global__ void fields_kernel(const S* __restrict__ buf, long long N, long long 
 // ------------------------------------------------------------------------ launchers
 template <typename S, bool NTLD>
 hipError_t launch_sweep_n(const InstDev* insts, const int4* tiles, int ntiles, int grid, int block, size_t lds,
-                          const void* src, void* dst, const int* cellmap, PairDev pairs, PartDev parts,
+                          const void* src, void* dst, const int* cellmap, PairDev pairs, PartDev parts, bool occ6,
                           hipStream_t st) {
+  if constexpr (sizeof(S) < 8) {
+    if (occ6 && !cellmap) {
+      hipLaunchKernelGGL((sweep_kernel_occ6<S, NTLD>), dim3(grid), dim3(block), lds, st, insts, tiles, ntiles,
+                         (const S*)src, (S*)dst);
+      return hipGetLastError();
+    }
+  }
   if (cellmap)
     hipLaunchKernelGGL((sweep_kernel<S, NTLD, true>), dim3(grid), dim3(block), lds, st, insts, tiles, ntiles,
                        (const S*)src, (S*)dst, cellmap, pairs, parts);
@@ -276,9 +300,10 @@ hipError_t launch_sweep_t(const InstDev* insts, const int4* tiles, int ntiles, i
                           int flags, const void* src, void* dst, const int* cellmap, PairDev pairs, PartDev parts,
                           hipStream_t st) {
   const size_t lds = (size_t)NXSHIFT * max_tile_cells * sizeof(S);
+  const bool occ6 = (flags & SWEEP_OCC6) != 0;
   if (flags & SWEEP_NT_LOADS)
-    return launch_sweep_n<S, true>(insts, tiles, ntiles, grid, block, lds, src, dst, cellmap, pairs, parts, st);
-  return launch_sweep_n<S, false>(insts, tiles, ntiles, grid, block, lds, src, dst, cellmap, pairs, parts, st);
+    return launch_sweep_n<S, true>(insts, tiles, ntiles, grid, block, lds, src, dst, cellmap, pairs, parts, occ6, st);
+  return launch_sweep_n<S, false>(insts, tiles, ntiles, grid, block, lds, src, dst, cellmap, pairs, parts, occ6, st);
 }
 
 hipError_t launch_sweep(int prec, const InstDev* insts, const int4* tiles, int ntiles, int grid, int block,

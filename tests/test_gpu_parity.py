@@ -242,3 +242,19 @@ def test_closed_form_estimators(mode):
         e, _ = pdf_error(ora, sim)
         say("  t=%d e_f=%.2e e_F=%.2e e_T=%.2e" % (ora.time, e, eF, eT))
         assert e < 1e-11 and eF < 1e-11 and eT < 1e-11
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_six_wave_sweep_build_is_bitwise_identical(precision):
+    from paper_1702_04910_amd import lbmps
+
+    nx, ny, nz = 37, 23, 19
+    g0 = inputs.random_pdfs((nz, ny, nx), 1e-3, seed=25)
+    out = []
+    for flags in (0, lbmps.SWEEP_OCC6, lbmps.SWEEP_OCC6 | lbmps.SWEEP_NT_LOADS):
+        ora, sim = make_pair(nx, ny, nz, 0.07, collision="trt", f_ext=(1e-5, -2e-5, 3e-5), precision=precision,
+                             g0=g0, sweep_flags=flags)
+        sim.step(6)
+        out.append(sim.get_pdfs())
+        sim.close()
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
