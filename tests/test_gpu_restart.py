@@ -55,17 +55,25 @@ def test_checkpoint_restart_continues_bitwise(coupling):
 def test_graph_replay_moving_particles(mode):
     import torch
 
-    from oracle import mlp as om
-
     say("graph replay", mode)
     coupling = "mem_cli" if mode == "mem_cli" else "psm"
     kw = dict(eps_mode=lbmps.EPS_LEARNED, eps_n=16) if mode == "psm_learned" else {}
     sims = [lbmps.Sim(_cfg(coupling, **kw), stream=torch.cuda.Stream()) for _ in range(2)]
-    params = inputs.mlp_init(3)
+    params = None
+    if mode == "psm_learned":  # a quickly trained network for R in [3, 4.2]
+        n = 32768
+        m = lbmps.Mlp(n)
+        m.set_samples(inputs.eps_training_cells(5, n, r_min=3.0, r_max=4.2))
+        m.set_params(inputs.mlp_init(5))
+        m.label(16)
+        mult, add = inputs.affine_orders(5, n, 8)
+        m.train(mult, add, batch=512, lr=2e-3)
+        params = m.params()
+        m.close()
     for s in sims:
         s.init_equilibrium()
-        if mode == "psm_learned":
-            s.set_eps_model(params, 3.0, 4.0)  # an untrained network: exercises the path, not accuracy
+        if params is not None:
+            s.set_eps_model(params, 3.0, 4.2)
         p = PARTS
         s.set_particles(p["X"], p["U"], p["Om"], p["D"], p["rho"], p["fixed"])
     eager, graph = sims
