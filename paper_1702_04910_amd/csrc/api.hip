@@ -845,7 +845,7 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
     if (c->n_psm) {
       if (!fused)
         HIPCHK(c, launch_psm_collide(L.prec, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap,
-                                     src, dst, c->st));
+                                     src, dst, !(c->cfg[0].sweep_flags & SWEEP_PSM_NOSPLIT), c->st));
       HIPCHK(c, launch_reduce(psm_list(c), c->n_psm, c->pbeg, c->pend, 0, c->pairs.out, c->pairs.ostride, c->parts,
                               c->st));
     }

@@ -533,11 +533,91 @@ hipError_t launch_psm_cellmap(int stage, const int* count, int cap, const InstDe
   return hipGetLastError();
 }
 
+// A cell covered by one particle with weight B = 1 (every interior cell:
+// eps_s = 1 gives B = 1 for B1 and B2).  Eq. LBM_Collide_PSM then reduces to
+// f~ = f + Omega: the general per-cell function yields exactly these bits
+// (its (1 - B) terms vanish and the weighted sum of one Omega with B = 1 is
+// Omega itself), so such cells take a light kernel that streams each value
+// out as soon as it is computed and keeps few registers.
+__device__ __forceinline__ bool psm_simple_cell(const PairDev& pairs, int L) {
+  return pairs.next[L] < 0 && pairs.B[L] == 1.0;
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void psm_collide_simple_kernel(const int* __restrict__ count, int cap,
+                                                                 const InstDev* __restrict__ insts, PartDev P,
+                                                                 PairDev pairs, const int* __restrict__ cellmap,
+                                                                 const S* __restrict__ src, S* __restrict__ dst) {
+  using R = typename CompOf<S>::type;
+  const int npairs = min(*count, cap);
+  for (int L = blockIdx.x * blockDim.x + threadIdx.x; L < npairs; L += gridDim.x * blockDim.x) {
+    const int p0 = pairs.p[L];
+    const InstDev& I = insts[P.inst[p0]];
+    const int c = pairs.cell[L];
+    if (cellmap[I.cellmap_off + c] != L || !psm_simple_cell(pairs, L)) continue;
+    const S* s = src + I.pdf_off;
+    S* d = dst + I.pdf_off;
+    R g[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) g[q] = Codec<S>::ld(s[pdf_at(c, q)]);
+    R drho = 0, ux = 0, uy = 0, uz = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      drho += g[q];
+      ux += (R)cx(q) * g[q];
+      uy += (R)cy(q) * g[q];
+      uz += (R)cz(q) * g[q];
+    }
+    const R baseU = drho - (R)1.5 * (ux * ux + uy * uy + uz * uz);
+    const int nx = I.nx, ny = I.ny, nz = I.nz;
+    const int x = c % nx, yz = c / nx, y = yz % ny, z = yz / ny;
+    const R inv_tau = (R)(1.0 / I.tau);
+    double r[3];
+    r[0] = min_image(((double)x + 0.5) - P.X[3 * p0 + 0], (double)nx);
+    r[1] = min_image(((double)y + 0.5) - P.X[3 * p0 + 1], (double)ny);
+    r[2] = min_image(((double)z + 0.5) - P.X[3 * p0 + 2], (double)nz);
+    const double* Up = P.U + 3 * p0;
+    const double* Wp = P.Om + 3 * p0;
+    const double v0 = Up[0] + (Wp[1] * r[2] - Wp[2] * r[1]);
+    const double v1 = Up[1] + (Wp[2] * r[0] - Wp[0] * r[2]);
+    const double v2 = Up[2] + (Wp[0] * r[1] - Wp[1] * r[0]);
+    const R vx = (R)v0, vy = (R)v1, vz = (R)v2;
+    const R baseV = drho - (R)1.5 * (vx * vx + vy * vy + vz * vz);
+    R mx = 0, my = 0, mz = 0;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int qb = opp(q);
+      R om;
+      if (I.psm_m == 1)
+        om = (g[qb] - geq1<R>(qb, baseU, ux, uy, uz)) - (g[q] - geq1<R>(q, baseV, vx, vy, vz));
+      else if (I.psm_m == 2)
+        om = (geq1<R>(q, baseV, vx, vy, vz) - g[q]) + ((R)1 - inv_tau) * (g[q] - geq1<R>(q, baseU, ux, uy, uz));
+      else
+        om = (g[qb] - geq1<R>(qb, baseV, vx, vy, vz)) - (g[q] - geq1<R>(q, baseV, vx, vy, vz));
+      mx -= (R)cx(q) * om;
+      my -= (R)cy(q) * om;
+      mz -= (R)cz(q) * om;
+      const int xa = wrapi(x + cx(q), nx), ya = wrapi(y + cy(q), ny), za = wrapi(z + cz(q), nz);
+      d[pdf_at(((long long)za * ny + ya) * nx + xa, q)] = Codec<S>::st(g[q] + om);
+    }
+    const double Fx = (double)mx, Fy = (double)my, Fz = (double)mz;
+    double* o = pairs.out + L;
+    const long long ost = pairs.ostride;
+    o[0] = Fx;
+    o[ost] = Fy;
+    o[2 * ost] = Fz;
+    o[3 * ost] = r[1] * Fz - r[2] * Fy;
+    o[4 * ost] = r[2] * Fx - r[0] * Fz;
+    o[5 * ost] = r[0] * Fy - r[1] * Fx;
+  }
+}
+
 template <typename S>
 __global__ __launch_bounds__(256) void psm_collide_kernel(const int* __restrict__ count, int cap,
                                                           const InstDev* __restrict__ insts, PartDev P,
                                                           PairDev pairs, const int* __restrict__ cellmap,
-                                                          const S* __restrict__ src, S* __restrict__ dst) {
+                                                          const S* __restrict__ src, S* __restrict__ dst,
+                                                          int skip_simple) {
   using R = typename CompOf<S>::type;
   const int npairs = min(*count, cap);
   for (int L = blockIdx.x * blockDim.x + threadIdx.x; L < npairs; L += gridDim.x * blockDim.x) {
@@ -545,6 +625,7 @@ __global__ __launch_bounds__(256) void psm_collide_kernel(const int* __restrict_
     const InstDev& I = insts[P.inst[p0]];
     const int c = pairs.cell[L];
     if (cellmap[I.cellmap_off + c] != L) continue;  // not the cell's leader
+    if (skip_simple && psm_simple_cell(pairs, L)) continue;
     const S* s = src + I.pdf_off;
     S* d = dst + I.pdf_off;
     R g[Q], out[Q];
@@ -571,10 +652,14 @@ __global__ __launch_bounds__(256) void psm_collide_kernel(const int* __restrict_
   }
 
 hipError_t launch_psm_collide(int prec, const int* count, int cap, const InstDev* insts, PartDev parts,
-                              PairDev pairs, const int* cellmap, const void* src, void* dst, hipStream_t st) {
+                              PairDev pairs, const int* cellmap, const void* src, void* dst, bool split,
+                              hipStream_t st) {
   const int grid = 2048;
+  if (split)
+    LBM_DISPATCH(prec, hipLaunchKernelGGL(psm_collide_simple_kernel<S>, dim3(4 * grid), dim3(256), 0, st, count, cap,
+                                          insts, parts, pairs, cellmap, (const S*)src, (S*)dst));
   LBM_DISPATCH(prec, hipLaunchKernelGGL(psm_collide_kernel<S>, dim3(grid), dim3(256), 0, st, count, cap, insts, parts,
-                                        pairs, cellmap, (const S*)src, (S*)dst));
+                                        pairs, cellmap, (const S*)src, (S*)dst, split ? 1 : 0));
   return hipGetLastError();
 }
 
