@@ -533,16 +533,8 @@ hipError_t launch_psm_cellmap(int stage, const int* count, int cap, const InstDe
   return hipGetLastError();
 }
 
-// A cell covered by one particle with weight B = 1 (every interior cell:
-// eps_s = 1 gives B = 1 for B1 and B2).  Eq. LBM_Collide_PSM then reduces to
-// f~ = f + Omega: the general per-cell function yields exactly these bits
-// (its (1 - B) terms vanish and the weighted sum of one Omega with B = 1 is
-// Omega itself), so such cells take a light kernel that streams each value
-// out as soon as it is computed and keeps few registers.
-__device__ __forceinline__ bool psm_simple_cell(const PairDev& pairs, int L) {
-  return pairs.next[L] < 0 && pairs.B[L] == 1.0;
-}
-
+// Single-particle cells with B = 1 (psm_single_cell): a light kernel that
+// streams each value out as soon as it is computed and keeps few registers.
 template <typename S>
 __global__ __launch_bounds__(256) void psm_collide_simple_kernel(const int* __restrict__ count, int cap,
                                                                  const InstDev* __restrict__ insts, PartDev P,
@@ -560,55 +552,14 @@ __global__ __launch_bounds__(256) void psm_collide_simple_kernel(const int* __re
     R g[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) g[q] = Codec<S>::ld(s[pdf_at(c, q)]);
-    R drho = 0, ux = 0, uy = 0, uz = 0;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      drho += g[q];
-      ux += (R)cx(q) * g[q];
-      uy += (R)cy(q) * g[q];
-      uz += (R)cz(q) * g[q];
-    }
-    const R baseU = drho - (R)1.5 * (ux * ux + uy * uy + uz * uz);
     const int nx = I.nx, ny = I.ny, nz = I.nz;
     const int x = c % nx, yz = c / nx, y = yz % ny, z = yz / ny;
-    const R inv_tau = (R)(1.0 / I.tau);
-    double r[3];
-    r[0] = min_image(((double)x + 0.5) - P.X[3 * p0 + 0], (double)nx);
-    r[1] = min_image(((double)y + 0.5) - P.X[3 * p0 + 1], (double)ny);
-    r[2] = min_image(((double)z + 0.5) - P.X[3 * p0 + 2], (double)nz);
-    const double* Up = P.U + 3 * p0;
-    const double* Wp = P.Om + 3 * p0;
-    const double v0 = Up[0] + (Wp[1] * r[2] - Wp[2] * r[1]);
-    const double v1 = Up[1] + (Wp[2] * r[0] - Wp[0] * r[2]);
-    const double v2 = Up[2] + (Wp[0] * r[1] - Wp[1] * r[0]);
-    const R vx = (R)v0, vy = (R)v1, vz = (R)v2;
-    const R baseV = drho - (R)1.5 * (vx * vx + vy * vy + vz * vz);
-    R mx = 0, my = 0, mz = 0;
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int qb = opp(q);
-      R om;
-      if (I.psm_m == 1)
-        om = (g[qb] - geq1<R>(qb, baseU, ux, uy, uz)) - (g[q] - geq1<R>(q, baseV, vx, vy, vz));
-      else if (I.psm_m == 2)
-        om = (geq1<R>(q, baseV, vx, vy, vz) - g[q]) + ((R)1 - inv_tau) * (g[q] - geq1<R>(q, baseU, ux, uy, uz));
-      else
-        om = (g[qb] - geq1<R>(qb, baseV, vx, vy, vz)) - (g[q] - geq1<R>(q, baseV, vx, vy, vz));
-      mx -= (R)cx(q) * om;
-      my -= (R)cy(q) * om;
-      mz -= (R)cz(q) * om;
+    double F6[6];
+    psm_single_cell<R>(g, I, P, p0, c, F6, [&](int q, R v) {
       const int xa = wrapi(x + cx(q), nx), ya = wrapi(y + cy(q), ny), za = wrapi(z + cz(q), nz);
-      d[pdf_at(((long long)za * ny + ya) * nx + xa, q)] = Codec<S>::st(g[q] + om);
-    }
-    const double Fx = (double)mx, Fy = (double)my, Fz = (double)mz;
-    double* o = pairs.out + L;
-    const long long ost = pairs.ostride;
-    o[0] = Fx;
-    o[ost] = Fy;
-    o[2 * ost] = Fz;
-    o[3 * ost] = r[1] * Fz - r[2] * Fy;
-    o[4 * ost] = r[2] * Fx - r[0] * Fz;
-    o[5 * ost] = r[0] * Fy - r[1] * Fx;
+      d[pdf_at(((long long)za * ny + ya) * nx + xa, q)] = Codec<S>::st(v);
+    });
+    store_pair_out(pairs, L, F6);
   }
 }
 
