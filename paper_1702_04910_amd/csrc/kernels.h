@@ -79,9 +79,12 @@ hipError_t launch_psm_fill(const int* list, int nlist, int side, int nsplit, con
                            const int* slots, const int* offsets, int cap, PairDev pairs, hipStream_t st);
 hipError_t launch_psm_cellmap(int stage, const int* count, int cap, const InstDev* insts, PartDev parts,
                               PairDev pairs, int* cellmap, hipStream_t st);
-hipError_t launch_psm_collide(int prec, const int* count, int cap, const InstDev* insts, PartDev parts,
-                              PairDev pairs, const int* cellmap, const void* src, void* dst, bool split,
-                              hipStream_t st);
+hipError_t launch_psm_leaders(const int* count, int cap, const InstDev* insts, PartDev parts, PairDev pairs,
+                              const int* cellmap, int* tot_s, int* tot_g, int* off_s, int* off_g, int* list_s,
+                              int* list_g, int* n_s, int* n_g, int* scratch4, unsigned* err, hipStream_t st);
+hipError_t launch_psm_collide(int prec, const int* list_s, const int* n_s, const int* list_g, const int* n_g,
+                              const InstDev* insts, PartDev parts, PairDev pairs, const void* src, void* dst,
+                              bool split, hipStream_t st);
 hipError_t launch_psm_fields(int prec, const int* count, int cap, const InstDev* insts, PartDev parts, PairDev pairs,
                              const int* cellmap, const void* buf, int inst, long long c0, long long n, double* out,
                              hipStream_t st);
