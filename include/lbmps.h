@@ -92,9 +92,7 @@ typedef struct lbmps_config {
   int32_t sweep_flags;   /* launch tuning only, results unchanged: bit 0 non-temporal loads in the sweep;
                             bit 1 collide PSM cells inside the sweep (reads the cell map of every cell);
                             bit 2 or neither: collide them in a separate pass over the overlap list;
-                            bit 3 the sweep built for six waves per SIMD (FP32/FP16/BF16 storage);
-                            bit 4 the separate PSM pass without its light kernel for single-particle cells
-                            with B = 1 */
+                            bit 3 the sweep built for six waves per SIMD (FP32/FP16/BF16 storage) */
   int32_t reserved;
   double max_diameter;   /* largest particle diameter that will be set (cells) */
   double nu;             /* kinematic viscosity, nu = (tau - 1/2)/3 (Eq. Viscosity) */

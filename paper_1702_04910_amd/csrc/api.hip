@@ -50,7 +50,7 @@ struct Layout {
   long long chunk = 0;
   // byte offsets
   size_t o_bufA, o_bufB, o_owner, o_cellmap, o_inst, o_parts, o_plists, o_slots, o_totals, o_offsets, o_ranges,
-      o_counts, o_links, o_wallv, o_pairs, o_refill, o_scratch, o_tiles, o_cuts, o_cutx, o_mlp, o_judge, o_leaders, total;
+      o_counts, o_links, o_wallv, o_pairs, o_refill, o_scratch, o_tiles, o_cuts, o_cutx, o_mlp, o_judge, total;
   int ntiles = 0;
   int max_tile_cells = 0;
 };
@@ -201,10 +201,6 @@ Layout make_layout(int n, const lbmps_config* cfgs) {
   L.o_cutx = take(L.learned ? (size_t)L.cut_cap * (8 + 1) * 4 : 0);
   L.o_mlp = take((size_t)mlp_nparam() * 4);
   L.o_judge = take(4 * 8);  // own aligned block: the judge updates it with 8-byte atomics
-  {
-    const size_t nb = ((size_t)L.pair_cap + 255) / 256;
-    L.o_leaders = take(((size_t)L.pair_cap * 2 + nb * 4) * 4 + 6 * ALIGN);
-  }
   L.total = o;
   L.ok = true;
   return L;
@@ -249,9 +245,6 @@ struct lbmps_ctx {
   float* cut_x = nullptr;  // features [cut_cap][8], then outputs [cut_cap]
   float* mlp_p = nullptr;  // network parameters (learned eps_s)
   double* judge = nullptr; // error statistics of lbmps_eps_judge
-  // overlapped cells by kind (single particle with B = 1 / other), see launch_psm_leaders
-  int *lead_s = nullptr, *lead_g = nullptr, *lead_tot_s = nullptr, *lead_tot_g = nullptr, *lead_off_s = nullptr,
-      *lead_off_g = nullptr;
   bool mlp_set = false;
   double mlp_rmin = 0.0, mlp_rmax = -1.0;
   bool psm_exact = true;           // some PSM cut cell needs supersampling
@@ -404,9 +397,6 @@ lbmps_status rebuild_psm(lbmps_ctx* c) {
                             c->pairs, c->st));
   HIPCHK(c, launch_psm_cellmap(1, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap, c->st));
   HIPCHK(c, launch_psm_cellmap(2, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap, c->st));
-  HIPCHK(c, launch_psm_leaders(c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap, c->lead_tot_s,
-                               c->lead_tot_g, c->lead_off_s, c->lead_off_g, c->lead_s, c->lead_g, c->counts + 5,
-                               c->counts + 6, c->counts + 8, err, c->st));
   return LBMPS_OK;
 }
 
@@ -567,16 +557,6 @@ lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* ws, s
     c->cut_x = L.learned ? (float*)(w + L.o_cutx) : nullptr;
     c->mlp_p = (float*)(w + L.o_mlp);
     c->judge = (double*)(w + L.o_judge);
-  }
-  {
-    const size_t nb = ((size_t)L.pair_cap + 255) / 256;
-    char* b = w + L.o_leaders;
-    c->lead_s = (int*)b; b += align_up((size_t)L.pair_cap * 4);
-    c->lead_g = (int*)b; b += align_up((size_t)L.pair_cap * 4);
-    c->lead_tot_s = (int*)b; b += align_up(nb * 4);
-    c->lead_tot_g = (int*)b; b += align_up(nb * 4);
-    c->lead_off_s = (int*)b; b += align_up(nb * 4);
-    c->lead_off_g = (int*)b;
   }
 
   // instance table and sweep tiles
@@ -864,8 +844,8 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
     }
     if (c->n_psm) {
       if (!fused)
-        HIPCHK(c, launch_psm_collide(L.prec, c->lead_s, c->counts + 5, c->lead_g, c->counts + 6, c->inst_d, c->parts,
-                                     c->pairs, src, dst, !(c->cfg[0].sweep_flags & SWEEP_PSM_NOSPLIT), c->st));
+        HIPCHK(c, launch_psm_collide(L.prec, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap,
+                                     src, dst, c->st));
       HIPCHK(c, launch_reduce(psm_list(c), c->n_psm, c->pbeg, c->pend, 0, c->pairs.out, c->pairs.ostride, c->parts,
                               c->st));
     }

@@ -9,13 +9,9 @@ namespace lbm {
 // ---- sweep.hip
 // sweep_flags: bit 0 non-temporal loads; bit 1 collide PSM cells inside the
 // sweep; bit 2 (or neither) collide them in the separate overlap kernel;
-// bit 3 the sweep compiled for six waves per SIMD (4- and 2-byte storage);
-// bit 4 the separate PSM pass without its light kernel for single-particle
-// cells with B = 1.  Results never depend on them.
-enum {
-  SWEEP_NT_LOADS = 1, SWEEP_PSM_FUSED = 2, SWEEP_PSM_SEPARATE = 4, SWEEP_OCC6 = 8, SWEEP_PSM_NOSPLIT = 16,
-  SWEEP_FLAGS_ALL = 31
-};
+// bit 3 the sweep compiled for six waves per SIMD (4- and 2-byte storage).
+// Results never depend on them.
+enum { SWEEP_NT_LOADS = 1, SWEEP_PSM_FUSED = 2, SWEEP_PSM_SEPARATE = 4, SWEEP_OCC6 = 8, SWEEP_FLAGS_ALL = 15 };
 hipError_t launch_sweep(int prec, const InstDev* insts, const int4* tiles, int ntiles, int grid, int block,
                         int max_tile_cells, int flags, const void* src, void* dst, const int* cellmap, PairDev pairs,
                         PartDev parts, hipStream_t st);
@@ -79,12 +75,8 @@ hipError_t launch_psm_fill(const int* list, int nlist, int side, int nsplit, con
                            const int* slots, const int* offsets, int cap, PairDev pairs, hipStream_t st);
 hipError_t launch_psm_cellmap(int stage, const int* count, int cap, const InstDev* insts, PartDev parts,
                               PairDev pairs, int* cellmap, hipStream_t st);
-hipError_t launch_psm_leaders(const int* count, int cap, const InstDev* insts, PartDev parts, PairDev pairs,
-                              const int* cellmap, int* tot_s, int* tot_g, int* off_s, int* off_g, int* list_s,
-                              int* list_g, int* n_s, int* n_g, int* scratch4, unsigned* err, hipStream_t st);
-hipError_t launch_psm_collide(int prec, const int* list_s, const int* n_s, const int* list_g, const int* n_g,
-                              const InstDev* insts, PartDev parts, PairDev pairs, const void* src, void* dst,
-                              bool split, hipStream_t st);
+hipError_t launch_psm_collide(int prec, const int* count, int cap, const InstDev* insts, PartDev parts,
+                              PairDev pairs, const int* cellmap, const void* src, void* dst, hipStream_t st);
 hipError_t launch_psm_fields(int prec, const int* count, int cap, const InstDev* insts, PartDev parts, PairDev pairs,
                              const int* cellmap, const void* buf, int inst, long long c0, long long n, double* out,
                              hipStream_t st);

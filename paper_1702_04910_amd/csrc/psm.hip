@@ -533,97 +533,21 @@ hipError_t launch_psm_cellmap(int stage, const int* count, int cap, const InstDe
   return hipGetLastError();
 }
 
-// Leader lists: the overlapped cells (their leader pairs) split into
-// single-particle cells with B = 1 and the others, each in pair order, built
-// with per-workgroup counts, a scan and a fill (no atomics).  The two kinds
-// go to different kernels: interior cells would otherwise wait, lane by lane,
-// on the heavy general path of the cut cells in the same wave.
-__device__ __forceinline__ void leader_kind(const int* __restrict__ count, int cap, const InstDev* __restrict__ insts,
-                                            const PartDev& P, const PairDev& pairs, const int* __restrict__ cellmap,
-                                            int L, int& simple, int& general) {
-  simple = general = 0;
-  if (L >= min(*count, cap)) return;
-  const InstDev& I = insts[P.inst[pairs.p[L]]];
-  if (cellmap[I.cellmap_off + pairs.cell[L]] != L) return;
-  if (psm_simple_cell(pairs, L)) simple = 1;
-  else general = 1;
-}
-
-__global__ __launch_bounds__(256) void psm_leaders_count_kernel(const int* __restrict__ count, int cap,
-                                                                const InstDev* __restrict__ insts, PartDev P,
-                                                                PairDev pairs, const int* __restrict__ cellmap,
-                                                                int* __restrict__ tot_s, int* __restrict__ tot_g) {
-  __shared__ int sh[256];
-  int a, b, ta, tb;
-  leader_kind(count, cap, insts, P, pairs, cellmap, blockIdx.x * 256 + threadIdx.x, a, b);
-  block_excl_scan256(a, sh, &ta);
-  block_excl_scan256(b, sh, &tb);
-  if (threadIdx.x == 0) {
-    tot_s[blockIdx.x] = ta;
-    tot_g[blockIdx.x] = tb;
-  }
-}
-
-__global__ __launch_bounds__(256) void psm_leaders_fill_kernel(const int* __restrict__ count, int cap,
-                                                               const InstDev* __restrict__ insts, PartDev P,
-                                                               PairDev pairs, const int* __restrict__ cellmap,
-                                                               const int* __restrict__ off_s,
-                                                               const int* __restrict__ off_g, int* __restrict__ list_s,
-                                                               int* __restrict__ list_g) {
-  __shared__ int sh[256];
-  const int L = blockIdx.x * 256 + threadIdx.x;
-  int a, b, ta, tb;
-  leader_kind(count, cap, insts, P, pairs, cellmap, L, a, b);
-  const int ra = block_excl_scan256(a, sh, &ta);
-  const int rb = block_excl_scan256(b, sh, &tb);
-  if (a) list_s[off_s[blockIdx.x] + ra] = L;
-  if (b) list_g[off_g[blockIdx.x] + rb] = L;
-}
-
-// Single-particle cells with B = 1 (psm_single_cell): a light kernel that
-// streams each value out as soon as it is computed and keeps few registers.
+// Every overlapped cell, visited through its leader pair in pair order (the
+// list is ordered by particle, slab and row, so neighbouring lanes touch
+// neighbouring cells and share cache lines).
 template <typename S>
-__global__ __launch_bounds__(256) void psm_collide_simple_kernel(const int* __restrict__ list,
-                                                                 const int* __restrict__ nlist,
-                                                                 const InstDev* __restrict__ insts, PartDev P,
-                                                                 PairDev pairs, const S* __restrict__ src,
-                                                                 S* __restrict__ dst) {
-  using R = typename CompOf<S>::type;
-  const int n = *nlist;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const int L = list[i];
-    const int p0 = pairs.p[L];
-    const InstDev& I = insts[P.inst[p0]];
-    const int c = pairs.cell[L];
-    const S* s = src + I.pdf_off;
-    S* d = dst + I.pdf_off;
-    R g[Q];
-#pragma unroll
-    for (int q = 0; q < Q; ++q) g[q] = Codec<S>::ld(s[pdf_at(c, q)]);
-    const int nx = I.nx, ny = I.ny, nz = I.nz;
-    const int x = c % nx, yz = c / nx, y = yz % ny, z = yz / ny;
-    double F6[6];
-    psm_single_cell<R>(g, I, P, p0, c, F6, [&](int q, R v) {
-      const int xa = wrapi(x + cx(q), nx), ya = wrapi(y + cy(q), ny), za = wrapi(z + cz(q), nz);
-      d[pdf_at(((long long)za * ny + ya) * nx + xa, q)] = Codec<S>::st(v);
-    });
-    store_pair_out(pairs, L, F6);
-  }
-}
-
-// Any overlapped cell (the general per-cell function), over a leader list.
-template <typename S>
-__global__ __launch_bounds__(256) void psm_collide_kernel(const int* __restrict__ list, const int* __restrict__ nlist,
+__global__ __launch_bounds__(256) void psm_collide_kernel(const int* __restrict__ count, int cap,
                                                           const InstDev* __restrict__ insts, PartDev P,
-                                                          PairDev pairs, const S* __restrict__ src,
-                                                          S* __restrict__ dst) {
+                                                          PairDev pairs, const int* __restrict__ cellmap,
+                                                          const S* __restrict__ src, S* __restrict__ dst) {
   using R = typename CompOf<S>::type;
-  const int n = *nlist;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const int L = list[i];
+  const int npairs = min(*count, cap);
+  for (int L = blockIdx.x * blockDim.x + threadIdx.x; L < npairs; L += gridDim.x * blockDim.x) {
     const int p0 = pairs.p[L];
     const InstDev& I = insts[P.inst[p0]];
     const int c = pairs.cell[L];
+    if (cellmap[I.cellmap_off + c] != L) continue;  // not the cell's leader
     const S* s = src + I.pdf_off;
     S* d = dst + I.pdf_off;
     R g[Q], out[Q];
@@ -649,35 +573,11 @@ __global__ __launch_bounds__(256) void psm_collide_kernel(const int* __restrict_
     default: return hipErrorInvalidValue;                 \
   }
 
-hipError_t launch_psm_leaders(const int* count, int cap, const InstDev* insts, PartDev parts, PairDev pairs,
-                              const int* cellmap, int* tot_s, int* tot_g, int* off_s, int* off_g, int* list_s,
-                              int* list_g, int* n_s, int* n_g, int* scratch4, unsigned* err, hipStream_t st) {
-  const int nb = (cap + 255) / 256;
-  if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL(psm_leaders_count_kernel, dim3(nb), dim3(256), 0, st, count, cap, insts, parts, pairs, cellmap,
-                     tot_s, tot_g);
-  hipError_t e = launch_scan(tot_s, off_s, nb, nb, 1, scratch4, scratch4 + 1, n_s, cap, err, 0u, st);
-  if (e != hipSuccess) return e;
-  e = launch_scan(tot_g, off_g, nb, nb, 1, scratch4 + 2, scratch4 + 3, n_g, cap, err, 0u, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(psm_leaders_fill_kernel, dim3(nb), dim3(256), 0, st, count, cap, insts, parts, pairs, cellmap,
-                     off_s, off_g, list_s, list_g);
-  return hipGetLastError();
-}
-
-hipError_t launch_psm_collide(int prec, const int* list_s, const int* n_s, const int* list_g, const int* n_g,
-                              const InstDev* insts, PartDev parts, PairDev pairs, const void* src, void* dst,
-                              bool split, hipStream_t st) {
+hipError_t launch_psm_collide(int prec, const int* count, int cap, const InstDev* insts, PartDev parts,
+                              PairDev pairs, const int* cellmap, const void* src, void* dst, hipStream_t st) {
   const int grid = 2048;
-  if (split) {
-    LBM_DISPATCH(prec, hipLaunchKernelGGL(psm_collide_simple_kernel<S>, dim3(4 * grid), dim3(256), 0, st, list_s, n_s,
-                                          insts, parts, pairs, (const S*)src, (S*)dst));
-  } else {
-    LBM_DISPATCH(prec, hipLaunchKernelGGL(psm_collide_kernel<S>, dim3(grid), dim3(256), 0, st, list_s, n_s, insts,
-                                          parts, pairs, (const S*)src, (S*)dst));
-  }
-  LBM_DISPATCH(prec, hipLaunchKernelGGL(psm_collide_kernel<S>, dim3(grid), dim3(256), 0, st, list_g, n_g, insts, parts,
-                                        pairs, (const S*)src, (S*)dst));
+  LBM_DISPATCH(prec, hipLaunchKernelGGL(psm_collide_kernel<S>, dim3(grid), dim3(256), 0, st, count, cap, insts, parts,
+                                        pairs, cellmap, (const S*)src, (S*)dst));
   return hipGetLastError();
 }
 

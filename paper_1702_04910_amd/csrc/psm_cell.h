@@ -32,83 +32,15 @@ __device__ __forceinline__ int gather_members(const PairDev& pairs, int L, int (
   return k;
 }
 
-// Equilibrium deviation of direction q, Eq. LBM_EQ minus w_q, with
-// base = delta rho - 3/2 u.u.  Recomputed where needed instead of kept in 19
-// registers per velocity: the overlap kernel is bound by memory latency and
-// lives on occupancy.
+// Equilibrium deviation, Eq. LBM_EQ minus w_q, for all q.
 template <typename R>
-__device__ __forceinline__ R geq1(int q, R base, R ux, R uy, R uz) {
-#pragma clang fp contract(off)
-  const R cu = (R)cx(q) * ux + (R)cy(q) * uy + (R)cz(q) * uz;
-  return (R)wq(q) * (base + cu * ((R)3 + (R)4.5 * cu));
-}
-
-// A cell covered by one particle p with weight B = 1 (every interior cell:
-// eps_s = 1 gives B = 1 for B1 and B2): Eq. LBM_Collide_PSM reduces to
-// f~_q = f_q + Omega_q.  emit(q, value) receives each post-collision value as
-// soon as it is known; F6 receives the force and torque of the pair.
-// Contraction into fused multiply-adds is off here and in psm_cell_collide,
-// so every caller (the overlap kernels and the sweep's inline variant)
-// produces the same bits.
-template <typename R, typename Emit>
-__device__ __forceinline__ void psm_single_cell(const R (&g)[Q], const InstDev& I, const PartDev& P, int p0, int c,
-                                                double (&F6)[6], Emit emit) {
-#pragma clang fp contract(off)
-  R drho = 0, ux = 0, uy = 0, uz = 0;
+__device__ __forceinline__ void geq_all(R drho, R ux, R uy, R uz, R (&e)[Q]) {
+  const R base = drho - (R)1.5 * (ux * ux + uy * uy + uz * uz);
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    drho += g[q];
-    ux += (R)cx(q) * g[q];
-    uy += (R)cy(q) * g[q];
-    uz += (R)cz(q) * g[q];
+    const R cu = (R)cx(q) * ux + (R)cy(q) * uy + (R)cz(q) * uz;
+    e[q] = (R)wq(q) * (base + cu * ((R)3 + (R)4.5 * cu));
   }
-  const R baseU = drho - (R)1.5 * (ux * ux + uy * uy + uz * uz);
-  const int x = c % I.nx, yz = c / I.nx, y = yz % I.ny, z = yz / I.ny;
-  const R inv_tau = (R)(1.0 / I.tau);
-  double r[3];
-  r[0] = min_image(((double)x + 0.5) - P.X[3 * p0 + 0], (double)I.nx);
-  r[1] = min_image(((double)y + 0.5) - P.X[3 * p0 + 1], (double)I.ny);
-  r[2] = min_image(((double)z + 0.5) - P.X[3 * p0 + 2], (double)I.nz);
-  const double* Up = P.U + 3 * p0;
-  const double* Wp = P.Om + 3 * p0;
-  const double v0 = Up[0] + (Wp[1] * r[2] - Wp[2] * r[1]);
-  const double v1 = Up[1] + (Wp[2] * r[0] - Wp[0] * r[2]);
-  const double v2 = Up[2] + (Wp[0] * r[1] - Wp[1] * r[0]);
-  const R vx = (R)v0, vy = (R)v1, vz = (R)v2;
-  const R baseV = drho - (R)1.5 * (vx * vx + vy * vy + vz * vz);
-  R mx = 0, my = 0, mz = 0;
-#pragma unroll
-  for (int q = 0; q < Q; ++q) {
-    const int qb = opp(q);
-    R om;
-    if (I.psm_m == 1)
-      om = (g[qb] - geq1<R>(qb, baseU, ux, uy, uz)) - (g[q] - geq1<R>(q, baseV, vx, vy, vz));
-    else if (I.psm_m == 2)
-      om = (geq1<R>(q, baseV, vx, vy, vz) - g[q]) + ((R)1 - inv_tau) * (g[q] - geq1<R>(q, baseU, ux, uy, uz));
-    else
-      om = (g[qb] - geq1<R>(qb, baseV, vx, vy, vz)) - (g[q] - geq1<R>(q, baseV, vx, vy, vz));
-    mx -= (R)cx(q) * om;
-    my -= (R)cy(q) * om;
-    mz -= (R)cz(q) * om;
-    emit(q, g[q] + om);
-  }
-  F6[0] = (double)mx;
-  F6[1] = (double)my;
-  F6[2] = (double)mz;
-  F6[3] = r[1] * F6[2] - r[2] * F6[1];
-  F6[4] = r[2] * F6[0] - r[0] * F6[2];
-  F6[5] = r[0] * F6[1] - r[1] * F6[0];
-}
-
-__device__ __forceinline__ bool psm_simple_cell(const PairDev& pairs, int L) {
-  return pairs.next[L] < 0 && pairs.B[L] == 1.0;
-}
-
-__device__ __forceinline__ void store_pair_out(const PairDev& pairs, int i, const double (&F6)[6]) {
-  double* o = pairs.out + i;
-  const long long s = pairs.ostride;
-#pragma unroll
-  for (int k = 0; k < 6; ++k) o[k * s] = F6[k];
 }
 
 // g: pre-collision deviations of cell c (instance I), L: the cell's leader
@@ -117,13 +49,6 @@ __device__ __forceinline__ void store_pair_out(const PairDev& pairs, int i, cons
 template <typename R>
 __device__ __forceinline__ void psm_cell_collide(const R (&g)[Q], R (&out)[Q], const InstDev& I, const PartDev& P,
                                                  const PairDev& pairs, int L, int c) {
-#pragma clang fp contract(off)
-  if (psm_simple_cell(pairs, L)) {
-    double F6[6];
-    psm_single_cell<R>(g, I, P, pairs.p[L], c, F6, [&](int q, R v) { out[q] = v; });
-    store_pair_out(pairs, L, F6);
-    return;
-  }
   int mem[KMAX];
   const int k = gather_members(pairs, L, mem);
   R drho = 0, ux = 0, uy = 0, uz = 0;
@@ -134,7 +59,8 @@ __device__ __forceinline__ void psm_cell_collide(const R (&g)[Q], R (&out)[Q], c
     uy += (R)cy(q) * g[q];
     uz += (R)cz(q) * g[q];
   }
-  const R baseU = drho - (R)1.5 * (ux * ux + uy * uy + uz * uz);
+  R eU[Q];
+  geq_all<R>(drho, ux, uy, uz, eU);
   const R lp = (R)I.lam_p, lm = (R)I.lam_m;
   const R fx = (R)I.fext[0], fy = (R)I.fext[1], fz = (R)I.fext[2];
   const R fu = ux * fx + uy * fy + uz * fz;
@@ -166,20 +92,17 @@ __device__ __forceinline__ void psm_cell_collide(const R (&g)[Q], R (&out)[Q], c
     const double v0 = Up[0] + (Wp[1] * r[2] - Wp[2] * r[1]);
     const double v1 = Up[1] + (Wp[2] * r[0] - Wp[0] * r[2]);
     const double v2 = Up[2] + (Wp[0] * r[1] - Wp[1] * r[0]);
-    const R vx = (R)v0, vy = (R)v1, vz = (R)v2;
-    const R baseV = drho - (R)1.5 * (vx * vx + vy * vy + vz * vz);
+    R eV[Q];
+    geq_all<R>(drho, (R)v0, (R)v1, (R)v2, eV);
     const R B = (R)Bs[m];
     R mx = 0, my = 0, mz = 0;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int qb = opp(q);
       R om;
-      if (I.psm_m == 1)
-        om = (g[qb] - geq1<R>(qb, baseU, ux, uy, uz)) - (g[q] - geq1<R>(q, baseV, vx, vy, vz));
-      else if (I.psm_m == 2)
-        om = (geq1<R>(q, baseV, vx, vy, vz) - g[q]) + ((R)1 - inv_tau) * (g[q] - geq1<R>(q, baseU, ux, uy, uz));
-      else
-        om = (g[qb] - geq1<R>(qb, baseV, vx, vy, vz)) - (g[q] - geq1<R>(q, baseV, vx, vy, vz));
+      if (I.psm_m == 1) om = (g[qb] - eU[qb]) - (g[q] - eV[q]);
+      else if (I.psm_m == 2) om = (eV[q] - g[q]) + ((R)1 - inv_tau) * (g[q] - eU[q]);
+      else om = (g[qb] - eV[qb]) - (g[q] - eV[q]);
       acc[q] += B * om;
       mx -= (R)cx(q) * om;
       my -= (R)cy(q) * om;
@@ -187,13 +110,20 @@ __device__ __forceinline__ void psm_cell_collide(const R (&g)[Q], R (&out)[Q], c
     }
     // F_s = B_s sum_q Omega_q c_qbar, T_s = (x_s - X_p) x F_s
     const double Fx = Bs[m] * (double)mx, Fy = Bs[m] * (double)my, Fz = Bs[m] * (double)mz;
-    const double F6[6] = {Fx, Fy, Fz, r[1] * Fz - r[2] * Fy, r[2] * Fx - r[0] * Fz, r[0] * Fy - r[1] * Fx};
-    store_pair_out(pairs, mem[m], F6);
+    double* o = pairs.out + mem[m];
+    const long long s = pairs.ostride;
+    o[0] = Fx;
+    o[s] = Fy;
+    o[2 * s] = Fz;
+    o[3 * s] = r[1] * Fz - r[2] * Fy;
+    o[4 * s] = r[2] * Fx - r[0] * Fz;
+    o[5 * s] = r[0] * Fy - r[1] * Fx;
   }
   const R omB = (R)(1.0 - Bsum);
   // fluid operator and forcing, then Eq. LBM_Collide_PSM
   {
-    const R C0 = lp * (g[0] - (R)wq(0) * baseU);
+    const R base = drho - (R)1.5 * (ux * ux + uy * uy + uz * uz);
+    const R C0 = lp * (g[0] - (R)wq(0) * base);
     const R F0 = -(R)wq(0) * (R)3 * fu;
     out[0] = g[0] + omB * C0 + acc[0] + omB * F0;
 #pragma unroll
@@ -203,8 +133,7 @@ __device__ __forceinline__ void psm_cell_collide(const R (&g)[Q], R (&out)[Q], c
       const R cu = (R)cx(qa) * ux + (R)cy(qa) * uy + (R)cz(qa) * uz;
       const R cf = (R)cx(qa) * fx + (R)cy(qa) * fy + (R)cz(qa) * fz;
       const R gp = (R)0.5 * (g[qa] + g[qb]), gm = (R)0.5 * (g[qa] - g[qb]);
-      const R eUa = geq1<R>(qa, baseU, ux, uy, uz), eUb = geq1<R>(qb, baseU, ux, uy, uz);
-      const R ep = (R)0.5 * (eUa + eUb), em = (R)0.5 * (eUa - eUb);
+      const R ep = (R)0.5 * (eU[qa] + eU[qb]), em = (R)0.5 * (eU[qa] - eU[qb]);
       const R cp = lp * (gp - ep), cm = lm * (gm - em);
       const R Fp = w * ((R)9 * cu * cf - (R)3 * fu), Fm = w * ((R)3 * cf);
       out[qa] = g[qa] + omB * (cp + cm) + acc[qa] + omB * (Fp + Fm);

@@ -258,24 +258,3 @@ def test_six_wave_sweep_build_is_bitwise_identical(precision):
         out.append(sim.get_pdfs())
         sim.close()
     assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
-
-
-@pytest.mark.parametrize("m,b", [(1, 1), (2, 2), (3, 2)])
-def test_psm_light_kernel_for_interior_cells_is_bitwise_identical(m, b):
-    # single-particle cells with B = 1 take the light overlap kernel; the
-    # general kernel alone must give the same bits
-    from paper_1702_04910_amd import lbmps
-
-    parts = dict(X=[[10.2, 12.1, 12.3], [17.4, 12.6, 12.0]], U=[[0.01, 0, 0], [-0.005, 0.004, 0]],
-                 Om=[[0, 0, 0.001], [0, 0.002, 0]], D=[7.0, 6.5], rho=[1.5, 1.3], fixed=[False, False])
-    res = []
-    for flags in (0, lbmps.SWEEP_PSM_NOSPLIT):
-        ora, sim = make_pair(28, 24, 24, 0.05, coupling="psm", collision="trt", psm_m=m, psm_b=b,
-                             f_ext=(1e-5, 0, 0), gravity=(0, 0, -1e-4), parts=parts, eps_n=4, n_sub=2,
-                             sweep_flags=flags)
-        sim.step(20)
-        res.append((sim.get_pdfs(), sim.particles()))
-        sim.close()
-    assert np.array_equal(res[0][0], res[1][0])
-    for k in ("F", "T", "U", "X"):
-        assert np.array_equal(res[0][1][k], res[1][1][k]), k
