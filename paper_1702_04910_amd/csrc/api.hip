@@ -44,12 +44,14 @@ struct Layout {
   std::vector<int> part_begin;
   long long pdf_elems = 0, owner_elems = 0, cellmap_elems = 0;
   int link_cap = 0, wall_cap = 0, pair_cap = 0, refill_cap = 0, cut_cap = 0;
+  int red_blocks = 1;   // reduction workgroups per particle
+  int link_blocks = 1;  // link-kernel workgroups per particle
   bool learned = false;  // some instance estimates eps_s with the network
   long long slot_elems = 0;
   int box_total = 0;  // ptotal * side * side: work units at the finest split
   long long chunk = 0;
   // byte offsets
-  size_t o_bufA, o_bufB, o_owner, o_cellmap, o_inst, o_parts, o_plists, o_slots, o_totals, o_offsets, o_ranges,
+  size_t o_bufA, o_bufB, o_owner, o_cellmap, o_inst, o_parts, o_plists, o_slots, o_totals, o_offsets, o_totals2, o_offsets2, o_ranges, o_red,
       o_counts, o_links, o_wallv, o_pairs, o_refill, o_scratch, o_tiles, o_cuts, o_cutx, o_mlp, o_judge, total;
   int ntiles = 0;
   int max_tile_cells = 0;
@@ -148,8 +150,13 @@ Layout make_layout(int n, const lbmps_config* cfgs) {
     L.part_begin.push_back(L.ptotal);
     L.ptotal += c.max_particles;
     const long long sd = L.side;
-    links += (long long)c.max_particles * 40 * sd * sd;
-    pairs += (long long)c.max_particles * (long long)std::ceil(4.2 * std::pow(rmax + 1.8, 3));
+    const long long lp = 40 * sd * sd, pp = (long long)std::ceil(4.2 * std::pow(rmax + 1.8, 3));
+    links += (long long)c.max_particles * lp;
+    pairs += (long long)c.max_particles * pp;
+    if (c.max_particles > 0 && c.coupling == LBMPS_PSM)
+      L.red_blocks = (int)std::max<long long>(L.red_blocks, (pp + RED_CHUNK - 1) / RED_CHUNK);
+    if (c.max_particles > 0 && c.coupling != LBMPS_PSM)
+      L.link_blocks = (int)std::max<long long>(L.link_blocks, (lp + SUM_THREADS - 1) / SUM_THREADS);
     if (c.coupling == LBMPS_PSM) {
       // cells cut by a sphere surface lie within sqrt(3)/2 of it: a shell of
       // volume below 8 pi (R + 1)^2
@@ -189,9 +196,12 @@ Layout make_layout(int n, const lbmps_config* cfgs) {
   L.o_slots = take((size_t)L.slot_elems * 4);
   L.o_totals = take((size_t)L.box_total * 4);
   L.o_offsets = take((size_t)L.box_total * 4);
+  L.o_totals2 = take((size_t)L.box_total * 4);
+  L.o_offsets2 = take((size_t)L.box_total * 4);
   L.o_ranges = take((size_t)L.ptotal * 8 * 4);
+  L.o_red = take((size_t)L.ptotal * (std::max(L.red_blocks, L.link_blocks) * 6 * 8 + 4));
   L.o_counts = take(16 * 4);
-  L.o_links = take((size_t)(L.link_cap + L.wall_cap) * (5 * 4 + 8 + 6 * 8) + 2 * ALIGN);
+  L.o_links = take((size_t)(L.link_cap + L.wall_cap) * (5 * 4 + 8) + 2 * ALIGN);
   L.o_wallv = take((size_t)n * 16 * 3 * 8);
   L.o_pairs = take((size_t)L.pair_cap * (3 * 4 + 2 * 8 + 6 * 8) + 2 * ALIGN);
   L.o_refill = take((size_t)L.refill_cap * 2 * 4);
@@ -231,6 +241,10 @@ struct lbmps_ctx {
   int* slots = nullptr;
   int* totals = nullptr;
   int* offsets = nullptr;
+  int* totals2 = nullptr;  // second per-unit count (refill cells of the MEM remap)
+  int* offsets2 = nullptr;
+  double* red_partial = nullptr;  // per-chunk force/torque sums
+  unsigned* red_arrivals = nullptr;
   int *lbeg = nullptr, *lend = nullptr, *pbeg = nullptr, *pend = nullptr, *rbeg = nullptr, *rend = nullptr,
       *cbeg = nullptr, *cend = nullptr;
   int* counts = nullptr;  // [0] links, [1] pairs, [2] refill, [4] error bits (unsigned)
@@ -336,22 +350,24 @@ lbmps_status rebuild_mem(lbmps_ctx* c, bool refill) {
   unsigned* err = err_word(c);
   const int ns = nsplit_for(c->n_mem, L.side);
   const int units = L.side * ns;
-  if (refill) {
-    HIPCHK(c, launch_mem_count(1, mem_list(c), c->n_mem, L.side, ns, c->inst_d, c->parts, c->owner, c->slots,
-                               c->totals, c->st));
-    HIPCHK(c, launch_scan(c->totals, c->offsets, c->n_mem * units, units, c->n_mem, c->rbeg, c->rend, c->counts + 2,
-                          L.refill_cap, err, ERR_REFILL_CAP, c->st));
-    HIPCHK(c, launch_mem_fill_refill(mem_list(c), c->n_mem, L.side, ns, c->inst_d, c->parts, c->owner, c->slots,
-                                     c->offsets, L.refill_cap, c->rcell, c->rpart, c->st));
+  // one pass counts links and uncovered cells, one launch scans both, one
+  // pass writes both lists; the refill only reads the owner field, so it can
+  // follow the link list
+  HIPCHK(c, launch_mem_count(refill, mem_list(c), c->n_mem, L.side, ns, c->inst_d, c->parts, c->owner,
+                             c->slots, c->totals, c->totals2, c->st));
+  if (refill)
+    HIPCHK(c, launch_scan2(c->totals, c->offsets, c->n_mem * units, units, c->n_mem, c->lbeg, c->lend, c->counts + 0,
+                           L.link_cap, ERR_LINK_CAP, c->totals2, c->offsets2, c->n_mem * units, units, c->n_mem,
+                           c->rbeg, c->rend, c->counts + 2, L.refill_cap, ERR_REFILL_CAP, err, c->st));
+  else
+    HIPCHK(c, launch_scan(c->totals, c->offsets, c->n_mem * units, units, c->n_mem, c->lbeg, c->lend, c->counts + 0,
+                          L.link_cap, err, ERR_LINK_CAP, c->st));
+  HIPCHK(c, launch_mem_fill_links(mem_list(c), c->n_mem, L.side, ns, c->inst_d, c->parts, c->owner, c->slots,
+                                  c->offsets, c->n_wall, L.link_cap, c->links, c->offsets2, L.refill_cap,
+                                  refill ? c->rcell : nullptr, c->rpart, c->st));
+  if (refill)
     HIPCHK(c, launch_mem_refill(L.prec, c->counts + 2, L.refill_cap, c->rcell, c->rpart, c->inst_d, c->parts, c->owner,
                                 c->buf[c->cur], c->st));
-  }
-  HIPCHK(c, launch_mem_count(0, mem_list(c), c->n_mem, L.side, ns, c->inst_d, c->parts, c->owner, c->slots, c->totals,
-                             c->st));
-  HIPCHK(c, launch_scan(c->totals, c->offsets, c->n_mem * units, units, c->n_mem, c->lbeg, c->lend, c->counts + 0,
-                        L.link_cap, err, ERR_LINK_CAP, c->st));
-  HIPCHK(c, launch_mem_fill_links(mem_list(c), c->n_mem, L.side, ns, c->inst_d, c->parts, c->owner, c->slots,
-                                  c->offsets, c->n_wall, L.link_cap, c->links, c->st));
   HIPCHK(c, launch_mem_clear_was(mem_list(c), c->n_mem, L.side, ns, c->inst_d, c->parts, c->owner, c->st));
   return LBMPS_OK;
 }
@@ -509,6 +525,8 @@ lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* ws, s
   c->slots = (int*)(w + L.o_slots);
   c->totals = (int*)(w + L.o_totals);
   c->offsets = (int*)(w + L.o_offsets);
+  c->totals2 = (int*)(w + L.o_totals2);
+  c->offsets2 = (int*)(w + L.o_offsets2);
   {
     int* r = (int*)(w + L.o_ranges);
     const int P = L.ptotal;
@@ -516,6 +534,8 @@ lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* ws, s
     c->cbeg = r + 6 * P; c->cend = r + 7 * P;
   }
   c->counts = (int*)(w + L.o_counts);
+  c->red_partial = (double*)(w + L.o_red);
+  c->red_arrivals = (unsigned*)(w + L.o_red + (size_t)L.ptotal * std::max(L.red_blocks, L.link_blocks) * 6 * 8);
   {
     const size_t nl = (size_t)L.link_cap + L.wall_cap;
     char* b = w + L.o_links;
@@ -525,9 +545,7 @@ lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* ws, s
     c->links.inst = (int*)b; b += nl * 4;
     c->links.cli_ok = (int*)b; b += nl * 4;
     b = w + L.o_links + align_up(nl * 20);
-    c->links.delta = (double*)b; b += nl * 8;
-    c->links.out = (double*)b;
-    c->links.ostride = (long long)nl;
+    c->links.delta = (double*)b;
   }
   c->wall_v = (double*)(w + L.o_wallv);
   {
@@ -608,6 +626,7 @@ lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* ws, s
   bail(hipMemcpyAsync(c->inst_d, c->inst_h.data(), sizeof(InstDev) * n, hipMemcpyHostToDevice, c->st), "copy instances");
   bail(hipMemcpyAsync(c->tiles_d, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, c->st), "copy tiles");
   bail(hipMemsetAsync(c->counts, 0, 16 * 4, c->st), "clear counters");
+  bail(hipMemsetAsync(c->red_arrivals, 0, (size_t)L.ptotal * 4, c->st), "clear reduction counters");
   bail(hipMemsetAsync(w + L.o_parts, 0, L.o_plists - L.o_parts, c->st), "clear particles");
   if (s == LBMPS_OK) s = fill_int(c, c->owner, L.owner_elems, OWN_FLUID);
   if (s == LBMPS_OK) s = fill_int(c, c->cellmap, L.cellmap_elems, 0x7fffffff);
@@ -842,31 +861,29 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
       HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->st));
       c->ev_used += 2;
     }
+    // the reduction that completes a rigid-body step also takes it
+    const bool psm_rb = c->n_psm && ((c->sweeps + 1) % L.psm_nsub) == 0;
+    const bool mem_rb = c->n_mem && ((c->sweeps + 1) % L.mem_nsub) == 0;
     if (c->n_psm) {
       if (!fused)
         HIPCHK(c, launch_psm_collide(L.prec, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap,
                                      src, dst, c->st));
       HIPCHK(c, launch_reduce(psm_list(c), c->n_psm, c->pbeg, c->pend, 0, c->pairs.out, c->pairs.ostride, c->parts,
+                              L.red_blocks, c->red_partial, c->red_arrivals, psm_rb ? c->inst_d : nullptr, err,
                               c->st));
     }
     if (c->n_mem || c->n_wall) {
-      HIPCHK(c, launch_links_bc(L.prec, c->n_wall, c->counts + 0, L.link_cap, c->links, c->wall_v, c->inst_d, c->parts,
-                                dst, c->st));
-      if (c->n_mem)
-        HIPCHK(c, launch_reduce(mem_list(c), c->n_mem, c->lbeg, c->lend, c->n_wall, c->links.out, c->links.ostride,
-                                c->parts, c->st));
+      HIPCHK(c, launch_links_bc(L.prec, c->n_wall, mem_list(c), c->n_mem, c->lbeg, c->lend, L.link_blocks, c->links,
+                                c->wall_v, c->inst_d, c->parts, dst, c->red_partial, c->red_arrivals,
+                                mem_rb ? c->inst_d : nullptr, err, c->st));
     }
     c->cur = 1 - c->cur;
     c->sweeps++;
-    if (c->n_psm && (c->sweeps % L.psm_nsub) == 0) {
-      HIPCHK(c, launch_rigid(psm_list(c), c->n_psm, c->inst_d, c->parts, err, c->st));
-      if (c->psm_moving) {
-        lbmps_status r = rebuild_psm(c);
-        if (r) return r;
-      }
+    if (psm_rb && c->psm_moving) {
+      lbmps_status r = rebuild_psm(c);
+      if (r) return r;
     }
-    if (c->n_mem && (c->sweeps % L.mem_nsub) == 0) {
-      HIPCHK(c, launch_rigid(mem_list(c), c->n_mem, c->inst_d, c->parts, err, c->st));
+    if (mem_rb) {
       if (c->mem_moving) {
         lbmps_status r = remap_mem(c);
         if (r) return r;

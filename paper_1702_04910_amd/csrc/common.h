@@ -93,9 +93,6 @@ struct PartDev {
 struct LinkDev {
   int *cell, *q, *p, *inst, *cli_ok;  // p >= 0 particle, p <= -2 wall group
   double *delta;
-  double *out;                         // 6 components per link, component k at out[k * ostride + link]:
-                                       // F^q (deviation part), (x_b - X_p) x F^q
-  long long ostride;
 };
 
 // PSM (cell, particle) overlap pairs.

@@ -28,33 +28,47 @@ hipError_t launch_fields(int prec, const void* buf, long long N, long long c0, l
 // [begin, end).  Sets err_bit in *err when the total exceeds cap.
 hipError_t launch_scan(const int* totals, int* offsets, int m, int side, int nlist, int* begin, int* end, int* count,
                        int cap, unsigned* err, unsigned err_bit, hipStream_t st);
-// Per-particle sum of 6-double records [begin[j], end[j]) (+ base) into Facc/Tacc of particle list[j].
-hipError_t launch_reduce(const int* list, int nlist, const int* begin, const int* end, int base, const double* out,
-                         long long ostride, PartDev parts, hipStream_t st);
-// Explicit Euler rigid-body step of the listed particles (averaging Facc over n_sub sweeps).
-hipError_t launch_rigid(const int* list, int nlist, const InstDev* insts, PartDev parts, unsigned* err,
+// Two independent scans in one launch (second array: *2 arguments).
+hipError_t launch_scan2(const int* totals, int* offsets, int m, int side, int nlist, int* begin, int* end, int* count,
+                        int cap, unsigned err_bit, const int* totals2, int* offsets2, int m2, int side2, int nlist2,
+                        int* begin2, int* end2, int* count2, int cap2, unsigned err_bit2, unsigned* err,
                         hipStream_t st);
+// Per-particle sum of 6-double records [begin[j], end[j]) (+ base) into Facc/Tacc of particle list[j],
+// nchunk_blocks workgroups per particle over chunks of RED_CHUNK records; partial holds
+// nlist * nchunk_blocks * 6 doubles, arrivals nlist counters that start (and are left) at zero.
+// With rigid_insts != nullptr, each particle's explicit Euler rigid-body step (averaging Facc over
+// n_sub sweeps) follows its sum.
+constexpr int RED_CHUNK = 1024;
+constexpr int SUM_THREADS = 256;  // workgroup size of the summing kernels (one link per thread and chunk)
+hipError_t launch_reduce(const int* list, int nlist, const int* begin, const int* end, int base, const double* out,
+                         long long ostride, PartDev parts, int nchunk_blocks, double* partial, unsigned* arrivals,
+                         const InstDev* rigid_insts, unsigned* err, hipStream_t st);
 
 // ---- mem.hip
 hipError_t launch_mem_unmap(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
                             int* owner, hipStream_t st);
 hipError_t launch_mem_map(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
                           int* owner, hipStream_t st);
-// kind 0: links, kind 1: uncovered cells (refill list)
-hipError_t launch_mem_count(int kind, const int* list, int nlist, int side, int nsplit, const InstDev* insts,
-                            PartDev parts, const int* owner, int* slots, int* totals, hipStream_t st);
+// Link masks per cell and per-unit link counts; with `uncovered`, also the
+// uncovered cells (bit 0) and their per-unit counts in totals2.
+hipError_t launch_mem_count(bool uncovered, const int* list, int nlist, int side, int nsplit, const InstDev* insts,
+                            PartDev parts, const int* owner, int* slots, int* totals, int* totals2, hipStream_t st);
+// Link list at the scanned offsets; with rcell, also the refill list at offsets2.
 hipError_t launch_mem_fill_links(const int* list, int nlist, int side, int nsplit, const InstDev* insts,
                                  PartDev parts, int* owner, const int* slots, const int* offsets, int base, int cap,
-                                 LinkDev links, hipStream_t st);
-hipError_t launch_mem_fill_refill(const int* list, int nlist, int side, int nsplit, const InstDev* insts,
-                                  PartDev parts, int* owner, const int* slots, const int* offsets, int cap, int* rcell,
-                                  int* rpart, hipStream_t st);
+                                 LinkDev links, const int* offsets2, int cap2, int* rcell, int* rpart,
+                                 hipStream_t st);
 hipError_t launch_mem_refill(int prec, const int* count, int cap, const int* rcell, const int* rpart,
                              const InstDev* insts, PartDev parts, const int* owner, void* buf, hipStream_t st);
 hipError_t launch_mem_clear_was(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
                                 int* owner, hipStream_t st);
-hipError_t launch_links_bc(int prec, int n_wall, const int* count, int cap, LinkDev links, const double* wall_v,
-                           const InstDev* insts, PartDev parts, void* buf, hipStream_t st);
+// Link rules of the wall links [0, n_wall) and of the particle links [n_wall + lbeg[j], n_wall + lend[j]) of
+// list[j], with each particle's link force and torque summed into Facc/Tacc (width workgroups per particle;
+// partial as for launch_reduce with nchunk_blocks = width) and, with rigid_insts != nullptr, its rigid-body step.
+hipError_t launch_links_bc(int prec, int n_wall, const int* list, int nlist, const int* lbeg, const int* lend,
+                           int width, LinkDev links, const double* wall_v, const InstDev* insts, PartDev parts,
+                           void* buf, double* partial, unsigned* arrivals, const InstDev* rigid_insts, unsigned* err,
+                           hipStream_t st);
 
 // ---- psm.hip
 hipError_t launch_psm_classify(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,

@@ -13,6 +13,7 @@
 // None of these slots is written by another link, so links are independent.
 #include "common.h"
 #include "kernels.h"
+#include "particle_sum.h"
 
 namespace lbm {
 
@@ -95,29 +96,30 @@ hipError_t launch_mem_map(const int* list, int nlist, int side, int nsplit, cons
   return hipGetLastError();
 }
 
-// kind 0: per fluid cell the mask of directions q whose neighbour x + c_q is a
-// solid cell of p (one link each); kind 1: 1 for a cell uncovered by p.
-__global__ __launch_bounds__(256) void mem_count_kernel(int kind, const int* __restrict__ list, int side, int nsplit,
-                                                        const InstDev* __restrict__ insts, PartDev P,
+// Per fluid cell the mask of directions q whose neighbour x + c_q is a solid
+// cell of p (one link each, bits 1..18), link counts to totals; with
+// `uncovered`, also bit 0 = the cell was uncovered by p, whose counts go to
+// totals2.
+__global__ __launch_bounds__(256) void mem_count_kernel(bool uncovered, const int* __restrict__ list, int side,
+                                                        int nsplit, const InstDev* __restrict__ insts, PartDev P,
                                                         int* __restrict__ owner, int* __restrict__ slots,
-                                                        int* __restrict__ totals) {
+                                                        int* __restrict__ totals, int* __restrict__ totals2) {
   MEM_BBOX_PROLOGUE
-  int local = 0;
+  int local = 0, local2 = 0;
   for (int c = ca; c < cb; ++c) {
     MEM_CELL_COORDS(c)
     int v = 0;
-    if (kind == 0) {
-      if (own_is_fluid(own[cell])) {
+    if (own_is_fluid(own[cell])) {
 #pragma unroll
-        for (int q = 1; q < Q; ++q) {
-          const int ni = wrapi(ci + cx(q), I.nx), nj = wrapi(cj + cy(q), I.ny), nk = wrapi(ck + cz(q), I.nz);
-          if (own[(nk * I.ny + nj) * I.nx + ni] == p) v |= 1 << q;
-        }
+      for (int q = 1; q < Q; ++q) {
+        const int ni = wrapi(ci + cx(q), I.nx), nj = wrapi(cj + cy(q), I.ny), nk = wrapi(ck + cz(q), I.nz);
+        if (own[(nk * I.ny + nj) * I.nx + ni] == p) v |= 1 << q;
       }
-      local += __popc(v);
-    } else {
-      v = own[cell] == (WAS_BIT | p) ? 1 : 0;
-      local += v;
+    }
+    local += __popc(v);
+    if (uncovered && own[cell] == (WAS_BIT | p)) {
+      v |= 1;
+      ++local2;
     }
     slots[sidx] = v;
   }
@@ -125,17 +127,23 @@ __global__ __launch_bounds__(256) void mem_count_kernel(int kind, const int* __r
   int total;
   block_excl_scan256(local, sh, &total);
   if (threadIdx.x == 0) totals[jl * (side * nsplit) + blockIdx.x] = total;
+  if (uncovered) {
+    block_excl_scan256(local2, sh, &total);
+    if (threadIdx.x == 0) totals2[jl * (side * nsplit) + blockIdx.x] = total;
+  }
 }
 
-hipError_t launch_mem_count(int kind, const int* list, int nlist, int side, int nsplit, const InstDev* insts,
-                            PartDev parts, const int* owner, int* slots, int* totals, hipStream_t st) {
+hipError_t launch_mem_count(bool uncovered, const int* list, int nlist, int side, int nsplit, const InstDev* insts,
+                            PartDev parts, const int* owner, int* slots, int* totals, int* totals2, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(mem_count_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, kind, list, side, nsplit, insts,
-                     parts, (int*)owner, slots, totals);
+  hipLaunchKernelGGL(mem_count_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, uncovered, list, side, nsplit,
+                     insts, parts, (int*)owner, slots, totals, totals2);
   return hipGetLastError();
 }
 
-// Writes the links of each fluid cell in increasing q, with delta_q = the
+// Writes the links of each fluid cell in increasing q (slot bits 1..18) and,
+// with refill lists (rcell != nullptr), the uncovered cells (slot bit 0) at
+// their own scanned offsets.  Links carry delta_q = the
 // smallest root in (0, 1] of |d + delta c|^2 = R^2 computed as e/(-b + sqrt(b^2 - a e))
 // (a = c.c, b = d.c, e = |d|^2 - R^2), and whether x - c_q is fluid (needed by
 // CLI).  Clears the "was solid" marks of the cells it visits afterwards.
@@ -143,21 +151,33 @@ __global__ __launch_bounds__(256) void mem_fill_links_kernel(const int* __restri
                                                              const InstDev* __restrict__ insts, PartDev P,
                                                              int* __restrict__ owner, const int* __restrict__ slots,
                                                              const int* __restrict__ offsets, int base, int cap,
-                                                             LinkDev L) {
+                                                             LinkDev L, const int* __restrict__ offsets2, int cap2,
+                                                             int* __restrict__ rcell, int* __restrict__ rpart) {
   MEM_BBOX_PROLOGUE
-  int local = 0;
+  int local = 0, local2 = 0;
   for (int c = ca; c < cb; ++c) {
     MEM_CELL_COORDS(c)
-    local += __popc(slots[sidx]);
+    const int m = slots[sidx];
+    local += __popc(m & ~1);
+    local2 += m & 1;
   }
   __shared__ int sh[256];
   int total;
   int pos = base + offsets[jl * (side * nsplit) + blockIdx.x] + block_excl_scan256(local, sh, &total);
+  int pos2 = 0;
+  if (rcell) pos2 = offsets2[jl * (side * nsplit) + blockIdx.x] + block_excl_scan256(local2, sh, &total);
   const double R = 0.5 * P.D[p];
   for (int c = ca; c < cb; ++c) {
     MEM_CELL_COORDS(c)
     const int m = slots[sidx];
-    if (m == 0) continue;
+    if (rcell && (m & 1)) {
+      if (pos2 < cap2) {
+        rcell[pos2] = cell;
+        rpart[pos2] = p;
+      }
+      ++pos2;
+    }
+    if ((m & ~1) == 0) continue;
     double d[3];
     disp(I, P, p, ci, cj, ck, d);
     const double e = sq3m(d[0], d[1], d[2]) - R * R;
@@ -182,10 +202,11 @@ __global__ __launch_bounds__(256) void mem_fill_links_kernel(const int* __restri
 
 hipError_t launch_mem_fill_links(const int* list, int nlist, int side, int nsplit, const InstDev* insts,
                                  PartDev parts, int* owner, const int* slots, const int* offsets, int base, int cap,
-                                 LinkDev links, hipStream_t st) {
+                                 LinkDev links, const int* offsets2, int cap2, int* rcell, int* rpart,
+                                 hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
   hipLaunchKernelGGL(mem_fill_links_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts,
-                     parts, owner, slots, offsets, base, cap, links);
+                     parts, owner, slots, offsets, base, cap, links, offsets2, cap2, rcell, rpart);
   return hipGetLastError();
 }
 
@@ -204,40 +225,6 @@ hipError_t launch_mem_clear_was(const int* list, int nlist, int side, int nsplit
   if (nlist <= 0) return hipSuccess;
   hipLaunchKernelGGL(mem_clear_was_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts,
                      parts, owner);
-  return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void mem_fill_refill_kernel(const int* __restrict__ list, int side, int nsplit,
-                                                              const InstDev* __restrict__ insts, PartDev P,
-                                                              int* __restrict__ owner, const int* __restrict__ slots,
-                                                              const int* __restrict__ offsets, int cap,
-                                                              int* __restrict__ rcell, int* __restrict__ rpart) {
-  MEM_BBOX_PROLOGUE
-  int local = 0;
-  for (int c = ca; c < cb; ++c) {
-    MEM_CELL_COORDS(c)
-    local += slots[sidx];
-  }
-  __shared__ int sh[256];
-  int total;
-  int pos = offsets[jl * (side * nsplit) + blockIdx.x] + block_excl_scan256(local, sh, &total);
-  for (int c = ca; c < cb; ++c) {
-    MEM_CELL_COORDS(c)
-    if (!slots[sidx]) continue;
-    if (pos < cap) {
-      rcell[pos] = cell;
-      rpart[pos] = p;
-    }
-    ++pos;
-  }
-}
-
-hipError_t launch_mem_fill_refill(const int* list, int nlist, int side, int nsplit, const InstDev* insts,
-                                  PartDev parts, int* owner, const int* slots, const int* offsets, int cap, int* rcell,
-                                  int* rpart, hipStream_t st) {
-  if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(mem_fill_refill_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts,
-                     parts, owner, slots, offsets, cap, rcell, rpart);
   return hipGetLastError();
 }
 
@@ -359,81 +346,126 @@ hipError_t launch_mem_refill(int prec, const int* count, int cap, const int* rce
   return hipGetLastError();
 }
 
-// Link rule and link force for links [0, n_wall + *count).  Walls (p <= -2) use
-// BB with their wall velocity; particle links use BB or CLI (CLI falls back to
-// BB where x - c_q is not fluid).  Output per particle link: the deviation part
+// Link rule and link force of link i.  Walls (p <= -2) use BB with their wall
+// velocity; particle links use BB or CLI (CLI falls back to BB where x - c_q
+// is not fluid).  For a particle link ft gets the deviation part
 // (c_q - v) g~_q + (c_q + v) g_qbar of Eq. MEM_Force and its torque about X_p.
 template <typename S>
-__global__ void links_bc_kernel(int n_wall, const int* __restrict__ count, int cap, LinkDev L,
-                                const double* __restrict__ wall_v, const InstDev* __restrict__ insts, PartDev P,
-                                S* __restrict__ buf) {
-  const int n = n_wall + min(*count, cap);
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const int inst = L.inst[i];
-    const InstDev& I = insts[inst];
-    const int cell = L.cell[i], q = L.q[i], p = L.p[i];
-    const int qb = opp(q);
-    const int x = cell % I.nx, yz = cell / I.nx, y = yz % I.ny, z = yz / I.ny;
-    const long long N = I.ncell;
-    S* b = buf + I.pdf_off;
-    const int c[3] = {cx(q), cy(q), cz(q)};
-    const int xs = wrapi(x + c[0], I.nx), ys = wrapi(y + c[1], I.ny), zs = wrapi(z + c[2], I.nz);
-    const double gtq = (double)Codec<S>::ld(b[pdf_at(((long long)zs * I.ny + ys) * I.nx + xs, q)]);
-    double v[3], arm[3] = {0, 0, 0};
-    bool cli = false;
-    double delta = 0.5;
-    if (p >= 0) {
-      cli = I.coupling == COUP_MEM_CLI && L.cli_ok[i];
-      if (cli) delta = L.delta[i];
-      double d[3];
-      disp(I, P, p, x, y, z, d);
-      for (int k = 0; k < 3; ++k) arm[k] = d[k] + delta * c[k];
-      const double* Up = P.U + 3 * p;
-      const double* Wp = P.Om + 3 * p;
-      v[0] = Up[0] + (Wp[1] * arm[2] - Wp[2] * arm[1]);
-      v[1] = Up[1] + (Wp[2] * arm[0] - Wp[0] * arm[2]);
-      v[2] = Up[2] + (Wp[0] * arm[1] - Wp[1] * arm[0]);
-    } else {
-      const int gid = -2 - p;
-      v[0] = wall_v[3 * gid];
-      v[1] = wall_v[3 * gid + 1];
-      v[2] = wall_v[3 * gid + 2];
-    }
-    const double vc = v[0] * c[0] + v[1] * c[1] + v[2] * c[2];
-    const double w = wq(q);
-    double val;
-    if (cli) {
-      const double k0 = (1.0 - 2.0 * delta) / (1.0 + 2.0 * delta);
-      const double alpha = 4.0 / (1.0 + 2.0 * delta);
-      const int xm = wrapi(x - c[0], I.nx), ym = wrapi(y - c[1], I.ny), zm = wrapi(z - c[2], I.nz);
-      const double gq_m = (double)Codec<S>::ld(b[pdf_at(cell, q)]);
-      const double gqb = (double)Codec<S>::ld(b[pdf_at(((long long)zm * I.ny + ym) * I.nx + xm, qb)]);
-      val = gtq + k0 * gq_m - k0 * gqb - 3.0 * alpha * w * vc;
-    } else {
-      val = gtq - 6.0 * w * vc;
-    }
-    const S sv = Codec<S>::st((typename CompOf<S>::type)val);
-    b[pdf_at(cell, qb)] = sv;
-    if (p >= 0) {
-      const double vs = (double)Codec<S>::ld(sv);
-      double F[3];
-      for (int k = 0; k < 3; ++k) F[k] = (c[k] - v[k]) * gtq + (c[k] + v[k]) * vs;
-      double* o = L.out + i;
-      const long long s = L.ostride;
-      o[0] = F[0];
-      o[s] = F[1];
-      o[2 * s] = F[2];
-      o[3 * s] = arm[1] * F[2] - arm[2] * F[1];
-      o[4 * s] = arm[2] * F[0] - arm[0] * F[2];
-      o[5 * s] = arm[0] * F[1] - arm[1] * F[0];
-    }
+__device__ __forceinline__ void link_rule(int i, const LinkDev& L, const double* __restrict__ wall_v,
+                                          const InstDev* __restrict__ insts, const PartDev& P, S* __restrict__ buf,
+                                          double (&ft)[6]) {
+  const int inst = L.inst[i];
+  const InstDev& I = insts[inst];
+  const int cell = L.cell[i], q = L.q[i], p = L.p[i];
+  const int qb = opp(q);
+  const int x = cell % I.nx, yz = cell / I.nx, y = yz % I.ny, z = yz / I.ny;
+  S* b = buf + I.pdf_off;
+  const int c[3] = {cx(q), cy(q), cz(q)};
+  const int xs = wrapi(x + c[0], I.nx), ys = wrapi(y + c[1], I.ny), zs = wrapi(z + c[2], I.nz);
+  const double gtq = (double)Codec<S>::ld(b[pdf_at(((long long)zs * I.ny + ys) * I.nx + xs, q)]);
+  double v[3], arm[3] = {0, 0, 0};
+  bool cli = false;
+  double delta = 0.5;
+  if (p >= 0) {
+    cli = I.coupling == COUP_MEM_CLI && L.cli_ok[i];
+    if (cli) delta = L.delta[i];
+    double d[3];
+    disp(I, P, p, x, y, z, d);
+    for (int k = 0; k < 3; ++k) arm[k] = d[k] + delta * c[k];
+    const double* Up = P.U + 3 * p;
+    const double* Wp = P.Om + 3 * p;
+    v[0] = Up[0] + (Wp[1] * arm[2] - Wp[2] * arm[1]);
+    v[1] = Up[1] + (Wp[2] * arm[0] - Wp[0] * arm[2]);
+    v[2] = Up[2] + (Wp[0] * arm[1] - Wp[1] * arm[0]);
+  } else {
+    const int gid = -2 - p;
+    v[0] = wall_v[3 * gid];
+    v[1] = wall_v[3 * gid + 1];
+    v[2] = wall_v[3 * gid + 2];
+  }
+  const double vc = v[0] * c[0] + v[1] * c[1] + v[2] * c[2];
+  const double w = wq(q);
+  double val;
+  if (cli) {
+    const double k0 = (1.0 - 2.0 * delta) / (1.0 + 2.0 * delta);
+    const double alpha = 4.0 / (1.0 + 2.0 * delta);
+    const int xm = wrapi(x - c[0], I.nx), ym = wrapi(y - c[1], I.ny), zm = wrapi(z - c[2], I.nz);
+    const double gq_m = (double)Codec<S>::ld(b[pdf_at(cell, q)]);
+    const double gqb = (double)Codec<S>::ld(b[pdf_at(((long long)zm * I.ny + ym) * I.nx + xm, qb)]);
+    val = gtq + k0 * gq_m - k0 * gqb - 3.0 * alpha * w * vc;
+  } else {
+    val = gtq - 6.0 * w * vc;
+  }
+  const S sv = Codec<S>::st((typename CompOf<S>::type)val);
+  b[pdf_at(cell, qb)] = sv;
+  if (p >= 0) {
+    const double vs = (double)Codec<S>::ld(sv);
+    double F[3];
+    for (int k = 0; k < 3; ++k) F[k] = (c[k] - v[k]) * gtq + (c[k] + v[k]) * vs;
+    ft[0] = F[0];
+    ft[1] = F[1];
+    ft[2] = F[2];
+    ft[3] = arm[1] * F[2] - arm[2] * F[1];
+    ft[4] = arm[2] * F[0] - arm[0] * F[2];
+    ft[5] = arm[0] * F[1] - arm[1] * F[0];
   }
 }
 
-hipError_t launch_links_bc(int prec, int n_wall, const int* count, int cap, LinkDev links, const double* wall_v,
-                           const InstDev* insts, PartDev parts, void* buf, hipStream_t st) {
-  LBM_DISPATCH(prec, hipLaunchKernelGGL(links_bc_kernel<S>, dim3(512), dim3(256), 0, st, n_wall, count, cap, links,
-                                        wall_v, insts, parts, (S*)buf));
+// Row j < nlist of the grid: the links [n_wall + lbeg[j], n_wall + lend[j]) of
+// particle list[j], one link per thread in chunks of SUM_THREADS; workgroup
+// k < width takes chunks k, k + width, ... (the rest of the row is idle).  Each thread keeps the sum of its links'
+// force and torque, and the particle's sum is formed in a fixed order
+// (block_sum6, then finish_particle_sum), so it repeats bit for bit.
+// Row nlist: the wall links [0, n_wall), strided over the whole row.
+template <typename S>
+__global__ __launch_bounds__(SUM_THREADS) void links_bc_kernel(int n_wall, const int* __restrict__ list, int nlist,
+                                                               const int* __restrict__ lbeg,
+                                                               const int* __restrict__ lend, LinkDev L,
+                                                               const double* __restrict__ wall_v,
+                                                               const InstDev* __restrict__ insts, PartDev P,
+                                                               S* __restrict__ buf, double* __restrict__ partial,
+                                                               unsigned* __restrict__ arrivals,
+                                                               const InstDev* __restrict__ rigid_insts, unsigned* err,
+                                                               int width) {
+  const int j = blockIdx.y, kb = blockIdx.x;
+  double ft[6];
+  if (j == nlist) {
+    for (int i = kb * SUM_THREADS + (int)threadIdx.x; i < n_wall; i += gridDim.x * SUM_THREADS)
+      link_rule<S>(i, L, wall_v, insts, P, buf, ft);
+    return;
+  }
+  const int nb = width;  // workgroups per particle: the rows of `partial` are this wide
+  const int b = n_wall + lbeg[j], e = n_wall + lend[j];
+  const int nch = (e - b + SUM_THREADS - 1) / SUM_THREADS;
+  if (nch == 0) {  // no links: only the rigid-body step, if due
+    if (rigid_insts && kb == 0 && threadIdx.x == 0) rigid_update(list[j], rigid_insts, P, err);
+    return;
+  }
+  if (kb >= nch || kb >= nb) return;  // no links for this workgroup; it takes no part
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int ch = kb; ch < nch; ch += nb) {
+    const int i = b + ch * SUM_THREADS + (int)threadIdx.x;
+    if (i < e) {
+      link_rule<S>(i, L, wall_v, insts, P, buf, ft);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) acc[k] += ft[k];
+    }
+  }
+  double s[6];
+  block_sum6(acc, s);
+  finish_particle_sum(j, list[j], s, min(nch, nb), kb, nb, partial, arrivals, P, rigid_insts, err);
+}
+
+hipError_t launch_links_bc(int prec, int n_wall, const int* list, int nlist, const int* lbeg, const int* lend,
+                           int width, LinkDev links, const double* wall_v, const InstDev* insts, PartDev parts,
+                           void* buf, double* partial, unsigned* arrivals, const InstDev* rigid_insts, unsigned* err,
+                           hipStream_t st) {
+  if (nlist <= 0 && n_wall <= 0) return hipSuccess;
+  // wall links get at least enough workgroups for one link per thread, up to 512
+  const int blocks = std::max(width, std::min(512, (n_wall + SUM_THREADS - 1) / SUM_THREADS));
+  LBM_DISPATCH(prec, hipLaunchKernelGGL(links_bc_kernel<S>, dim3(blocks, nlist + (n_wall > 0 ? 1 : 0)),
+                                        dim3(SUM_THREADS), 0, st, n_wall, list, nlist, lbeg, lend, links, wall_v,
+                                        insts, parts, (S*)buf, partial, arrivals, rigid_insts, err, width));
   return hipGetLastError();
 }
 

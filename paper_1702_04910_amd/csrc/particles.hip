@@ -4,6 +4,7 @@
 // Euler rigid-body update (Sec. 4.1).
 #include "common.h"
 #include "kernels.h"
+#include "particle_sum.h"
 
 namespace lbm {
 
@@ -15,10 +16,9 @@ namespace lbm {
 // of scheduling.
 constexpr int SCAN_TILE = 8192;
 
-__global__ __launch_bounds__(1024) void scan_kernel(const int* __restrict__ totals, int* __restrict__ offsets, int m,
-                                                    int side, int nlist, int* __restrict__ begin,
-                                                    int* __restrict__ end, int* __restrict__ count, int cap,
-                                                    unsigned* err, unsigned err_bit) {
+__device__ void scan_body(const int* __restrict__ totals, int* __restrict__ offsets, int m, int side, int nlist,
+                          int* __restrict__ begin, int* __restrict__ end, int* __restrict__ count, int cap,
+                          unsigned* err, unsigned err_bit) {
   __shared__ int tile[SCAN_TILE];
   __shared__ long long wsum[16];
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
@@ -75,6 +75,26 @@ __global__ __launch_bounds__(1024) void scan_kernel(const int* __restrict__ tota
     begin[j] = min(b0, cap);
     end[j] = min(e0, cap);
   }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void scan_kernel(const int* __restrict__ totals, int* __restrict__ offsets, int m,
+                                                    int side, int nlist, int* __restrict__ begin,
+                                                    int* __restrict__ end, int* __restrict__ count, int cap,
+                                                    unsigned* err, unsigned err_bit) {
+  scan_body(totals, offsets, m, side, nlist, begin, end, count, cap, err, err_bit);
+}
+
+__global__ __launch_bounds__(1024) void scan2_kernel(const int* __restrict__ totals, int* __restrict__ offsets, int m,
+                                                     int side, int nlist, int* __restrict__ begin,
+                                                     int* __restrict__ end, int* __restrict__ count, int cap,
+                                                     unsigned err_bit, const int* __restrict__ totals2,
+                                                     int* __restrict__ offsets2, int m2, int side2, int nlist2,
+                                                     int* __restrict__ begin2, int* __restrict__ end2,
+                                                     int* __restrict__ count2, int cap2, unsigned err_bit2,
+                                                     unsigned* err) {
+  scan_body(totals, offsets, m, side, nlist, begin, end, count, cap, err, err_bit);
+  scan_body(totals2, offsets2, m2, side2, nlist2, begin2, end2, count2, cap2, err, err_bit2);
 }
 
 hipError_t launch_scan(const int* totals, int* offsets, int m, int side, int nlist, int* begin, int* end, int* count,
@@ -84,107 +104,58 @@ hipError_t launch_scan(const int* totals, int* offsets, int m, int side, int nli
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------------------ reduction
-// Workgroup j sums the records [base + begin[j], base + end[j]) (6 components,
-// component k of record i at out[k * ostride + i]) in a
-// fixed order: strided per-thread partial sums, a butterfly over the 64 lanes of
-// each wave, then the waves in order.  The result is added to Facc/Tacc.
-constexpr int RED_THREADS = 256;  // fixed: the summation order must not depend on the particle count
-__global__ __launch_bounds__(RED_THREADS) void reduce_kernel(const int* __restrict__ list, const int* __restrict__ begin,
-                                                     const int* __restrict__ end, int base,
-                                                     const double* __restrict__ out, long long ostride,
-                                                     PartDev parts) {
-  const int j = blockIdx.x;
-  const int p = list[j];
-  const int b = base + begin[j], e = base + end[j];
-  double acc[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll 4
-  for (int i = b + (int)threadIdx.x; i < e; i += blockDim.x) {
-#pragma unroll
-    for (int k = 0; k < 6; ++k) acc[k] += out[k * ostride + i];
-  }
-#pragma unroll
-  for (int k = 0; k < 6; ++k) {
-    double v = acc[k];
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
-    acc[k] = v;
-  }
-  __shared__ double wsum[RED_THREADS / 64][6];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (lane == 0) {
-#pragma unroll
-    for (int k = 0; k < 6; ++k) wsum[wave][k] = acc[k];
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int nw = (blockDim.x + 63) / 64;
-    double s[6] = {0, 0, 0, 0, 0, 0};
-    for (int w = 0; w < nw; ++w)
-      for (int k = 0; k < 6; ++k) s[k] += wsum[w][k];
-    for (int k = 0; k < 3; ++k) {
-      parts.Facc[3 * p + k] += s[k];
-      parts.Tacc[3 * p + k] += s[3 + k];
-    }
-  }
-}
-
-hipError_t launch_reduce(const int* list, int nlist, const int* begin, const int* end, int base, const double* out,
-                         long long ostride, PartDev parts, hipStream_t st) {
-  if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_kernel, dim3(nlist), dim3(RED_THREADS), 0, st, list, begin, end, base, out, ostride,
-                     parts);
+hipError_t launch_scan2(const int* totals, int* offsets, int m, int side, int nlist, int* begin, int* end, int* count,
+                        int cap, unsigned err_bit, const int* totals2, int* offsets2, int m2, int side2, int nlist2,
+                        int* begin2, int* end2, int* count2, int cap2, unsigned err_bit2, unsigned* err,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(scan2_kernel, dim3(1), dim3(1024), 0, st, totals, offsets, m, side, nlist, begin, end, count, cap,
+                     err_bit, totals2, offsets2, m2, side2, nlist2, begin2, end2, count2, cap2, err_bit2, err);
   return hipGetLastError();
 }
 
-// ------------------------------------------------------------------------ rigid body
-// Forward Euler with dt = n_sub (the number of sweeps per rigid-body step):
-//   F_tot = F_h + (rho_p - 1) V g + V f_ext,  U += dt F_tot/m,  X += dt U_old,
-//   Omega += dt T/I,  with V = pi D^3/6, m = rho_p V, I = m D^2/10.
-// The hydrodynamic force is the average of the n_sub sweeps (Sec. 2.2.4).
-__global__ void rigid_kernel(const int* __restrict__ list, int nlist, const InstDev* __restrict__ insts, PartDev P,
-                             unsigned* err) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nlist) return;
-  const int p = list[j];
-  const InstDev& I = insts[P.inst[p]];
-  const double dt = (double)I.n_sub;
-  double F[3], T[3];
-  for (int k = 0; k < 3; ++k) {
-    F[k] = P.Facc[3 * p + k] / dt;
-    T[k] = P.Tacc[3 * p + k] / dt;
-    P.F[3 * p + k] = F[k];
-    P.T[3 * p + k] = T[k];
-    P.Facc[3 * p + k] = 0.0;
-    P.Tacc[3 * p + k] = 0.0;
-    P.Xold[3 * p + k] = P.X[3 * p + k];
+// ------------------------------------------------------------------------ reduction
+// The records [base + begin[j], base + end[j]) of particle list[j] (6
+// components, component k of record i at out[k * ostride + i]) are cut into
+// chunks of RED_CHUNK consecutive records; workgroup (k, j) sums chunks k,
+// k + gridDim.x, ... in a fixed order (strided per-thread sums, then
+// block_sum6), and finish_particle_sum adds the workgroup sums in order.  The
+// order depends only on the record count, so results repeat bit for bit.
+__global__ __launch_bounds__(SUM_THREADS) void reduce_kernel(const int* __restrict__ list, const int* __restrict__ begin,
+                                                     const int* __restrict__ end, int base,
+                                                     const double* __restrict__ out, long long ostride,
+                                                     PartDev parts, double* __restrict__ partial,
+                                                     unsigned* __restrict__ arrivals,
+                                                     const InstDev* __restrict__ insts, unsigned* err) {
+  const int j = blockIdx.y, kb = blockIdx.x, nb = gridDim.x;
+  const int b = base + begin[j], e = base + end[j];
+  const int nch = (e - b + RED_CHUNK - 1) / RED_CHUNK;
+  if (nch == 0) {  // no records: only the rigid-body step, if due
+    if (insts && kb == 0 && threadIdx.x == 0) rigid_update(list[j], insts, parts, err);
+    return;
   }
-  bool bad = false;
-  for (int k = 0; k < 3; ++k) bad |= !isfinite(F[k]) || !isfinite(T[k]);
-  if (!P.fixed[p]) {
-    const double D = P.D[p];
-    const double V = M_PI * (D * D * D) / 6.0;
-    const double m = P.rho[p] * V;
-    const double inertia = m * D * D / 10.0;
-    const double L[3] = {(double)I.nx, (double)I.ny, (double)I.nz};
-    for (int k = 0; k < 3; ++k) {
-      const double ftot = (F[k] + (P.rho[p] - 1.0) * V * I.grav[k]) + V * I.fext[k];
-      const double u_old = P.U[3 * p + k];
-      P.U[3 * p + k] = u_old + dt * ftot / m;
-      double x = P.X[3 * p + k] + dt * u_old;
-      if (x >= L[k]) x -= L[k];
-      if (x < 0.0) x += L[k];
-      P.X[3 * p + k] = x;
-      P.Om[3 * p + k] = P.Om[3 * p + k] + dt * T[k] / inertia;
-      bad |= !isfinite(P.U[3 * p + k]) || fabs(dt * u_old) >= 1.0;
+  if (kb >= nch) return;  // no records for this workgroup; it takes no part
+  double s[6] = {0, 0, 0, 0, 0, 0};
+  for (int ch = kb; ch < nch; ch += nb) {
+    const int cb = b + ch * RED_CHUNK, ce = min(e, cb + RED_CHUNK);
+    double acc[6] = {0, 0, 0, 0, 0, 0}, t[6];
+#pragma unroll 4
+    for (int i = cb + (int)threadIdx.x; i < ce; i += SUM_THREADS) {
+#pragma unroll
+      for (int k = 0; k < 6; ++k) acc[k] += out[k * ostride + i];
     }
+    block_sum6(acc, t);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) s[k] += t[k];
   }
-  if (bad) atomicOr(err, (unsigned)ERR_UNSTABLE);
+  finish_particle_sum(j, list[j], s, min(nch, nb), kb, nb, partial, arrivals, parts, insts, err);
 }
 
-hipError_t launch_rigid(const int* list, int nlist, const InstDev* insts, PartDev parts, unsigned* err,
-                        hipStream_t st) {
+hipError_t launch_reduce(const int* list, int nlist, const int* begin, const int* end, int base, const double* out,
+                         long long ostride, PartDev parts, int nchunk_blocks, double* partial, unsigned* arrivals,
+                         const InstDev* rigid_insts, unsigned* err, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(rigid_kernel, dim3((nlist + 127) / 128), dim3(128), 0, st, list, nlist, insts, parts, err);
+  hipLaunchKernelGGL(reduce_kernel, dim3(nchunk_blocks, nlist), dim3(SUM_THREADS), 0, st, list, begin, end, base, out,
+                     ostride, parts, partial, arrivals, rigid_insts, err);
   return hipGetLastError();
 }
 
