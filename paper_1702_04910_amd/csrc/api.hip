@@ -39,6 +39,7 @@ struct Layout {
   bool ok = false;
   std::string err;
   int n = 0, prec = 0, side = 0, ptotal = 0, mem_nsub = 0, psm_nsub = 0;
+  int psm_m = -1;  // solid operator shared by the PSM instances, 0 if they differ
   size_t ssz = 0;
   std::vector<long long> pdf_off, owner_off, cellmap_off, ncell;
   std::vector<int> part_begin;
@@ -124,6 +125,7 @@ Layout make_layout(int n, const lbmps_config* cfgs) {
     if (cfgs[i].coupling == LBMPS_PSM) {
       if (L.psm_nsub && L.psm_nsub != eff_nsub(cfgs[i])) { L.err = "PSM instances of a batch must share n_sub"; return L; }
       L.psm_nsub = eff_nsub(cfgs[i]);
+      L.psm_m = (L.psm_m < 0 || L.psm_m == cfgs[i].psm_m) ? cfgs[i].psm_m : 0;
     }
     if (cfgs[i].max_particles > 0) dmax = std::max(dmax, cfgs[i].max_diameter);
   }
@@ -199,7 +201,7 @@ Layout make_layout(int n, const lbmps_config* cfgs) {
   L.o_totals2 = take((size_t)L.box_total * 4);
   L.o_offsets2 = take((size_t)L.box_total * 4);
   L.o_ranges = take((size_t)L.ptotal * 8 * 4);
-  L.o_red = take((size_t)L.ptotal * (std::max(L.red_blocks, L.link_blocks) * 6 * 8 + 4));
+  L.o_red = take((size_t)L.ptotal * std::max(L.red_blocks, L.link_blocks) * 6 * 8);
   L.o_counts = take(16 * 4);
   L.o_links = take((size_t)(L.link_cap + L.wall_cap) * (5 * 4 + 8) + 2 * ALIGN);
   L.o_wallv = take((size_t)n * 16 * 3 * 8);
@@ -244,7 +246,6 @@ struct lbmps_ctx {
   int* totals2 = nullptr;  // second per-unit count (refill cells of the MEM remap)
   int* offsets2 = nullptr;
   double* red_partial = nullptr;  // per-chunk force/torque sums
-  unsigned* red_arrivals = nullptr;
   int *lbeg = nullptr, *lend = nullptr, *pbeg = nullptr, *pend = nullptr, *rbeg = nullptr, *rend = nullptr,
       *cbeg = nullptr, *cend = nullptr;
   int* counts = nullptr;  // [0] links, [1] pairs, [2] refill, [4] error bits (unsigned)
@@ -535,7 +536,6 @@ lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* ws, s
   }
   c->counts = (int*)(w + L.o_counts);
   c->red_partial = (double*)(w + L.o_red);
-  c->red_arrivals = (unsigned*)(w + L.o_red + (size_t)L.ptotal * std::max(L.red_blocks, L.link_blocks) * 6 * 8);
   {
     const size_t nl = (size_t)L.link_cap + L.wall_cap;
     char* b = w + L.o_links;
@@ -626,7 +626,6 @@ lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* ws, s
   bail(hipMemcpyAsync(c->inst_d, c->inst_h.data(), sizeof(InstDev) * n, hipMemcpyHostToDevice, c->st), "copy instances");
   bail(hipMemcpyAsync(c->tiles_d, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, c->st), "copy tiles");
   bail(hipMemsetAsync(c->counts, 0, 16 * 4, c->st), "clear counters");
-  bail(hipMemsetAsync(c->red_arrivals, 0, (size_t)L.ptotal * 4, c->st), "clear reduction counters");
   bail(hipMemsetAsync(w + L.o_parts, 0, L.o_plists - L.o_parts, c->st), "clear particles");
   if (s == LBMPS_OK) s = fill_int(c, c->owner, L.owner_elems, OWN_FLUID);
   if (s == LBMPS_OK) s = fill_int(c, c->cellmap, L.cellmap_elems, 0x7fffffff);
@@ -866,15 +865,15 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
     const bool mem_rb = c->n_mem && ((c->sweeps + 1) % L.mem_nsub) == 0;
     if (c->n_psm) {
       if (!fused)
-        HIPCHK(c, launch_psm_collide(L.prec, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap,
-                                     src, dst, c->st));
+        HIPCHK(c, launch_psm_collide(L.prec, L.psm_m, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs,
+                                     c->cellmap, src, dst, c->st));
       HIPCHK(c, launch_reduce(psm_list(c), c->n_psm, c->pbeg, c->pend, 0, c->pairs.out, c->pairs.ostride, c->parts,
-                              L.red_blocks, c->red_partial, c->red_arrivals, psm_rb ? c->inst_d : nullptr, err,
+                              L.red_blocks, c->red_partial, psm_rb ? c->inst_d : nullptr, err,
                               c->st));
     }
     if (c->n_mem || c->n_wall) {
       HIPCHK(c, launch_links_bc(L.prec, c->n_wall, mem_list(c), c->n_mem, c->lbeg, c->lend, L.link_blocks, c->links,
-                                c->wall_v, c->inst_d, c->parts, dst, c->red_partial, c->red_arrivals,
+                                c->wall_v, c->inst_d, c->parts, dst, c->red_partial,
                                 mem_rb ? c->inst_d : nullptr, err, c->st));
     }
     c->cur = 1 - c->cur;

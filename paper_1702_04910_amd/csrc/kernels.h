@@ -33,16 +33,20 @@ hipError_t launch_scan2(const int* totals, int* offsets, int m, int side, int nl
                         int cap, unsigned err_bit, const int* totals2, int* offsets2, int m2, int side2, int nlist2,
                         int* begin2, int* end2, int* count2, int cap2, unsigned err_bit2, unsigned* err,
                         hipStream_t st);
-// Per-particle sum of 6-double records [begin[j], end[j]) (+ base) into Facc/Tacc of particle list[j],
-// nchunk_blocks workgroups per particle over chunks of RED_CHUNK records; partial holds
-// nlist * nchunk_blocks * 6 doubles, arrivals nlist counters that start (and are left) at zero.
-// With rigid_insts != nullptr, each particle's explicit Euler rigid-body step (averaging Facc over
-// n_sub sweeps) follows its sum.
+// Per-particle sum of 6-double records [begin[j], end[j]) (+ base) into Facc/Tacc of particle list[j]:
+// nchunk_blocks workgroups per particle over chunks of RED_CHUNK records store their sums in partial
+// (nlist * nchunk_blocks * 6 doubles), then launch_finish_sums adds them.
 constexpr int RED_CHUNK = 1024;
 constexpr int SUM_THREADS = 256;  // workgroup size of the summing kernels (one link per thread and chunk)
 hipError_t launch_reduce(const int* list, int nlist, const int* begin, const int* end, int base, const double* out,
-                         long long ostride, PartDev parts, int nchunk_blocks, double* partial, unsigned* arrivals,
+                         long long ostride, PartDev parts, int nchunk_blocks, double* partial,
                          const InstDev* rigid_insts, unsigned* err, hipStream_t st);
+// Adds the min(ceil((end[j] - begin[j]) / chunk), width) chunk sums of list position j (rows of partial are
+// width wide) in order to Facc/Tacc of particle list[j]; with rigid_insts != nullptr each particle's explicit
+// Euler rigid-body step (averaging Facc over n_sub sweeps) follows.
+hipError_t launch_finish_sums(const int* list, int nlist, const int* begin, const int* end, int chunk, int width,
+                              const double* partial, PartDev parts, const InstDev* rigid_insts, unsigned* err,
+                              hipStream_t st);
 
 // ---- mem.hip
 hipError_t launch_mem_unmap(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
@@ -67,8 +71,7 @@ hipError_t launch_mem_clear_was(const int* list, int nlist, int side, int nsplit
 // partial as for launch_reduce with nchunk_blocks = width) and, with rigid_insts != nullptr, its rigid-body step.
 hipError_t launch_links_bc(int prec, int n_wall, const int* list, int nlist, const int* lbeg, const int* lend,
                            int width, LinkDev links, const double* wall_v, const InstDev* insts, PartDev parts,
-                           void* buf, double* partial, unsigned* arrivals, const InstDev* rigid_insts, unsigned* err,
-                           hipStream_t st);
+                           void* buf, double* partial, const InstDev* rigid_insts, unsigned* err, hipStream_t st);
 
 // ---- psm.hip
 hipError_t launch_psm_classify(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
@@ -89,7 +92,9 @@ hipError_t launch_psm_fill(const int* list, int nlist, int side, int nsplit, con
                            const int* slots, const int* offsets, int cap, PairDev pairs, hipStream_t st);
 hipError_t launch_psm_cellmap(int stage, const int* count, int cap, const InstDev* insts, PartDev parts,
                               PairDev pairs, int* cellmap, hipStream_t st);
-hipError_t launch_psm_collide(int prec, const int* count, int cap, const InstDev* insts, PartDev parts,
+// Collision of every overlapped cell (two launches: single-pair cells, then shared cells).  psm_m: the solid
+// operator shared by every PSM instance (1..3), or 0 when they differ.
+hipError_t launch_psm_collide(int prec, int psm_m, const int* count, int cap, const InstDev* insts, PartDev parts,
                               PairDev pairs, const int* cellmap, const void* src, void* dst, hipStream_t st);
 hipError_t launch_psm_fields(int prec, const int* count, int cap, const InstDev* insts, PartDev parts, PairDev pairs,
                              const int* cellmap, const void* buf, int inst, long long c0, long long n, double* out,

@@ -413,9 +413,10 @@ __device__ __forceinline__ void link_rule(int i, const LinkDev& L, const double*
 
 // Row j < nlist of the grid: the links [n_wall + lbeg[j], n_wall + lend[j]) of
 // particle list[j], one link per thread in chunks of SUM_THREADS; workgroup
-// k < width takes chunks k, k + width, ... (the rest of the row is idle).  Each thread keeps the sum of its links'
-// force and torque, and the particle's sum is formed in a fixed order
-// (block_sum6, then finish_particle_sum), so it repeats bit for bit.
+// k < width takes chunks k, k + width, ... (the rest of the row is idle).
+// Each thread keeps the sum of its links' force and torque; the workgroup
+// stores their block_sum6, and finish_sums_kernel adds a particle's workgroup
+// sums in order, so the total repeats bit for bit.
 // Row nlist: the wall links [0, n_wall), strided over the whole row.
 template <typename S>
 __global__ __launch_bounds__(SUM_THREADS) void links_bc_kernel(int n_wall, const int* __restrict__ list, int nlist,
@@ -424,8 +425,6 @@ __global__ __launch_bounds__(SUM_THREADS) void links_bc_kernel(int n_wall, const
                                                                const double* __restrict__ wall_v,
                                                                const InstDev* __restrict__ insts, PartDev P,
                                                                S* __restrict__ buf, double* __restrict__ partial,
-                                                               unsigned* __restrict__ arrivals,
-                                                               const InstDev* __restrict__ rigid_insts, unsigned* err,
                                                                int width) {
   const int j = blockIdx.y, kb = blockIdx.x;
   double ft[6];
@@ -437,10 +436,6 @@ __global__ __launch_bounds__(SUM_THREADS) void links_bc_kernel(int n_wall, const
   const int nb = width;  // workgroups per particle: the rows of `partial` are this wide
   const int b = n_wall + lbeg[j], e = n_wall + lend[j];
   const int nch = (e - b + SUM_THREADS - 1) / SUM_THREADS;
-  if (nch == 0) {  // no links: only the rigid-body step, if due
-    if (rigid_insts && kb == 0 && threadIdx.x == 0) rigid_update(list[j], rigid_insts, P, err);
-    return;
-  }
   if (kb >= nch || kb >= nb) return;  // no links for this workgroup; it takes no part
   double acc[6] = {0, 0, 0, 0, 0, 0};
   for (int ch = kb; ch < nch; ch += nb) {
@@ -453,20 +448,21 @@ __global__ __launch_bounds__(SUM_THREADS) void links_bc_kernel(int n_wall, const
   }
   double s[6];
   block_sum6(acc, s);
-  finish_particle_sum(j, list[j], s, min(nch, nb), kb, nb, partial, arrivals, P, rigid_insts, err);
+  store_chunk_sum(j, kb, nb, s, partial);
 }
 
 hipError_t launch_links_bc(int prec, int n_wall, const int* list, int nlist, const int* lbeg, const int* lend,
                            int width, LinkDev links, const double* wall_v, const InstDev* insts, PartDev parts,
-                           void* buf, double* partial, unsigned* arrivals, const InstDev* rigid_insts, unsigned* err,
-                           hipStream_t st) {
+                           void* buf, double* partial, const InstDev* rigid_insts, unsigned* err, hipStream_t st) {
   if (nlist <= 0 && n_wall <= 0) return hipSuccess;
   // wall links get at least enough workgroups for one link per thread, up to 512
   const int blocks = std::max(width, std::min(512, (n_wall + SUM_THREADS - 1) / SUM_THREADS));
   LBM_DISPATCH(prec, hipLaunchKernelGGL(links_bc_kernel<S>, dim3(blocks, nlist + (n_wall > 0 ? 1 : 0)),
                                         dim3(SUM_THREADS), 0, st, n_wall, list, nlist, lbeg, lend, links, wall_v,
-                                        insts, parts, (S*)buf, partial, arrivals, rigid_insts, err, width));
-  return hipGetLastError();
+                                        insts, parts, (S*)buf, partial, width));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finish_sums(list, nlist, lbeg, lend, SUM_THREADS, width, partial, parts, rigid_insts, err, st);
 }
 
 }  // namespace lbm

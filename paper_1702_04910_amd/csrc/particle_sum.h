@@ -1,7 +1,9 @@
 // Per-particle sums of force and torque records (Eqs. MEM_TotForce/TotTorque,
 // PSM_TotForce/TotTorque) in a fixed order, and the rigid-body step that
 // follows the last sum of a rigid-body cycle.  Shared by the reduction kernel
-// and the MEM link kernel, which sums its own link forces.
+// and the MEM link kernel, which sums its own link forces per chunk: each
+// workgroup stores the sum of its chunks, and finish_sums_kernel (the next
+// launch) adds a particle's chunk sums in chunk order.
 #pragma once
 
 #include "common.h"
@@ -75,59 +77,14 @@ __device__ __forceinline__ void block_sum6(const double (&acc)[6], double (&s)[6
   __syncthreads();  // wsum may be reused
 }
 
-// Called by every thread of the parts_n workgroups (index kb < parts_n) that
-// hold a chunk sum s of particle p (list position j).  With one workgroup the
-// sum goes straight to Facc/Tacc; otherwise each stores its sum in
-// partial[(j * nb + kb) * 6 ..], and the one that arrives last at arrivals[j]
-// adds all of them in workgroup order and resets the counter.  With insts !=
-// nullptr the finishing thread then takes the rigid-body step.
-__device__ __forceinline__ void finish_particle_sum(int j, int p, const double (&s)[6], int parts_n, int kb, int nb,
-                                                    double* __restrict__ partial, unsigned* __restrict__ arrivals,
-                                                    const PartDev& parts, const InstDev* __restrict__ insts,
-                                                    unsigned* err) {
-  if (parts_n == 1) {
-    if (threadIdx.x == 0) {
-      for (int k = 0; k < 3; ++k) {
-        parts.Facc[3 * p + k] += s[k];
-        parts.Tacc[3 * p + k] += s[3 + k];
-      }
-      if (insts) rigid_update(p, insts, parts, err);
-    }
-    return;
-  }
-  __shared__ int last;
+// Workgroup kb's chunk sum s of list position j, kept for finish_sums_kernel
+// (partial rows are nb wide).
+__device__ __forceinline__ void store_chunk_sum(int j, int kb, int nb, const double (&s)[6],
+                                                double* __restrict__ partial) {
   if (threadIdx.x == 0) {
     double* mine = partial + ((long long)j * nb + kb) * 6;
-    for (int k = 0; k < 6; ++k) mine[k] = s[k];
-    __threadfence();
-    last = atomicAdd(&arrivals[j], 1u) == (unsigned)(parts_n - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  // every chunk sum is loaded at once (one double per thread), then added in order
-  __shared__ double ps[SUM_THREADS];
-  constexpr int PER = SUM_THREADS / 6;  // chunk sums per round
-  double tot[6] = {0, 0, 0, 0, 0, 0};
-  for (int k0 = 0; k0 < parts_n; k0 += PER) {
-    const int n = min(PER, parts_n - k0);
-    if ((int)threadIdx.x < 6 * n)
-      ps[threadIdx.x] = __hip_atomic_load(partial + ((long long)j * nb + k0) * 6 + threadIdx.x, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    if (threadIdx.x == 0)
-      for (int i = 0; i < n; ++i)
 #pragma unroll
-        for (int k = 0; k < 6; ++k) tot[k] += ps[6 * i + k];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < 3; ++k) {
-      parts.Facc[3 * p + k] += tot[k];
-      parts.Tacc[3 * p + k] += tot[3 + k];
-    }
-    arrivals[j] = 0;
-    if (insts) rigid_update(p, insts, parts, err);
+    for (int k = 0; k < 6; ++k) mine[k] = s[k];
   }
 }
 

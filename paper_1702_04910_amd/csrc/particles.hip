@@ -118,21 +118,16 @@ hipError_t launch_scan2(const int* totals, int* offsets, int m, int side, int nl
 // components, component k of record i at out[k * ostride + i]) are cut into
 // chunks of RED_CHUNK consecutive records; workgroup (k, j) sums chunks k,
 // k + gridDim.x, ... in a fixed order (strided per-thread sums, then
-// block_sum6), and finish_particle_sum adds the workgroup sums in order.  The
-// order depends only on the record count, so results repeat bit for bit.
-__global__ __launch_bounds__(SUM_THREADS) void reduce_kernel(const int* __restrict__ list, const int* __restrict__ begin,
+// block_sum6) and stores the result; finish_sums_kernel adds the workgroup
+// sums in order.  The order depends only on the record count, so results
+// repeat bit for bit.
+__global__ __launch_bounds__(SUM_THREADS) void reduce_kernel(const int* __restrict__ begin,
                                                      const int* __restrict__ end, int base,
                                                      const double* __restrict__ out, long long ostride,
-                                                     PartDev parts, double* __restrict__ partial,
-                                                     unsigned* __restrict__ arrivals,
-                                                     const InstDev* __restrict__ insts, unsigned* err) {
+                                                     double* __restrict__ partial) {
   const int j = blockIdx.y, kb = blockIdx.x, nb = gridDim.x;
   const int b = base + begin[j], e = base + end[j];
   const int nch = (e - b + RED_CHUNK - 1) / RED_CHUNK;
-  if (nch == 0) {  // no records: only the rigid-body step, if due
-    if (insts && kb == 0 && threadIdx.x == 0) rigid_update(list[j], insts, parts, err);
-    return;
-  }
   if (kb >= nch) return;  // no records for this workgroup; it takes no part
   double s[6] = {0, 0, 0, 0, 0, 0};
   for (int ch = kb; ch < nch; ch += nb) {
@@ -147,16 +142,62 @@ __global__ __launch_bounds__(SUM_THREADS) void reduce_kernel(const int* __restri
 #pragma unroll
     for (int k = 0; k < 6; ++k) s[k] += t[k];
   }
-  finish_particle_sum(j, list[j], s, min(nch, nb), kb, nb, partial, arrivals, parts, insts, err);
+  store_chunk_sum(j, kb, nb, s, partial);
+}
+
+// One wave per particle: the min(ceil(n / chunk), width) chunk sums of list
+// position j (n = end[j] - begin[j] records) are loaded at once and added in
+// chunk order to Facc/Tacc; with insts != nullptr the rigid-body step follows.
+constexpr int FIN_WAVES = 4;
+__global__ __launch_bounds__(64 * FIN_WAVES) void finish_sums_kernel(const int* __restrict__ list, int nlist,
+                                                                     const int* __restrict__ begin,
+                                                                     const int* __restrict__ end, int chunk,
+                                                                     int width, const double* __restrict__ partial,
+                                                                     PartDev parts, const InstDev* __restrict__ insts,
+                                                                     unsigned* err) {
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j = blockIdx.x * FIN_WAVES + w;
+  if (j >= nlist) return;  // whole wave
+  const int n = end[j] - begin[j];
+  const int parts_n = min((n + chunk - 1) / chunk, width);
+  double tot[6] = {0, 0, 0, 0, 0, 0};
+  constexpr int PER = 64 / 6;  // chunk sums per round
+  for (int k0 = 0; k0 < parts_n; k0 += PER) {
+    const int m = min(PER, parts_n - k0);
+    const double v = lane < 6 * m ? partial[((long long)j * width + k0) * 6 + lane] : 0.0;
+    for (int i = 0; i < m; ++i)
+#pragma unroll
+      for (int k = 0; k < 6; ++k) tot[k] += __shfl(v, 6 * i + k, 64);
+  }
+  if (lane == 0) {
+    const int p = list[j];
+    if (parts_n > 0)
+      for (int k = 0; k < 3; ++k) {
+        parts.Facc[3 * p + k] += tot[k];
+        parts.Tacc[3 * p + k] += tot[3 + k];
+      }
+    if (insts) rigid_update(p, insts, parts, err);
+  }
+}
+
+hipError_t launch_finish_sums(const int* list, int nlist, const int* begin, const int* end, int chunk, int width,
+                              const double* partial, PartDev parts, const InstDev* rigid_insts, unsigned* err,
+                              hipStream_t st) {
+  if (nlist <= 0) return hipSuccess;
+  hipLaunchKernelGGL(finish_sums_kernel, dim3((nlist + FIN_WAVES - 1) / FIN_WAVES), dim3(64 * FIN_WAVES), 0, st, list,
+                     nlist, begin, end, chunk, width, partial, parts, rigid_insts, err);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce(const int* list, int nlist, const int* begin, const int* end, int base, const double* out,
-                         long long ostride, PartDev parts, int nchunk_blocks, double* partial, unsigned* arrivals,
+                         long long ostride, PartDev parts, int nchunk_blocks, double* partial,
                          const InstDev* rigid_insts, unsigned* err, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(reduce_kernel, dim3(nchunk_blocks, nlist), dim3(SUM_THREADS), 0, st, list, begin, end, base, out,
-                     ostride, parts, partial, arrivals, rigid_insts, err);
-  return hipGetLastError();
+  hipLaunchKernelGGL(reduce_kernel, dim3(nchunk_blocks, nlist), dim3(SUM_THREADS), 0, st, begin, end, base, out,
+                     ostride, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_finish_sums(list, nlist, begin, end, RED_CHUNK, nchunk_blocks, partial, parts, rigid_insts, err, st);
 }
 
 }  // namespace lbm

@@ -533,17 +533,22 @@ hipError_t launch_psm_cellmap(int stage, const int* count, int cap, const InstDe
   return hipGetLastError();
 }
 
-// Every overlapped cell, visited through its leader pair in pair order (the
+// Overlapped cells, visited through their leader pairs in pair order (the
 // list is ordered by particle, slab and row, so neighbouring lanes touch
-// neighbouring cells and share cache lines).
-template <typename S>
-__global__ __launch_bounds__(256) void psm_collide_kernel(const int* __restrict__ count, int cap,
-                                                          const InstDev* __restrict__ insts, PartDev P,
-                                                          PairDev pairs, const int* __restrict__ cellmap,
-                                                          const S* __restrict__ src, S* __restrict__ dst) {
+// neighbouring cells and share cache lines).  MULTI = false: the cells with a
+// single pair, with the solid operator M fixed at compile time (0: per
+// instance) -- the common case, compiled for four waves per SIMD where the
+// storage is below 8 bytes and M is fixed; MULTI = true: the cells shared by
+// several particles.
+template <typename S, int M, bool MULTI>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(MULTI || M == 0 || sizeof(S) == 8 ? 1 : 4))) void psm_collide_kernel(
+    const int* __restrict__ count, int cap, const InstDev* __restrict__ insts, PartDev P, PairDev pairs,
+    const int* __restrict__ cellmap, const S* __restrict__ src, S* __restrict__ dst) {
   using R = typename CompOf<S>::type;
   const int npairs = min(*count, cap);
   for (int L = blockIdx.x * blockDim.x + threadIdx.x; L < npairs; L += gridDim.x * blockDim.x) {
+    if ((pairs.next[L] >= 0) != MULTI) continue;  // a single pair's cell has no chain
     const int p0 = pairs.p[L];
     const InstDev& I = insts[P.inst[p0]];
     const int c = pairs.cell[L];
@@ -553,7 +558,7 @@ __global__ __launch_bounds__(256) void psm_collide_kernel(const int* __restrict_
     R g[Q], out[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) g[q] = Codec<S>::ld(s[pdf_at(c, q)]);
-    psm_cell_collide<R>(g, out, I, P, pairs, L, c);
+    psm_cell_collide<M, !MULTI, R>(g, out, I, P, pairs, L, c);
     const int nx = I.nx, ny = I.ny, nz = I.nz;
     const int x = c % nx, yz = c / nx, y = yz % ny, z = yz / ny;
 #pragma unroll
@@ -573,11 +578,22 @@ __global__ __launch_bounds__(256) void psm_collide_kernel(const int* __restrict_
     default: return hipErrorInvalidValue;                 \
   }
 
-hipError_t launch_psm_collide(int prec, const int* count, int cap, const InstDev* insts, PartDev parts,
+hipError_t launch_psm_collide(int prec, int psm_m, const int* count, int cap, const InstDev* insts, PartDev parts,
                               PairDev pairs, const int* cellmap, const void* src, void* dst, hipStream_t st) {
   const int grid = 2048;
-  LBM_DISPATCH(prec, hipLaunchKernelGGL(psm_collide_kernel<S>, dim3(grid), dim3(256), 0, st, count, cap, insts, parts,
-                                        pairs, cellmap, (const S*)src, (S*)dst));
+#define PSM_COLLIDE(MM, MULTI)                                                                                      \
+  LBM_DISPATCH(prec, hipLaunchKernelGGL((psm_collide_kernel<S, MM, MULTI>), dim3(grid), dim3(256), 0, st, count, cap, \
+                                        insts, parts, pairs, cellmap, (const S*)src, (S*)dst))
+  switch (psm_m) {
+    case 1: PSM_COLLIDE(1, false); break;
+    case 2: PSM_COLLIDE(2, false); break;
+    case 3: PSM_COLLIDE(3, false); break;
+    default: PSM_COLLIDE(0, false); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  PSM_COLLIDE(0, true);
+#undef PSM_COLLIDE
   return hipGetLastError();
 }
 

@@ -150,7 +150,7 @@ __device__ __forceinline__ void sweep_body(const InstDev* __restrict__ insts, co
       }
       if constexpr (PSM) {
         const int L = I.cellmap_off >= 0 ? cellmap[I.cellmap_off + idx] : INT_MAX;
-        if (L != INT_MAX) psm_cell_collide<R>(g, o, I, P, pairs, L, idx);
+        if (L != INT_MAX) psm_cell_collide<0, false, R>(g, o, I, P, pairs, L, idx);
         else collide_cell<R>(g, o, lp, lm, fx, fy, fz);
       } else {
         collide_cell<R>(g, o, lp, lm, fx, fy, fz);
