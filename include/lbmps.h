@@ -91,8 +91,12 @@ typedef struct lbmps_config {
   int32_t wall_link_cap; /* capacity of static-wall links (0 = automatic) */
   int32_t sweep_flags;   /* launch tuning only, results unchanged: bit 0 non-temporal loads in the sweep;
                             bit 1 collide PSM cells inside the sweep (reads the cell map of every cell);
-                            bit 2 or neither: collide them in a separate pass over the overlap list;
-                            bit 3 the sweep built for six waves per SIMD (FP32/FP16/BF16 storage) */
+                            bit 2 collide them in a pass over the overlap list after the sweep;
+                            bit 3 the sweep built for six waves per SIMD (FP32/FP16/BF16 storage);
+                            bit 4 collide them in a pass over the overlap list before the sweep, into a
+                            staging array that the sweep pushes (reads the cell map of every cell);
+                            bits 1, 2, 4 are exclusive; with none of them the library stages when the
+                            spheres (diameter D + 2) cover at least 1 % of the PSM cells, else uses bit 2 */
   int32_t reserved;
   double max_diameter;   /* largest particle diameter that will be set (cells) */
   double nu;             /* kinematic viscosity, nu = (tau - 1/2)/3 (Eq. Viscosity) */

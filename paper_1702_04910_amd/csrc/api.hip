@@ -52,7 +52,7 @@ struct Layout {
   int box_total = 0;  // ptotal * side * side: work units at the finest split
   long long chunk = 0;
   // byte offsets
-  size_t o_bufA, o_bufB, o_owner, o_cellmap, o_inst, o_parts, o_plists, o_slots, o_totals, o_offsets, o_totals2, o_offsets2, o_ranges, o_red,
+  size_t o_bufA, o_bufB, o_owner, o_cellmap, o_inst, o_parts, o_plists, o_slots, o_totals, o_offsets, o_totals2, o_offsets2, o_ranges, o_red, o_stage,
       o_counts, o_links, o_wallv, o_pairs, o_refill, o_scratch, o_tiles, o_cuts, o_cutx, o_mlp, o_judge, total;
   int ntiles = 0;
   int max_tile_cells = 0;
@@ -82,8 +82,8 @@ bool valid_cfg(const lbmps_config& c, std::string& err) {
   if (c.eps_mode < 0 || c.eps_mode > 4) { err = "unknown eps_mode"; return false; }
   if (c.block_threads < 0 || c.block_threads > 256 || (c.block_threads % 64)) { err = "block_threads must be a multiple of 64, <= 256"; return false; }
   if (c.sweep_flags & ~SWEEP_FLAGS_ALL) { err = "unknown sweep_flags bits"; return false; }
-  if ((c.sweep_flags & SWEEP_PSM_FUSED) && (c.sweep_flags & SWEEP_PSM_SEPARATE)) {
-    err = "sweep_flags: PSM fused and separate are exclusive"; return false;
+  if (__builtin_popcount(c.sweep_flags & SWEEP_PSM_MODES) > 1) {
+    err = "sweep_flags: the PSM modes (fused, separate, staged) are exclusive"; return false;
   }
   if (c.n_sub < 0) { err = "n_sub must be >= 0"; return false; }
   if (10LL * (long long)storage_size(c.precision) * c.nx > SWEEP_LDS_LIMIT) {
@@ -213,12 +213,19 @@ Layout make_layout(int n, const lbmps_config* cfgs) {
   L.o_cutx = take(L.learned ? (size_t)L.cut_cap * (8 + 1) * 4 : 0);
   L.o_mlp = take((size_t)mlp_nparam() * 4);
   L.o_judge = take(4 * 8);  // own aligned block: the judge updates it with 8-byte atomics
+  // post-collision values of overlapped cells, per leader pair (staged PSM mode)
+  L.o_stage = take(L.cellmap_elems > 0 ? (size_t)Q * L.pair_cap * L.ssz : 0);
   L.total = o;
   L.ok = true;
   return L;
 }
 
 }  // namespace
+
+// PSM cells: collided by the overlap kernel after the sweep (which then
+// overwrites their pushes), inside the sweep, or by the overlap kernel before
+// the sweep into a staging array that the sweep pushes.
+enum { PSM_SEPARATE = 0, PSM_FUSED = 1, PSM_STAGED = 2 };
 
 struct lbmps_ctx {
   hipStream_t st = nullptr;
@@ -263,7 +270,8 @@ struct lbmps_ctx {
   bool mlp_set = false;
   double mlp_rmin = 0.0, mlp_rmax = -1.0;
   bool psm_exact = true;           // some PSM cut cell needs supersampling
-  bool psm_fused = false;          // PSM cells collided inside the sweep
+  int psm_mode = PSM_SEPARATE;      // how the sweep and the overlap kernel share the PSM cells
+  void* stage = nullptr;            // staged post-collision values (PSM_STAGED)
   std::vector<double> diam_h;      // per global particle
   double* scratch = nullptr;
   long long sweeps = 0;
@@ -319,12 +327,17 @@ int nsplit_for(int nlist, int side) {
 int* mem_list(lbmps_ctx* c) { return c->plist_d; }
 
 // Whether any current PSM particle needs supersampled cut cells (an exact
-// estimator, or the learned one outside its radius range), and whether PSM
-// cells are collided inside the sweep.  The inline variant reads one cell-map
-// entry per cell and raises the sweep's register count, which lowers its
-// occupancy; measured on 2000 spheres in 512^3 (4.5 % of the cells
-// overlapped) it is slower than the separate pass, so it is used only when
-// sweep_flags asks for it.
+// estimator, or the learned one outside its radius range), and how PSM cells
+// are collided.  Inline collision raises the sweep's register count, which
+// lowers its occupancy: slower than the other two modes, used only when
+// sweep_flags asks for it.  The separate pass after the sweep rewrites the
+// pushes of the overlapped cells as scattered partial cache lines; the staged
+// mode writes them as whole lines but makes the sweep read one cell-map entry
+// per cell.  Measured on 2000 spheres in 512^3 (4.3 % of the cells overlapped)
+// staging saves ~0.4 ms per sweep; with one sphere in 14 M cells the cell-map
+// reads cost more than they save.  Without a mode in sweep_flags, staging is
+// chosen when the current PSM spheres (bounding spheres of diameter D + 2)
+// cover at least 1 % of the PSM cells.
 void update_psm_exact(lbmps_ctx* c) {
   c->psm_exact = false;
   for (int k = 0; k < c->L.n; ++k) {
@@ -339,7 +352,25 @@ void update_psm_exact(lbmps_ctx* c) {
     }
   }
   const int fl = c->cfg[0].sweep_flags;
-  c->psm_fused = (fl & SWEEP_PSM_FUSED) != 0;
+  if (fl & SWEEP_PSM_FUSED) {
+    c->psm_mode = PSM_FUSED;
+  } else if (fl & SWEEP_PSM_STAGED) {
+    c->psm_mode = PSM_STAGED;
+  } else if (fl & SWEEP_PSM_SEPARATE) {
+    c->psm_mode = PSM_SEPARATE;
+  } else {
+    double vol = 0.0, cells = 0.0;
+    for (int k = 0; k < c->L.n; ++k) {
+      if (c->cfg[k].coupling != LBMPS_PSM) continue;
+      cells += (double)c->L.ncell[k];
+      const int b = c->L.part_begin[k];
+      for (int i = 0; i < c->n_active[k]; ++i) {
+        const double D = c->diam_h[b + i] + 2.0;
+        vol += M_PI / 6.0 * D * D * D;
+      }
+    }
+    c->psm_mode = (cells > 0 && vol >= 0.01 * cells) ? PSM_STAGED : PSM_SEPARATE;
+  }
 }
 
 int* psm_list(lbmps_ctx* c) { return c->plist_d + c->n_mem; }
@@ -575,6 +606,7 @@ lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* ws, s
     c->cut_x = L.learned ? (float*)(w + L.o_cutx) : nullptr;
     c->mlp_p = (float*)(w + L.o_mlp);
     c->judge = (double*)(w + L.o_judge);
+    c->stage = w + L.o_stage;
   }
 
   // instance table and sweep tiles
@@ -841,6 +873,10 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
   for (int s = 0; s < n; ++s) {
     void* src = c->buf[c->cur];
     void* dst = c->buf[1 - c->cur];
+    const int pm = c->n_psm ? c->psm_mode : PSM_SEPARATE;
+    if (pm == PSM_STAGED)  // overlapped cells first, from the same pre-collision values
+      HIPCHK(c, launch_psm_collide(L.prec, L.psm_m, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs,
+                                   c->cellmap, src, dst, c->stage, L.pair_cap, c->st));
     if (c->timing) {
       if (c->ev_used + 2 > c->ev.size()) {
         lbmps_status r = harvest_timing(c);
@@ -853,9 +889,10 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
       }
       HIPCHK(c, hipEventRecord(c->ev[c->ev_used], c->st));
     }
-    const bool fused = c->n_psm && c->psm_fused;
     HIPCHK(c, launch_sweep(L.prec, c->inst_d, c->tiles_d, c->ntiles, c->grid, c->block, L.max_tile_cells,
-                           c->cfg[0].sweep_flags, src, dst, fused ? c->cellmap : nullptr, c->pairs, c->parts, c->st));
+                           c->cfg[0].sweep_flags, pm == PSM_FUSED ? 1 : pm == PSM_STAGED ? 2 : 0, src, dst,
+                           pm != PSM_SEPARATE ? c->cellmap : nullptr, c->pairs, c->parts, c->stage, L.pair_cap,
+                           c->st));
     if (c->timing) {
       HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->st));
       c->ev_used += 2;
@@ -864,9 +901,9 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
     const bool psm_rb = c->n_psm && ((c->sweeps + 1) % L.psm_nsub) == 0;
     const bool mem_rb = c->n_mem && ((c->sweeps + 1) % L.mem_nsub) == 0;
     if (c->n_psm) {
-      if (!fused)
+      if (pm == PSM_SEPARATE)
         HIPCHK(c, launch_psm_collide(L.prec, L.psm_m, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs,
-                                     c->cellmap, src, dst, c->st));
+                                     c->cellmap, src, dst, nullptr, 0, c->st));
       HIPCHK(c, launch_reduce(psm_list(c), c->n_psm, c->pbeg, c->pend, 0, c->pairs.out, c->pairs.ostride, c->parts,
                               L.red_blocks, c->red_partial, psm_rb ? c->inst_d : nullptr, err,
                               c->st));
@@ -895,8 +932,7 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
 lbmps_status lbmps_set_launch(lbmps_ctx* c, int32_t block_threads, int32_t grid_blocks, int32_t sweep_flags) {
   if (!c) return LBMPS_EINVAL;
   if (block_threads < 0 || block_threads > 256 || (block_threads % 64)) return fail(c, LBMPS_EINVAL, "bad block size");
-  if (grid_blocks < 0 || (sweep_flags & ~SWEEP_FLAGS_ALL) ||
-      ((sweep_flags & SWEEP_PSM_FUSED) && (sweep_flags & SWEEP_PSM_SEPARATE)))
+  if (grid_blocks < 0 || (sweep_flags & ~SWEEP_FLAGS_ALL) || __builtin_popcount(sweep_flags & SWEEP_PSM_MODES) > 1)
     return fail(c, LBMPS_EINVAL, "bad grid or flags");
   drop_graph(c);
   c->block = block_threads ? block_threads : 256;

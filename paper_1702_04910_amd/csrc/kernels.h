@@ -8,13 +8,20 @@ namespace lbm {
 
 // ---- sweep.hip
 // sweep_flags: bit 0 non-temporal loads; bit 1 collide PSM cells inside the
-// sweep; bit 2 (or neither) collide them in the separate overlap kernel;
-// bit 3 the sweep compiled for six waves per SIMD (4- and 2-byte storage).
-// Results never depend on them.
-enum { SWEEP_NT_LOADS = 1, SWEEP_PSM_FUSED = 2, SWEEP_PSM_SEPARATE = 4, SWEEP_OCC6 = 8, SWEEP_FLAGS_ALL = 15 };
+// sweep; bit 2 collide them in the separate overlap kernel after the sweep;
+// bit 3 the sweep compiled for six waves per SIMD (4- and 2-byte storage);
+// bit 4 collide them in the overlap kernel before the sweep into a staging
+// array that the sweep pushes (none of bits 1, 2, 4: chosen from the expected
+// share of overlapped cells).  Results never depend on them.
+enum {
+  SWEEP_NT_LOADS = 1, SWEEP_PSM_FUSED = 2, SWEEP_PSM_SEPARATE = 4, SWEEP_OCC6 = 8, SWEEP_PSM_STAGED = 16,
+  SWEEP_FLAGS_ALL = 31, SWEEP_PSM_MODES = SWEEP_PSM_FUSED | SWEEP_PSM_SEPARATE | SWEEP_PSM_STAGED
+};
+// psm_mode: 0 no PSM cells (or they are re-collided afterwards), 1 inline, 2 staged
+// (stage[q * sstride + leader pair], written by launch_psm_collide).
 hipError_t launch_sweep(int prec, const InstDev* insts, const int4* tiles, int ntiles, int grid, int block,
-                        int max_tile_cells, int flags, const void* src, void* dst, const int* cellmap, PairDev pairs,
-                        PartDev parts, hipStream_t st);
+                        int max_tile_cells, int flags, int psm_mode, const void* src, void* dst, const int* cellmap,
+                        PairDev pairs, PartDev parts, const void* stage, long long sstride, hipStream_t st);
 constexpr int SWEEP_LDS_LIMIT = 64 * 1024;  // bytes of LDS staging per sweep workgroup
 hipError_t launch_init_eq(int prec, void* buf, long long N, double rho, const double u[3], hipStream_t st);
 hipError_t launch_to_f64(int prec, const void* a, int q, long long c0, double* b, long long n, hipStream_t st);
@@ -92,10 +99,12 @@ hipError_t launch_psm_fill(const int* list, int nlist, int side, int nsplit, con
                            const int* slots, const int* offsets, int cap, PairDev pairs, hipStream_t st);
 hipError_t launch_psm_cellmap(int stage, const int* count, int cap, const InstDev* insts, PartDev parts,
                               PairDev pairs, int* cellmap, hipStream_t st);
-// Collision of every overlapped cell (two launches: single-pair cells, then shared cells).  psm_m: the solid
-// operator shared by every PSM instance (1..3), or 0 when they differ.
+// Collision of every overlapped cell (two launches: single-pair cells, then shared cells), pushed into dst or,
+// with stage != nullptr, stored per leader pair for the sweep that follows.  psm_m: the solid operator shared by every
+// PSM instance (1..3), or 0 when they differ.
 hipError_t launch_psm_collide(int prec, int psm_m, const int* count, int cap, const InstDev* insts, PartDev parts,
-                              PairDev pairs, const int* cellmap, const void* src, void* dst, hipStream_t st);
+                              PairDev pairs, const int* cellmap, const void* src, void* dst, void* stage,
+                              long long sstride, hipStream_t st);
 hipError_t launch_psm_fields(int prec, const int* count, int cap, const InstDev* insts, PartDev parts, PairDev pairs,
                              const int* cellmap, const void* buf, int inst, long long c0, long long n, double* out,
                              hipStream_t st);

@@ -535,7 +535,9 @@ hipError_t launch_psm_cellmap(int stage, const int* count, int cap, const InstDe
 
 // Overlapped cells, visited through their leader pairs in pair order (the
 // list is ordered by particle, slab and row, so neighbouring lanes touch
-// neighbouring cells and share cache lines).  MULTI = false: the cells with a
+// neighbouring cells and share cache lines).  The post-collision values are
+// pushed into dst, or with stage != nullptr stored at stage[q * sstride + L]
+// (whole cache lines; the next sweep pushes them).  MULTI = false: the cells with a
 // single pair, with the solid operator M fixed at compile time (0: per
 // instance) -- the common case, compiled for four waves per SIMD where the
 // storage is below 8 bytes and M is fixed; MULTI = true: the cells shared by
@@ -544,7 +546,8 @@ template <typename S, int M, bool MULTI>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(MULTI || M == 0 || sizeof(S) == 8 ? 1 : 4))) void psm_collide_kernel(
     const int* __restrict__ count, int cap, const InstDev* __restrict__ insts, PartDev P, PairDev pairs,
-    const int* __restrict__ cellmap, const S* __restrict__ src, S* __restrict__ dst) {
+    const int* __restrict__ cellmap, const S* __restrict__ src, S* __restrict__ dst, S* __restrict__ stage,
+    long long sstride) {
   using R = typename CompOf<S>::type;
   const int npairs = min(*count, cap);
   for (int L = blockIdx.x * blockDim.x + threadIdx.x; L < npairs; L += gridDim.x * blockDim.x) {
@@ -559,6 +562,11 @@ __attribute__((amdgpu_waves_per_eu(MULTI || M == 0 || sizeof(S) == 8 ? 1 : 4))) 
 #pragma unroll
     for (int q = 0; q < Q; ++q) g[q] = Codec<S>::ld(s[pdf_at(c, q)]);
     psm_cell_collide<M, !MULTI, R>(g, out, I, P, pairs, L, c);
+    if (stage) {  // the sweep pushes them
+#pragma unroll
+      for (int q = 0; q < Q; ++q) stage[q * sstride + L] = Codec<S>::st(out[q]);
+      continue;
+    }
     const int nx = I.nx, ny = I.ny, nz = I.nz;
     const int x = c % nx, yz = c / nx, y = yz % ny, z = yz / ny;
 #pragma unroll
@@ -579,11 +587,12 @@ __attribute__((amdgpu_waves_per_eu(MULTI || M == 0 || sizeof(S) == 8 ? 1 : 4))) 
   }
 
 hipError_t launch_psm_collide(int prec, int psm_m, const int* count, int cap, const InstDev* insts, PartDev parts,
-                              PairDev pairs, const int* cellmap, const void* src, void* dst, hipStream_t st) {
+                              PairDev pairs, const int* cellmap, const void* src, void* dst, void* stage,
+                              long long sstride, hipStream_t st) {
   const int grid = 2048;
 #define PSM_COLLIDE(MM, MULTI)                                                                                      \
   LBM_DISPATCH(prec, hipLaunchKernelGGL((psm_collide_kernel<S, MM, MULTI>), dim3(grid), dim3(256), 0, st, count, cap, \
-                                        insts, parts, pairs, cellmap, (const S*)src, (S*)dst))
+                                        insts, parts, pairs, cellmap, (const S*)src, (S*)dst, (S*)stage, sstride))
   switch (psm_m) {
     case 1: PSM_COLLIDE(1, false); break;
     case 2: PSM_COLLIDE(2, false); break;

@@ -5,11 +5,15 @@
 // (aligned, coalesced along x), collides them with BGK or TRT plus the body
 // force, and pushes f~_q(x, t) to x + c_q in buffer `dst` (periodic wrap).
 // MEM coupling is applied afterwards by the link kernel, which overwrites the
-// few affected values.  PSM cells are either collided here (the variant that
-// reads the cell map and applies the partially saturated collision to
-// overlapped cells inline) or re-collided afterwards by the overlap kernel;
-// both use the same per-cell function.  Each workgroup owns whole x-rows and realigns the +-x
-// shifted values through LDS, so all stores are aligned row segments.
+// few affected values.  PSM cells are handled in one of three ways, with
+// identical results: collided here (the sweep reads the cell map and applies
+// the partially saturated collision to overlapped cells inline), re-collided
+// afterwards by the overlap kernel, or collided beforehand by the overlap
+// kernel into a staging array indexed by the cell's leader pair, from which
+// the sweep takes their post-collision values (so every store of the
+// overlapped cells is part of the sweep's aligned row writes).  Each workgroup
+// owns whole x-rows and realigns the +-x shifted values through LDS, so all
+// stores are aligned row segments.
 #include <climits>
 
 #include "common.h"
@@ -118,10 +122,13 @@ __device__ __forceinline__ __bf16 ld_nt<__bf16>(const __bf16* p) {
   return __builtin_bit_cast(__bf16, __builtin_nontemporal_load((const unsigned short*)p));
 }
 
-template <typename S, bool NTLD, bool PSM>
+// PSM: 0 no overlapped cells, 1 collide them inline, 2 take their staged
+// post-collision values (stage[q * sstride + leader pair]).
+template <typename S, bool NTLD, int PSM>
 __device__ __forceinline__ void sweep_body(const InstDev* __restrict__ insts, const int4* __restrict__ tiles,
                                            int ntiles, const S* __restrict__ src, S* __restrict__ dst,
-                                           const int* __restrict__ cellmap, const PairDev& pairs, const PartDev& P) {
+                                           const int* __restrict__ cellmap, const PairDev& pairs, const PartDev& P,
+                                           const S* __restrict__ stage, long long sstride) {
   using R = typename CompOf<S>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   S* sh = reinterpret_cast<S*>(smem_raw);
@@ -148,10 +155,18 @@ __device__ __forceinline__ void sweep_body(const InstDev* __restrict__ insts, co
         const S* a = &s[pdf_at(idx, q)];
         g[q] = Codec<S>::ld(NTLD ? ld_nt(a) : *a);
       }
-      if constexpr (PSM) {
+      if constexpr (PSM == 1) {
         const int L = I.cellmap_off >= 0 ? cellmap[I.cellmap_off + idx] : INT_MAX;
         if (L != INT_MAX) psm_cell_collide<0, false, R>(g, o, I, P, pairs, L, idx);
         else collide_cell<R>(g, o, lp, lm, fx, fy, fz);
+      } else if constexpr (PSM == 2) {
+        const int L = I.cellmap_off >= 0 ? cellmap[I.cellmap_off + idx] : INT_MAX;
+        if (L != INT_MAX) {
+#pragma unroll
+          for (int q = 0; q < Q; ++q) o[q] = Codec<S>::ld(stage[q * sstride + L]);
+        } else {
+          collide_cell<R>(g, o, lp, lm, fx, fy, fz);
+        }
       } else {
         collide_cell<R>(g, o, lp, lm, fx, fy, fz);
       }
@@ -193,11 +208,12 @@ __device__ __forceinline__ void sweep_body(const InstDev* __restrict__ insts, co
   }
 }
 
-template <typename S, bool NTLD, bool PSM>
+template <typename S, bool NTLD, int PSM>
 __global__ __launch_bounds__(256) void sweep_kernel(const InstDev* __restrict__ insts, const int4* __restrict__ tiles,
                                                     int ntiles, const S* __restrict__ src, S* __restrict__ dst,
-                                                    const int* __restrict__ cellmap, PairDev pairs, PartDev P) {
-  sweep_body<S, NTLD, PSM>(insts, tiles, ntiles, src, dst, cellmap, pairs, P);
+                                                    const int* __restrict__ cellmap, PairDev pairs, PartDev P,
+                                                    const S* __restrict__ stage, long long sstride) {
+  sweep_body<S, NTLD, PSM>(insts, tiles, ntiles, src, dst, cellmap, pairs, P, stage, sstride);
 }
 
 // The same sweep compiled for six waves per SIMD (at most 80 registers per
@@ -207,7 +223,7 @@ template <typename S, bool NTLD>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void sweep_kernel_occ6(
     const InstDev* __restrict__ insts, const int4* __restrict__ tiles, int ntiles, const S* __restrict__ src,
     S* __restrict__ dst) {
-  sweep_body<S, NTLD, false>(insts, tiles, ntiles, src, dst, nullptr, PairDev{}, PartDev{});
+  sweep_body<S, NTLD, 0>(insts, tiles, ntiles, src, dst, nullptr, PairDev{}, PartDev{}, nullptr, 0);
 }
 
 // Uniform equilibrium initial state, Eq. LBM_EQ: g_q = w_q (rho - 1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u).
@@ -277,51 +293,52 @@ __global__ void fields_kernel(const S* __restrict__ buf, long long N, long long 
 // ------------------------------------------------------------------------ launchers
 template <typename S, bool NTLD>
 hipError_t launch_sweep_n(const InstDev* insts, const int4* tiles, int ntiles, int grid, int block, size_t lds,
-                          const void* src, void* dst, const int* cellmap, PairDev pairs, PartDev parts, bool occ6,
-                          hipStream_t st) {
+                          int psm_mode, const void* src, void* dst, const int* cellmap, PairDev pairs, PartDev parts,
+                          const void* stage, long long sstride, bool occ6, hipStream_t st) {
   if constexpr (sizeof(S) < 8) {
-    if (occ6 && !cellmap) {
+    if (occ6 && psm_mode == 0) {
       hipLaunchKernelGGL((sweep_kernel_occ6<S, NTLD>), dim3(grid), dim3(block), lds, st, insts, tiles, ntiles,
                          (const S*)src, (S*)dst);
       return hipGetLastError();
     }
   }
-  if (cellmap)
-    hipLaunchKernelGGL((sweep_kernel<S, NTLD, true>), dim3(grid), dim3(block), lds, st, insts, tiles, ntiles,
-                       (const S*)src, (S*)dst, cellmap, pairs, parts);
-  else
-    hipLaunchKernelGGL((sweep_kernel<S, NTLD, false>), dim3(grid), dim3(block), lds, st, insts, tiles, ntiles,
-                       (const S*)src, (S*)dst, cellmap, pairs, parts);
+#define LBM_SWEEP(MODE)                                                                                          \
+  hipLaunchKernelGGL((sweep_kernel<S, NTLD, MODE>), dim3(grid), dim3(block), lds, st, insts, tiles, ntiles,       \
+                     (const S*)src, (S*)dst, cellmap, pairs, parts, (const S*)stage, sstride)
+  if (psm_mode == 1) LBM_SWEEP(1);
+  else if (psm_mode == 2) LBM_SWEEP(2);
+  else LBM_SWEEP(0);
+#undef LBM_SWEEP
   return hipGetLastError();
 }
-
 template <typename S>
 hipError_t launch_sweep_t(const InstDev* insts, const int4* tiles, int ntiles, int grid, int block, int max_tile_cells,
-                          int flags, const void* src, void* dst, const int* cellmap, PairDev pairs, PartDev parts,
-                          hipStream_t st) {
+                          int flags, int psm_mode, const void* src, void* dst, const int* cellmap, PairDev pairs,
+                          PartDev parts, const void* stage, long long sstride, hipStream_t st) {
   const size_t lds = (size_t)NXSHIFT * max_tile_cells * sizeof(S);
   const bool occ6 = (flags & SWEEP_OCC6) != 0;
   if (flags & SWEEP_NT_LOADS)
-    return launch_sweep_n<S, true>(insts, tiles, ntiles, grid, block, lds, src, dst, cellmap, pairs, parts, occ6, st);
-  return launch_sweep_n<S, false>(insts, tiles, ntiles, grid, block, lds, src, dst, cellmap, pairs, parts, occ6, st);
+    return launch_sweep_n<S, true>(insts, tiles, ntiles, grid, block, lds, psm_mode, src, dst, cellmap, pairs, parts,
+                                   stage, sstride, occ6, st);
+  return launch_sweep_n<S, false>(insts, tiles, ntiles, grid, block, lds, psm_mode, src, dst, cellmap, pairs, parts,
+                                  stage, sstride, occ6, st);
 }
-
 hipError_t launch_sweep(int prec, const InstDev* insts, const int4* tiles, int ntiles, int grid, int block,
-                        int max_tile_cells, int flags, const void* src, void* dst, const int* cellmap, PairDev pairs,
-                        PartDev parts, hipStream_t st) {
+                        int max_tile_cells, int flags, int psm_mode, const void* src, void* dst, const int* cellmap,
+                        PairDev pairs, PartDev parts, const void* stage, long long sstride, hipStream_t st) {
   switch (prec) {
     case PREC_FP64:
-      return launch_sweep_t<double>(insts, tiles, ntiles, grid, block, max_tile_cells, flags, src, dst, cellmap, pairs,
-                                    parts, st);
+      return launch_sweep_t<double>(insts, tiles, ntiles, grid, block, max_tile_cells, flags, psm_mode, src, dst,
+                                    cellmap, pairs, parts, stage, sstride, st);
     case PREC_FP32:
-      return launch_sweep_t<float>(insts, tiles, ntiles, grid, block, max_tile_cells, flags, src, dst, cellmap, pairs,
-                                   parts, st);
+      return launch_sweep_t<float>(insts, tiles, ntiles, grid, block, max_tile_cells, flags, psm_mode, src, dst,
+                                   cellmap, pairs, parts, stage, sstride, st);
     case PREC_FP16:
-      return launch_sweep_t<_Float16>(insts, tiles, ntiles, grid, block, max_tile_cells, flags, src, dst, cellmap,
-                                      pairs, parts, st);
+      return launch_sweep_t<_Float16>(insts, tiles, ntiles, grid, block, max_tile_cells, flags, psm_mode, src, dst,
+                                      cellmap, pairs, parts, stage, sstride, st);
     case PREC_BF16:
-      return launch_sweep_t<__bf16>(insts, tiles, ntiles, grid, block, max_tile_cells, flags, src, dst, cellmap,
-                                    pairs, parts, st);
+      return launch_sweep_t<__bf16>(insts, tiles, ntiles, grid, block, max_tile_cells, flags, psm_mode, src, dst,
+                                    cellmap, pairs, parts, stage, sstride, st);
   }
   return hipErrorInvalidValue;
 }

@@ -33,7 +33,7 @@ def _small_batch(seed=3):
     return out
 
 
-@pytest.mark.parametrize("flags", [0, lbmps.SWEEP_PSM_FUSED])
+@pytest.mark.parametrize("flags", [0, lbmps.SWEEP_PSM_FUSED, lbmps.SWEEP_PSM_STAGED])
 def test_batched_instances_equal_solo_runs_bitwise(flags):
     insts = _small_batch()
     dmax = max(d["D"] for d in insts)

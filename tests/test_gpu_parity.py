@@ -194,16 +194,19 @@ def test_poiseuille_walls_on_gpu():
 
 
 @pytest.mark.parametrize("m,b", [(3, 2), (1, 1)])
-def test_psm_collision_inside_sweep_equals_separate_pass(m, b):
-    # the same moving case with PSM cells collided inside the sweep and in the
-    # separate overlap pass: identical bits, and both on the oracle
+def test_psm_collision_modes_agree_bitwise(m, b):
+    # the same moving case with PSM cells collided inside the sweep, in the
+    # overlap pass after the sweep and staged by the overlap pass before it:
+    # identical bits, and all on the oracle
     from paper_1702_04910_amd import lbmps
 
     parts = dict(X=[[10.2, 12.1, 12.3], [17.4, 12.6, 12.0]], U=[[0.01, 0, 0], [-0.005, 0.004, 0]],
                  Om=[[0, 0, 0.001], [0, 0, 0]], D=[7.0, 6.5], rho=[1.5, 1.3], fixed=[False, False])
     sims = []
-    for flags in (lbmps.SWEEP_PSM_FUSED, lbmps.SWEEP_PSM_SEPARATE):
-        say("PSM inside sweep" if flags == lbmps.SWEEP_PSM_FUSED else "PSM separate pass", m, b)
+    names = {lbmps.SWEEP_PSM_FUSED: "inside sweep", lbmps.SWEEP_PSM_SEPARATE: "separate pass",
+             lbmps.SWEEP_PSM_STAGED: "staged"}
+    for flags in (lbmps.SWEEP_PSM_FUSED, lbmps.SWEEP_PSM_SEPARATE, lbmps.SWEEP_PSM_STAGED):
+        say("PSM", names[flags], m, b)
         ora, sim = make_pair(28, 24, 24, 0.05, coupling="psm", collision="trt", psm_m=m, psm_b=b,
                              f_ext=(1e-5, 0, 0), gravity=(0, 0, -1e-4), parts=parts, eps_n=4, n_sub=2,
                              sweep_flags=flags)
@@ -215,11 +218,13 @@ def test_psm_collision_inside_sweep_equals_separate_pass(m, b):
         for eF, eT, _ in errs:
             assert eF < 1e-11 and eT < 1e-11
         sims.append(sim)
-    a, b_ = sims
-    assert np.array_equal(a.get_pdfs(), b_.get_pdfs())
-    pa, pb = a.particles(), b_.particles()
-    for k in ("F", "T", "U", "X"):
-        assert np.array_equal(pa[k], pb[k])
+    a = sims[0]
+    pa = a.particles()
+    for b_ in sims[1:]:
+        assert np.array_equal(a.get_pdfs(), b_.get_pdfs())
+        pb = b_.particles()
+        for k in ("F", "T", "U", "X"):
+            assert np.array_equal(pa[k], pb[k])
 
 
 @pytest.mark.parametrize("mode", [3, 4])  # edge intersection, surface distance
