@@ -96,7 +96,9 @@ typedef struct lbmps_config {
                             bit 4 collide them in a pass over the overlap list before the sweep, into a
                             staging array that the sweep pushes (reads the cell map of every cell);
                             bits 1, 2, 4 are exclusive; with none of them the library stages when the
-                            spheres (diameter D + 2) cover at least 1 % of the PSM cells, else uses bit 2 */
+                            spheres (diameter D + 2) cover at least 1 % of the PSM cells, else uses bit 2;
+                            bits 5-6: at most 3 (value 1) or 2 (value 2) sweep workgroups per CU, by
+                            reserving LDS (value 3 is invalid) */
   int32_t reserved;
   double max_diameter;   /* largest particle diameter that will be set (cells) */
   double nu;             /* kinematic viscosity, nu = (tau - 1/2)/3 (Eq. Viscosity) */

@@ -3,10 +3,13 @@
 For a box shape and storage precision it times the sweep kernel (HIP events
 recorded by the library around every launch) over a grid of launch shapes:
 rows per tile (sized by the LDS staging they need), workgroup size, a
-persistent grid or one workgroup per tile, and plain or non-temporal loads.
-The timing instance is a coupling-free copy of the box (the sweep kernel does
-not depend on the coupling).  Results are cached in a JSON file keyed by the
-device name, shape and precision.
+persistent grid or one workgroup per tile, plain or non-temporal loads, the
+six-wave build, and a cap on the sweep workgroups resident per CU (fewer
+concurrent streams can raise the achieved HBM bandwidth).  The timing instance
+is a coupling-free copy of the box (the sweep kernel does not depend on the
+coupling); one instance per row count, the other parameters switched with
+set_launch.  Results are cached in a JSON file keyed by the device name, shape
+and precision.
 
     python -m paper_1702_04910_amd.autotune 192 192 384 fp32
 """
@@ -26,7 +29,11 @@ def _key(nx, ny, nz, precision):
     return "%s|%dx%dx%d|%s" % (torch.cuda.get_device_name(0), nx, ny, nz, precision)
 
 
+CAPS = (0, lbmps.SWEEP_WG_CAP3, lbmps.SWEEP_WG_CAP2)
+
+
 def candidates(nx, precision):
+    """Launch shapes to time, grouped by tile_rows (one timing instance each)."""
     s = lbmps.STORAGE_BYTES[lbmps.PRECISION[precision]]
     max_rows = max(1, 65536 // (10 * s * nx))
     rows = sorted({max(1, min(max_rows, t // nx)) for t in (256, 512, 1024, 2048, 4096)})
@@ -35,7 +42,23 @@ def candidates(nx, precision):
         for block in (128, 256):
             for grid in (0, 2048):
                 for flags in ((0, 1, 8, 9) if s < 8 else (0, 1)):  # + six-wave build (bit 3) for 4/2-byte storage
-                    out.append(dict(tile_rows=r, block_threads=block, grid_blocks=grid, sweep_flags=flags))
+                    for cap in CAPS:
+                        out.append(dict(tile_rows=r, block_threads=block, grid_blocks=grid, sweep_flags=flags | cap))
+    return out
+
+
+def _time_launches(sim, shapes, sweeps, warmup):
+    """Microseconds per sweep launch for each shape, on one instance."""
+    out = []
+    for sh in shapes:
+        sim.set_launch(sh["block_threads"], sh["grid_blocks"], sh["sweep_flags"])
+        sim.step(warmup)
+        sim.sync()
+        sim.set_timing(True)
+        sim.step(sweeps)
+        ms, n = sim.timing()
+        sim.set_timing(False)
+        out.append(ms / n * 1e3)
     return out
 
 
@@ -44,12 +67,7 @@ def time_shape(nx, ny, nz, precision, shape, sweeps=20, warmup=4):
     sim = lbmps.Sim(cfg)
     try:
         sim.init_equilibrium()
-        sim.step(warmup)
-        sim.sync()
-        sim.set_timing(True)
-        sim.step(sweeps)
-        ms, n = sim.timing()
-        return ms / n * 1e3  # microseconds per sweep launch
+        return _time_launches(sim, [shape], sweeps, warmup)[0]
     finally:
         sim.close()
 
@@ -67,12 +85,20 @@ def tune(nx, ny, nz, precision, sweeps=20, cache=CACHE, force=False, verbose=Fal
     if key in db and not force:
         return db[key]
     best = None
-    for shape in candidates(nx, precision):
-        us = time_shape(nx, ny, nz, precision, shape, sweeps=sweeps)
-        if verbose:
-            print("  %s -> %.1f us" % (shape, us), file=sys.stderr, flush=True)
-        if best is None or us < best["us"]:
-            best = dict(shape, us=us)
+    cands = candidates(nx, precision)
+    for r in sorted({c["tile_rows"] for c in cands}):
+        group = [c for c in cands if c["tile_rows"] == r]
+        sim = lbmps.Sim(lbmps.make_config(nx, ny, nz, 0.05, precision=precision, **group[0]))
+        try:
+            sim.init_equilibrium()
+            times = _time_launches(sim, group, sweeps, 4)
+        finally:
+            sim.close()
+        for shape, us in zip(group, times):
+            if verbose:
+                print("  %s -> %.1f us" % (shape, us), file=sys.stderr, flush=True)
+            if best is None or us < best["us"]:
+                best = dict(shape, us=us)
     if cache:
         os.makedirs(os.path.dirname(cache), exist_ok=True)
         db[key] = best
@@ -92,7 +118,7 @@ def tune_batch(make_sim, tile_cells=(256, 512, 1024), grids=(0, 1024, 2048, 4096
         sim = make_sim(tc)
         try:
             for grid in grids:
-                for flags in (0, 1, 8, 9):
+                for flags in [f | cap for f in (0, 1, 8, 9) for cap in CAPS]:
                     sim.set_launch(256, grid, flags)
                     sim.set_timing(True)
                     sim.step(sweeps)

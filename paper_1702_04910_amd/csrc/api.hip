@@ -82,6 +82,7 @@ bool valid_cfg(const lbmps_config& c, std::string& err) {
   if (c.eps_mode < 0 || c.eps_mode > 4) { err = "unknown eps_mode"; return false; }
   if (c.block_threads < 0 || c.block_threads > 256 || (c.block_threads % 64)) { err = "block_threads must be a multiple of 64, <= 256"; return false; }
   if (c.sweep_flags & ~SWEEP_FLAGS_ALL) { err = "unknown sweep_flags bits"; return false; }
+  if ((c.sweep_flags & SWEEP_WG_CAP_MASK) == SWEEP_WG_CAP_MASK) { err = "sweep_flags: workgroup cap 3 is invalid"; return false; }
   if (__builtin_popcount(c.sweep_flags & SWEEP_PSM_MODES) > 1) {
     err = "sweep_flags: the PSM modes (fused, separate, staged) are exclusive"; return false;
   }
@@ -932,7 +933,8 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
 lbmps_status lbmps_set_launch(lbmps_ctx* c, int32_t block_threads, int32_t grid_blocks, int32_t sweep_flags) {
   if (!c) return LBMPS_EINVAL;
   if (block_threads < 0 || block_threads > 256 || (block_threads % 64)) return fail(c, LBMPS_EINVAL, "bad block size");
-  if (grid_blocks < 0 || (sweep_flags & ~SWEEP_FLAGS_ALL) || __builtin_popcount(sweep_flags & SWEEP_PSM_MODES) > 1)
+  if (grid_blocks < 0 || (sweep_flags & ~SWEEP_FLAGS_ALL) || __builtin_popcount(sweep_flags & SWEEP_PSM_MODES) > 1 ||
+      (sweep_flags & SWEEP_WG_CAP_MASK) == SWEEP_WG_CAP_MASK)
     return fail(c, LBMPS_EINVAL, "bad grid or flags");
   drop_graph(c);
   c->block = block_threads ? block_threads : 256;

@@ -12,11 +12,23 @@ namespace lbm {
 // bit 3 the sweep compiled for six waves per SIMD (4- and 2-byte storage);
 // bit 4 collide them in the overlap kernel before the sweep into a staging
 // array that the sweep pushes (none of bits 1, 2, 4: chosen from the expected
-// share of overlapped cells).  Results never depend on them.
+// share of overlapped cells); bits 5-6 cap the sweep workgroups resident per
+// CU (0 no cap, 1 three, 2 two; 3 is invalid) by reserving LDS.  Results never
+// depend on them.
 enum {
   SWEEP_NT_LOADS = 1, SWEEP_PSM_FUSED = 2, SWEEP_PSM_SEPARATE = 4, SWEEP_OCC6 = 8, SWEEP_PSM_STAGED = 16,
-  SWEEP_FLAGS_ALL = 31, SWEEP_PSM_MODES = SWEEP_PSM_FUSED | SWEEP_PSM_SEPARATE | SWEEP_PSM_STAGED
+  SWEEP_WG_CAP_SHIFT = 5, SWEEP_WG_CAP_MASK = 3 << SWEEP_WG_CAP_SHIFT, SWEEP_FLAGS_ALL = 127,
+  SWEEP_PSM_MODES = SWEEP_PSM_FUSED | SWEEP_PSM_SEPARATE | SWEEP_PSM_STAGED
 };
+constexpr int LDS_PER_CU = 160 * 1024;
+// LDS a sweep workgroup reserves: what its staging needs, raised under a cap
+// so that only (4 - cap) workgroups fit on one CU.
+inline size_t sweep_lds_bytes(size_t need, int flags) {
+  const int cap = (flags & SWEEP_WG_CAP_MASK) >> SWEEP_WG_CAP_SHIFT;
+  if (cap == 0) return need;
+  const size_t floor = (size_t)LDS_PER_CU / (size_t)(5 - cap) + 256;
+  return need > floor ? need : floor;
+}
 // psm_mode: 0 no PSM cells (or they are re-collided afterwards), 1 inline, 2 staged
 // (stage[q * sstride + leader pair], written by launch_psm_collide).
 hipError_t launch_sweep(int prec, const InstDev* insts, const int4* tiles, int ntiles, int grid, int block,

@@ -315,7 +315,7 @@ template <typename S>
 hipError_t launch_sweep_t(const InstDev* insts, const int4* tiles, int ntiles, int grid, int block, int max_tile_cells,
                           int flags, int psm_mode, const void* src, void* dst, const int* cellmap, PairDev pairs,
                           PartDev parts, const void* stage, long long sstride, hipStream_t st) {
-  const size_t lds = (size_t)NXSHIFT * max_tile_cells * sizeof(S);
+  const size_t lds = sweep_lds_bytes((size_t)NXSHIFT * max_tile_cells * sizeof(S), flags);
   const bool occ6 = (flags & SWEEP_OCC6) != 0;
   if (flags & SWEEP_NT_LOADS)
     return launch_sweep_n<S, true>(insts, tiles, ntiles, grid, block, lds, psm_mode, src, dst, cellmap, pairs, parts,
