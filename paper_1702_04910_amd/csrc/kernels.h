@@ -61,8 +61,8 @@ hipError_t launch_reduce(const int* list, int nlist, const int* begin, const int
                          long long ostride, PartDev parts, int nchunk_blocks, double* partial,
                          const InstDev* rigid_insts, unsigned* err, hipStream_t st);
 // Adds the min(ceil((end[j] - begin[j]) / chunk), width) chunk sums of list position j (rows of partial are
-// width wide) in order to Facc/Tacc of particle list[j]; with rigid_insts != nullptr each particle's explicit
-// Euler rigid-body step (averaging Facc over n_sub sweeps) follows.
+// width wide) in a fixed order to Facc/Tacc of particle list[j]; with rigid_insts != nullptr each particle's
+// explicit Euler rigid-body step (averaging Facc over n_sub sweeps) follows.
 hipError_t launch_finish_sums(const int* list, int nlist, const int* begin, const int* end, int chunk, int width,
                               const double* partial, PartDev parts, const InstDev* rigid_insts, unsigned* err,
                               hipStream_t st);
@@ -112,8 +112,8 @@ hipError_t launch_psm_fill(const int* list, int nlist, int side, int nsplit, con
 hipError_t launch_psm_cellmap(int stage, const int* count, int cap, const InstDev* insts, PartDev parts,
                               PairDev pairs, int* cellmap, hipStream_t st);
 // Collision of every overlapped cell (two launches: single-pair cells, then shared cells), pushed into dst or,
-// with stage != nullptr, stored per leader pair for the sweep that follows.  psm_m: the solid operator shared by every
-// PSM instance (1..3), or 0 when they differ.
+// with stage != nullptr, stored per leader pair for the sweep that follows.  psm_m: the solid operator shared by
+// every PSM instance (1..3), or 0 when they differ.
 hipError_t launch_psm_collide(int prec, int psm_m, const int* count, int cap, const InstDev* insts, PartDev parts,
                               PairDev pairs, const int* cellmap, const void* src, void* dst, void* stage,
                               long long sstride, hipStream_t st);

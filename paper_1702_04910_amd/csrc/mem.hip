@@ -416,7 +416,7 @@ __device__ __forceinline__ void link_rule(int i, const LinkDev& L, const double*
 // k < width takes chunks k, k + width, ... (the rest of the row is idle).
 // Each thread keeps the sum of its links' force and torque; the workgroup
 // stores their block_sum6, and finish_sums_kernel adds a particle's workgroup
-// sums in order, so the total repeats bit for bit.
+// sums in a fixed order, so the total repeats bit for bit.
 // Row nlist: the wall links [0, n_wall), strided over the whole row.
 template <typename S>
 __global__ __launch_bounds__(SUM_THREADS) void links_bc_kernel(int n_wall, const int* __restrict__ list, int nlist,

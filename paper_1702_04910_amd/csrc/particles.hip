@@ -119,7 +119,7 @@ hipError_t launch_scan2(const int* totals, int* offsets, int m, int side, int nl
 // chunks of RED_CHUNK consecutive records; workgroup (k, j) sums chunks k,
 // k + gridDim.x, ... in a fixed order (strided per-thread sums, then
 // block_sum6) and stores the result; finish_sums_kernel adds the workgroup
-// sums in order.  The order depends only on the record count, so results
+// sums in a fixed order.  The order depends only on the record count, so results
 // repeat bit for bit.
 __global__ __launch_bounds__(SUM_THREADS) void reduce_kernel(const int* __restrict__ begin,
                                                      const int* __restrict__ end, int base,
@@ -146,8 +146,11 @@ __global__ __launch_bounds__(SUM_THREADS) void reduce_kernel(const int* __restri
 }
 
 // One wave per particle: the min(ceil(n / chunk), width) chunk sums of list
-// position j (n = end[j] - begin[j] records) are loaded at once and added in
-// chunk order to Facc/Tacc; with insts != nullptr the rigid-body step follows.
+// position j (n = end[j] - begin[j] records): lane l loads chunks l, l + 64, ...
+// (all loads of a lane in flight together) and adds them in that order, then a
+// butterfly over the 64 lanes forms the total.  The order depends only on the
+// chunk count.  The total goes to Facc/Tacc; with insts != nullptr the
+// rigid-body step follows.
 constexpr int FIN_WAVES = 4;
 __global__ __launch_bounds__(64 * FIN_WAVES) void finish_sums_kernel(const int* __restrict__ list, int nlist,
                                                                      const int* __restrict__ begin,
@@ -161,14 +164,14 @@ __global__ __launch_bounds__(64 * FIN_WAVES) void finish_sums_kernel(const int* 
   const int n = end[j] - begin[j];
   const int parts_n = min((n + chunk - 1) / chunk, width);
   double tot[6] = {0, 0, 0, 0, 0, 0};
-  constexpr int PER = 64 / 6;  // chunk sums per round
-  for (int k0 = 0; k0 < parts_n; k0 += PER) {
-    const int m = min(PER, parts_n - k0);
-    const double v = lane < 6 * m ? partial[((long long)j * width + k0) * 6 + lane] : 0.0;
-    for (int i = 0; i < m; ++i)
+  for (int i = lane; i < parts_n; i += 64) {
+    const double* src = partial + ((long long)j * width + i) * 6;
 #pragma unroll
-      for (int k = 0; k < 6; ++k) tot[k] += __shfl(v, 6 * i + k, 64);
+    for (int k = 0; k < 6; ++k) tot[k] += src[k];
   }
+#pragma unroll
+  for (int k = 0; k < 6; ++k)
+    for (int m = 32; m >= 1; m >>= 1) tot[k] += __shfl_xor(tot[k], m, 64);
   if (lane == 0) {
     const int p = list[j];
     if (parts_n > 0)
