@@ -250,16 +250,19 @@ def test_closed_form_estimators(mode):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp16"])
-def test_six_wave_sweep_build_is_bitwise_identical(precision):
+def test_sweep_launch_variants_are_bitwise_identical(precision):
     from paper_1702_04910_amd import lbmps
 
     nx, ny, nz = 37, 23, 19
     g0 = inputs.random_pdfs((nz, ny, nx), 1e-3, seed=25)
     out = []
-    for flags in (0, lbmps.SWEEP_OCC6, lbmps.SWEEP_OCC6 | lbmps.SWEEP_NT_LOADS):
+    # and the caps on resident workgroups per CU (LDS reservation only)
+    for flags in (0, lbmps.SWEEP_OCC6, lbmps.SWEEP_OCC6 | lbmps.SWEEP_NT_LOADS, lbmps.SWEEP_WG_CAP3,
+                  lbmps.SWEEP_WG_CAP2 | lbmps.SWEEP_NT_LOADS):
         ora, sim = make_pair(nx, ny, nz, 0.07, collision="trt", f_ext=(1e-5, -2e-5, 3e-5), precision=precision,
                              g0=g0, sweep_flags=flags)
         sim.step(6)
         out.append(sim.get_pdfs())
         sim.close()
-    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+    for o in out[1:]:
+        assert np.array_equal(out[0], o)
