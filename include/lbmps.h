@@ -98,7 +98,9 @@ typedef struct lbmps_config {
                             bits 1, 2, 4 are exclusive; with none of them the library stages when the
                             spheres (diameter D + 2) cover at least 1 % of the PSM cells, else uses bit 2;
                             bits 5-6: at most 3 (value 1) or 2 (value 2) sweep workgroups per CU, by
-                            reserving LDS (value 3 is invalid) */
+                            reserving LDS (value 3 is invalid);
+                            bit 7 two x-adjacent cells per sweep thread, moved as one word per direction
+                            (needs an even nx; ignored with bit 3 and while bit 1 or 4 is in effect) */
   int32_t reserved;
   double max_diameter;   /* largest particle diameter that will be set (cells) */
   double nu;             /* kinematic viscosity, nu = (tau - 1/2)/3 (Eq. Viscosity) */

@@ -4,8 +4,9 @@ For a box shape and storage precision it times the sweep kernel (HIP events
 recorded by the library around every launch) over a grid of launch shapes:
 rows per tile (sized by the LDS staging they need), workgroup size, a
 persistent grid or one workgroup per tile, plain or non-temporal loads, the
-six-wave build, and a cap on the sweep workgroups resident per CU (fewer
-concurrent streams can raise the achieved HBM bandwidth).  The timing instance
+six-wave build, a cap on the sweep workgroups resident per CU (fewer
+concurrent streams can raise the achieved HBM bandwidth) and one or two cells
+per thread.  The timing instance
 is a coupling-free copy of the box (the sweep kernel does not depend on the
 coupling); one instance per row count, the other parameters switched with
 set_launch.  Results are cached in a JSON file keyed by the device name, shape
@@ -43,7 +44,9 @@ def candidates(nx, precision):
             for grid in (0, 2048):
                 for flags in ((0, 1, 8, 9) if s < 8 else (0, 1)):  # + six-wave build (bit 3) for 4/2-byte storage
                     for cap in CAPS:
-                        out.append(dict(tile_rows=r, block_threads=block, grid_blocks=grid, sweep_flags=flags | cap))
+                        for pairs in ((0, lbmps.SWEEP_CELL_PAIRS) if nx % 2 == 0 and not flags & 8 else (0,)):
+                            out.append(dict(tile_rows=r, block_threads=block, grid_blocks=grid,
+                                            sweep_flags=flags | cap | pairs))
     return out
 
 
@@ -118,8 +121,12 @@ def tune_batch(make_sim, tile_cells=(256, 512, 1024), grids=(0, 1024, 2048, 4096
         sim = make_sim(tc)
         try:
             for grid in grids:
-                for flags in [f | cap for f in (0, 1, 8, 9) for cap in CAPS]:
-                    sim.set_launch(256, grid, flags)
+                for flags in [f | cap | pr for f in (0, 1, 8, 9) for cap in CAPS
+                              for pr in ((0,) if f & 8 else (0, lbmps.SWEEP_CELL_PAIRS))]:
+                    try:
+                        sim.set_launch(256, grid, flags)
+                    except lbmps.LbmpsError:  # cell pairs need every instance's nx even
+                        continue
                     sim.set_timing(True)
                     sim.step(sweeps)
                     ms, n = sim.timing()

@@ -83,6 +83,7 @@ bool valid_cfg(const lbmps_config& c, std::string& err) {
   if (c.block_threads < 0 || c.block_threads > 256 || (c.block_threads % 64)) { err = "block_threads must be a multiple of 64, <= 256"; return false; }
   if (c.sweep_flags & ~SWEEP_FLAGS_ALL) { err = "unknown sweep_flags bits"; return false; }
   if ((c.sweep_flags & SWEEP_WG_CAP_MASK) == SWEEP_WG_CAP_MASK) { err = "sweep_flags: workgroup cap 3 is invalid"; return false; }
+  if ((c.sweep_flags & SWEEP_CELL_PAIRS) && (c.nx & 1)) { err = "sweep_flags: cell pairs need an even nx"; return false; }
   if (__builtin_popcount(c.sweep_flags & SWEEP_PSM_MODES) > 1) {
     err = "sweep_flags: the PSM modes (fused, separate, staged) are exclusive"; return false;
   }
@@ -936,6 +937,9 @@ lbmps_status lbmps_set_launch(lbmps_ctx* c, int32_t block_threads, int32_t grid_
   if (grid_blocks < 0 || (sweep_flags & ~SWEEP_FLAGS_ALL) || __builtin_popcount(sweep_flags & SWEEP_PSM_MODES) > 1 ||
       (sweep_flags & SWEEP_WG_CAP_MASK) == SWEEP_WG_CAP_MASK)
     return fail(c, LBMPS_EINVAL, "bad grid or flags");
+  if (sweep_flags & SWEEP_CELL_PAIRS)
+    for (const auto& cf : c->cfg)
+      if (cf.nx & 1) return fail(c, LBMPS_EINVAL, "cell pairs need an even nx");
   drop_graph(c);
   c->block = block_threads ? block_threads : 256;
   c->grid = grid_blocks > 0 ? std::min(grid_blocks, c->ntiles) : c->ntiles;

@@ -13,11 +13,13 @@ namespace lbm {
 // bit 4 collide them in the overlap kernel before the sweep into a staging
 // array that the sweep pushes (none of bits 1, 2, 4: chosen from the expected
 // share of overlapped cells); bits 5-6 cap the sweep workgroups resident per
-// CU (0 no cap, 1 three, 2 two; 3 is invalid) by reserving LDS.  Results never
+// CU (0 no cap, 1 three, 2 two; 3 is invalid) by reserving LDS; bit 7 every
+// sweep thread handles two x-adjacent cells (needs even nx; not used with bit 3
+// or while the sweep handles overlapped cells, bits 1 and 4).  Results never
 // depend on them.
 enum {
   SWEEP_NT_LOADS = 1, SWEEP_PSM_FUSED = 2, SWEEP_PSM_SEPARATE = 4, SWEEP_OCC6 = 8, SWEEP_PSM_STAGED = 16,
-  SWEEP_WG_CAP_SHIFT = 5, SWEEP_WG_CAP_MASK = 3 << SWEEP_WG_CAP_SHIFT, SWEEP_FLAGS_ALL = 127,
+  SWEEP_WG_CAP_SHIFT = 5, SWEEP_WG_CAP_MASK = 3 << SWEEP_WG_CAP_SHIFT, SWEEP_CELL_PAIRS = 128, SWEEP_FLAGS_ALL = 255,
   SWEEP_PSM_MODES = SWEEP_PSM_FUSED | SWEEP_PSM_SEPARATE | SWEEP_PSM_STAGED
 };
 constexpr int LDS_PER_CU = 160 * 1024;

@@ -122,6 +122,136 @@ __device__ __forceinline__ __bf16 ld_nt<__bf16>(const __bf16* p) {
   return __builtin_bit_cast(__bf16, __builtin_nontemporal_load((const unsigned short*)p));
 }
 
+// Two x-adjacent values of storage type S moved as one word (the cell-pair
+// variant of the sweep): W is the word, U the bit pattern of one value.
+template <typename S> struct Twin;
+template <> struct Twin<double> {
+  typedef unsigned long long W __attribute__((ext_vector_type(2)));
+  using U = unsigned long long;
+};
+template <> struct Twin<float> { using W = unsigned long long; using U = unsigned int; };
+template <> struct Twin<_Float16> { using W = unsigned int; using U = unsigned short; };
+template <> struct Twin<__bf16> { using W = unsigned int; using U = unsigned short; };
+
+template <typename S>
+__device__ __forceinline__ typename Twin<S>::W twin_pack(S a, S b) {
+  using U = typename Twin<S>::U;
+  using W = typename Twin<S>::W;
+  const U ua = __builtin_bit_cast(U, a), ub = __builtin_bit_cast(U, b);
+  if constexpr (sizeof(S) == 8) {
+    W w;
+    w.x = ua;
+    w.y = ub;
+    return w;
+  } else {
+    return (W)ua | ((W)ub << (8 * sizeof(S)));  // the lower address holds the low bits
+  }
+}
+template <typename S>
+__device__ __forceinline__ void twin_unpack(typename Twin<S>::W w, S& a, S& b) {
+  using U = typename Twin<S>::U;
+  if constexpr (sizeof(S) == 8) {
+    a = __builtin_bit_cast(S, (U)w.x);
+    b = __builtin_bit_cast(S, (U)w.y);
+  } else {
+    a = __builtin_bit_cast(S, (U)w);
+    b = __builtin_bit_cast(S, (U)(w >> (8 * sizeof(S))));
+  }
+}
+template <typename S, bool NT>
+__device__ __forceinline__ typename Twin<S>::W twin_ld(const S* p) {
+  const typename Twin<S>::W* q = reinterpret_cast<const typename Twin<S>::W*>(p);
+  if constexpr (NT)
+    return __builtin_nontemporal_load(q);
+  else
+    return *q;
+}
+template <typename S>
+__device__ __forceinline__ void twin_st_nt(S* p, typename Twin<S>::W w) {
+  __builtin_nontemporal_store(w, reinterpret_cast<typename Twin<S>::W*>(p));
+}
+
+// The sweep with every thread handling the two adjacent cells (x, x + 1), x
+// even (nx even, so a pair never straddles rows; every pair address is aligned
+// to two values): one word per q and cell pair for loads, c_x = 0 pushes and
+// the aligned row writes of the LDS-staged c_x = +-1 pushes.  More bytes in
+// flight per wave.  No overlapped-cell handling (PSM collided after the sweep).
+template <typename S, bool NTLD>
+__device__ __forceinline__ void sweep_body_twin(const InstDev* __restrict__ insts, const int4* __restrict__ tiles,
+                                                int ntiles, const S* __restrict__ src, S* __restrict__ dst) {
+  using R = typename CompOf<S>::type;
+  using W = typename Twin<S>::W;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  S* sh = reinterpret_cast<S*>(smem_raw);
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int4 tl = tiles[t];
+    const InstDev& I = insts[tl.x];
+    const int nx = I.nx, ny = I.ny, nz = I.nz;
+    const S* __restrict__ s = src + I.pdf_off;
+    S* __restrict__ d = dst + I.pdf_off;
+    const R lp = (R)I.lam_p, lm = (R)I.lam_m;
+    const R fx = (R)I.fext[0], fy = (R)I.fext[1], fz = (R)I.fext[2];
+    const int ncells = tl.z * nx;
+    for (int ip = threadIdx.x; 2 * ip < ncells; ip += blockDim.x) {
+      const int i = 2 * ip;
+      const int r = i / nx;
+      const int x = i - r * nx;  // even; x + 1 < nx
+      const int row = tl.y + r;
+      const int z = row / ny;
+      const int y = row - z * ny;
+      const int idx = row * nx + x;
+      R g0[Q], g1[Q], o0[Q], o1[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        S a, b;
+        twin_unpack<S>(twin_ld<S, NTLD>(&s[pdf_at(idx, q)]), a, b);
+        g0[q] = Codec<S>::ld(a);
+        g1[q] = Codec<S>::ld(b);
+      }
+      collide_cell<R>(g0, o0, lp, lm, fx, fy, fz);
+      collide_cell<R>(g1, o1, lp, lm, fx, fy, fz);
+      const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+      const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+      const int xm = x == 0 ? nx - 1 : x - 1, xpp = x + 2 == nx ? 0 : x + 2;
+      const int lrow = r * nx;
+#define LBM_PUSH2(qq)                                                                       \
+  if constexpr (cx(qq) == 0) {                                                              \
+    const int ya = pick<cy(qq)>(ym, y, yp), za = pick<cz(qq)>(zm, z, zp);                   \
+    twin_st_nt<S>(&d[pdf_at((za * ny + ya) * nx + x, qq)],                                  \
+                  twin_pack<S>(Codec<S>::st(o0[qq]), Codec<S>::st(o1[qq])));                \
+  } else {                                                                                  \
+    sh[xslot(qq) * ncells + lrow + (cx(qq) > 0 ? x + 1 : xm)] = Codec<S>::st(o0[qq]);      \
+    sh[xslot(qq) * ncells + lrow + (cx(qq) > 0 ? xpp : x)] = Codec<S>::st(o1[qq]);         \
+  }
+      LBM_PUSH2(0) LBM_PUSH2(1) LBM_PUSH2(2) LBM_PUSH2(3) LBM_PUSH2(4) LBM_PUSH2(5) LBM_PUSH2(6)
+      LBM_PUSH2(7) LBM_PUSH2(8) LBM_PUSH2(9) LBM_PUSH2(10) LBM_PUSH2(11) LBM_PUSH2(12) LBM_PUSH2(13)
+      LBM_PUSH2(14) LBM_PUSH2(15) LBM_PUSH2(16) LBM_PUSH2(17) LBM_PUSH2(18)
+#undef LBM_PUSH2
+    }
+    __syncthreads();
+    for (int ip = threadIdx.x; 2 * ip < ncells; ip += blockDim.x) {
+      const int i = 2 * ip;
+      const int r = i / nx;
+      const int x = i - r * nx;
+      const int row = tl.y + r;
+      const int z = row / ny;
+      const int y = row - z * ny;
+      const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+      const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+#define LBM_FLUSH2(qq)                                                                      \
+  {                                                                                         \
+    const int ya = pick<cy(qq)>(ym, y, yp), za = pick<cz(qq)>(zm, z, zp);                   \
+    twin_st_nt<S>(&d[pdf_at((za * ny + ya) * nx + x, qq)],                                  \
+                  *reinterpret_cast<const W*>(&sh[xslot(qq) * ncells + i]));                \
+  }
+      LBM_FLUSH2(1) LBM_FLUSH2(2) LBM_FLUSH2(7) LBM_FLUSH2(8) LBM_FLUSH2(9) LBM_FLUSH2(10) LBM_FLUSH2(11)
+      LBM_FLUSH2(12) LBM_FLUSH2(13) LBM_FLUSH2(14)
+#undef LBM_FLUSH2
+    }
+    __syncthreads();
+  }
+}
+
 // PSM: 0 no overlapped cells, 1 collide them inline, 2 take their staged
 // post-collision values (stage[q * sstride + leader pair]).
 template <typename S, bool NTLD, int PSM>
@@ -216,6 +346,13 @@ __global__ __launch_bounds__(256) void sweep_kernel(const InstDev* __restrict__ 
   sweep_body<S, NTLD, PSM>(insts, tiles, ntiles, src, dst, cellmap, pairs, P, stage, sstride);
 }
 
+template <typename S, bool NTLD>
+__global__ __launch_bounds__(256) void sweep_kernel_twin(const InstDev* __restrict__ insts,
+                                                         const int4* __restrict__ tiles, int ntiles,
+                                                         const S* __restrict__ src, S* __restrict__ dst) {
+  sweep_body_twin<S, NTLD>(insts, tiles, ntiles, src, dst);
+}
+
 // The same sweep compiled for six waves per SIMD (at most 80 registers per
 // lane instead of ~105): more loads in flight per CU.  Chosen by the launch
 // tuner; without spills for 4- and 2-byte storage only.
@@ -294,13 +431,18 @@ __global__ void fields_kernel(const S* __restrict__ buf, long long N, long long 
 template <typename S, bool NTLD>
 hipError_t launch_sweep_n(const InstDev* insts, const int4* tiles, int ntiles, int grid, int block, size_t lds,
                           int psm_mode, const void* src, void* dst, const int* cellmap, PairDev pairs, PartDev parts,
-                          const void* stage, long long sstride, bool occ6, hipStream_t st) {
+                          const void* stage, long long sstride, bool occ6, bool twin, hipStream_t st) {
   if constexpr (sizeof(S) < 8) {
-    if (occ6 && psm_mode == 0) {
+    if (occ6 && psm_mode == 0) {  // single cells only: the pair variant would spill within 80 registers
       hipLaunchKernelGGL((sweep_kernel_occ6<S, NTLD>), dim3(grid), dim3(block), lds, st, insts, tiles, ntiles,
                          (const S*)src, (S*)dst);
       return hipGetLastError();
     }
+  }
+  if (twin && psm_mode == 0) {
+    hipLaunchKernelGGL((sweep_kernel_twin<S, NTLD>), dim3(grid), dim3(block), lds, st, insts, tiles, ntiles,
+                       (const S*)src, (S*)dst);
+    return hipGetLastError();
   }
 #define LBM_SWEEP(MODE)                                                                                          \
   hipLaunchKernelGGL((sweep_kernel<S, NTLD, MODE>), dim3(grid), dim3(block), lds, st, insts, tiles, ntiles,       \
@@ -316,12 +458,12 @@ hipError_t launch_sweep_t(const InstDev* insts, const int4* tiles, int ntiles, i
                           int flags, int psm_mode, const void* src, void* dst, const int* cellmap, PairDev pairs,
                           PartDev parts, const void* stage, long long sstride, hipStream_t st) {
   const size_t lds = sweep_lds_bytes((size_t)NXSHIFT * max_tile_cells * sizeof(S), flags);
-  const bool occ6 = (flags & SWEEP_OCC6) != 0;
+  const bool occ6 = (flags & SWEEP_OCC6) != 0, twin = (flags & SWEEP_CELL_PAIRS) != 0;
   if (flags & SWEEP_NT_LOADS)
     return launch_sweep_n<S, true>(insts, tiles, ntiles, grid, block, lds, psm_mode, src, dst, cellmap, pairs, parts,
-                                   stage, sstride, occ6, st);
+                                   stage, sstride, occ6, twin, st);
   return launch_sweep_n<S, false>(insts, tiles, ntiles, grid, block, lds, psm_mode, src, dst, cellmap, pairs, parts,
-                                  stage, sstride, occ6, st);
+                                  stage, sstride, occ6, twin, st);
 }
 hipError_t launch_sweep(int prec, const InstDev* insts, const int4* tiles, int ntiles, int grid, int block,
                         int max_tile_cells, int flags, int psm_mode, const void* src, void* dst, const int* cellmap,
