@@ -54,19 +54,54 @@ struct Fwd {
   float y;
 };
 
-__device__ __forceinline__ void mlp_forward(const float* __restrict__ P, const float (&xin)[4], Fwd& f) {
+// The weight matrices as this lane's bf16 A operands (loaded and converted
+// once, reused for every tile of samples a wave processes).
+struct MlpA {
+  s4 w1[2];
+  s4 w2[2][2][4];
+};
+
+__device__ __forceinline__ void mlp_load_a(const float* __restrict__ P, MlpA& A) {
   const int lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) A.w1[t][e] = bfbits(P[OFF_W1 + (32 * t + i) * NIN + 4 * h + e]);
+#pragma unroll
+  for (int t2 = 0; t2 < 2; ++t2)
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          A.w2[t2][t][s][e] = bfbits(P[OFF_W2 + (32 * t2 + i) * NH + 32 * t + 8 * s + 4 * h + e]);
+}
+
+// Biases and output weights are read through V (b1[64] b2[64] W3[64] b3, the
+// blob's layout from OFF_B1 on with W2 skipped): the parameter blob itself, or
+// a copy in LDS.
+struct MlpV {
+  const float* b1;
+  const float* b2;
+  const float* w3;
+  float b3;
+};
+
+__device__ __forceinline__ MlpV mlp_v_global(const float* __restrict__ P) {
+  return MlpV{P + OFF_B1, P + OFF_B2, P + OFF_W3, P[OFF_B3]};
+}
+
+__device__ __forceinline__ void mlp_forward(const MlpV& V, const MlpA& A, const float (&xin)[4], Fwd& f) {
+  const int lane = threadIdx.x & 63, h = lane >> 5;
   s4 xb;
 #pragma unroll
   for (int e = 0; e < 4; ++e) xb[e] = bfbits(xin[e]);
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
-    s4 a;
+    f16v d = mfma(A.w1[t], xb, zero16());
 #pragma unroll
-    for (int e = 0; e < 4; ++e) a[e] = bfbits(P[OFF_W1 + (32 * t + i) * NIN + 4 * h + e]);
-    f16v d = mfma(a, xb, zero16());
-#pragma unroll
-    for (int e = 0; e < 16; ++e) d[e] += P[OFF_B1 + 32 * t + 8 * (e >> 2) + 4 * h + (e & 3)];
+    for (int e = 0; e < 16; ++e) d[e] += V.b1[32 * t + 8 * (e >> 2) + 4 * h + (e & 3)];
     f.z1[t] = d;
 #pragma unroll
     for (int s = 0; s < 4; ++s)
@@ -79,14 +114,9 @@ __device__ __forceinline__ void mlp_forward(const float* __restrict__ P, const f
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        s4 a;
+      for (int s = 0; s < 4; ++s) acc = mfma(A.w2[t2][t][s], f.h1b[t][s], acc);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) a[e] = bfbits(P[OFF_W2 + (32 * t2 + i) * NH + 32 * t + 8 * s + 4 * h + e]);
-        acc = mfma(a, f.h1b[t][s], acc);
-      }
-#pragma unroll
-    for (int e = 0; e < 16; ++e) acc[e] += P[OFF_B2 + 32 * t2 + 8 * (e >> 2) + 4 * h + (e & 3)];
+    for (int e = 0; e < 16; ++e) acc[e] += V.b2[32 * t2 + 8 * (e >> 2) + 4 * h + (e & 3)];
     f.z2[t2] = acc;
   }
   float part = 0.f;
@@ -94,9 +124,9 @@ __device__ __forceinline__ void mlp_forward(const float* __restrict__ P, const f
   for (int t2 = 0; t2 < 2; ++t2)
 #pragma unroll
     for (int e = 0; e < 16; ++e)
-      part += P[OFF_W3 + 32 * t2 + 8 * (e >> 2) + 4 * h + (e & 3)] * fmaxf(f.z2[t2][e], 0.f);
+      part += V.w3[32 * t2 + 8 * (e >> 2) + 4 * h + (e & 3)] * fmaxf(f.z2[t2][e], 0.f);
   part += __shfl_xor(part, 32, 64);
-  f.y = part + P[OFF_B3];
+  f.y = part + V.b3;
 }
 
 // Inference over n samples given as features X[n][8] (fp32); y clamped to [0, 1].
@@ -104,17 +134,40 @@ __device__ __forceinline__ void mlp_forward(const float* __restrict__ P, const f
 __global__ __launch_bounds__(256) void mlp_infer_kernel(const float* __restrict__ P, const float* __restrict__ X,
                                                         long long n, const int* __restrict__ count,
                                                         float* __restrict__ y) {
+  // biases and output weights in LDS (read by every tile), matrices in registers
+  __shared__ float sv[3 * NH];
+  for (int k = threadIdx.x; k < 3 * NH; k += blockDim.x)
+    sv[k] = P[k < NH ? OFF_B1 + k : OFF_B2 + (k - NH)];  // b2 and W3 are adjacent in the blob
+  __syncthreads();
+  const MlpV V{sv, sv + NH, sv + 2 * NH, P[OFF_B3]};
   if (count) n = min(n, (long long)*count);
   const int lane = threadIdx.x & 63, i = lane & 31, h = lane >> 5;
   const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
-  for (long long tile = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6; tile * 32 < n; tile += nw) {
-    const long long s = tile * 32 + i;
-    float xin[4];
+  MlpA A;
+  mlp_load_a(P, A);
+  // the inputs of the next PREF tiles are in flight while a tile is evaluated
+  constexpr int PREF = 4;
+  const long long tile0 = (blockIdx.x * (long long)blockDim.x + threadIdx.x) >> 6;
+  float xq[PREF][4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) xin[e] = s < n ? X[s * NIN + 4 * h + e] : 0.f;
-    Fwd f;
-    mlp_forward(P, xin, f);
-    if (h == 0 && s < n) y[s] = fminf(fmaxf(f.y, 0.f), 1.f);
+  for (int k = 0; k < PREF; ++k) {
+    const long long s = (tile0 + k * nw) * 32 + i;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) xq[k][e] = s < n ? X[s * NIN + 4 * h + e] : 0.f;
+  }
+  for (long long tile = tile0; tile * 32 < n; tile += PREF * nw) {
+#pragma unroll
+    for (int k = 0; k < PREF; ++k) {
+      const long long tk = tile + k * nw;
+      if (tk * 32 >= n) break;  // whole wave
+      const long long s = tk * 32 + i;
+      Fwd f;
+      mlp_forward(V, A, xq[k], f);
+      const long long sn = s + (long long)PREF * nw * 32;  // refill the slot with tile tk + PREF * nw
+#pragma unroll
+      for (int e = 0; e < 4; ++e) xq[k][e] = sn < n ? X[sn * NIN + 4 * h + e] : 0.f;
+      if (h == 0 && s < n) y[s] = fminf(fmaxf(f.y, 0.f), 1.f);
+    }
   }
 }
 
@@ -141,7 +194,9 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(const float* __restrict__
 #pragma unroll
   for (int e = 0; e < 4; ++e) xin[e] = valid ? X[idx * NIN + 4 * h + e] : 0.f;
   Fwd f;
-  mlp_forward(P, xin, f);
+  MlpA A;
+  mlp_load_a(P, A);
+  mlp_forward(mlp_v_global(P), A, xin, f);
   const float dy = valid ? 2.f * (f.y - T[idx]) / (float)batch : 0.f;
   float* G = partial + (long long)tile * NPARAM;
   // dZ2 = W3 dy [Z2 > 0]; dW3 = sum_n dy H2; db2 = sum_n dZ2; db3 = sum_n dy
@@ -326,7 +381,8 @@ hipError_t launch_mlp_infer_count(const float* P, const float* X, const int* cou
                                   hipStream_t st) {
   if (cap <= 0) return hipSuccess;
   const long long tiles = (cap + 31) / 32;
-  const unsigned grid = (unsigned)std::min<long long>((tiles + 3) / 4, 8192);
+  // about eight tiles per wave (four waves per workgroup), so that prefetching pays
+  const unsigned grid = (unsigned)std::max<long long>(1, std::min<long long>((tiles + 31) / 32, 8192));
   hipLaunchKernelGGL(mlp_infer_kernel, dim3(grid), dim3(256), 0, st, P, X, cap, count, y);
   return hipGetLastError();
 }
