@@ -188,21 +188,29 @@ __device__ inline long long slot_index(int j, int side, int z, int y, int x) {
   return (((long long)j * side + z) * side + y) * side + x;
 }
 
-// Block-wide exclusive scan of one int per thread (blockDim.x == 256).
+// Block-wide exclusive scan of one int per thread (blockDim.x == 256): an
+// inclusive scan within each wave by shuffles, then the four wave totals
+// through LDS (sh: at least 4 ints).  *total gets the block's sum.
 __device__ inline int block_excl_scan256(int v, int* sh, int* total) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int off = 1; off < 256; off <<= 1) {
-    const int a = t >= off ? sh[t - off] : 0;
-    __syncthreads();
-    sh[t] += a;
-    __syncthreads();
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  int x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
   }
-  const int incl = sh[t];
-  *total = sh[255];
+  if (lane == 63) sh[w] = x;
   __syncthreads();
-  return incl - v;
+  int before = 0, all = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int s = sh[k];
+    before += k < w ? s : 0;
+    all += s;
+  }
+  *total = all;
+  __syncthreads();  // sh may be reused by the caller
+  return before + x - v;
 }
 
 }  // namespace lbm
