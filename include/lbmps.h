@@ -208,10 +208,11 @@ lbmps_status lbmps_get_links(lbmps_ctx* ctx, int64_t cap, int32_t* cell, int32_t
 lbmps_status lbmps_get_overlaps(lbmps_ctx* ctx, int64_t cap, int32_t* cell, int32_t* particle, double* eps,
                                 int64_t* n_out);
 
-/* Measurement hook: when enabled, every sweep-kernel launch of lbmps_step is
- * bracketed by HIP events recorded on the context's stream.  set_timing resets
- * the totals; get_timing synchronises and returns the summed kernel time (ms)
- * and the number of launches timed. */
+/* Measurement hook: with enable = k > 0, every k-th sweep-kernel launch of
+ * lbmps_step from now on (the first included) is bracketed by HIP events
+ * recorded on the context's stream; 0 switches timing off, k < 0 is
+ * LBMPS_EINVAL.  set_timing resets the totals; get_timing synchronises and
+ * returns the summed kernel time (ms) and the number of launches timed. */
 lbmps_status lbmps_set_timing(lbmps_ctx* ctx, int32_t enable);
 lbmps_status lbmps_get_timing(lbmps_ctx* ctx, double* sweep_ms, int64_t* launches);
 

@@ -282,8 +282,11 @@ struct lbmps_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   int graph_period = 0, graph_cur = -1;
-  // optional per-launch timing of the sweep kernel (HIP events on the stream)
+  // optional timing of sweep-kernel launches (HIP events on the stream): every
+  // timing_stride-th launch after set_timing
   bool timing = false;
+  int timing_stride = 1;
+  long long timing_seq = 0;
   std::vector<hipEvent_t> ev;  // pairs (start, stop)
   size_t ev_used = 0;
   double sweep_ms = 0.0;
@@ -879,7 +882,8 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
     if (pm == PSM_STAGED)  // overlapped cells first, from the same pre-collision values
       HIPCHK(c, launch_psm_collide(L.prec, L.psm_m, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs,
                                    c->cellmap, src, dst, c->stage, L.pair_cap, c->st));
-    if (c->timing) {
+    const bool timed = c->timing && (c->timing_seq++ % c->timing_stride) == 0;
+    if (timed) {
       if (c->ev_used + 2 > c->ev.size()) {
         lbmps_status r = harvest_timing(c);
         if (r) return r;
@@ -895,7 +899,7 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
                            c->cfg[0].sweep_flags, pm == PSM_FUSED ? 1 : pm == PSM_STAGED ? 2 : 0, src, dst,
                            pm != PSM_SEPARATE ? c->cellmap : nullptr, c->pairs, c->parts, c->stage, L.pair_cap,
                            c->st));
-    if (c->timing) {
+    if (timed) {
       HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->st));
       c->ev_used += 2;
     }
@@ -1124,7 +1128,10 @@ lbmps_status lbmps_set_timing(lbmps_ctx* c, int32_t enable) {
   if (!c) return LBMPS_EINVAL;
   lbmps_status s = harvest_timing(c);
   if (s) return s;
+  if (enable < 0) return fail(c, LBMPS_EINVAL, "timing stride must be >= 0");
   c->timing = enable != 0;
+  c->timing_stride = enable > 0 ? enable : 1;
+  c->timing_seq = 0;
   c->sweep_ms = 0.0;
   c->sweep_launches = 0;
   return LBMPS_OK;

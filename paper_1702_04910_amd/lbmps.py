@@ -316,8 +316,9 @@ class Sim:
                                            ctypes.byref(n)))
         return dict(cell=cell, p=p, eps=e)
 
-    def set_timing(self, enable):
-        self._chk(lib().lbmps_set_timing(self._ctx, 1 if enable else 0))
+    def set_timing(self, enable, stride=1):
+        """Time every `stride`-th sweep launch from now on (enable False: off)."""
+        self._chk(lib().lbmps_set_timing(self._ctx, int(stride) if enable else 0))
 
     def timing(self):
         """(summed sweep-kernel milliseconds, number of sweep launches) since set_timing."""

@@ -123,3 +123,21 @@ def test_set_particles_argument_checks():
     sim.step(2)
     sim.sync()
     sim.close()
+
+
+def test_sampled_sweep_timing():
+    # every third sweep launch is timed; a negative stride is rejected
+    cfg = lbmps.make_config(32, 24, 16, 0.05)
+    sim = lbmps.Sim(cfg)
+    sim.init_equilibrium()
+    sim.set_timing(True, 3)
+    sim.step(10)
+    ms, n = sim.timing()
+    assert n == 4 and ms > 0  # launches 0, 3, 6, 9
+    with pytest.raises(lbmps.LbmpsError):
+        sim.set_timing(True, -2)
+    sim.set_timing(True)
+    sim.step(5)
+    assert sim.timing()[1] == 5
+    sim.set_timing(False)
+    sim.close()
