@@ -405,7 +405,6 @@ lbmps_status rebuild_mem(lbmps_ctx* c, bool refill) {
   if (refill)
     HIPCHK(c, launch_mem_refill(L.prec, c->counts + 2, L.refill_cap, c->rcell, c->rpart, c->inst_d, c->parts, c->owner,
                                 c->buf[c->cur], c->st));
-  HIPCHK(c, launch_mem_clear_was(mem_list(c), c->n_mem, L.side, ns, c->inst_d, c->parts, c->owner, c->st));
   return LBMPS_OK;
 }
 
@@ -739,7 +738,7 @@ lbmps_status lbmps_set_static_solid(lbmps_ctx* c, int32_t inst, const uint8_t* m
       for (int y = 0; y < ck.ny; ++y)
         for (int x = 0; x < ck.nx; ++x) {
           const int cell = (z * ck.ny + y) * ck.nx + x;
-          if ((*o)[cell] != OWN_FLUID) continue;
+          if (!own_is_fluid((*o)[cell])) continue;
           for (int q = 1; q < 19; ++q) {
             const int xi = (x + cx(q) + ck.nx) % ck.nx, yi = (y + cy(q) + ck.ny) % ck.ny, zi = (z + cz(q) + ck.nz) % ck.nz;
             const int nb = (*o)[(zi * ck.ny + yi) * ck.nx + xi];

@@ -57,8 +57,9 @@ enum { PREC_FP64 = 0, PREC_FP32 = 1, PREC_FP16 = 2, PREC_BF16 = 3 };
 enum { EPS_FLAT = 0, EPS_RECURSIVE = 1, EPS_LEARNED = 2, EPS_EDGE = 3, EPS_DISTANCE = 4 };
 
 // Owner field values (MEM): -1 fluid, <= -2 static wall group (-2 - k),
-// 0 <= p < WAS_BIT solid cell of particle p, WAS_BIT | p: was solid of p before
-// the current remap and is fluid now (cleared after refill).
+// 0 <= p < WAS_BIT solid cell of particle p, WAS_BIT | p: uncovered by p's last
+// remap, fluid now (the mark tells the refill which cells are new; p's next
+// unmap clears it).
 constexpr int OWN_FLUID = -1;
 constexpr int WAS_BIT = 1 << 30;
 __host__ __device__ inline bool own_is_fluid(int o) { return o == OWN_FLUID || (o >= WAS_BIT); }

@@ -85,8 +85,6 @@ hipError_t launch_mem_fill_links(const int* list, int nlist, int side, int nspli
                                  hipStream_t st);
 hipError_t launch_mem_refill(int prec, const int* count, int cap, const int* rcell, const int* rpart,
                              const InstDev* insts, PartDev parts, const int* owner, void* buf, hipStream_t st);
-hipError_t launch_mem_clear_was(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
-                                int* owner, hipStream_t st);
 // Link rules of the wall links [0, n_wall) and of the particle links [n_wall + lbeg[j], n_wall + lend[j]) of
 // list[j], with each particle's link force and torque summed into Facc/Tacc (width workgroups per particle;
 // partial as for launch_reduce with nchunk_blocks = width) and, with rigid_insts != nullptr, its rigid-body step.

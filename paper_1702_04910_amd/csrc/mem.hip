@@ -62,7 +62,11 @@ __global__ __launch_bounds__(256) void mem_unmap_kernel(const int* __restrict__ 
   MEM_BBOX_PROLOGUE
   for (int c = ca; c < cb; ++c) {
     MEM_CELL_COORDS(c)
-    if (own[cell] == p) own[cell] = WAS_BIT | p;
+    // solid cells of p become "was solid of p"; the marks of p's previous
+    // remap (cells it uncovered then, all within this box) become plain fluid
+    const int o = own[cell];
+    if (o == p) own[cell] = WAS_BIT | p;
+    else if (o == (WAS_BIT | p)) own[cell] = OWN_FLUID;
   }
 }
 
@@ -143,10 +147,10 @@ hipError_t launch_mem_count(bool uncovered, const int* list, int nlist, int side
 
 // Writes the links of each fluid cell in increasing q (slot bits 1..18) and,
 // with refill lists (rcell != nullptr), the uncovered cells (slot bit 0) at
-// their own scanned offsets.  Links carry delta_q = the
-// smallest root in (0, 1] of |d + delta c|^2 = R^2 computed as e/(-b + sqrt(b^2 - a e))
+// their own scanned offsets.  Links carry delta_q = the smallest root in
+// (0, 1] of |d + delta c|^2 = R^2 computed as e/(-b + sqrt(b^2 - a e))
 // (a = c.c, b = d.c, e = |d|^2 - R^2), and whether x - c_q is fluid (needed by
-// CLI).  Clears the "was solid" marks of the cells it visits afterwards.
+// CLI).
 __global__ __launch_bounds__(256) void mem_fill_links_kernel(const int* __restrict__ list, int side, int nsplit,
                                                              const InstDev* __restrict__ insts, PartDev P,
                                                              int* __restrict__ owner, const int* __restrict__ slots,
@@ -207,24 +211,6 @@ hipError_t launch_mem_fill_links(const int* list, int nlist, int side, int nspli
   if (nlist <= 0) return hipSuccess;
   hipLaunchKernelGGL(mem_fill_links_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts,
                      parts, owner, slots, offsets, base, cap, links, offsets2, cap2, rcell, rpart);
-  return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void mem_clear_was_kernel(const int* __restrict__ list, int side, int nsplit,
-                                                            const InstDev* __restrict__ insts, PartDev P,
-                                                            int* __restrict__ owner) {
-  MEM_BBOX_PROLOGUE
-  for (int c = ca; c < cb; ++c) {
-    MEM_CELL_COORDS(c)
-    if (own[cell] >= WAS_BIT) own[cell] = OWN_FLUID;
-  }
-}
-
-hipError_t launch_mem_clear_was(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
-                                int* owner, hipStream_t st) {
-  if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(mem_clear_was_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts,
-                     parts, owner);
   return hipGetLastError();
 }
 
