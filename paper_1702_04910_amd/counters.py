@@ -25,7 +25,7 @@ COPY_BYTES = 1 << 30
 SWEEPS = 20
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SWEEP_SOURCES = ("csrc/sweep.hip", "csrc/common.h", "csrc/psm_cell.h")
+SWEEP_SOURCES = ("csrc/sweep.hip", "csrc/common.h", "csrc/psm_cell.h", "csrc/kernels.h")
 
 
 def sweep_source_hash():

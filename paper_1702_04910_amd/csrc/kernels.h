@@ -6,6 +6,13 @@
 
 namespace lbm {
 
+// Workgroups along x for the per-unit bounding-box kernels (grid y = particle
+// list): about 8192 in all, each looping over units x, x + grid, ...
+inline int unit_grid(int units, int nlist) {
+  const int g = nlist > 0 ? (8192 + nlist - 1) / nlist : 1;
+  return units < g ? units : g;
+}
+
 // ---- sweep.hip
 // sweep_flags: bit 0 non-temporal loads; bit 1 collide PSM cells inside the
 // sweep; bit 2 collide them in the separate overlap kernel after the sweep;

@@ -33,20 +33,23 @@ __device__ __forceinline__ void disp(const InstDev& I, const PartDev& P, int p, 
   d[2] = min_image(((double)k + 0.5) - P.X[3 * p + 2], (double)I.nz);
 }
 
-// Each workgroup handles one work unit (a row range of one slab) of the
-// bounding box of particle list[blockIdx.y], in contiguous per-thread chunks.
-#define MEM_BBOX_PROLOGUE                                                              \
+// Workgroup (x, j) handles the work units x, x + gridDim.x, ... (a unit is a
+// row range of one slab) of the bounding box of particle list[j], each in
+// contiguous per-thread chunks; MEM_BBOX_END closes the loop over units.
+#define MEM_BBOX_BEGIN                                                                 \
   const int jl = blockIdx.y;                                                           \
-  const Unit U_ = unit_of(blockIdx.x, side, nsplit);                                   \
   const int p = list[jl];                                                              \
   const InstDev& I = insts[P.inst[p]];                                                 \
   int lo[3];                                                                           \
   mem_bbox_lo(P, p, lo);                                                               \
-  const int ncs = (U_.y1 - U_.y0) * side;                                              \
-  const int chunk = (ncs + 255) / 256;                                                 \
-  const int ca = min(ncs, (int)threadIdx.x * chunk), cb = min(ncs, ca + chunk);        \
   int* own = owner + I.owner_off;                                                      \
-  (void)own;
+  (void)own;                                                                           \
+  for (int ub = blockIdx.x; ub < side * nsplit; ub += gridDim.x) {                     \
+    const Unit U_ = unit_of(ub, side, nsplit);                                         \
+    const int ncs = (U_.y1 - U_.y0) * side;                                            \
+    const int chunk = (ncs + 255) / 256;                                               \
+    const int ca = min(ncs, (int)threadIdx.x * chunk), cb = min(ncs, ca + chunk);
+#define MEM_BBOX_END }
 
 #define MEM_CELL_COORDS(c)                                                 \
   const int dy_ = U_.y0 + (c) / side, dx_ = (c) % side;                    \
@@ -59,7 +62,7 @@ __device__ __forceinline__ void disp(const InstDev& I, const PartDev& P, int p, 
 __global__ __launch_bounds__(256) void mem_unmap_kernel(const int* __restrict__ list, int side, int nsplit,
                                                         const InstDev* __restrict__ insts, PartDev P,
                                                         int* __restrict__ owner) {
-  MEM_BBOX_PROLOGUE
+  MEM_BBOX_BEGIN
   for (int c = ca; c < cb; ++c) {
     MEM_CELL_COORDS(c)
     // solid cells of p become "was solid of p"; the marks of p's previous
@@ -68,12 +71,13 @@ __global__ __launch_bounds__(256) void mem_unmap_kernel(const int* __restrict__ 
     if (o == p) own[cell] = WAS_BIT | p;
     else if (o == (WAS_BIT | p)) own[cell] = OWN_FLUID;
   }
+  MEM_BBOX_END
 }
 
 __global__ __launch_bounds__(256) void mem_map_kernel(const int* __restrict__ list, int side, int nsplit,
                                                       const InstDev* __restrict__ insts, PartDev P,
                                                       int* __restrict__ owner) {
-  MEM_BBOX_PROLOGUE
+  MEM_BBOX_BEGIN
   const double R = 0.5 * P.D[p];
   const double R2 = __dmul_rn(R, R);
   for (int c = ca; c < cb; ++c) {
@@ -82,12 +86,14 @@ __global__ __launch_bounds__(256) void mem_map_kernel(const int* __restrict__ li
     disp(I, P, p, ci, cj, ck, d);
     if (sq3m(d[0], d[1], d[2]) <= R2 && own_is_fluid(own[cell])) own[cell] = p;
   }
+  MEM_BBOX_END
 }
 
 hipError_t launch_mem_unmap(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
                             int* owner, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(mem_unmap_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts, parts,
+  const dim3 grid(unit_grid(side * nsplit, nlist), nlist);
+  hipLaunchKernelGGL(mem_unmap_kernel, grid, dim3(256), 0, st, list, side, nsplit, insts, parts,
                      owner);
   return hipGetLastError();
 }
@@ -95,7 +101,8 @@ hipError_t launch_mem_unmap(const int* list, int nlist, int side, int nsplit, co
 hipError_t launch_mem_map(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
                           int* owner, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(mem_map_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts, parts,
+  const dim3 grid(unit_grid(side * nsplit, nlist), nlist);
+  hipLaunchKernelGGL(mem_map_kernel, grid, dim3(256), 0, st, list, side, nsplit, insts, parts,
                      owner);
   return hipGetLastError();
 }
@@ -108,7 +115,7 @@ __global__ __launch_bounds__(256) void mem_count_kernel(bool uncovered, const in
                                                         int nsplit, const InstDev* __restrict__ insts, PartDev P,
                                                         int* __restrict__ owner, int* __restrict__ slots,
                                                         int* __restrict__ totals, int* __restrict__ totals2) {
-  MEM_BBOX_PROLOGUE
+  MEM_BBOX_BEGIN
   int local = 0, local2 = 0;
   for (int c = ca; c < cb; ++c) {
     MEM_CELL_COORDS(c)
@@ -130,17 +137,19 @@ __global__ __launch_bounds__(256) void mem_count_kernel(bool uncovered, const in
   __shared__ int sh[256];
   int total;
   block_excl_scan256(local, sh, &total);
-  if (threadIdx.x == 0) totals[jl * (side * nsplit) + blockIdx.x] = total;
+  if (threadIdx.x == 0) totals[jl * (side * nsplit) + ub] = total;
   if (uncovered) {
     block_excl_scan256(local2, sh, &total);
-    if (threadIdx.x == 0) totals2[jl * (side * nsplit) + blockIdx.x] = total;
+    if (threadIdx.x == 0) totals2[jl * (side * nsplit) + ub] = total;
   }
+  MEM_BBOX_END
 }
 
 hipError_t launch_mem_count(bool uncovered, const int* list, int nlist, int side, int nsplit, const InstDev* insts,
                             PartDev parts, const int* owner, int* slots, int* totals, int* totals2, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(mem_count_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, uncovered, list, side, nsplit,
+  const dim3 grid(unit_grid(side * nsplit, nlist), nlist);
+  hipLaunchKernelGGL(mem_count_kernel, grid, dim3(256), 0, st, uncovered, list, side, nsplit,
                      insts, parts, (int*)owner, slots, totals, totals2);
   return hipGetLastError();
 }
@@ -157,7 +166,7 @@ __global__ __launch_bounds__(256) void mem_fill_links_kernel(const int* __restri
                                                              const int* __restrict__ offsets, int base, int cap,
                                                              LinkDev L, const int* __restrict__ offsets2, int cap2,
                                                              int* __restrict__ rcell, int* __restrict__ rpart) {
-  MEM_BBOX_PROLOGUE
+  MEM_BBOX_BEGIN
   int local = 0, local2 = 0;
   for (int c = ca; c < cb; ++c) {
     MEM_CELL_COORDS(c)
@@ -167,9 +176,9 @@ __global__ __launch_bounds__(256) void mem_fill_links_kernel(const int* __restri
   }
   __shared__ int sh[256];
   int total;
-  int pos = base + offsets[jl * (side * nsplit) + blockIdx.x] + block_excl_scan256(local, sh, &total);
+  int pos = base + offsets[jl * (side * nsplit) + ub] + block_excl_scan256(local, sh, &total);
   int pos2 = 0;
-  if (rcell) pos2 = offsets2[jl * (side * nsplit) + blockIdx.x] + block_excl_scan256(local2, sh, &total);
+  if (rcell) pos2 = offsets2[jl * (side * nsplit) + ub] + block_excl_scan256(local2, sh, &total);
   const double R = 0.5 * P.D[p];
   for (int c = ca; c < cb; ++c) {
     MEM_CELL_COORDS(c)
@@ -202,6 +211,7 @@ __global__ __launch_bounds__(256) void mem_fill_links_kernel(const int* __restri
       ++pos;
     }
   }
+  MEM_BBOX_END
 }
 
 hipError_t launch_mem_fill_links(const int* list, int nlist, int side, int nsplit, const InstDev* insts,
@@ -209,7 +219,8 @@ hipError_t launch_mem_fill_links(const int* list, int nlist, int side, int nspli
                                  LinkDev links, const int* offsets2, int cap2, int* rcell, int* rpart,
                                  hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(mem_fill_links_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts,
+  const dim3 grid(unit_grid(side * nsplit, nlist), nlist);
+  hipLaunchKernelGGL(mem_fill_links_kernel, grid, dim3(256), 0, st, list, side, nsplit, insts,
                      parts, owner, slots, offsets, base, cap, links, offsets2, cap2, rcell, rpart);
   return hipGetLastError();
 }

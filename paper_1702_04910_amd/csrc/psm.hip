@@ -218,7 +218,6 @@ __global__ __launch_bounds__(256) void psm_classify_kernel(const int* __restrict
                                                            int* __restrict__ slots, int* __restrict__ totals) {
   __shared__ int sh[256];
   const int j = blockIdx.y;
-  const Unit U = unit_of(blockIdx.x, side, nsplit);
   const int p = list[j];
   const InstDev& I = insts[P.inst[p]];
   int lo[3];
@@ -226,34 +225,37 @@ __global__ __launch_bounds__(256) void psm_classify_kernel(const int* __restrict
   const double R = 0.5 * P.D[p];
   const double R2 = __dmul_rn(R, R);
   const int n = I.eps_n;
-  const int ncu = (U.y1 - U.y0) * side;
   const double o0 = sample_off(0, n), o1 = sample_off(n - 1, n);
-  const int k = wrapi(lo[2] + U.z, I.nz);
-  const double dz = min_image(((double)k + 0.5) - P.X[3 * p + 2], (double)I.nz);
-  int ncut = 0;
-  for (int c = threadIdx.x; c < ncu; c += blockDim.x) {
-    const int dy = U.y0 + c / side, dx = c % side;
-    const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny);
-    const double dc[3] = {min_image(((double)i + 0.5) - P.X[3 * p + 0], (double)I.nx),
-                          min_image(((double)jj + 0.5) - P.X[3 * p + 1], (double)I.ny), dz};
-    double blo[3], bhi[3];
+  for (int ub = blockIdx.x; ub < side * nsplit; ub += gridDim.x) {
+    const Unit U = unit_of(ub, side, nsplit);
+    const int ncu = (U.y1 - U.y0) * side;
+    const int k = wrapi(lo[2] + U.z, I.nz);
+    const double dz = min_image(((double)k + 0.5) - P.X[3 * p + 2], (double)I.nz);
+    int ncut = 0;
+    for (int c = threadIdx.x; c < ncu; c += blockDim.x) {
+      const int dy = U.y0 + c / side, dx = c % side;
+      const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny);
+      const double dc[3] = {min_image(((double)i + 0.5) - P.X[3 * p + 0], (double)I.nx),
+                            min_image(((double)jj + 0.5) - P.X[3 * p + 1], (double)I.ny), dz};
+      double blo[3], bhi[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      blo[q] = __dadd_rn(dc[q], o0);
-      bhi[q] = __dadd_rn(dc[q], o1);
+      for (int q = 0; q < 3; ++q) {
+        blo[q] = __dadd_rn(dc[q], o0);
+        bhi[q] = __dadd_rn(dc[q], o1);
+      }
+      const int cl = classify(blo, bhi, R2);
+      int v = cl == 1 ? n * n * n : (cl == 0 ? -1 : 0);
+      if (I.eps_mode >= EPS_EDGE) {  // closed forms: evaluated here, counts out of n^3
+        const double e = I.eps_mode == EPS_EDGE ? eps_edge(dc, R2) : eps_distance(dc, R);
+        v = (int)rint(e * ((double)n * n * n));
+      }
+      slots[slot_index(j, side, U.z, dy, dx)] = v;
+      ncut += v < 0 ? 1 : 0;
     }
-    const int cl = classify(blo, bhi, R2);
-    int v = cl == 1 ? n * n * n : (cl == 0 ? -1 : 0);
-    if (I.eps_mode >= EPS_EDGE) {  // closed forms: evaluated here, counts out of n^3
-      const double e = I.eps_mode == EPS_EDGE ? eps_edge(dc, R2) : eps_distance(dc, R);
-      v = (int)rint(e * ((double)n * n * n));
-    }
-    slots[slot_index(j, side, U.z, dy, dx)] = v;
-    ncut += v < 0 ? 1 : 0;
+    int total;
+    block_excl_scan256(ncut, sh, &total);
+    if (threadIdx.x == 0) totals[j * (side * nsplit) + ub] = total;
   }
-  int total;
-  block_excl_scan256(ncut, sh, &total);
-  if (threadIdx.x == 0) totals[j * (side * nsplit) + blockIdx.x] = total;
 }
 
 // Stage 1b: the cut cells of each unit, in cell order, at the unit's scanned
@@ -264,34 +266,36 @@ __global__ __launch_bounds__(256) void psm_cut_fill_kernel(const int* __restrict
                                                            const int* __restrict__ offsets, CutDev cuts, int cap) {
   __shared__ int sh[256];
   const int j = blockIdx.y;
-  const Unit U = unit_of(blockIdx.x, side, nsplit);
   const int p = list[j];
   const InstDev& I = insts[P.inst[p]];
   int lo[3];
   bbox_lo(P, p, lo);
-  const int ncu = (U.y1 - U.y0) * side;
-  const int chunk = (ncu + 255) / 256;
-  const int a = min(ncu, (int)threadIdx.x * chunk), b = min(ncu, a + chunk);
-  int local = 0;
-  for (int c = a; c < b; ++c) local += slots[slot_index(j, side, U.z, U.y0 + c / side, c % side)] < 0 ? 1 : 0;
-  int total;
-  int pos = offsets[j * (side * nsplit) + blockIdx.x] + block_excl_scan256(local, sh, &total);
-  for (int c = a; c < b; ++c) {
-    const int dy = U.y0 + c / side, dx = c % side;
-    const long long si = slot_index(j, side, U.z, dy, dx);
-    if (slots[si] >= 0) continue;
-    if (pos < cap) {
-      const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny), k = wrapi(lo[2] + U.z, I.nz);
-      double dc[3];
-      centre_disp(I, P, p, i, jj, k, dc);
-      cuts.slot[pos] = si;
-      cuts.p[pos] = p;
-      cuts.use[pos] = 0;
-      cuts.d[3 * pos] = dc[0];
-      cuts.d[3 * pos + 1] = dc[1];
-      cuts.d[3 * pos + 2] = dc[2];
+  for (int ub = blockIdx.x; ub < side * nsplit; ub += gridDim.x) {
+    const Unit U = unit_of(ub, side, nsplit);
+    const int ncu = (U.y1 - U.y0) * side;
+    const int chunk = (ncu + 255) / 256;
+    const int a = min(ncu, (int)threadIdx.x * chunk), b = min(ncu, a + chunk);
+    int local = 0;
+    for (int c = a; c < b; ++c) local += slots[slot_index(j, side, U.z, U.y0 + c / side, c % side)] < 0 ? 1 : 0;
+    int total;
+    int pos = offsets[j * (side * nsplit) + ub] + block_excl_scan256(local, sh, &total);
+    for (int c = a; c < b; ++c) {
+      const int dy = U.y0 + c / side, dx = c % side;
+      const long long si = slot_index(j, side, U.z, dy, dx);
+      if (slots[si] >= 0) continue;
+      if (pos < cap) {
+        const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny), k = wrapi(lo[2] + U.z, I.nz);
+        double dc[3];
+        centre_disp(I, P, p, i, jj, k, dc);
+        cuts.slot[pos] = si;
+        cuts.p[pos] = p;
+        cuts.use[pos] = 0;
+        cuts.d[3 * pos] = dc[0];
+        cuts.d[3 * pos + 1] = dc[1];
+        cuts.d[3 * pos + 2] = dc[2];
+      }
+      ++pos;
     }
-    ++pos;
   }
 }
 
@@ -351,14 +355,16 @@ __global__ __launch_bounds__(256) void psm_unit_totals_kernel(int side, int nspl
                                                               int* __restrict__ totals) {
   __shared__ int sh[256];
   const int j = blockIdx.y;
-  const Unit U = unit_of(blockIdx.x, side, nsplit);
-  const int ncu = (U.y1 - U.y0) * side;
-  int local = 0;
-  for (int c = threadIdx.x; c < ncu; c += blockDim.x)
-    local += slots[slot_index(j, side, U.z, U.y0 + c / side, c % side)] > 0 ? 1 : 0;
-  int total;
-  block_excl_scan256(local, sh, &total);
-  if (threadIdx.x == 0) totals[j * (side * nsplit) + blockIdx.x] = total;
+  for (int ub = blockIdx.x; ub < side * nsplit; ub += gridDim.x) {
+    const Unit U = unit_of(ub, side, nsplit);
+    const int ncu = (U.y1 - U.y0) * side;
+    int local = 0;
+    for (int c = threadIdx.x; c < ncu; c += blockDim.x)
+      local += slots[slot_index(j, side, U.z, U.y0 + c / side, c % side)] > 0 ? 1 : 0;
+    int total;
+    block_excl_scan256(local, sh, &total);
+    if (threadIdx.x == 0) totals[j * (side * nsplit) + ub] = total;
+  }
 }
 
 // Labels for training samples (R, dx, dy, dz): exact eps by flat n^3
@@ -405,7 +411,8 @@ __global__ __launch_bounds__(256) void psm_judge_kernel(const InstDev* __restric
 hipError_t launch_psm_classify(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
                                int* slots, int* totals, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(psm_classify_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts,
+  const dim3 grid(unit_grid(side * nsplit, nlist), nlist);
+  hipLaunchKernelGGL(psm_classify_kernel, grid, dim3(256), 0, st, list, side, nsplit, insts,
                      parts, slots, totals);
   return hipGetLastError();
 }
@@ -413,7 +420,8 @@ hipError_t launch_psm_classify(const int* list, int nlist, int side, int nsplit,
 hipError_t launch_psm_cut_fill(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
                                const int* slots, const int* offsets, CutDev cuts, int cap, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(psm_cut_fill_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts,
+  const dim3 grid(unit_grid(side * nsplit, nlist), nlist);
+  hipLaunchKernelGGL(psm_cut_fill_kernel, grid, dim3(256), 0, st, list, side, nsplit, insts,
                      parts, slots, offsets, cuts, cap);
   return hipGetLastError();
 }
@@ -440,7 +448,8 @@ hipError_t launch_psm_cut_scatter(const InstDev* insts, PartDev parts, CutDev cu
 
 hipError_t launch_psm_unit_totals(int nlist, int side, int nsplit, const int* slots, int* totals, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(psm_unit_totals_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, side, nsplit, slots, totals);
+  const dim3 grid(unit_grid(side * nsplit, nlist), nlist);
+  hipLaunchKernelGGL(psm_unit_totals_kernel, grid, dim3(256), 0, st, side, nsplit, slots, totals);
   return hipGetLastError();
 }
 
@@ -462,8 +471,8 @@ __global__ __launch_bounds__(256) void psm_fill_kernel(const int* __restrict__ l
                                                        const InstDev* __restrict__ insts, PartDev P,
                                                        const int* __restrict__ slots, const int* __restrict__ offsets,
                                                        int cap, PairDev pairs) {
+  __shared__ int sh[256];
   const int j = blockIdx.y;
-  const Unit U = unit_of(blockIdx.x, side, nsplit);
   const int p = list[j];
   const InstDev& I = insts[P.inst[p]];
   int lo[3];
@@ -471,35 +480,38 @@ __global__ __launch_bounds__(256) void psm_fill_kernel(const int* __restrict__ l
   const int n = I.eps_n;
   const double nn = (double)n * (double)n * (double)n;
   const double t = I.tau - 0.5;
-  const int ncu = (U.y1 - U.y0) * side;
-  const int chunk = (ncu + 255) / 256;
-  const int a = min(ncu, (int)threadIdx.x * chunk), b = min(ncu, a + chunk);
-  int local = 0;
-  for (int c = a; c < b; ++c) local += slots[slot_index(j, side, U.z, U.y0 + c / side, c % side)] > 0 ? 1 : 0;
-  __shared__ int sh[256];
-  int total;
-  int pos = offsets[j * (side * nsplit) + blockIdx.x] + block_excl_scan256(local, sh, &total);
-  for (int c = a; c < b; ++c) {
-    const int dy = U.y0 + c / side, dx = c % side;
-    const int v = slots[slot_index(j, side, U.z, dy, dx)];
-    if (v <= 0) continue;
-    if (pos < cap) {
-      const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny), k = wrapi(lo[2] + U.z, I.nz);
-      const double eps = (double)v / nn;
-      pairs.cell[pos] = (k * I.ny + jj) * I.nx + i;
-      pairs.p[pos] = p;
-      pairs.eps[pos] = eps;
-      pairs.B[pos] = I.psm_b == 1 ? eps : eps * t / ((1.0 - eps) + t);
-      pairs.next[pos] = -1;
+  for (int ub = blockIdx.x; ub < side * nsplit; ub += gridDim.x) {
+    const Unit U = unit_of(ub, side, nsplit);
+    const int ncu = (U.y1 - U.y0) * side;
+    const int chunk = (ncu + 255) / 256;
+    const int a = min(ncu, (int)threadIdx.x * chunk), b = min(ncu, a + chunk);
+    int local = 0;
+    for (int c = a; c < b; ++c) local += slots[slot_index(j, side, U.z, U.y0 + c / side, c % side)] > 0 ? 1 : 0;
+    int total;
+    int pos = offsets[j * (side * nsplit) + ub] + block_excl_scan256(local, sh, &total);
+    for (int c = a; c < b; ++c) {
+      const int dy = U.y0 + c / side, dx = c % side;
+      const int v = slots[slot_index(j, side, U.z, dy, dx)];
+      if (v <= 0) continue;
+      if (pos < cap) {
+        const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny), k = wrapi(lo[2] + U.z, I.nz);
+        const double eps = (double)v / nn;
+        pairs.cell[pos] = (k * I.ny + jj) * I.nx + i;
+        pairs.p[pos] = p;
+        pairs.eps[pos] = eps;
+        pairs.B[pos] = I.psm_b == 1 ? eps : eps * t / ((1.0 - eps) + t);
+        pairs.next[pos] = -1;
+      }
+      ++pos;
     }
-    ++pos;
   }
 }
 
 hipError_t launch_psm_fill(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
                            const int* slots, const int* offsets, int cap, PairDev pairs, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
-  hipLaunchKernelGGL(psm_fill_kernel, dim3(side * nsplit, nlist), dim3(256), 0, st, list, side, nsplit, insts, parts,
+  const dim3 grid(unit_grid(side * nsplit, nlist), nlist);
+  hipLaunchKernelGGL(psm_fill_kernel, grid, dim3(256), 0, st, list, side, nsplit, insts, parts,
                      slots, offsets, cap, pairs);
   return hipGetLastError();
 }
