@@ -42,37 +42,43 @@ __device__ __forceinline__ R dot3(R x, R y, R z) {
 // TRT collision of the pair (QA, QA + 1) in deviation variables; see the
 // collision operator of Eq. MEM_TRT with f^+- = (f_q +- f_qbar)/2 and the
 // forcing of Eq. Forcing split into its symmetric and antisymmetric parts.
+// As in the partially saturated cell collision, contraction is off and the
+// fused multiply-adds are explicit (fmac): every sweep variant, whatever code
+// surrounds this, produces the same bits.
 template <typename R, int QA>
 __device__ __forceinline__ void trt_pair(const R (&g)[Q], R (&o)[Q], R base, R ux, R uy, R uz, R fx, R fy, R fz,
                                          R fu, R lp, R lm) {
+#pragma clang fp contract(off)
   constexpr int QB = QA + 1;
   const R w = (R)wq(QA);
   const R cu = dot3<R, cx(QA), cy(QA), cz(QA)>(ux, uy, uz);
   const R cf = dot3<R, cx(QA), cy(QA), cz(QA)>(fx, fy, fz);
-  const R eqp = w * (base + (R)4.5 * cu * cu);
-  const R eqm = w * ((R)3 * cu);
-  const R Fp = w * ((R)9 * cu * cf - (R)3 * fu);
-  const R Fm = w * ((R)3 * cf);
+  // f^+- - f^eq+-, with f^eq+ = w (base + 4.5 cu^2) and f^eq- = w 3 cu
   const R gp = (R)0.5 * (g[QA] + g[QB]);
   const R gm = (R)0.5 * (g[QA] - g[QB]);
-  const R cp = lp * (gp - eqp) + Fp;
-  const R cm = lm * (gm - eqm) + Fm;
-  o[QA] = g[QA] + cp + cm;
-  o[QB] = g[QB] + cp - cm;
+  const R dp = fmac<R>(-w, fmac<R>((R)4.5 * cu, cu, base), gp);
+  const R dm = fmac<R>(-w, (R)3 * cu, gm);
+  const R Fp = w * fmac<R>((R)9 * cu, cf, (R)-3 * fu);
+  const R Fm = w * ((R)3 * cf);
+  const R cp = fmac<R>(lp, dp, Fp);
+  const R cm = fmac<R>(lm, dm, Fm);
+  o[QA] = (g[QA] + cp) + cm;
+  o[QB] = (g[QB] + cp) - cm;
 }
 
 template <typename R>
 __device__ __forceinline__ void collide_cell(const R (&g)[Q], R (&o)[Q], R lp, R lm, R fx, R fy, R fz) {
+#pragma clang fp contract(off)
   R drho = g[0];
 #pragma unroll
   for (int q = 1; q < Q; ++q) drho += g[q];
   const R ux = (g[1] - g[2]) + (g[7] - g[8]) + (g[9] - g[10]) + (g[11] - g[12]) + (g[13] - g[14]);
   const R uy = (g[3] - g[4]) + (g[7] - g[8]) + (g[10] - g[9]) + (g[15] - g[16]) + (g[17] - g[18]);
   const R uz = (g[5] - g[6]) + (g[11] - g[12]) + (g[14] - g[13]) + (g[15] - g[16]) + (g[18] - g[17]);
-  const R uu = ux * ux + uy * uy + uz * uz;
-  const R fu = ux * fx + uy * fy + uz * fz;
-  const R base = drho - (R)1.5 * uu;
-  o[0] = g[0] + lp * (g[0] - (R)wq(0) * base) - (R)wq(0) * (R)3 * fu;
+  const R uu = fmac<R>(uz, uz, fmac<R>(uy, uy, ux * ux));
+  const R fu = fmac<R>(uz, fz, fmac<R>(uy, fy, ux * fx));
+  const R base = fmac<R>((R)-1.5, uu, drho);
+  o[0] = fmac<R>(-(R)wq(0) * (R)3, fu, fmac<R>(lp, fmac<R>(-(R)wq(0), base, g[0]), g[0]));
   trt_pair<R, 1>(g, o, base, ux, uy, uz, fx, fy, fz, fu, lp, lm);
   trt_pair<R, 3>(g, o, base, ux, uy, uz, fx, fy, fz, fu, lp, lm);
   trt_pair<R, 5>(g, o, base, ux, uy, uz, fx, fy, fz, fu, lp, lm);
