@@ -880,7 +880,7 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
     const int pm = c->n_psm ? c->psm_mode : PSM_SEPARATE;
     if (pm == PSM_STAGED)  // overlapped cells first, from the same pre-collision values
       HIPCHK(c, launch_psm_collide(L.prec, L.psm_m, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs,
-                                   c->cellmap, src, dst, c->stage, L.pair_cap, c->st));
+                                   c->cellmap, src, dst, c->stage, L.pair_cap, false, c->st));
     const bool timed = c->timing && (c->timing_seq++ % c->timing_stride) == 0;
     if (timed) {
       if (c->ev_used + 2 > c->ev.size()) {
@@ -906,9 +906,9 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
     const bool psm_rb = c->n_psm && ((c->sweeps + 1) % L.psm_nsub) == 0;
     const bool mem_rb = c->n_mem && ((c->sweeps + 1) % L.mem_nsub) == 0;
     if (c->n_psm) {
-      if (pm == PSM_SEPARATE)
+      if (pm != PSM_STAGED)  // after the sweep: every overlapped cell, or (inline mode) the shared ones
         HIPCHK(c, launch_psm_collide(L.prec, L.psm_m, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs,
-                                     c->cellmap, src, dst, nullptr, 0, c->st));
+                                     c->cellmap, src, dst, nullptr, 0, pm == PSM_FUSED, c->st));
       HIPCHK(c, launch_reduce(psm_list(c), c->n_psm, c->pbeg, c->pend, 0, c->pairs.out, c->pairs.ostride, c->parts,
                               L.red_blocks, c->red_partial, psm_rb ? c->inst_d : nullptr, err,
                               c->st));

@@ -118,12 +118,13 @@ hipError_t launch_psm_fill(const int* list, int nlist, int side, int nsplit, con
                            const int* slots, const int* offsets, int cap, PairDev pairs, hipStream_t st);
 hipError_t launch_psm_cellmap(int stage, const int* count, int cap, const InstDev* insts, PartDev parts,
                               PairDev pairs, int* cellmap, hipStream_t st);
-// Collision of every overlapped cell (two launches: single-pair cells, then shared cells), pushed into dst or,
+// Collision of every overlapped cell (two launches: single-pair cells unless shared_only, then shared cells),
+// pushed into dst or,
 // with stage != nullptr, stored per leader pair for the sweep that follows.  psm_m: the solid operator shared by
 // every PSM instance (1..3), or 0 when they differ.
 hipError_t launch_psm_collide(int prec, int psm_m, const int* count, int cap, const InstDev* insts, PartDev parts,
                               PairDev pairs, const int* cellmap, const void* src, void* dst, void* stage,
-                              long long sstride, hipStream_t st);
+                              long long sstride, bool shared_only, hipStream_t st);
 hipError_t launch_psm_fields(int prec, const int* count, int cap, const InstDev* insts, PartDev parts, PairDev pairs,
                              const int* cellmap, const void* buf, int inst, long long c0, long long n, double* out,
                              hipStream_t st);

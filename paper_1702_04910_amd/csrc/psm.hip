@@ -600,19 +600,21 @@ __attribute__((amdgpu_waves_per_eu(MULTI || M == 0 || sizeof(S) == 8 ? 1 : 4))) 
 
 hipError_t launch_psm_collide(int prec, int psm_m, const int* count, int cap, const InstDev* insts, PartDev parts,
                               PairDev pairs, const int* cellmap, const void* src, void* dst, void* stage,
-                              long long sstride, hipStream_t st) {
+                              long long sstride, bool shared_only, hipStream_t st) {
   const int grid = 2048;
 #define PSM_COLLIDE(MM, MULTI)                                                                                      \
   LBM_DISPATCH(prec, hipLaunchKernelGGL((psm_collide_kernel<S, MM, MULTI>), dim3(grid), dim3(256), 0, st, count, cap, \
                                         insts, parts, pairs, cellmap, (const S*)src, (S*)dst, (S*)stage, sstride))
-  switch (psm_m) {
-    case 1: PSM_COLLIDE(1, false); break;
-    case 2: PSM_COLLIDE(2, false); break;
-    case 3: PSM_COLLIDE(3, false); break;
-    default: PSM_COLLIDE(0, false); break;
+  if (!shared_only) {
+    switch (psm_m) {
+      case 1: PSM_COLLIDE(1, false); break;
+      case 2: PSM_COLLIDE(2, false); break;
+      case 3: PSM_COLLIDE(3, false); break;
+      default: PSM_COLLIDE(0, false); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
   PSM_COLLIDE(0, true);
 #undef PSM_COLLIDE
   return hipGetLastError();

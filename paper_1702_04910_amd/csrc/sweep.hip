@@ -258,8 +258,9 @@ __device__ __forceinline__ void sweep_body_twin(const InstDev* __restrict__ inst
   }
 }
 
-// PSM: 0 no overlapped cells, 1 collide them inline, 2 take their staged
-// post-collision values (stage[q * sstride + leader pair]).
+// PSM: 0 no overlapped cells, 1 collide single-pair cells inline, 2 take the
+// staged post-collision values of overlapped cells (stage[q * sstride +
+// leader pair]).
 template <typename S, bool NTLD, int PSM>
 __device__ __forceinline__ void sweep_body(const InstDev* __restrict__ insts, const int4* __restrict__ tiles,
                                            int ntiles, const S* __restrict__ src, S* __restrict__ dst,
@@ -292,9 +293,17 @@ __device__ __forceinline__ void sweep_body(const InstDev* __restrict__ insts, co
         g[q] = Codec<S>::ld(NTLD ? ld_nt(a) : *a);
       }
       if constexpr (PSM == 1) {
+        // cells of a single pair are collided here, with the solid operator
+        // fixed per branch; cells shared by several particles get the fluid
+        // collision, which the overlap kernel overwrites after the sweep
         const int L = I.cellmap_off >= 0 ? cellmap[I.cellmap_off + idx] : INT_MAX;
-        if (L != INT_MAX) psm_cell_collide<0, false, R>(g, o, I, P, pairs, L, idx);
-        else collide_cell<R>(g, o, lp, lm, fx, fy, fz);
+        if (L != INT_MAX && pairs.next[L] < 0) {
+          if (I.psm_m == 1) psm_cell_collide<1, true, R>(g, o, I, P, pairs, L, idx);
+          else if (I.psm_m == 2) psm_cell_collide<2, true, R>(g, o, I, P, pairs, L, idx);
+          else psm_cell_collide<3, true, R>(g, o, I, P, pairs, L, idx);
+        } else {
+          collide_cell<R>(g, o, lp, lm, fx, fy, fz);
+        }
       } else if constexpr (PSM == 2) {
         const int L = I.cellmap_off >= 0 ? cellmap[I.cellmap_off + idx] : INT_MAX;
         if (L != INT_MAX) {
