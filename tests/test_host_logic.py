@@ -1,0 +1,49 @@
+"""Host-side logic that needs no GPU: the launch tuner's candidate shapes, the
+source hash that ties committed hardware counters to the sweep sources, and
+the benchmark's refusal of multi-GPU runs."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+from paper_1702_04910_amd import autotune, counters, lbmps
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.mark.parametrize("nx,precision", [(192, "fp32"), (512, "fp32"), (192, "fp16"), (37, "fp32"), (96, "fp64")])
+def test_tuner_candidates_are_valid_configurations(nx, precision):
+    cands = autotune.candidates(nx, precision)
+    assert len(cands) == len({tuple(sorted(c.items())) for c in cands})  # no duplicates
+    s = lbmps.STORAGE_BYTES[lbmps.PRECISION[precision]]
+    for c in cands:
+        f = c["sweep_flags"]
+        cfg = lbmps.make_config(nx, 16, 16, 0.05, precision=precision, **c)
+        assert lbmps.workspace_bytes(cfg) > 0, c  # the library accepts it
+        assert c["tile_rows"] * nx * 10 * s <= 65536  # LDS staging fits
+        assert not (f & lbmps.SWEEP_CELL_PAIRS and (nx % 2 or f & lbmps.SWEEP_OCC6))
+        assert not (f & lbmps.SWEEP_OCC6 and s == 8)  # six-wave build only for 4- and 2-byte storage
+        assert (f & (lbmps.SWEEP_WG_CAP3 | lbmps.SWEEP_WG_CAP2)) != (lbmps.SWEEP_WG_CAP3 | lbmps.SWEEP_WG_CAP2)
+    # every option is offered where it applies
+    flags = {c["sweep_flags"] for c in cands}
+    assert any(f & lbmps.SWEEP_WG_CAP2 for f in flags) and any(f & lbmps.SWEEP_WG_CAP3 for f in flags)
+    assert any(f & lbmps.SWEEP_CELL_PAIRS for f in flags) == (nx % 2 == 0)
+
+
+def test_counter_hash_follows_the_sweep_sources():
+    h = counters.sweep_source_hash()
+    assert len(h) == 16 and h == counters.sweep_source_hash()
+    # the hash covers every file the sweep kernel is compiled from
+    src = open(os.path.join(ROOT, "paper_1702_04910_amd", "csrc", "sweep.hip")).read()
+    for inc in ("common.h", "kernels.h", "psm_cell.h"):
+        assert '#include "%s"' % inc in src
+        assert "csrc/" + inc in counters.SWEEP_SOURCES
+
+
+def test_bench_refuses_several_gpus():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
