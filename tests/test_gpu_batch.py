@@ -33,7 +33,8 @@ def _small_batch(seed=3):
     return out
 
 
-@pytest.mark.parametrize("flags", [0, lbmps.SWEEP_PSM_FUSED, lbmps.SWEEP_PSM_STAGED])
+@pytest.mark.parametrize("flags", [0, lbmps.SWEEP_PSM_FUSED, lbmps.SWEEP_PSM_STAGED,
+                                   lbmps.SWEEP_CELL_PAIRS | lbmps.SWEEP_WG_CAP2 | lbmps.SWEEP_NT_LOADS])
 def test_batched_instances_equal_solo_runs_bitwise(flags):
     insts = _small_batch()
     dmax = max(d["D"] for d in insts)
