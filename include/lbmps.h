@@ -90,7 +90,8 @@ typedef struct lbmps_config {
   int32_t grid_blocks;   /* sweep workgroups; 0 = one per tile, > 0 = persistent grid of that size */
   int32_t wall_link_cap; /* capacity of static-wall links (0 = automatic) */
   int32_t sweep_flags;   /* launch tuning only, results unchanged: bit 0 non-temporal loads in the sweep;
-                            bit 1 collide PSM cells inside the sweep (reads the cell map of every cell);
+                            bit 1 collide PSM cells of a single particle inside the sweep (reads the cell map
+                            of every cell; shared cells are collided after the sweep);
                             bit 2 collide them in a pass over the overlap list after the sweep;
                             bit 3 the sweep built for six waves per SIMD (FP32/FP16/BF16 storage);
                             bit 4 collide them in a pass over the overlap list before the sweep, into a

@@ -7,7 +7,8 @@
 // MEM coupling is applied afterwards by the link kernel, which overwrites the
 // few affected values.  PSM cells are handled in one of three ways, with
 // identical results: collided here (the sweep reads the cell map and applies
-// the partially saturated collision to overlapped cells inline), re-collided
+// the partially saturated collision to cells of a single particle inline;
+// cells shared by several particles are re-collided afterwards), re-collided
 // afterwards by the overlap kernel, or collided beforehand by the overlap
 // kernel into a staging array indexed by the cell's leader pair, from which
 // the sweep takes their post-collision values (so every store of the
