@@ -30,8 +30,12 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "MLUPS + % HBM roofline; FP16-storage/batched vs FP32 at stated velocity error"
 
 
+_T0 = time.perf_counter()
+
+
 def log(*a):
-    print(*a, file=sys.stderr, flush=True)
+    """Progress on stderr, stamped with the seconds since the start."""
+    print("[%6.1f s]" % (time.perf_counter() - _T0), *a, file=sys.stderr, flush=True)
 
 
 def tuned_shape(inp, precision):
