@@ -107,10 +107,17 @@ hipError_t launch_mem_map(const int* list, int nlist, int side, int nsplit, cons
   return hipGetLastError();
 }
 
-// Per fluid cell the mask of directions q whose neighbour x + c_q is a solid
-// cell of p (one link each, bits 1..18), link counts to totals; with
-// `uncovered`, also bit 0 = the cell was uncovered by p, whose counts go to
-// totals2.
+// Slot word of a bounding-box cell: bits 1..18 = the directions q whose
+// neighbour x + c_q is a solid cell of p (one link each); bit 0 = the cell
+// was uncovered by p; bit 19 + k for the opposite pair (2k + 1, 2k + 2) =
+// the pair has one link and the neighbour on its other side, x - c_q, is a
+// fluid cell (the CLI condition of that link).  Both members of a pair cannot
+// be links with the other side fluid, so one bit per pair suffices.
+constexpr int SLOT_LINKS = ((1 << Q) - 1) & ~1;
+__device__ __forceinline__ int slot_cli_bit(int q) { return 1 << (Q + ((q - 1) >> 1)); }
+
+// Per fluid cell the slot word (see above); link counts to totals and, with
+// `uncovered`, uncovered-cell counts to totals2.
 __global__ __launch_bounds__(256) void mem_count_kernel(bool uncovered, const int* __restrict__ list, int side,
                                                         int nsplit, const InstDev* __restrict__ insts, PartDev P,
                                                         int* __restrict__ owner, int* __restrict__ slots,
@@ -121,13 +128,19 @@ __global__ __launch_bounds__(256) void mem_count_kernel(bool uncovered, const in
     MEM_CELL_COORDS(c)
     int v = 0;
     if (own_is_fluid(own[cell])) {
+      int fl = 0;
 #pragma unroll
       for (int q = 1; q < Q; ++q) {
         const int ni = wrapi(ci + cx(q), I.nx), nj = wrapi(cj + cy(q), I.ny), nk = wrapi(ck + cz(q), I.nz);
-        if (own[(nk * I.ny + nj) * I.nx + ni] == p) v |= 1 << q;
+        const int o = own[(nk * I.ny + nj) * I.nx + ni];
+        if (o == p) v |= 1 << q;
+        if (own_is_fluid(o)) fl |= 1 << q;
       }
+#pragma unroll
+      for (int q = 1; q < Q; ++q)
+        if ((v & (1 << q)) && (fl & (1 << opp(q)))) v |= slot_cli_bit(q);
     }
-    local += __popc(v);
+    local += __popc(v & SLOT_LINKS);
     if (uncovered && own[cell] == (WAS_BIT | p)) {
       v |= 1;
       ++local2;
@@ -159,7 +172,7 @@ hipError_t launch_mem_count(bool uncovered, const int* list, int nlist, int side
 // their own scanned offsets.  Links carry delta_q = the smallest root in
 // (0, 1] of |d + delta c|^2 = R^2 computed as e/(-b + sqrt(b^2 - a e))
 // (a = c.c, b = d.c, e = |d|^2 - R^2), and whether x - c_q is fluid (needed by
-// CLI).
+// CLI; taken from the slot word, so the fill reads no owner entries).
 __global__ __launch_bounds__(256) void mem_fill_links_kernel(const int* __restrict__ list, int side, int nsplit,
                                                              const InstDev* __restrict__ insts, PartDev P,
                                                              int* __restrict__ owner, const int* __restrict__ slots,
@@ -171,7 +184,7 @@ __global__ __launch_bounds__(256) void mem_fill_links_kernel(const int* __restri
   for (int c = ca; c < cb; ++c) {
     MEM_CELL_COORDS(c)
     const int m = slots[sidx];
-    local += __popc(m & ~1);
+    local += __popc(m & SLOT_LINKS);
     local2 += m & 1;
   }
   __shared__ int sh[256];
@@ -190,7 +203,7 @@ __global__ __launch_bounds__(256) void mem_fill_links_kernel(const int* __restri
       }
       ++pos2;
     }
-    if ((m & ~1) == 0) continue;
+    if ((m & SLOT_LINKS) == 0) continue;
     double d[3];
     disp(I, P, p, ci, cj, ck, d);
     const double e = sq3m(d[0], d[1], d[2]) - R * R;
@@ -200,13 +213,12 @@ __global__ __launch_bounds__(256) void mem_fill_links_kernel(const int* __restri
         const double a = (double)speed2(q);
         const double b = d[0] * cx(q) + d[1] * cy(q) + d[2] * cz(q);
         const double delta = e / (-b + sqrt(b * b - a * e));
-        const int bi = wrapi(ci - cx(q), I.nx), bj = wrapi(cj - cy(q), I.ny), bk = wrapi(ck - cz(q), I.nz);
         L.cell[pos] = cell;
         L.q[pos] = q;
         L.p[pos] = p;
         L.inst[pos] = P.inst[p];
         L.delta[pos] = delta;
-        L.cli_ok[pos] = own_is_fluid(own[(bk * I.ny + bj) * I.nx + bi]) ? 1 : 0;
+        L.cli_ok[pos] = (m & slot_cli_bit(q)) ? 1 : 0;
       }
       ++pos;
     }
@@ -279,8 +291,11 @@ __global__ __launch_bounds__(256) void mem_refill_kernel(const int* __restrict__
       const int xi = wrapi(x + k * cx(qn), I.nx), yi = wrapi(y + k * cy(qn), I.ny), zi = wrapi(z + k * cz(qn), I.nz);
       src_cell[k - 1] = (zi * I.ny + yi) * I.nx + xi;
     }
+    // all three owner entries and (below) source PDFs are read before any is
+    // tested, so their loads are in flight together
+    const int os[3] = {own[src_cell[0]], own[src_cell[1]], own[src_cell[2]]};
     for (int k = 0; k < 3; ++k) {
-      if (own[src_cell[k]] != OWN_FLUID) break;
+      if (os[k] != OWN_FLUID) break;
       ++ns;
     }
     const double* Up = P.U + 3 * p;
@@ -289,9 +304,10 @@ __global__ __launch_bounds__(256) void mem_refill_kernel(const int* __restrict__
                          Up[2] + (Wp[0] * d[1] - Wp[1] * d[0])};
     const int q = lane < Q ? lane : 0;
     double o = 0.0;
+    double f[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[k] = (double)Codec<S>::ld(b[pdf_at(src_cell[k], q)]);
     if (ns > 0) {
-      double f[3] = {0, 0, 0};
-      for (int k = 0; k < ns; ++k) f[k] = (double)Codec<S>::ld(b[pdf_at(src_cell[k], q)]);
       o = ns == 3 ? 3.0 * f[0] - 3.0 * f[1] + f[2] : (ns == 2 ? 2.0 * f[0] - f[1] : f[0]);
     } else {
       // lane q' < 18 inspects neighbour q' + 1; fluctuation sum over its 19 PDFs
@@ -352,33 +368,52 @@ __device__ __forceinline__ void link_rule(int i, const LinkDev& L, const double*
                                           const InstDev* __restrict__ insts, const PartDev& P, S* __restrict__ buf,
                                           double (&ft)[6]) {
   const int inst = L.inst[i];
-  const InstDev& I = insts[inst];
   const int cell = L.cell[i], q = L.q[i], p = L.p[i];
+  const int cli_ok = L.cli_ok[i];  // read with the other link fields, used by particle links
+  const double delta_l = L.delta[i];
+  // body state (particle centre, velocity, angular velocity; wall velocity),
+  // requested before the instance fields and PDFs so the loads overlap
+  double Xb[3] = {0, 0, 0}, Ub[3], Wb[3] = {0, 0, 0};
+  if (p >= 0) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      Xb[k] = P.X[3 * p + k];
+      Ub[k] = P.U[3 * p + k];
+      Wb[k] = P.Om[3 * p + k];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) Ub[k] = wall_v[3 * (-2 - p) + k];
+  }
+  const InstDev& I = insts[inst];
   const int qb = opp(q);
   const int x = cell % I.nx, yz = cell / I.nx, y = yz % I.ny, z = yz / I.ny;
   S* b = buf + I.pdf_off;
   const int c[3] = {cx(q), cy(q), cz(q)};
   const int xs = wrapi(x + c[0], I.nx), ys = wrapi(y + c[1], I.ny), zs = wrapi(z + c[2], I.nz);
+  // the three PDFs a link may need are requested together, before the CLI
+  // test, so one memory latency covers them
+  const int xm = wrapi(x - c[0], I.nx), ym = wrapi(y - c[1], I.ny), zm = wrapi(z - c[2], I.nz);
   const double gtq = (double)Codec<S>::ld(b[pdf_at(((long long)zs * I.ny + ys) * I.nx + xs, q)]);
+  const double gq_m = (double)Codec<S>::ld(b[pdf_at(cell, q)]);
+  const double gqb = (double)Codec<S>::ld(b[pdf_at(((long long)zm * I.ny + ym) * I.nx + xm, qb)]);
   double v[3], arm[3] = {0, 0, 0};
   bool cli = false;
   double delta = 0.5;
   if (p >= 0) {
-    cli = I.coupling == COUP_MEM_CLI && L.cli_ok[i];
-    if (cli) delta = L.delta[i];
-    double d[3];
-    disp(I, P, p, x, y, z, d);
+    cli = I.coupling == COUP_MEM_CLI && cli_ok;
+    if (cli) delta = delta_l;
+    const double d[3] = {min_image(((double)x + 0.5) - Xb[0], (double)I.nx),
+                         min_image(((double)y + 0.5) - Xb[1], (double)I.ny),
+                         min_image(((double)z + 0.5) - Xb[2], (double)I.nz)};
     for (int k = 0; k < 3; ++k) arm[k] = d[k] + delta * c[k];
-    const double* Up = P.U + 3 * p;
-    const double* Wp = P.Om + 3 * p;
-    v[0] = Up[0] + (Wp[1] * arm[2] - Wp[2] * arm[1]);
-    v[1] = Up[1] + (Wp[2] * arm[0] - Wp[0] * arm[2]);
-    v[2] = Up[2] + (Wp[0] * arm[1] - Wp[1] * arm[0]);
+    v[0] = Ub[0] + (Wb[1] * arm[2] - Wb[2] * arm[1]);
+    v[1] = Ub[1] + (Wb[2] * arm[0] - Wb[0] * arm[2]);
+    v[2] = Ub[2] + (Wb[0] * arm[1] - Wb[1] * arm[0]);
   } else {
-    const int gid = -2 - p;
-    v[0] = wall_v[3 * gid];
-    v[1] = wall_v[3 * gid + 1];
-    v[2] = wall_v[3 * gid + 2];
+    v[0] = Ub[0];
+    v[1] = Ub[1];
+    v[2] = Ub[2];
   }
   const double vc = v[0] * c[0] + v[1] * c[1] + v[2] * c[2];
   const double w = wq(q);
@@ -386,9 +421,6 @@ __device__ __forceinline__ void link_rule(int i, const LinkDev& L, const double*
   if (cli) {
     const double k0 = (1.0 - 2.0 * delta) / (1.0 + 2.0 * delta);
     const double alpha = 4.0 / (1.0 + 2.0 * delta);
-    const int xm = wrapi(x - c[0], I.nx), ym = wrapi(y - c[1], I.ny), zm = wrapi(z - c[2], I.nz);
-    const double gq_m = (double)Codec<S>::ld(b[pdf_at(cell, q)]);
-    const double gqb = (double)Codec<S>::ld(b[pdf_at(((long long)zm * I.ny + ym) * I.nx + xm, qb)]);
     val = gtq + k0 * gq_m - k0 * gqb - 3.0 * alpha * w * vc;
   } else {
     val = gtq - 6.0 * w * vc;

@@ -93,8 +93,11 @@ __global__ __launch_bounds__(1024) void scan2_kernel(const int* __restrict__ tot
                                                      int* __restrict__ begin2, int* __restrict__ end2,
                                                      int* __restrict__ count2, int cap2, unsigned err_bit2,
                                                      unsigned* err) {
-  scan_body(totals, offsets, m, side, nlist, begin, end, count, cap, err, err_bit);
-  scan_body(totals2, offsets2, m2, side2, nlist2, begin2, end2, count2, cap2, err, err_bit2);
+  // the two scans are independent: one workgroup each, running side by side
+  if (blockIdx.x == 0)
+    scan_body(totals, offsets, m, side, nlist, begin, end, count, cap, err, err_bit);
+  else
+    scan_body(totals2, offsets2, m2, side2, nlist2, begin2, end2, count2, cap2, err, err_bit2);
 }
 
 hipError_t launch_scan(const int* totals, int* offsets, int m, int side, int nlist, int* begin, int* end, int* count,
@@ -108,7 +111,7 @@ hipError_t launch_scan2(const int* totals, int* offsets, int m, int side, int nl
                         int cap, unsigned err_bit, const int* totals2, int* offsets2, int m2, int side2, int nlist2,
                         int* begin2, int* end2, int* count2, int cap2, unsigned err_bit2, unsigned* err,
                         hipStream_t st) {
-  hipLaunchKernelGGL(scan2_kernel, dim3(1), dim3(1024), 0, st, totals, offsets, m, side, nlist, begin, end, count, cap,
+  hipLaunchKernelGGL(scan2_kernel, dim3(2), dim3(1024), 0, st, totals, offsets, m, side, nlist, begin, end, count, cap,
                      err_bit, totals2, offsets2, m2, side2, nlist2, begin2, end2, count2, cap2, err_bit2, err);
   return hipGetLastError();
 }
@@ -161,6 +164,7 @@ __global__ __launch_bounds__(64 * FIN_WAVES) void finish_sums_kernel(const int* 
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int j = blockIdx.x * FIN_WAVES + w;
   if (j >= nlist) return;  // whole wave
+  const int p = list[j];  // requested with the record range, used after the sums
   const int n = end[j] - begin[j];
   const int parts_n = min((n + chunk - 1) / chunk, width);
   double tot[6] = {0, 0, 0, 0, 0, 0};
@@ -173,7 +177,6 @@ __global__ __launch_bounds__(64 * FIN_WAVES) void finish_sums_kernel(const int* 
   for (int k = 0; k < 6; ++k)
     for (int m = 32; m >= 1; m >>= 1) tot[k] += __shfl_xor(tot[k], m, 64);
   if (lane == 0) {
-    const int p = list[j];
     if (parts_n > 0)
       for (int k = 0; k < 3; ++k) {
         parts.Facc[3 * p + k] += tot[k];
