@@ -66,6 +66,36 @@ def test_several_mem_spheres():
     sim.close()
 
 
+def test_mem_cli_falls_back_to_bounce_back_in_narrow_gaps():
+    # Two spheres one fluid cell apart along x, and a fixed sphere one fluid
+    # cell above a static wall: fluid cells with a solid cell on both sides of
+    # a link, where CLI takes the bounce-back rule for that link.
+    say("MEM-CLI narrow gaps")
+    nx, ny, nz = 30, 24, 24
+    wall = np.zeros((nz, ny, nx), bool)
+    wall[0] = True
+    parts = dict(X=[[10.5, 12.3, 11.7], [18.9, 12.1, 11.9], [5.0, 5.0, 5.2]],
+                 U=[[0.002, 0, 0], [-0.002, 0.001, 0], [0, 0, 0]], Om=[[0, 0, 0.001], [0, 0, 0], [0, 0, 0]],
+                 D=[7.0, 7.0, 6.0], rho=[1.5, 1.2, 2.0], fixed=[False, False, True])
+    ora, sim = make_pair(nx, ny, nz, 0.05, coupling="mem_cli", collision="trt", f_ext=(1e-6, 0, 0),
+                         gravity=(0, 0, -1e-5), parts=parts, n_sub=2, walls=[(wall, (0, 0, 0))])
+    L = ora.links
+    fallback = L["is_particle"] & ~L["cli_ok"]
+    say("  particle links %d, of them with x - c_q solid: %d" % (int(L["is_particle"].sum()), int(fallback.sum())))
+    assert fallback.sum() >= 2  # the case is exercised
+    for k in range(3):
+        ora.step(20)
+        sim.step(20)
+        errs, po, pg = force_errors(ora, sim)
+        e, _ = pdf_error(ora, sim)
+        say("  t=%d e_f=%.2e" % (ora.time, e), [("%.1e" % a, "%.1e" % b) for a, b, _ in errs])
+        assert e < 1e-11
+        for eF, eT, _ in errs:
+            assert eF < 1e-11 and eT < 1e-11
+        assert np.abs(pg["X"] - po["X"]).max() < 1e-13
+    sim.close()
+
+
 @pytest.mark.parametrize("coupling", ["mem_cli", "psm"])
 def test_largest_sphere(coupling):
     # D = 58: bounding boxes of 64 cells per axis, the library's limit
