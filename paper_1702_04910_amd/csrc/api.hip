@@ -278,6 +278,12 @@ struct lbmps_ctx {
   double* scratch = nullptr;
   long long sweeps = 0;
   bool have_psm = false, have_links_inst = false;
+  // MEM remap overlapped with the next sweep: the remap runs on `side`
+  // (forked after the rigid-body step, joined before the link rules of that
+  // sweep, which then re-sweeps the refilled cells)
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+  bool join_pending = false;
   // captured step graph (one period of sweeps), invalidated when lists change
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -381,7 +387,7 @@ void update_psm_exact(lbmps_ctx* c) {
 int* psm_list(lbmps_ctx* c) { return c->plist_d + c->n_mem; }
 
 // Rebuild links of every MEM particle (after mapping); refill first when `refill`.
-lbmps_status rebuild_mem(lbmps_ctx* c, bool refill) {
+lbmps_status rebuild_mem(lbmps_ctx* c, bool refill, hipStream_t st) {
   const Layout& L = c->L;
   if (c->n_mem == 0) return LBMPS_OK;
   unsigned* err = err_word(c);
@@ -391,28 +397,28 @@ lbmps_status rebuild_mem(lbmps_ctx* c, bool refill) {
   // pass writes both lists; the refill only reads the owner field, so it can
   // follow the link list
   HIPCHK(c, launch_mem_count(refill, mem_list(c), c->n_mem, L.side, ns, c->inst_d, c->parts, c->owner,
-                             c->slots, c->totals, c->totals2, c->st));
+                             c->slots, c->totals, c->totals2, st));
   if (refill)
     HIPCHK(c, launch_scan2(c->totals, c->offsets, c->n_mem * units, units, c->n_mem, c->lbeg, c->lend, c->counts + 0,
                            L.link_cap, ERR_LINK_CAP, c->totals2, c->offsets2, c->n_mem * units, units, c->n_mem,
-                           c->rbeg, c->rend, c->counts + 2, L.refill_cap, ERR_REFILL_CAP, err, c->st));
+                           c->rbeg, c->rend, c->counts + 2, L.refill_cap, ERR_REFILL_CAP, err, st));
   else
     HIPCHK(c, launch_scan(c->totals, c->offsets, c->n_mem * units, units, c->n_mem, c->lbeg, c->lend, c->counts + 0,
-                          L.link_cap, err, ERR_LINK_CAP, c->st));
+                          L.link_cap, err, ERR_LINK_CAP, st));
   HIPCHK(c, launch_mem_fill_links(mem_list(c), c->n_mem, L.side, ns, c->inst_d, c->parts, c->owner, c->slots,
                                   c->offsets, c->n_wall, L.link_cap, c->links, c->offsets2, L.refill_cap,
-                                  refill ? c->rcell : nullptr, c->rpart, c->st));
+                                  refill ? c->rcell : nullptr, c->rpart, st));
   if (refill)
     HIPCHK(c, launch_mem_refill(L.prec, c->counts + 2, L.refill_cap, c->rcell, c->rpart, c->inst_d, c->parts, c->owner,
-                                c->buf[c->cur], c->st));
+                                c->buf[c->cur], st));
   return LBMPS_OK;
 }
 
-lbmps_status remap_mem(lbmps_ctx* c) {
+lbmps_status remap_mem(lbmps_ctx* c, hipStream_t st) {
   const int ns = nsplit_for(c->n_mem, c->L.side);
-  HIPCHK(c, launch_mem_unmap(mem_list(c), c->n_mem, c->L.side, ns, c->inst_d, c->parts, c->owner, c->st));
-  HIPCHK(c, launch_mem_map(mem_list(c), c->n_mem, c->L.side, ns, c->inst_d, c->parts, c->owner, c->st));
-  return rebuild_mem(c, true);
+  HIPCHK(c, launch_mem_unmap(mem_list(c), c->n_mem, c->L.side, ns, c->inst_d, c->parts, c->owner, st));
+  HIPCHK(c, launch_mem_map(mem_list(c), c->n_mem, c->L.side, ns, c->inst_d, c->parts, c->owner, st));
+  return rebuild_mem(c, true, st);
 }
 
 __global__ void fill_int_kernel(int* a, long long n, int v);
@@ -684,6 +690,12 @@ lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* ws, s
 void lbmps_destroy(lbmps_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->st);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipEventDestroy(c->fork_ev);
+    (void)hipEventDestroy(c->join_ev);
+    (void)hipStreamDestroy(c->side);
+  }
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -858,7 +870,7 @@ lbmps_status lbmps_set_particles(lbmps_ctx* c, int32_t inst, int32_t n, const lb
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, launch_mem_map(mem_list(c), c->n_mem, c->L.side, nsplit_for(c->n_mem, c->L.side), c->inst_d, c->parts,
                              c->owner, c->st));
-    s = rebuild_mem(c, false);
+    s = rebuild_mem(c, false, c->st);
     if (s) return s;
   } else if (cf.coupling == LBMPS_PSM) {
     s = rebuild_psm(c);
@@ -867,12 +879,51 @@ lbmps_status lbmps_set_particles(lbmps_ctx* c, int32_t inst, int32_t n, const lb
   return check_device_errors(c);
 }
 
+// Side stream and events of the overlapped MEM remap, created on first use
+// (default priority).  False when they cannot be created: the remap then
+// runs in order on the context's stream.
+static bool ensure_side_stream(lbmps_ctx* c) {
+  if (c->side) return true;
+  hipStream_t s = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return false;
+  // both streams are on one device: no system-scope fence (cache writeback) is needed
+  const unsigned fl = hipEventDisableTiming | hipEventDisableSystemFence;
+  if (hipEventCreateWithFlags(&a, fl) != hipSuccess || hipEventCreateWithFlags(&b, fl) != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
+    (void)hipStreamDestroy(s);
+    return false;
+  }
+  c->side = s;
+  c->fork_ev = a;
+  c->join_ev = b;
+  return true;
+}
+
+// A stream under graph capture keeps all work on itself (no fork).
+static bool stream_capturing(hipStream_t st) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  return hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone;
+}
+
+static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n);
+
 lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
   if (!c) return LBMPS_EINVAL;
   if (n < 0) return fail(c, LBMPS_EINVAL, "negative step count");
   const Layout& L = c->L;
   if (L.mem_nsub && (n % L.mem_nsub)) return fail(c, LBMPS_EINVAL, "MEM steps must be a multiple of n_sub");
   if (L.psm_nsub && (n % L.psm_nsub)) return fail(c, LBMPS_EINVAL, "PSM steps must be a multiple of n_sub");
+  lbmps_status r = step_sweeps(c, n);
+  if (c->join_pending) {  // only after an error: the forked remap still joins the stream
+    (void)hipStreamWaitEvent(c->st, c->join_ev, 0);
+    c->join_pending = false;
+  }
+  return r;
+}
+
+static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
+  const Layout& L = c->L;
   unsigned* err = err_word(c);
   for (int s = 0; s < n; ++s) {
     void* src = c->buf[c->cur];
@@ -888,7 +939,8 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
         if (r) return r;
         while (c->ev.size() < 4096) {
           hipEvent_t e;
-          HIPCHK(c, hipEventCreate(&e));
+          // timestamps only (read after a stream synchronisation): no system-scope fence
+          HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
           c->ev.push_back(e);
         }
       }
@@ -913,6 +965,12 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
                               L.red_blocks, c->red_partial, psm_rb ? c->inst_d : nullptr, err,
                               c->st));
     }
+    if (c->join_pending) {  // the remap forked after the previous rigid-body step has refilled src
+      HIPCHK(c, hipStreamWaitEvent(c->st, c->join_ev, 0));
+      c->join_pending = false;
+      HIPCHK(c, launch_resweep_cells(L.prec, c->counts + 2, L.refill_cap, c->rcell, c->rpart, c->inst_d, c->parts,
+                                     src, dst, c->st));
+    }
     if (c->n_mem || c->n_wall) {
       HIPCHK(c, launch_links_bc(L.prec, c->n_wall, mem_list(c), c->n_mem, c->lbeg, c->lend, L.link_blocks, c->links,
                                 c->wall_v, c->inst_d, c->parts, dst, c->red_partial,
@@ -924,9 +982,22 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
       lbmps_status r = rebuild_psm(c);
       if (r) return r;
     }
-    if (mem_rb) {
-      if (c->mem_moving) {
-        lbmps_status r = remap_mem(c);
+    if (mem_rb && c->mem_moving) {
+      // With another sweep to come in this call (and no PSM particles, whose
+      // list building shares the work arrays), the remap runs on the side
+      // stream while that sweep runs: the sweep's results depend on the
+      // uncovered cells only through what those cells push, which the
+      // re-sweep after the join recomputes from the refilled values.
+      const bool overlap = s + 1 < n && c->n_psm == 0 && !stream_capturing(c->st) && ensure_side_stream(c);
+      if (overlap) {
+        HIPCHK(c, hipEventRecord(c->fork_ev, c->st));
+        HIPCHK(c, hipStreamWaitEvent(c->side, c->fork_ev, 0));
+        lbmps_status r = remap_mem(c, c->side);
+        HIPCHK(c, hipEventRecord(c->join_ev, c->side));
+        c->join_pending = true;
+        if (r) return r;
+      } else {
+        lbmps_status r = remap_mem(c, c->st);
         if (r) return r;
       }
     }

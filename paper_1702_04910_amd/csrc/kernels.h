@@ -43,6 +43,10 @@ inline size_t sweep_lds_bytes(size_t need, int flags) {
 hipError_t launch_sweep(int prec, const InstDev* insts, const int4* tiles, int ntiles, int grid, int block,
                         int max_tile_cells, int flags, int psm_mode, const void* src, void* dst, const int* cellmap,
                         PairDev pairs, PartDev parts, const void* stage, long long sstride, hipStream_t st);
+// Collide-and-push of the first min(*count, cap) cells of the MEM refill list (rcell, rpart) from src to dst, with
+// the sweep's arithmetic: repairs a sweep that ran while those cells were being refilled.
+hipError_t launch_resweep_cells(int prec, const int* count, int cap, const int* rcell, const int* rpart,
+                                const InstDev* insts, PartDev parts, const void* src, void* dst, hipStream_t st);
 constexpr int SWEEP_LDS_LIMIT = 64 * 1024;  // bytes of LDS staging per sweep workgroup
 hipError_t launch_init_eq(int prec, void* buf, long long N, double rho, const double u[3], hipStream_t st);
 hipError_t launch_to_f64(int prec, const void* a, int q, long long c0, double* b, long long n, hipStream_t st);

@@ -443,6 +443,40 @@ __global__ void fields_kernel(const S* __restrict__ buf, long long N, long long 
   out[3 * n + i] = uz;
 }
 
+// Collide-and-push of listed cells only: the cells that a MEM remap uncovered
+// (count, rcell, rpart as written by the link-list fill), when the sweep ran
+// while their refill was still in progress.  Each listed cell is collided
+// from its refilled values in `src` and its 19 values are pushed to `dst`
+// exactly as the sweep pushes them (same collision, same rounding), replacing
+// what the sweep pushed from its earlier values; no other cell's sweep result
+// depends on a listed cell, and the remap writes no other PDFs.
+template <typename S>
+__global__ __launch_bounds__(256) void resweep_cells_kernel(const int* __restrict__ count, int cap,
+                                                            const int* __restrict__ rcell,
+                                                            const int* __restrict__ rpart,
+                                                            const InstDev* __restrict__ insts, PartDev P,
+                                                            const S* __restrict__ src, S* __restrict__ dst) {
+  using R = typename CompOf<S>::type;
+  const int n = min(*count, cap);
+  for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+    const int cell = rcell[r];
+    const InstDev& I = insts[P.inst[rpart[r]]];
+    const int nx = I.nx, ny = I.ny, nz = I.nz;
+    const S* __restrict__ s = src + I.pdf_off;
+    S* __restrict__ d = dst + I.pdf_off;
+    R g[Q], o[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) g[q] = Codec<S>::ld(s[pdf_at(cell, q)]);
+    collide_cell<R>(g, o, (R)I.lam_p, (R)I.lam_m, (R)I.fext[0], (R)I.fext[1], (R)I.fext[2]);
+    const int x = cell % nx, yz = cell / nx, y = yz % ny, z = yz / ny;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int xa = wrapi(x + cx(q), nx), ya = wrapi(y + cy(q), ny), za = wrapi(z + cz(q), nz);
+      d[pdf_at(((long long)za * ny + ya) * nx + xa, q)] = Codec<S>::st(o[q]);
+    }
+  }
+}
+
 // ------------------------------------------------------------------------ launchers
 template <typename S, bool NTLD>
 hipError_t launch_sweep_n(const InstDev* insts, const int4* tiles, int ntiles, int grid, int block, size_t lds,
@@ -528,6 +562,15 @@ hipError_t launch_from_f64(int prec, const double* a, void* b, int q, long long 
   const int bl = 256;
   const unsigned g = (unsigned)((n + bl - 1) / bl);
   LBM_DISPATCH(prec, hipLaunchKernelGGL(from_f64_kernel<S>, dim3(g), dim3(bl), 0, st, a, (S*)b, q, c0, n));
+  return hipGetLastError();
+}
+
+hipError_t launch_resweep_cells(int prec, const int* count, int cap, const int* rcell, const int* rpart,
+                                const InstDev* insts, PartDev parts, const void* src, void* dst, hipStream_t st) {
+  // the list is a few cells per rigid-body step and particle; a grid-stride
+  // loop covers longer ones
+  LBM_DISPATCH(prec, hipLaunchKernelGGL(resweep_cells_kernel<S>, dim3(16), dim3(256), 0, st, count, cap, rcell, rpart,
+                                        insts, parts, (const S*)src, (S*)dst));
   return hipGetLastError();
 }
 
