@@ -168,7 +168,13 @@ lbmps_status lbmps_set_static_solid(lbmps_ctx* ctx, int32_t inst, const uint8_t*
 lbmps_status lbmps_set_particles(lbmps_ctx* ctx, int32_t inst, int32_t n, const lbmps_particle* host);
 
 /* Advance every instance by n_steps LBM time steps (Alg. 1 / Alg. 2);
- * n_steps must be a multiple of every n_sub in the context.  Asynchronous. */
+ * n_steps must be a multiple of every n_sub in the context.  Asynchronous.
+ * Within one call, when the context has MEM particles and no PSM particles
+ * and its stream is not being captured, the remap after a rigid-body step
+ * runs on a second stream of the library beside the next sweep (results are
+ * bit-identical to running it in order); that stream waits for the caller's
+ * stream and the caller's stream waits for it before the call returns, so all
+ * of the call's work stays ordered on the caller's stream. */
 lbmps_status lbmps_step(lbmps_ctx* ctx, int32_t n_steps);
 
 /* Change the sweep launch shape of an existing context (workgroup size, grid:
