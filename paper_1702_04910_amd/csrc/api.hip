@@ -448,7 +448,7 @@ lbmps_status rebuild_psm(lbmps_ctx* c) {
   }
   if (c->psm_exact)
     HIPCHK(c, launch_psm_cut_exact(c->inst_d, c->parts, c->slots, c->cuts, L.cut_cap, rmin, rmax, c->st));
-  HIPCHK(c, launch_psm_unit_totals(c->n_psm, L.side, ns, c->slots, c->totals, c->st));
+  HIPCHK(c, launch_psm_unit_totals(psm_list(c), c->n_psm, L.side, ns, c->parts, c->slots, c->totals, c->st));
   HIPCHK(c, launch_scan(c->totals, c->offsets, c->n_psm * units, units, c->n_psm, c->pbeg, c->pend, c->counts + 1,
                         L.pair_cap, err, ERR_PAIR_CAP, c->st));
   HIPCHK(c, launch_psm_fill(psm_list(c), c->n_psm, L.side, ns, c->inst_d, c->parts, c->slots, c->offsets, L.pair_cap,

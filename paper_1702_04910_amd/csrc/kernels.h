@@ -114,7 +114,8 @@ hipError_t launch_psm_cut_features(const InstDev* insts, PartDev parts, CutDev c
                                    double rmax, float* X, hipStream_t st);
 hipError_t launch_psm_cut_scatter(const InstDev* insts, PartDev parts, CutDev cuts, int cap, const float* y,
                                   int* slots, hipStream_t st);
-hipError_t launch_psm_unit_totals(int nlist, int side, int nsplit, const int* slots, int* totals, hipStream_t st);
+hipError_t launch_psm_unit_totals(const int* list, int nlist, int side, int nsplit, PartDev parts, const int* slots,
+                                  int* totals, hipStream_t st);
 hipError_t launch_psm_label(const double* rd, long long ns, int n, float* eps, hipStream_t st);
 hipError_t launch_psm_judge(const InstDev* insts, PartDev parts, const int* slots, CutDev cuts, int cap, int stride,
                             double* stats, hipStream_t st);

@@ -33,9 +33,20 @@ __device__ __forceinline__ void disp(const InstDev& I, const PartDev& P, int p, 
   d[2] = min_image(((double)k + 0.5) - P.X[3 * p + 2], (double)I.nz);
 }
 
+// Cells per axis of particle p's own bounding box (from mem_bbox_lo): the
+// slot grid is `side` wide for the largest particle; ceil(D) + 6 cells reach
+// R + 3 beyond the centre, past every solid cell, link and uncovered cell of
+// p, and past the cells p uncovered in its previous remap (it moves less than
+// one cell per rigid-body step).
+__device__ __forceinline__ int mem_extent(const PartDev& P, int p, int side) {
+  return min(side, (int)ceil(P.D[p]) + 6);
+}
+
 // Workgroup (x, j) handles the work units x, x + gridDim.x, ... (a unit is a
-// row range of one slab) of the bounding box of particle list[j], each in
-// contiguous per-thread chunks; MEM_BBOX_END closes the loop over units.
+// row range of one slab) of the bounding box of particle list[j], restricted
+// to the particle's own extent (rows [U.y0, min(U.y1, ext)) of slab U.z < ext,
+// ext cells each), in contiguous per-thread chunks; MEM_BBOX_END closes the
+// loop over units.
 #define MEM_BBOX_BEGIN                                                                 \
   const int jl = blockIdx.y;                                                           \
   const int p = list[jl];                                                              \
@@ -44,15 +55,17 @@ __device__ __forceinline__ void disp(const InstDev& I, const PartDev& P, int p, 
   mem_bbox_lo(P, p, lo);                                                               \
   int* own = owner + I.owner_off;                                                      \
   (void)own;                                                                           \
+  const int ext_ = mem_extent(P, p, side);                                             \
   for (int ub = blockIdx.x; ub < side * nsplit; ub += gridDim.x) {                     \
     const Unit U_ = unit_of(ub, side, nsplit);                                         \
-    const int ncs = (U_.y1 - U_.y0) * side;                                            \
+    const int y1_ = min(U_.y1, ext_);                                                  \
+    const int ncs = (U_.z < ext_ && y1_ > U_.y0) ? (y1_ - U_.y0) * ext_ : 0;           \
     const int chunk = (ncs + 255) / 256;                                               \
     const int ca = min(ncs, (int)threadIdx.x * chunk), cb = min(ncs, ca + chunk);
 #define MEM_BBOX_END }
 
 #define MEM_CELL_COORDS(c)                                                 \
-  const int dy_ = U_.y0 + (c) / side, dx_ = (c) % side;                    \
+  const int dy_ = U_.y0 + (c) / ext_, dx_ = (c) % ext_;                    \
   const int ci = wrapi(lo[0] + dx_, I.nx), cj = wrapi(lo[1] + dy_, I.ny),  \
             ck = wrapi(lo[2] + U_.z, I.nz);                                \
   const int cell = (ck * I.ny + cj) * I.nx + ci;                           \

@@ -170,6 +170,19 @@ __device__ __forceinline__ void bbox_lo(const PartDev& P, int p, int (&lo)[3]) {
   for (int k = 0; k < 3; ++k) lo[k] = (int)floor(P.X[3 * p + k] - R - 2.0);
 }
 
+// Cells per axis of particle p's own bounding box (from bbox_lo): the slot
+// grid is `side` wide for the largest particle, and the cells beyond
+// ceil(D) + 6 lie more than R + 3 from the centre, outside every estimator's
+// reach.  Every stage below visits exactly the rows [U.y0, min(U.y1, e)) of
+// slab U.z < e, e cells each, so the scanned offsets agree between stages.
+__device__ __forceinline__ int own_extent(const PartDev& P, int p, int side) {
+  return min(side, (int)ceil(P.D[p]) + 6);
+}
+__device__ __forceinline__ int unit_cells(const Unit& U, int e) {
+  const int y1 = min(U.y1, e);
+  return (U.z < e && y1 > U.y0) ? (y1 - U.y0) * e : 0;
+}
+
 __device__ __forceinline__ void centre_disp(const InstDev& I, const PartDev& P, int p, int i, int j, int k,
                                             double (&d)[3]) {
   d[0] = min_image(((double)i + 0.5) - P.X[3 * p + 0], (double)I.nx);
@@ -226,14 +239,15 @@ __global__ __launch_bounds__(256) void psm_classify_kernel(const int* __restrict
   const double R2 = __dmul_rn(R, R);
   const int n = I.eps_n;
   const double o0 = sample_off(0, n), o1 = sample_off(n - 1, n);
+  const int ext = own_extent(P, p, side);
   for (int ub = blockIdx.x; ub < side * nsplit; ub += gridDim.x) {
     const Unit U = unit_of(ub, side, nsplit);
-    const int ncu = (U.y1 - U.y0) * side;
+    const int ncu = unit_cells(U, ext);
     const int k = wrapi(lo[2] + U.z, I.nz);
     const double dz = min_image(((double)k + 0.5) - P.X[3 * p + 2], (double)I.nz);
     int ncut = 0;
     for (int c = threadIdx.x; c < ncu; c += blockDim.x) {
-      const int dy = U.y0 + c / side, dx = c % side;
+      const int dy = U.y0 + c / ext, dx = c % ext;
       const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny);
       const double dc[3] = {min_image(((double)i + 0.5) - P.X[3 * p + 0], (double)I.nx),
                             min_image(((double)jj + 0.5) - P.X[3 * p + 1], (double)I.ny), dz};
@@ -270,17 +284,18 @@ __global__ __launch_bounds__(256) void psm_cut_fill_kernel(const int* __restrict
   const InstDev& I = insts[P.inst[p]];
   int lo[3];
   bbox_lo(P, p, lo);
+  const int ext = own_extent(P, p, side);
   for (int ub = blockIdx.x; ub < side * nsplit; ub += gridDim.x) {
     const Unit U = unit_of(ub, side, nsplit);
-    const int ncu = (U.y1 - U.y0) * side;
+    const int ncu = unit_cells(U, ext);
     const int chunk = (ncu + 255) / 256;
     const int a = min(ncu, (int)threadIdx.x * chunk), b = min(ncu, a + chunk);
     int local = 0;
-    for (int c = a; c < b; ++c) local += slots[slot_index(j, side, U.z, U.y0 + c / side, c % side)] < 0 ? 1 : 0;
+    for (int c = a; c < b; ++c) local += slots[slot_index(j, side, U.z, U.y0 + c / ext, c % ext)] < 0 ? 1 : 0;
     int total;
     int pos = offsets[j * (side * nsplit) + ub] + block_excl_scan256(local, sh, &total);
     for (int c = a; c < b; ++c) {
-      const int dy = U.y0 + c / side, dx = c % side;
+      const int dy = U.y0 + c / ext, dx = c % ext;
       const long long si = slot_index(j, side, U.z, dy, dx);
       if (slots[si] >= 0) continue;
       if (pos < cap) {
@@ -351,16 +366,18 @@ __global__ void psm_cut_scatter_kernel(const InstDev* __restrict__ insts, PartDe
 }
 
 // Stage 3: number of cells with eps > 0 (count > 0) per work unit.
-__global__ __launch_bounds__(256) void psm_unit_totals_kernel(int side, int nsplit, const int* __restrict__ slots,
+__global__ __launch_bounds__(256) void psm_unit_totals_kernel(const int* __restrict__ list, int side, int nsplit,
+                                                              PartDev P, const int* __restrict__ slots,
                                                               int* __restrict__ totals) {
   __shared__ int sh[256];
   const int j = blockIdx.y;
+  const int ext = own_extent(P, list[j], side);
   for (int ub = blockIdx.x; ub < side * nsplit; ub += gridDim.x) {
     const Unit U = unit_of(ub, side, nsplit);
-    const int ncu = (U.y1 - U.y0) * side;
+    const int ncu = unit_cells(U, ext);
     int local = 0;
     for (int c = threadIdx.x; c < ncu; c += blockDim.x)
-      local += slots[slot_index(j, side, U.z, U.y0 + c / side, c % side)] > 0 ? 1 : 0;
+      local += slots[slot_index(j, side, U.z, U.y0 + c / ext, c % ext)] > 0 ? 1 : 0;
     int total;
     block_excl_scan256(local, sh, &total);
     if (threadIdx.x == 0) totals[j * (side * nsplit) + ub] = total;
@@ -446,10 +463,11 @@ hipError_t launch_psm_cut_scatter(const InstDev* insts, PartDev parts, CutDev cu
   return hipGetLastError();
 }
 
-hipError_t launch_psm_unit_totals(int nlist, int side, int nsplit, const int* slots, int* totals, hipStream_t st) {
+hipError_t launch_psm_unit_totals(const int* list, int nlist, int side, int nsplit, PartDev parts, const int* slots,
+                                  int* totals, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
   const dim3 grid(unit_grid(side * nsplit, nlist), nlist);
-  hipLaunchKernelGGL(psm_unit_totals_kernel, grid, dim3(256), 0, st, side, nsplit, slots, totals);
+  hipLaunchKernelGGL(psm_unit_totals_kernel, grid, dim3(256), 0, st, list, side, nsplit, parts, slots, totals);
   return hipGetLastError();
 }
 
@@ -480,17 +498,18 @@ __global__ __launch_bounds__(256) void psm_fill_kernel(const int* __restrict__ l
   const int n = I.eps_n;
   const double nn = (double)n * (double)n * (double)n;
   const double t = I.tau - 0.5;
+  const int ext = own_extent(P, p, side);
   for (int ub = blockIdx.x; ub < side * nsplit; ub += gridDim.x) {
     const Unit U = unit_of(ub, side, nsplit);
-    const int ncu = (U.y1 - U.y0) * side;
+    const int ncu = unit_cells(U, ext);
     const int chunk = (ncu + 255) / 256;
     const int a = min(ncu, (int)threadIdx.x * chunk), b = min(ncu, a + chunk);
     int local = 0;
-    for (int c = a; c < b; ++c) local += slots[slot_index(j, side, U.z, U.y0 + c / side, c % side)] > 0 ? 1 : 0;
+    for (int c = a; c < b; ++c) local += slots[slot_index(j, side, U.z, U.y0 + c / ext, c % ext)] > 0 ? 1 : 0;
     int total;
     int pos = offsets[j * (side * nsplit) + ub] + block_excl_scan256(local, sh, &total);
     for (int c = a; c < b; ++c) {
-      const int dy = U.y0 + c / side, dx = c % side;
+      const int dy = U.y0 + c / ext, dx = c % ext;
       const int v = slots[slot_index(j, side, U.z, dy, dx)];
       if (v <= 0) continue;
       if (pos < cap) {
