@@ -11,6 +11,7 @@
 //   f~_q(x - c_q, t)  -- pushed by the fluid cell x - c_q into x, slot q;
 //   f~_qbar(x, t)     -- pushed by x into x - c_q, slot qbar.
 // None of these slots is written by another link, so links are independent.
+#include "bbox.h"
 #include "common.h"
 #include "kernels.h"
 #include "particle_sum.h"
@@ -33,15 +34,6 @@ __device__ __forceinline__ void disp(const InstDev& I, const PartDev& P, int p, 
   d[2] = min_image(((double)k + 0.5) - P.X[3 * p + 2], (double)I.nz);
 }
 
-// Cells per axis of particle p's own bounding box (from mem_bbox_lo): the
-// slot grid is `side` wide for the largest particle; ceil(D) + 6 cells reach
-// R + 3 beyond the centre, past every solid cell, link and uncovered cell of
-// p, and past the cells p uncovered in its previous remap (it moves less than
-// one cell per rigid-body step).
-__device__ __forceinline__ int mem_extent(const PartDev& P, int p, int side) {
-  return min(side, (int)ceil(P.D[p]) + 6);
-}
-
 // Workgroup (x, j) handles the work units x, x + gridDim.x, ... (a unit is a
 // row range of one slab) of the bounding box of particle list[j], restricted
 // to the particle's own extent (rows [U.y0, min(U.y1, ext)) of slab U.z < ext,
@@ -55,19 +47,20 @@ __device__ __forceinline__ int mem_extent(const PartDev& P, int p, int side) {
   mem_bbox_lo(P, p, lo);                                                               \
   int* own = owner + I.owner_off;                                                      \
   (void)own;                                                                           \
-  const int ext_ = mem_extent(P, p, side);                                             \
+  const int ext_ = bbox_extent(P, p, side);                                            \
   for (int ub = blockIdx.x; ub < side * nsplit; ub += gridDim.x) {                     \
     const Unit U_ = unit_of(ub, side, nsplit);                                         \
-    const int y1_ = min(U_.y1, ext_);                                                  \
-    const int ncs = (U_.z < ext_ && y1_ > U_.y0) ? (y1_ - U_.y0) * ext_ : 0;           \
+    const int ncs = unit_cells(U_, ext_);                                              \
     const int chunk = (ncs + 255) / 256;                                               \
     const int ca = min(ncs, (int)threadIdx.x * chunk), cb = min(ncs, ca + chunk);
 #define MEM_BBOX_END }
 
-#define MEM_CELL_COORDS(c)                                                 \
-  const int dy_ = U_.y0 + (c) / ext_, dx_ = (c) % ext_;                    \
-  const int ci = wrapi(lo[0] + dx_, I.nx), cj = wrapi(lo[1] + dy_, I.ny),  \
-            ck = wrapi(lo[2] + U_.z, I.nz);                                \
+// The unit's cells of this thread's chunk, each with its lattice cell and
+// slot index.
+#define MEM_FOR_CELLS BBOX_FOR_CELLS(c, ca, cb, U_.y0, ext_, dy_, dx_)
+#define MEM_CELL_COORDS                                                              \
+  const int ci = wrap_near(lo[0] + dx_, I.nx), cj = wrap_near(lo[1] + dy_, I.ny),  \
+            ck = wrap_near(lo[2] + U_.z, I.nz);                                    \
   const int cell = (ck * I.ny + cj) * I.nx + ci;                           \
   const long long sidx = slot_index(jl, side, U_.z, dy_, dx_);             \
   (void)sidx;
@@ -76,8 +69,8 @@ __global__ __launch_bounds__(256) void mem_unmap_kernel(const int* __restrict__ 
                                                         const InstDev* __restrict__ insts, PartDev P,
                                                         int* __restrict__ owner) {
   MEM_BBOX_BEGIN
-  for (int c = ca; c < cb; ++c) {
-    MEM_CELL_COORDS(c)
+  MEM_FOR_CELLS {
+    MEM_CELL_COORDS
     // solid cells of p become "was solid of p"; the marks of p's previous
     // remap (cells it uncovered then, all within this box) become plain fluid
     const int o = own[cell];
@@ -93,8 +86,8 @@ __global__ __launch_bounds__(256) void mem_map_kernel(const int* __restrict__ li
   MEM_BBOX_BEGIN
   const double R = 0.5 * P.D[p];
   const double R2 = __dmul_rn(R, R);
-  for (int c = ca; c < cb; ++c) {
-    MEM_CELL_COORDS(c)
+  MEM_FOR_CELLS {
+    MEM_CELL_COORDS
     double d[3];
     disp(I, P, p, ci, cj, ck, d);
     if (sq3m(d[0], d[1], d[2]) <= R2 && own_is_fluid(own[cell])) own[cell] = p;
@@ -137,14 +130,14 @@ __global__ __launch_bounds__(256) void mem_count_kernel(bool uncovered, const in
                                                         int* __restrict__ totals, int* __restrict__ totals2) {
   MEM_BBOX_BEGIN
   int local = 0, local2 = 0;
-  for (int c = ca; c < cb; ++c) {
-    MEM_CELL_COORDS(c)
+  MEM_FOR_CELLS {
+    MEM_CELL_COORDS
     int v = 0;
     if (own_is_fluid(own[cell])) {
       int fl = 0;
 #pragma unroll
       for (int q = 1; q < Q; ++q) {
-        const int ni = wrapi(ci + cx(q), I.nx), nj = wrapi(cj + cy(q), I.ny), nk = wrapi(ck + cz(q), I.nz);
+        const int ni = wrap_near(ci + cx(q), I.nx), nj = wrap_near(cj + cy(q), I.ny), nk = wrap_near(ck + cz(q), I.nz);
         const int o = own[(nk * I.ny + nj) * I.nx + ni];
         if (o == p) v |= 1 << q;
         if (own_is_fluid(o)) fl |= 1 << q;
@@ -194,8 +187,8 @@ __global__ __launch_bounds__(256) void mem_fill_links_kernel(const int* __restri
                                                              int* __restrict__ rcell, int* __restrict__ rpart) {
   MEM_BBOX_BEGIN
   int local = 0, local2 = 0;
-  for (int c = ca; c < cb; ++c) {
-    MEM_CELL_COORDS(c)
+  MEM_FOR_CELLS {
+    MEM_CELL_COORDS
     const int m = slots[sidx];
     local += __popc(m & SLOT_LINKS);
     local2 += m & 1;
@@ -206,8 +199,8 @@ __global__ __launch_bounds__(256) void mem_fill_links_kernel(const int* __restri
   int pos2 = 0;
   if (rcell) pos2 = offsets2[jl * (side * nsplit) + ub] + block_excl_scan256(local2, sh, &total);
   const double R = 0.5 * P.D[p];
-  for (int c = ca; c < cb; ++c) {
-    MEM_CELL_COORDS(c)
+  MEM_FOR_CELLS {
+    MEM_CELL_COORDS
     const int m = slots[sidx];
     if (rcell && (m & 1)) {
       if (pos2 < cap2) {

@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <climits>
 
+#include "bbox.h"
 #include "common.h"
 #include "kernels.h"
 #include "psm_cell.h"
@@ -170,19 +171,6 @@ __device__ __forceinline__ void bbox_lo(const PartDev& P, int p, int (&lo)[3]) {
   for (int k = 0; k < 3; ++k) lo[k] = (int)floor(P.X[3 * p + k] - R - 2.0);
 }
 
-// Cells per axis of particle p's own bounding box (from bbox_lo): the slot
-// grid is `side` wide for the largest particle, and the cells beyond
-// ceil(D) + 6 lie more than R + 3 from the centre, outside every estimator's
-// reach.  Every stage below visits exactly the rows [U.y0, min(U.y1, e)) of
-// slab U.z < e, e cells each, so the scanned offsets agree between stages.
-__device__ __forceinline__ int own_extent(const PartDev& P, int p, int side) {
-  return min(side, (int)ceil(P.D[p]) + 6);
-}
-__device__ __forceinline__ int unit_cells(const Unit& U, int e) {
-  const int y1 = min(U.y1, e);
-  return (U.z < e && y1 > U.y0) ? (y1 - U.y0) * e : 0;
-}
-
 __device__ __forceinline__ void centre_disp(const InstDev& I, const PartDev& P, int p, int i, int j, int k,
                                             double (&d)[3]) {
   d[0] = min_image(((double)i + 0.5) - P.X[3 * p + 0], (double)I.nx);
@@ -239,16 +227,16 @@ __global__ __launch_bounds__(256) void psm_classify_kernel(const int* __restrict
   const double R2 = __dmul_rn(R, R);
   const int n = I.eps_n;
   const double o0 = sample_off(0, n), o1 = sample_off(n - 1, n);
-  const int ext = own_extent(P, p, side);
+  const int ext = bbox_extent(P, p, side);
+  const int qs = (int)blockDim.x / ext, rs = (int)blockDim.x % ext;
   for (int ub = blockIdx.x; ub < side * nsplit; ub += gridDim.x) {
     const Unit U = unit_of(ub, side, nsplit);
     const int ncu = unit_cells(U, ext);
-    const int k = wrapi(lo[2] + U.z, I.nz);
+    const int k = wrap_near(lo[2] + U.z, I.nz);
     const double dz = min_image(((double)k + 0.5) - P.X[3 * p + 2], (double)I.nz);
     int ncut = 0;
-    for (int c = threadIdx.x; c < ncu; c += blockDim.x) {
-      const int dy = U.y0 + c / ext, dx = c % ext;
-      const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny);
+    BBOX_FOR_CELLS_STRIDED(c, (int)threadIdx.x, ncu, (int)blockDim.x, qs, rs, U.y0, ext, dy, dx) {
+      const int i = wrap_near(lo[0] + dx, I.nx), jj = wrap_near(lo[1] + dy, I.ny);
       const double dc[3] = {min_image(((double)i + 0.5) - P.X[3 * p + 0], (double)I.nx),
                             min_image(((double)jj + 0.5) - P.X[3 * p + 1], (double)I.ny), dz};
       double blo[3], bhi[3];
@@ -284,22 +272,21 @@ __global__ __launch_bounds__(256) void psm_cut_fill_kernel(const int* __restrict
   const InstDev& I = insts[P.inst[p]];
   int lo[3];
   bbox_lo(P, p, lo);
-  const int ext = own_extent(P, p, side);
+  const int ext = bbox_extent(P, p, side);
   for (int ub = blockIdx.x; ub < side * nsplit; ub += gridDim.x) {
     const Unit U = unit_of(ub, side, nsplit);
     const int ncu = unit_cells(U, ext);
     const int chunk = (ncu + 255) / 256;
     const int a = min(ncu, (int)threadIdx.x * chunk), b = min(ncu, a + chunk);
     int local = 0;
-    for (int c = a; c < b; ++c) local += slots[slot_index(j, side, U.z, U.y0 + c / ext, c % ext)] < 0 ? 1 : 0;
+    BBOX_FOR_CELLS(c, a, b, U.y0, ext, dy, dx) local += slots[slot_index(j, side, U.z, dy, dx)] < 0 ? 1 : 0;
     int total;
     int pos = offsets[j * (side * nsplit) + ub] + block_excl_scan256(local, sh, &total);
-    for (int c = a; c < b; ++c) {
-      const int dy = U.y0 + c / ext, dx = c % ext;
+    BBOX_FOR_CELLS(c, a, b, U.y0, ext, dy, dx) {
       const long long si = slot_index(j, side, U.z, dy, dx);
       if (slots[si] >= 0) continue;
       if (pos < cap) {
-        const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny), k = wrapi(lo[2] + U.z, I.nz);
+        const int i = wrap_near(lo[0] + dx, I.nx), jj = wrap_near(lo[1] + dy, I.ny), k = wrap_near(lo[2] + U.z, I.nz);
         double dc[3];
         centre_disp(I, P, p, i, jj, k, dc);
         cuts.slot[pos] = si;
@@ -371,13 +358,14 @@ __global__ __launch_bounds__(256) void psm_unit_totals_kernel(const int* __restr
                                                               int* __restrict__ totals) {
   __shared__ int sh[256];
   const int j = blockIdx.y;
-  const int ext = own_extent(P, list[j], side);
+  const int ext = bbox_extent(P, list[j], side);
+  const int qs = (int)blockDim.x / ext, rs = (int)blockDim.x % ext;
   for (int ub = blockIdx.x; ub < side * nsplit; ub += gridDim.x) {
     const Unit U = unit_of(ub, side, nsplit);
     const int ncu = unit_cells(U, ext);
     int local = 0;
-    for (int c = threadIdx.x; c < ncu; c += blockDim.x)
-      local += slots[slot_index(j, side, U.z, U.y0 + c / ext, c % ext)] > 0 ? 1 : 0;
+    BBOX_FOR_CELLS_STRIDED(c, (int)threadIdx.x, ncu, (int)blockDim.x, qs, rs, U.y0, ext, dy, dx)
+      local += slots[slot_index(j, side, U.z, dy, dx)] > 0 ? 1 : 0;
     int total;
     block_excl_scan256(local, sh, &total);
     if (threadIdx.x == 0) totals[j * (side * nsplit) + ub] = total;
@@ -498,22 +486,21 @@ __global__ __launch_bounds__(256) void psm_fill_kernel(const int* __restrict__ l
   const int n = I.eps_n;
   const double nn = (double)n * (double)n * (double)n;
   const double t = I.tau - 0.5;
-  const int ext = own_extent(P, p, side);
+  const int ext = bbox_extent(P, p, side);
   for (int ub = blockIdx.x; ub < side * nsplit; ub += gridDim.x) {
     const Unit U = unit_of(ub, side, nsplit);
     const int ncu = unit_cells(U, ext);
     const int chunk = (ncu + 255) / 256;
     const int a = min(ncu, (int)threadIdx.x * chunk), b = min(ncu, a + chunk);
     int local = 0;
-    for (int c = a; c < b; ++c) local += slots[slot_index(j, side, U.z, U.y0 + c / ext, c % ext)] > 0 ? 1 : 0;
+    BBOX_FOR_CELLS(c, a, b, U.y0, ext, dy, dx) local += slots[slot_index(j, side, U.z, dy, dx)] > 0 ? 1 : 0;
     int total;
     int pos = offsets[j * (side * nsplit) + ub] + block_excl_scan256(local, sh, &total);
-    for (int c = a; c < b; ++c) {
-      const int dy = U.y0 + c / ext, dx = c % ext;
+    BBOX_FOR_CELLS(c, a, b, U.y0, ext, dy, dx) {
       const int v = slots[slot_index(j, side, U.z, dy, dx)];
       if (v <= 0) continue;
       if (pos < cap) {
-        const int i = wrapi(lo[0] + dx, I.nx), jj = wrapi(lo[1] + dy, I.ny), k = wrapi(lo[2] + U.z, I.nz);
+        const int i = wrap_near(lo[0] + dx, I.nx), jj = wrap_near(lo[1] + dy, I.ny), k = wrap_near(lo[2] + U.z, I.nz);
         const double eps = (double)v / nn;
         pairs.cell[pos] = (k * I.ny + jj) * I.nx + i;
         pairs.p[pos] = p;
