@@ -52,7 +52,7 @@ struct Layout {
   int box_total = 0;  // ptotal * side * side: work units at the finest split
   long long chunk = 0;
   // byte offsets
-  size_t o_bufA, o_bufB, o_owner, o_cellmap, o_inst, o_parts, o_plists, o_slots, o_totals, o_offsets, o_totals2, o_offsets2, o_ranges, o_red, o_stage,
+  size_t o_bufA, o_bufB, o_owner, o_cellmap, o_inst, o_parts, o_plists, o_slots, o_totals, o_offsets, o_totals2, o_offsets2, o_ranges, o_red, o_redm, o_stage,
       o_counts, o_links, o_wallv, o_pairs, o_refill, o_scratch, o_tiles, o_cuts, o_cutx, o_mlp, o_judge, total;
   int ntiles = 0;
   int max_tile_cells = 0;
@@ -203,7 +203,9 @@ Layout make_layout(int n, const lbmps_config* cfgs) {
   L.o_totals2 = take((size_t)L.box_total * 4);
   L.o_offsets2 = take((size_t)L.box_total * 4);
   L.o_ranges = take((size_t)L.ptotal * 8 * 4);
-  L.o_red = take((size_t)L.ptotal * std::max(L.red_blocks, L.link_blocks) * 6 * 8);
+  L.o_red = take((size_t)L.ptotal * L.red_blocks * 6 * 8);
+  // MEM link sums of every sweep of a rigid-body step, added up after its last
+  L.o_redm = take((size_t)L.ptotal * L.link_blocks * 6 * 8 * std::max(1, L.mem_nsub));
   L.o_counts = take(16 * 4);
   L.o_links = take((size_t)(L.link_cap + L.wall_cap) * (5 * 4 + 8) + 2 * ALIGN);
   L.o_wallv = take((size_t)n * 16 * 3 * 8);
@@ -254,7 +256,8 @@ struct lbmps_ctx {
   int* offsets = nullptr;
   int* totals2 = nullptr;  // second per-unit count (refill cells of the MEM remap)
   int* offsets2 = nullptr;
-  double* red_partial = nullptr;  // per-chunk force/torque sums
+  double* red_partial = nullptr;  // per-chunk force/torque sums (PSM overlap records)
+  double* red_mem = nullptr;      // per-chunk MEM link sums, one set per sweep of a rigid-body step
   int *lbeg = nullptr, *lend = nullptr, *pbeg = nullptr, *pend = nullptr, *rbeg = nullptr, *rend = nullptr,
       *cbeg = nullptr, *cend = nullptr;
   int* counts = nullptr;  // [0] links, [1] pairs, [2] refill, [4] error bits (unsigned)
@@ -577,6 +580,7 @@ lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* ws, s
   }
   c->counts = (int*)(w + L.o_counts);
   c->red_partial = (double*)(w + L.o_red);
+  c->red_mem = (double*)(w + L.o_redm);
   {
     const size_t nl = (size_t)L.link_cap + L.wall_cap;
     char* b = w + L.o_links;
@@ -972,8 +976,12 @@ static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
                                      src, dst, c->st));
     }
     if (c->n_mem || c->n_wall) {
+      // the link sums of the sweeps of a rigid-body step wait in their own sets
+      // and are added up (in sweep order) after the last one
+      const int nsets = c->n_mem ? L.mem_nsub : 1;
+      const int set = c->n_mem ? (int)(c->sweeps % L.mem_nsub) : 0;
       HIPCHK(c, launch_links_bc(L.prec, c->n_wall, mem_list(c), c->n_mem, c->lbeg, c->lend, L.link_blocks, c->links,
-                                c->wall_v, c->inst_d, c->parts, dst, c->red_partial,
+                                c->wall_v, c->inst_d, c->parts, dst, c->red_mem, set, nsets,
                                 mem_rb ? c->inst_d : nullptr, err, c->st));
     }
     c->cur = 1 - c->cur;

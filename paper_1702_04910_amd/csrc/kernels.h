@@ -74,11 +74,12 @@ hipError_t launch_reduce(const int* list, int nlist, const int* begin, const int
                          long long ostride, PartDev parts, int nchunk_blocks, double* partial,
                          const InstDev* rigid_insts, unsigned* err, hipStream_t st);
 // Adds the min(ceil((end[j] - begin[j]) / chunk), width) chunk sums of list position j (rows of partial are
-// width wide) in a fixed order to Facc/Tacc of particle list[j]; with rigid_insts != nullptr each particle's
-// explicit Euler rigid-body step (averaging Facc over n_sub sweeps) follows.
+// width wide) in a fixed order to Facc/Tacc of particle list[j], for each of nsets sets (set s at
+// partial + s * set_stride doubles), set after set; with rigid_insts != nullptr each particle's explicit Euler
+// rigid-body step (averaging Facc over n_sub sweeps) follows.
 hipError_t launch_finish_sums(const int* list, int nlist, const int* begin, const int* end, int chunk, int width,
-                              const double* partial, PartDev parts, const InstDev* rigid_insts, unsigned* err,
-                              hipStream_t st);
+                              const double* partial, int nsets, long long set_stride, PartDev parts,
+                              const InstDev* rigid_insts, unsigned* err, hipStream_t st);
 
 // ---- mem.hip
 hipError_t launch_mem_unmap(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,
@@ -97,11 +98,13 @@ hipError_t launch_mem_fill_links(const int* list, int nlist, int side, int nspli
 hipError_t launch_mem_refill(int prec, const int* count, int cap, const int* rcell, const int* rpart,
                              const InstDev* insts, PartDev parts, const int* owner, void* buf, hipStream_t st);
 // Link rules of the wall links [0, n_wall) and of the particle links [n_wall + lbeg[j], n_wall + lend[j]) of
-// list[j], with each particle's link force and torque summed into Facc/Tacc (width workgroups per particle;
-// partial as for launch_reduce with nchunk_blocks = width) and, with rigid_insts != nullptr, its rigid-body step.
+// list[j].  Each particle's link force and torque chunk sums go to set `set` of partial (width workgroups per
+// particle, nlist * width * 6 doubles per set); after set nsets - 1 (the last sweep of a rigid-body step) the
+// sums of all nsets sets are added to Facc/Tacc and, with rigid_insts != nullptr, the rigid-body step follows.
 hipError_t launch_links_bc(int prec, int n_wall, const int* list, int nlist, const int* lbeg, const int* lend,
                            int width, LinkDev links, const double* wall_v, const InstDev* insts, PartDev parts,
-                           void* buf, double* partial, const InstDev* rigid_insts, unsigned* err, hipStream_t st);
+                           void* buf, double* partial, int set, int nsets, const InstDev* rigid_insts, unsigned* err,
+                           hipStream_t st);
 
 // ---- psm.hip
 hipError_t launch_psm_classify(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,

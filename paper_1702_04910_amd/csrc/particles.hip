@@ -149,16 +149,19 @@ __global__ __launch_bounds__(SUM_THREADS) void reduce_kernel(const int* __restri
 }
 
 // One wave per particle: the min(ceil(n / chunk), width) chunk sums of list
-// position j (n = end[j] - begin[j] records): lane l loads chunks l, l + 64, ...
-// (all loads of a lane in flight together) and adds them in that order, then a
-// butterfly over the 64 lanes forms the total.  The order depends only on the
-// chunk count.  The total goes to Facc/Tacc; with insts != nullptr the
+// position j (n = end[j] - begin[j] records) in each of nsets sets (set s at
+// partial + s * set_stride; the MEM link sums of the n_sub sweeps of one
+// rigid-body step): lane l loads chunks l, l + 64, ... (all loads of a lane in
+// flight together) and adds them in that order, then a butterfly over the 64
+// lanes forms the set's total, which is added to Facc/Tacc, set after set.
+// The order depends only on the chunk count.  With insts != nullptr the
 // rigid-body step follows.
 constexpr int FIN_WAVES = 4;
 __global__ __launch_bounds__(64 * FIN_WAVES) void finish_sums_kernel(const int* __restrict__ list, int nlist,
                                                                      const int* __restrict__ begin,
                                                                      const int* __restrict__ end, int chunk,
                                                                      int width, const double* __restrict__ partial,
+                                                                     int nsets, long long set_stride,
                                                                      PartDev parts, const InstDev* __restrict__ insts,
                                                                      unsigned* err) {
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -167,31 +170,31 @@ __global__ __launch_bounds__(64 * FIN_WAVES) void finish_sums_kernel(const int* 
   const int p = list[j];  // requested with the record range, used after the sums
   const int n = end[j] - begin[j];
   const int parts_n = min((n + chunk - 1) / chunk, width);
-  double tot[6] = {0, 0, 0, 0, 0, 0};
-  for (int i = lane; i < parts_n; i += 64) {
-    const double* src = partial + ((long long)j * width + i) * 6;
+  for (int s = 0; s < nsets; ++s) {
+    double tot[6] = {0, 0, 0, 0, 0, 0};
+    for (int i = lane; i < parts_n; i += 64) {
+      const double* src = partial + s * set_stride + ((long long)j * width + i) * 6;
 #pragma unroll
-    for (int k = 0; k < 6; ++k) tot[k] += src[k];
-  }
+      for (int k = 0; k < 6; ++k) tot[k] += src[k];
+    }
 #pragma unroll
-  for (int k = 0; k < 6; ++k)
-    for (int m = 32; m >= 1; m >>= 1) tot[k] += __shfl_xor(tot[k], m, 64);
-  if (lane == 0) {
-    if (parts_n > 0)
+    for (int k = 0; k < 6; ++k)
+      for (int m = 32; m >= 1; m >>= 1) tot[k] += __shfl_xor(tot[k], m, 64);
+    if (lane == 0 && parts_n > 0)
       for (int k = 0; k < 3; ++k) {
         parts.Facc[3 * p + k] += tot[k];
         parts.Tacc[3 * p + k] += tot[3 + k];
       }
-    if (insts) rigid_update(p, insts, parts, err);
   }
+  if (lane == 0 && insts) rigid_update(p, insts, parts, err);
 }
 
 hipError_t launch_finish_sums(const int* list, int nlist, const int* begin, const int* end, int chunk, int width,
-                              const double* partial, PartDev parts, const InstDev* rigid_insts, unsigned* err,
-                              hipStream_t st) {
+                              const double* partial, int nsets, long long set_stride, PartDev parts,
+                              const InstDev* rigid_insts, unsigned* err, hipStream_t st) {
   if (nlist <= 0) return hipSuccess;
   hipLaunchKernelGGL(finish_sums_kernel, dim3((nlist + FIN_WAVES - 1) / FIN_WAVES), dim3(64 * FIN_WAVES), 0, st, list,
-                     nlist, begin, end, chunk, width, partial, parts, rigid_insts, err);
+                     nlist, begin, end, chunk, width, partial, nsets, set_stride, parts, rigid_insts, err);
   return hipGetLastError();
 }
 
@@ -203,7 +206,8 @@ hipError_t launch_reduce(const int* list, int nlist, const int* begin, const int
                      ostride, partial);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_finish_sums(list, nlist, begin, end, RED_CHUNK, nchunk_blocks, partial, parts, rigid_insts, err, st);
+  return launch_finish_sums(list, nlist, begin, end, RED_CHUNK, nchunk_blocks, partial, 1, 0, parts, rigid_insts, err,
+                            st);
 }
 
 }  // namespace lbm
