@@ -281,12 +281,13 @@ struct lbmps_ctx {
   double* scratch = nullptr;
   long long sweeps = 0;
   bool have_psm = false, have_links_inst = false;
-  // MEM remap overlapped with the next sweep: the remap runs on `side`
-  // (forked after the rigid-body step, joined before the link rules of that
-  // sweep, which then re-sweeps the refilled cells)
+  // MEM remap or PSM list rebuild overlapped with the next sweep: it runs on
+  // `side` (forked after the rigid-body step, joined right after that sweep;
+  // a MEM remap is followed by a re-sweep of its refilled cells)
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   bool join_pending = false;
+  bool join_resweep = false;  // the forked work was a MEM remap: re-sweep its refilled cells
   // captured step graph (one period of sweeps), invalidated when lists change
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -430,34 +431,34 @@ __global__ void fill_int_kernel(int* a, long long n, int v);
 // classify bounding-box cells, evaluate the cut ones (supersampling, or the
 // network inside its radius range), count per work unit, scan, fill, and link
 // the pairs of shared cells.  Kernel launches only (graph capturable).
-lbmps_status rebuild_psm(lbmps_ctx* c) {
+lbmps_status rebuild_psm(lbmps_ctx* c, hipStream_t st) {
   const Layout& L = c->L;
   if (c->n_psm == 0) return LBMPS_OK;
   unsigned* err = err_word(c);
   const int ns = nsplit_for(c->n_psm, L.side);
   const int units = L.side * ns;
-  HIPCHK(c, launch_psm_cellmap(0, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap, c->st));
-  HIPCHK(c, launch_psm_classify(psm_list(c), c->n_psm, L.side, ns, c->inst_d, c->parts, c->slots, c->totals, c->st));
+  HIPCHK(c, launch_psm_cellmap(0, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap, st));
+  HIPCHK(c, launch_psm_classify(psm_list(c), c->n_psm, L.side, ns, c->inst_d, c->parts, c->slots, c->totals, st));
   HIPCHK(c, launch_scan(c->totals, c->offsets, c->n_psm * units, units, c->n_psm, c->cbeg, c->cend, c->cuts.count,
-                        L.cut_cap, err, ERR_CUT_CAP, c->st));
+                        L.cut_cap, err, ERR_CUT_CAP, st));
   HIPCHK(c, launch_psm_cut_fill(psm_list(c), c->n_psm, L.side, ns, c->inst_d, c->parts, c->slots, c->offsets,
-                                c->cuts, L.cut_cap, c->st));
+                                c->cuts, L.cut_cap, st));
   const double rmin = c->mlp_set ? c->mlp_rmin : 0.0, rmax = c->mlp_set ? c->mlp_rmax : -1.0;
   if (L.learned && c->mlp_set) {
     float* y = c->cut_x + (size_t)L.cut_cap * 8;
-    HIPCHK(c, launch_psm_cut_features(c->inst_d, c->parts, c->cuts, L.cut_cap, rmin, rmax, c->cut_x, c->st));
-    HIPCHK(c, launch_mlp_infer_count(c->mlp_p, c->cut_x, c->cuts.count, L.cut_cap, y, c->st));
-    HIPCHK(c, launch_psm_cut_scatter(c->inst_d, c->parts, c->cuts, L.cut_cap, y, c->slots, c->st));
+    HIPCHK(c, launch_psm_cut_features(c->inst_d, c->parts, c->cuts, L.cut_cap, rmin, rmax, c->cut_x, st));
+    HIPCHK(c, launch_mlp_infer_count(c->mlp_p, c->cut_x, c->cuts.count, L.cut_cap, y, st));
+    HIPCHK(c, launch_psm_cut_scatter(c->inst_d, c->parts, c->cuts, L.cut_cap, y, c->slots, st));
   }
   if (c->psm_exact)
-    HIPCHK(c, launch_psm_cut_exact(c->inst_d, c->parts, c->slots, c->cuts, L.cut_cap, rmin, rmax, c->st));
-  HIPCHK(c, launch_psm_unit_totals(psm_list(c), c->n_psm, L.side, ns, c->parts, c->slots, c->totals, c->st));
+    HIPCHK(c, launch_psm_cut_exact(c->inst_d, c->parts, c->slots, c->cuts, L.cut_cap, rmin, rmax, st));
+  HIPCHK(c, launch_psm_unit_totals(psm_list(c), c->n_psm, L.side, ns, c->parts, c->slots, c->totals, st));
   HIPCHK(c, launch_scan(c->totals, c->offsets, c->n_psm * units, units, c->n_psm, c->pbeg, c->pend, c->counts + 1,
-                        L.pair_cap, err, ERR_PAIR_CAP, c->st));
+                        L.pair_cap, err, ERR_PAIR_CAP, st));
   HIPCHK(c, launch_psm_fill(psm_list(c), c->n_psm, L.side, ns, c->inst_d, c->parts, c->slots, c->offsets, L.pair_cap,
-                            c->pairs, c->st));
-  HIPCHK(c, launch_psm_cellmap(1, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap, c->st));
-  HIPCHK(c, launch_psm_cellmap(2, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap, c->st));
+                            c->pairs, st));
+  HIPCHK(c, launch_psm_cellmap(1, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap, st));
+  HIPCHK(c, launch_psm_cellmap(2, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap, st));
   return LBMPS_OK;
 }
 
@@ -877,7 +878,7 @@ lbmps_status lbmps_set_particles(lbmps_ctx* c, int32_t inst, int32_t n, const lb
     s = rebuild_mem(c, false, c->st);
     if (s) return s;
   } else if (cf.coupling == LBMPS_PSM) {
-    s = rebuild_psm(c);
+    s = rebuild_psm(c, c->st);
     if (s) return s;
   }
   return check_device_errors(c);
@@ -961,6 +962,13 @@ static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
     // the reduction that completes a rigid-body step also takes it
     const bool psm_rb = c->n_psm && ((c->sweeps + 1) % L.psm_nsub) == 0;
     const bool mem_rb = c->n_mem && ((c->sweeps + 1) % L.mem_nsub) == 0;
+    if (c->join_pending) {  // the work forked after the previous rigid-body step
+      HIPCHK(c, hipStreamWaitEvent(c->st, c->join_ev, 0));
+      c->join_pending = false;
+      if (c->join_resweep)  // a MEM remap has refilled cells of src since the sweep read them
+        HIPCHK(c, launch_resweep_cells(L.prec, c->counts + 2, L.refill_cap, c->rcell, c->rpart, c->inst_d, c->parts,
+                                       src, dst, c->st));
+    }
     if (c->n_psm) {
       if (pm != PSM_STAGED)  // after the sweep: every overlapped cell, or (inline mode) the shared ones
         HIPCHK(c, launch_psm_collide(L.prec, L.psm_m, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs,
@@ -968,12 +976,6 @@ static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
       HIPCHK(c, launch_reduce(psm_list(c), c->n_psm, c->pbeg, c->pend, 0, c->pairs.out, c->pairs.ostride, c->parts,
                               L.red_blocks, c->red_partial, psm_rb ? c->inst_d : nullptr, err,
                               c->st));
-    }
-    if (c->join_pending) {  // the remap forked after the previous rigid-body step has refilled src
-      HIPCHK(c, hipStreamWaitEvent(c->st, c->join_ev, 0));
-      c->join_pending = false;
-      HIPCHK(c, launch_resweep_cells(L.prec, c->counts + 2, L.refill_cap, c->rcell, c->rpart, c->inst_d, c->parts,
-                                     src, dst, c->st));
     }
     if (c->n_mem || c->n_wall) {
       // the link sums of the sweeps of a rigid-body step wait in their own sets
@@ -986,23 +988,38 @@ static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
     }
     c->cur = 1 - c->cur;
     c->sweeps++;
+    // A rebuild or remap with another sweep to come in this call runs on the
+    // side stream beside that sweep when the sweep does not depend on it (the
+    // stream is not being captured, and MEM and PSM particles, whose list
+    // stages share work arrays, are not mixed).
+    const bool can_fork = s + 1 < n && (c->n_mem == 0 || c->n_psm == 0) && !stream_capturing(c->st);
     if (psm_rb && c->psm_moving) {
-      lbmps_status r = rebuild_psm(c);
-      if (r) return r;
+      // only a sweep that leaves the overlapped cells to the overlap kernel
+      // afterwards ignores the lists (no cell map, no staged values)
+      if (can_fork && c->psm_mode == PSM_SEPARATE && ensure_side_stream(c)) {
+        HIPCHK(c, hipEventRecord(c->fork_ev, c->st));
+        HIPCHK(c, hipStreamWaitEvent(c->side, c->fork_ev, 0));
+        lbmps_status r = rebuild_psm(c, c->side);
+        HIPCHK(c, hipEventRecord(c->join_ev, c->side));
+        c->join_pending = true;
+        c->join_resweep = false;
+        if (r) return r;
+      } else {
+        lbmps_status r = rebuild_psm(c, c->st);
+        if (r) return r;
+      }
     }
     if (mem_rb && c->mem_moving) {
-      // With another sweep to come in this call (and no PSM particles, whose
-      // list building shares the work arrays), the remap runs on the side
-      // stream while that sweep runs: the sweep's results depend on the
-      // uncovered cells only through what those cells push, which the
-      // re-sweep after the join recomputes from the refilled values.
-      const bool overlap = s + 1 < n && c->n_psm == 0 && !stream_capturing(c->st) && ensure_side_stream(c);
-      if (overlap) {
+      // the sweep's results depend on the uncovered cells only through what
+      // those cells push, which the re-sweep after the join recomputes from
+      // the refilled values
+      if (can_fork && ensure_side_stream(c)) {
         HIPCHK(c, hipEventRecord(c->fork_ev, c->st));
         HIPCHK(c, hipStreamWaitEvent(c->side, c->fork_ev, 0));
         lbmps_status r = remap_mem(c, c->side);
         HIPCHK(c, hipEventRecord(c->join_ev, c->side));
         c->join_pending = true;
+        c->join_resweep = true;
         if (r) return r;
       } else {
         lbmps_status r = remap_mem(c, c->st);
@@ -1237,14 +1254,14 @@ lbmps_status lbmps_set_eps_model(lbmps_ctx* c, const float* hp, double r_min, do
   c->mlp_rmin = r_min;
   c->mlp_rmax = r_max;
   update_psm_exact(c);
-  lbmps_status s = rebuild_psm(c);
+  lbmps_status s = rebuild_psm(c, c->st);
   if (s) return s;
   return check_device_errors(c);
 }
 
 lbmps_status lbmps_rebuild_overlaps(lbmps_ctx* c) {
   if (!c) return LBMPS_EINVAL;
-  return rebuild_psm(c);
+  return rebuild_psm(c, c->st);
 }
 
 lbmps_status lbmps_eps_judge(lbmps_ctx* c, int32_t stride, double out[3]) {
