@@ -56,6 +56,32 @@ def test_batched_instances_equal_solo_runs_bitwise(flags):
     batch.close()
 
 
+@pytest.mark.parametrize("coupling", ["mem_cli", "psm"])
+def test_batch_of_one_coupling_with_work_beside_the_sweep(coupling):
+    # a batch of MEM-only (PSM-only) instances runs its remaps (list rebuilds)
+    # beside the next sweep within one step call; each instance equals its
+    # solo run stepped one rigid-body step per call (in order), bit for bit
+    insts = [d for d in _small_batch() if d["coupling"] == coupling]
+    dmax = max(d["D"] for d in insts)
+    say("one-coupling batch", coupling, len(insts))
+    flags = lbmps.SWEEP_PSM_SEPARATE if coupling == "psm" else 0
+    batch = lbmps.Sim([_cfg(d, dmax, flags=flags) for d in insts])
+    for i, d in enumerate(insts):
+        _setup(batch, i, d)
+    batch.step(40)
+    for i, d in enumerate(insts):
+        solo = lbmps.Sim(_cfg(d, dmax, flags=flags))
+        _setup(solo, 0, d)
+        for k in range(20):
+            solo.step(2)
+        assert np.array_equal(solo.get_pdfs(), batch.get_pdfs(i))
+        ps, pb = solo.particles(), batch.particles(i)
+        for k in ("F", "T", "U", "Omega", "X"):
+            assert np.array_equal(ps[k], pb[k]), k
+        solo.close()
+    batch.close()
+
+
 def test_graph_replay_equals_eager_steps():
     import torch
 
