@@ -450,8 +450,9 @@ __device__ __forceinline__ void link_rule(int i, const LinkDev& L, const double*
 // particle list[j], one link per thread in chunks of SUM_THREADS; workgroup
 // k < width takes chunks k, k + width, ... (the rest of the row is idle).
 // Each thread keeps the sum of its links' force and torque; the workgroup
-// stores their block_sum6, and finish_sums_kernel adds a particle's workgroup
-// sums in a fixed order, so the total repeats bit for bit.
+// stores their block_sum6 (in the sweep's set of `partial`), and after the
+// last sweep of the rigid-body step finish_sums_kernel adds a particle's
+// workgroup sums in a fixed order, so the total repeats bit for bit.
 // Row nlist: the wall links [0, n_wall), strided over the whole row.
 template <typename S>
 __global__ __launch_bounds__(SUM_THREADS) void links_bc_kernel(int n_wall, const int* __restrict__ list, int nlist,

@@ -3,7 +3,8 @@
 // follows the last sum of a rigid-body cycle.  Shared by the reduction kernel
 // and the MEM link kernel, which sums its own link forces per chunk: each
 // workgroup stores the sum of its chunks, and finish_sums_kernel (the next
-// launch) adds a particle's chunk sums in a fixed order.
+// launch; for the link sums, the one after the last sweep of a rigid-body
+// step) adds a particle's chunk sums in a fixed order.
 #pragma once
 
 #include "common.h"
