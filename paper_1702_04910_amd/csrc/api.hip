@@ -933,7 +933,11 @@ static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
   for (int s = 0; s < n; ++s) {
     void* src = c->buf[c->cur];
     void* dst = c->buf[1 - c->cur];
-    const int pm = c->n_psm ? c->psm_mode : PSM_SEPARATE;
+    // a sweep beside which the PSM lists are being rebuilt reads none of them:
+    // it leaves every overlapped cell to the overlap kernel after the join
+    // (all modes give the same bits)
+    const bool lists_pending = c->join_pending && !c->join_resweep;
+    const int pm = c->n_psm && !lists_pending ? c->psm_mode : PSM_SEPARATE;
     if (pm == PSM_STAGED)  // overlapped cells first, from the same pre-collision values
       HIPCHK(c, launch_psm_collide(L.prec, L.psm_m, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs,
                                    c->cellmap, src, dst, c->stage, L.pair_cap, false, c->st));
@@ -994,9 +998,8 @@ static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
     // stages share work arrays, are not mixed).
     const bool can_fork = s + 1 < n && (c->n_mem == 0 || c->n_psm == 0) && !stream_capturing(c->st);
     if (psm_rb && c->psm_moving) {
-      // only a sweep that leaves the overlapped cells to the overlap kernel
-      // afterwards ignores the lists (no cell map, no staged values)
-      if (can_fork && c->psm_mode == PSM_SEPARATE && ensure_side_stream(c)) {
+      // the next sweep then runs in the separate mode whatever psm_mode says
+      if (can_fork && ensure_side_stream(c)) {
         HIPCHK(c, hipEventRecord(c->fork_ev, c->st));
         HIPCHK(c, hipStreamWaitEvent(c->side, c->fork_ev, 0));
         lbmps_status r = rebuild_psm(c, c->side);

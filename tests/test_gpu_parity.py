@@ -128,18 +128,21 @@ def test_moving_mem_sphere_with_refill(coupling):
 
 
 @pytest.mark.parametrize("coupling,precision", [("mem_cli", "fp64"), ("mem_cli", "fp32"), ("mem_cli", "fp16"),
-                                                ("mem_cli", "bf16"), ("psm", "fp64"), ("psm", "fp16")])
+                                                ("mem_cli", "bf16"), ("psm", "fp64"), ("psm", "fp16"),
+                                                ("psm_staged", "fp64"), ("psm_staged", "fp32")])
 def test_overlapped_remap_is_bitwise_identical(coupling, precision):
     # Within one step call the MEM remap (then the refilled cells are
-    # re-swept) or the PSM list rebuild (overlap kernel after the sweep) runs
-    # beside the next sweep; one rigid-body step per call runs it in order.
-    # Both give the same bits.
+    # re-swept) or the PSM list rebuild (the sweep beside it leaves every
+    # overlapped cell to the overlap kernel, also when staged values are
+    # configured) runs beside the next sweep; one rigid-body step per call
+    # runs it in order.  Both give the same bits.
     from paper_1702_04910_amd import lbmps
 
     say("overlapped remap", coupling, precision)
     parts = dict(X=[[10.3, 11.8, 12.2], [20.4, 12.6, 11.1]], U=[[0.04, -0.02, 0.03], [-0.03, 0.01, 0.02]],
                  Om=[[0.0, 0.002, 0.0], [0.001, 0.0, 0.0]], D=[7.0, 6.3], rho=[1.5, 1.3], fixed=[False, False])
-    flags = lbmps.SWEEP_PSM_SEPARATE if coupling == "psm" else 0
+    flags = {"psm": lbmps.SWEEP_PSM_SEPARATE, "psm_staged": lbmps.SWEEP_PSM_STAGED}.get(coupling, 0)
+    coupling = coupling.split("_staged")[0]
     runs = []
     for per_call in (2, 24):
         ora, sim = make_pair(30, 24, 24, 0.05, coupling=coupling, collision="trt", psm_m=3, psm_b=2,
