@@ -170,10 +170,11 @@ lbmps_status lbmps_set_particles(lbmps_ctx* ctx, int32_t inst, int32_t n, const 
 /* Advance every instance by n_steps LBM time steps (Alg. 1 / Alg. 2);
  * n_steps must be a multiple of every n_sub in the context.  Asynchronous.
  * Within one call, when the context does not mix MEM and PSM particles and
- * its stream is not being captured, the MEM remap after a rigid-body step
- * (and the PSM list rebuild when the sweep leaves the overlapped cells to the
- * overlap kernel after it) runs on a second stream of the library beside the
- * next sweep (results are bit-identical to running it in order); that stream
+ * its stream is not being captured, the MEM remap or PSM list rebuild after a
+ * rigid-body step runs on a second stream of the library beside the next
+ * sweep (that sweep then leaves the PSM cells to the overlap kernel after it,
+ * whatever sweep_flags select; results are bit-identical to running it in
+ * order); that stream
  * waits for the caller's stream and the caller's stream waits for it before
  * the call returns, so all of the call's work stays ordered on the caller's
  * stream. */
