@@ -169,9 +169,9 @@ lbmps_status lbmps_set_particles(lbmps_ctx* ctx, int32_t inst, int32_t n, const 
 
 /* Advance every instance by n_steps LBM time steps (Alg. 1 / Alg. 2);
  * n_steps must be a multiple of every n_sub in the context.  Asynchronous.
- * Within one call, when the context does not mix MEM and PSM particles and
- * its stream is not being captured, the MEM remap or PSM list rebuild after a
- * rigid-body step runs on a second stream of the library beside the next
+ * Within one call, when its stream is not being captured, the PSM list
+ * rebuild and the MEM remap after a rigid-body step run on a second stream of
+ * the library (one after the other) beside the next
  * sweep (that sweep then leaves the PSM cells to the overlap kernel after it,
  * whatever sweep_flags select; results are bit-identical to running it in
  * order); that stream

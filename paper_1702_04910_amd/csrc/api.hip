@@ -287,7 +287,8 @@ struct lbmps_ctx {
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   bool join_pending = false;
-  bool join_resweep = false;  // the forked work was a MEM remap: re-sweep its refilled cells
+  bool join_resweep = false;  // the forked work holds a MEM remap: re-sweep its refilled cells
+  bool join_lists = false;    // the forked work holds a PSM rebuild: the next sweep reads no list
   // captured step graph (one period of sweeps), invalidated when lists change
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -936,7 +937,7 @@ static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
     // a sweep beside which the PSM lists are being rebuilt reads none of them:
     // it leaves every overlapped cell to the overlap kernel after the join
     // (all modes give the same bits)
-    const bool lists_pending = c->join_pending && !c->join_resweep;
+    const bool lists_pending = c->join_pending && c->join_lists;
     const int pm = c->n_psm && !lists_pending ? c->psm_mode : PSM_SEPARATE;
     if (pm == PSM_STAGED)  // overlapped cells first, from the same pre-collision values
       HIPCHK(c, launch_psm_collide(L.prec, L.psm_m, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs,
@@ -992,42 +993,30 @@ static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
     }
     c->cur = 1 - c->cur;
     c->sweeps++;
-    // A rebuild or remap with another sweep to come in this call runs on the
-    // side stream beside that sweep when the sweep does not depend on it (the
-    // stream is not being captured, and MEM and PSM particles, whose list
-    // stages share work arrays, are not mixed).
-    const bool can_fork = s + 1 < n && (c->n_mem == 0 || c->n_psm == 0) && !stream_capturing(c->st);
-    if (psm_rb && c->psm_moving) {
-      // the next sweep then runs in the separate mode whatever psm_mode says
-      if (can_fork && ensure_side_stream(c)) {
+    // The PSM rebuild and the MEM remap after a rigid-body step, with another
+    // sweep to come in this call, run on the side stream (one after the
+    // other: their list stages share work arrays) beside that sweep: the sweep
+    // reads no PSM list (it leaves the PSM cells to the overlap kernel after
+    // the join), and its results depend on the cells a remap uncovers only
+    // through what those cells push, which the re-sweep after the join
+    // recomputes from the refilled values.
+    const bool psm_work = psm_rb && c->psm_moving, mem_work = mem_rb && c->mem_moving;
+    if (psm_work || mem_work) {
+      const bool fork = s + 1 < n && !stream_capturing(c->st) && ensure_side_stream(c);
+      hipStream_t ws = fork ? c->side : c->st;
+      if (fork) {
         HIPCHK(c, hipEventRecord(c->fork_ev, c->st));
         HIPCHK(c, hipStreamWaitEvent(c->side, c->fork_ev, 0));
-        lbmps_status r = rebuild_psm(c, c->side);
+      }
+      lbmps_status r = psm_work ? rebuild_psm(c, ws) : LBMPS_OK;
+      if (!r && mem_work) r = remap_mem(c, ws);
+      if (fork) {
         HIPCHK(c, hipEventRecord(c->join_ev, c->side));
         c->join_pending = true;
-        c->join_resweep = false;
-        if (r) return r;
-      } else {
-        lbmps_status r = rebuild_psm(c, c->st);
-        if (r) return r;
+        c->join_resweep = mem_work;
+        c->join_lists = psm_work;
       }
-    }
-    if (mem_rb && c->mem_moving) {
-      // the sweep's results depend on the uncovered cells only through what
-      // those cells push, which the re-sweep after the join recomputes from
-      // the refilled values
-      if (can_fork && ensure_side_stream(c)) {
-        HIPCHK(c, hipEventRecord(c->fork_ev, c->st));
-        HIPCHK(c, hipStreamWaitEvent(c->side, c->fork_ev, 0));
-        lbmps_status r = remap_mem(c, c->side);
-        HIPCHK(c, hipEventRecord(c->join_ev, c->side));
-        c->join_pending = true;
-        c->join_resweep = true;
-        if (r) return r;
-      } else {
-        lbmps_status r = remap_mem(c, c->st);
-        if (r) return r;
-      }
+      if (r) return r;
     }
   }
   return LBMPS_OK;
