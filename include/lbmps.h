@@ -170,14 +170,12 @@ lbmps_status lbmps_set_particles(lbmps_ctx* ctx, int32_t inst, int32_t n, const 
 /* Advance every instance by n_steps LBM time steps (Alg. 1 / Alg. 2);
  * n_steps must be a multiple of every n_sub in the context.  Asynchronous.
  * Within one call, when its stream is not being captured, the PSM list
- * rebuild and the MEM remap after a rigid-body step run on a second stream of
- * the library (one after the other) beside the next
- * sweep (that sweep then leaves the PSM cells to the overlap kernel after it,
- * whatever sweep_flags select; results are bit-identical to running it in
- * order); that stream
- * waits for the caller's stream and the caller's stream waits for it before
- * the call returns, so all of the call's work stays ordered on the caller's
- * stream. */
+ * rebuild and the MEM remap after a rigid-body step run (one after the other)
+ * on a second stream of the library beside the next sweep, which then leaves
+ * the PSM cells to the overlap kernel after it whatever sweep_flags select;
+ * results are bit-identical to running them in order.  That stream waits for
+ * the caller's stream, and the caller's stream waits for it before the call
+ * returns, so all of the call's work stays ordered on the caller's stream. */
 lbmps_status lbmps_step(lbmps_ctx* ctx, int32_t n_steps);
 
 /* Change the sweep launch shape of an existing context (workgroup size, grid:
