@@ -334,11 +334,17 @@ lbmps_status check_device_errors(lbmps_ctx* c) {
 }
 
 // Row ranges per bounding-box slab: enough work units (>= ~2048) to fill the GPU.
-int nsplit_for(int nlist, int side) {
+// Row splits per bounding-box slab so that about `target` work units exist.
+// In order, many small units keep the short remap and rebuild latency low;
+// beside a sweep (side stream) fewer, fuller workgroups take fewer of the
+// sweep's CU slots and still finish well within it.  The split does not
+// change the cell order of any list.
+int nsplit_for(int nlist, int side, int target = 2048) {
   if (nlist <= 0) return 1;
-  const int want = (2048 + nlist * side - 1) / (nlist * side);
+  const int want = (target + nlist * side - 1) / (nlist * side);
   return std::max(1, std::min(side, want));
 }
+int split_target(const lbmps_ctx* c, hipStream_t st) { return st == c->st ? 2048 : 256; }
 
 int* mem_list(lbmps_ctx* c) { return c->plist_d; }
 
@@ -396,7 +402,7 @@ lbmps_status rebuild_mem(lbmps_ctx* c, bool refill, hipStream_t st) {
   const Layout& L = c->L;
   if (c->n_mem == 0) return LBMPS_OK;
   unsigned* err = err_word(c);
-  const int ns = nsplit_for(c->n_mem, L.side);
+  const int ns = nsplit_for(c->n_mem, L.side, split_target(c, st));
   const int units = L.side * ns;
   // one pass counts links and uncovered cells, one launch scans both, one
   // pass writes both lists; the refill only reads the owner field, so it can
@@ -420,7 +426,7 @@ lbmps_status rebuild_mem(lbmps_ctx* c, bool refill, hipStream_t st) {
 }
 
 lbmps_status remap_mem(lbmps_ctx* c, hipStream_t st) {
-  const int ns = nsplit_for(c->n_mem, c->L.side);
+  const int ns = nsplit_for(c->n_mem, c->L.side, split_target(c, st));
   HIPCHK(c, launch_mem_unmap(mem_list(c), c->n_mem, c->L.side, ns, c->inst_d, c->parts, c->owner, st));
   HIPCHK(c, launch_mem_map(mem_list(c), c->n_mem, c->L.side, ns, c->inst_d, c->parts, c->owner, st));
   return rebuild_mem(c, true, st);
@@ -436,7 +442,7 @@ lbmps_status rebuild_psm(lbmps_ctx* c, hipStream_t st) {
   const Layout& L = c->L;
   if (c->n_psm == 0) return LBMPS_OK;
   unsigned* err = err_word(c);
-  const int ns = nsplit_for(c->n_psm, L.side);
+  const int ns = nsplit_for(c->n_psm, L.side, split_target(c, st));
   const int units = L.side * ns;
   HIPCHK(c, launch_psm_cellmap(0, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs, c->cellmap, st));
   HIPCHK(c, launch_psm_classify(psm_list(c), c->n_psm, L.side, ns, c->inst_d, c->parts, c->slots, c->totals, st));
