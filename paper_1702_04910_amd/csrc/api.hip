@@ -990,12 +990,10 @@ static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
     }
     if (c->n_mem || c->n_wall) {
       // the link sums of the sweeps of a rigid-body step wait in their own sets
-      // and are added up (in sweep order) after the last one
-      const int nsets = c->n_mem ? L.mem_nsub : 1;
+      // and are added up (in sweep order) after the last one, below
       const int set = c->n_mem ? (int)(c->sweeps % L.mem_nsub) : 0;
       HIPCHK(c, launch_links_bc(L.prec, c->n_wall, mem_list(c), c->n_mem, c->lbeg, c->lend, L.link_blocks, c->links,
-                                c->wall_v, c->inst_d, c->parts, dst, c->red_mem, set, nsets,
-                                mem_rb ? c->inst_d : nullptr, err, c->st));
+                                c->wall_v, c->inst_d, c->parts, dst, c->red_mem, set, c->st));
     }
     c->cur = 1 - c->cur;
     c->sweeps++;
@@ -1006,14 +1004,21 @@ static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
     // the join), and its results depend on the cells a remap uncovers only
     // through what those cells push, which the re-sweep after the join
     // recomputes from the refilled values.
+    // The MEM link sums of the rigid-body step and its rigid-body step go
+    // with the remap (the next sweep does not read particle state), so they
+    // leave the critical path too when the remap is forked.
     const bool psm_work = psm_rb && c->psm_moving, mem_work = mem_rb && c->mem_moving;
+    const bool fork = (psm_work || mem_work) && s + 1 < n && !stream_capturing(c->st) && ensure_side_stream(c);
+    hipStream_t ws = fork ? c->side : c->st;
+    if (fork) {
+      HIPCHK(c, hipEventRecord(c->fork_ev, c->st));
+      HIPCHK(c, hipStreamWaitEvent(c->side, c->fork_ev, 0));
+    }
+    if (mem_rb)
+      HIPCHK(c, launch_finish_sums(mem_list(c), c->n_mem, c->lbeg, c->lend, SUM_THREADS, L.link_blocks, c->red_mem,
+                                   L.mem_nsub, (long long)c->n_mem * L.link_blocks * 6, c->parts, c->inst_d, err,
+                                   mem_work ? ws : c->st));
     if (psm_work || mem_work) {
-      const bool fork = s + 1 < n && !stream_capturing(c->st) && ensure_side_stream(c);
-      hipStream_t ws = fork ? c->side : c->st;
-      if (fork) {
-        HIPCHK(c, hipEventRecord(c->fork_ev, c->st));
-        HIPCHK(c, hipStreamWaitEvent(c->side, c->fork_ev, 0));
-      }
       lbmps_status r = psm_work ? rebuild_psm(c, ws) : LBMPS_OK;
       if (!r && mem_work) r = remap_mem(c, ws);
       if (fork) {

@@ -99,12 +99,11 @@ hipError_t launch_mem_refill(int prec, const int* count, int cap, const int* rce
                              const InstDev* insts, PartDev parts, const int* owner, void* buf, hipStream_t st);
 // Link rules of the wall links [0, n_wall) and of the particle links [n_wall + lbeg[j], n_wall + lend[j]) of
 // list[j].  Each particle's link force and torque chunk sums go to set `set` of partial (width workgroups per
-// particle, nlist * width * 6 doubles per set); after set nsets - 1 (the last sweep of a rigid-body step) the
-// sums of all nsets sets are added to Facc/Tacc and, with rigid_insts != nullptr, the rigid-body step follows.
+// particle, nlist * width * 6 doubles per set); after the last sweep of a rigid-body step, launch_finish_sums
+// over all sets (SUM_THREADS records per chunk, set_stride nlist * width * 6) adds them to Facc/Tacc.
 hipError_t launch_links_bc(int prec, int n_wall, const int* list, int nlist, const int* lbeg, const int* lend,
                            int width, LinkDev links, const double* wall_v, const InstDev* insts, PartDev parts,
-                           void* buf, double* partial, int set, int nsets, const InstDev* rigid_insts, unsigned* err,
-                           hipStream_t st);
+                           void* buf, double* partial, int set, hipStream_t st);
 
 // ---- psm.hip
 hipError_t launch_psm_classify(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,

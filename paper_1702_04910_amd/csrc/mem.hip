@@ -489,20 +489,16 @@ __global__ __launch_bounds__(SUM_THREADS) void links_bc_kernel(int n_wall, const
 
 hipError_t launch_links_bc(int prec, int n_wall, const int* list, int nlist, const int* lbeg, const int* lend,
                            int width, LinkDev links, const double* wall_v, const InstDev* insts, PartDev parts,
-                           void* buf, double* partial, int set, int nsets, const InstDev* rigid_insts, unsigned* err,
-                           hipStream_t st) {
+                           void* buf, double* partial, int set, hipStream_t st) {
   if (nlist <= 0 && n_wall <= 0) return hipSuccess;
-  if (set < 0 || set >= nsets) return hipErrorInvalidValue;
+  if (set < 0) return hipErrorInvalidValue;
   const long long set_stride = (long long)nlist * width * 6;
   // wall links get at least enough workgroups for one link per thread, up to 512
   const int blocks = std::max(width, std::min(512, (n_wall + SUM_THREADS - 1) / SUM_THREADS));
   LBM_DISPATCH(prec, hipLaunchKernelGGL(links_bc_kernel<S>, dim3(blocks, nlist + (n_wall > 0 ? 1 : 0)),
                                         dim3(SUM_THREADS), 0, st, n_wall, list, nlist, lbeg, lend, links, wall_v,
                                         insts, parts, (S*)buf, partial + set * set_stride, width));
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || set != nsets - 1) return e;
-  return launch_finish_sums(list, nlist, lbeg, lend, SUM_THREADS, width, partial, nsets, set_stride, parts,
-                            rigid_insts, err, st);
+  return hipGetLastError();
 }
 
 }  // namespace lbm
