@@ -984,9 +984,9 @@ static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
       if (pm != PSM_STAGED)  // after the sweep: every overlapped cell, or (inline mode) the shared ones
         HIPCHK(c, launch_psm_collide(L.prec, L.psm_m, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs,
                                      c->cellmap, src, dst, nullptr, 0, pm == PSM_FUSED, c->st));
-      HIPCHK(c, launch_reduce(psm_list(c), c->n_psm, c->pbeg, c->pend, 0, c->pairs.out, c->pairs.ostride, c->parts,
-                              L.red_blocks, c->red_partial, psm_rb ? c->inst_d : nullptr, err,
-                              c->st));
+      if (!psm_rb)  // the rigid-body sweep's sum goes with the rebuild, below
+        HIPCHK(c, launch_reduce(psm_list(c), c->n_psm, c->pbeg, c->pend, 0, c->pairs.out, c->pairs.ostride,
+                                c->parts, L.red_blocks, c->red_partial, nullptr, err, c->st));
     }
     if (c->n_mem || c->n_wall) {
       // the link sums of the sweeps of a rigid-body step wait in their own sets
@@ -1004,9 +1004,10 @@ static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
     // the join), and its results depend on the cells a remap uncovers only
     // through what those cells push, which the re-sweep after the join
     // recomputes from the refilled values.
-    // The MEM link sums of the rigid-body step and its rigid-body step go
-    // with the remap (the next sweep does not read particle state), so they
-    // leave the critical path too when the remap is forked.
+    // The force sums that complete a rigid-body step, with the rigid-body
+    // step, go with the rebuild or remap (the next sweep does not read
+    // particle state), so they leave the critical path too when those are
+    // forked.
     const bool psm_work = psm_rb && c->psm_moving, mem_work = mem_rb && c->mem_moving;
     const bool fork = (psm_work || mem_work) && s + 1 < n && !stream_capturing(c->st) && ensure_side_stream(c);
     hipStream_t ws = fork ? c->side : c->st;
@@ -1014,6 +1015,9 @@ static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
       HIPCHK(c, hipEventRecord(c->fork_ev, c->st));
       HIPCHK(c, hipStreamWaitEvent(c->side, c->fork_ev, 0));
     }
+    if (psm_rb)
+      HIPCHK(c, launch_reduce(psm_list(c), c->n_psm, c->pbeg, c->pend, 0, c->pairs.out, c->pairs.ostride, c->parts,
+                              L.red_blocks, c->red_partial, c->inst_d, err, psm_work ? ws : c->st));
     if (mem_rb)
       HIPCHK(c, launch_finish_sums(mem_list(c), c->n_mem, c->lbeg, c->lend, SUM_THREADS, L.link_blocks, c->red_mem,
                                    L.mem_nsub, (long long)c->n_mem * L.link_blocks * 6, c->parts, c->inst_d, err,
