@@ -369,12 +369,16 @@ hipError_t launch_mem_refill(int prec, const int* count, int cap, const int* rce
 // velocity; particle links use BB or CLI (CLI falls back to BB where x - c_q
 // is not fluid).  For a particle link ft gets the deviation part
 // (c_q - v) g~_q + (c_q + v) g_qbar of Eq. MEM_Force and its torque about X_p.
-template <typename S>
+// ROW: the link belongs to particle p_row of instance inst_row (a particle
+// row of the link kernel, where both are the same for the whole workgroup,
+// so their fields come through scalar loads); otherwise both are read from
+// the link.
+template <typename S, bool ROW>
 __device__ __forceinline__ void link_rule(int i, const LinkDev& L, const double* __restrict__ wall_v,
                                           const InstDev* __restrict__ insts, const PartDev& P, S* __restrict__ buf,
-                                          double (&ft)[6]) {
-  const int inst = L.inst[i];
-  const int cell = L.cell[i], q = L.q[i], p = L.p[i];
+                                          int p_row, int inst_row, double (&ft)[6]) {
+  const int inst = ROW ? inst_row : L.inst[i];
+  const int cell = L.cell[i], q = L.q[i], p = ROW ? p_row : L.p[i];
   const int cli_ok = L.cli_ok[i];  // read with the other link fields, used by particle links
   const double delta_l = L.delta[i];
   // body state (particle centre, velocity, angular velocity; wall velocity),
@@ -396,10 +400,10 @@ __device__ __forceinline__ void link_rule(int i, const LinkDev& L, const double*
   const int x = cell % I.nx, yz = cell / I.nx, y = yz % I.ny, z = yz / I.ny;
   S* b = buf + I.pdf_off;
   const int c[3] = {cx(q), cy(q), cz(q)};
-  const int xs = wrapi(x + c[0], I.nx), ys = wrapi(y + c[1], I.ny), zs = wrapi(z + c[2], I.nz);
+  const int xs = wrap_near(x + c[0], I.nx), ys = wrap_near(y + c[1], I.ny), zs = wrap_near(z + c[2], I.nz);
   // the three PDFs a link may need are requested together, before the CLI
   // test, so one memory latency covers them
-  const int xm = wrapi(x - c[0], I.nx), ym = wrapi(y - c[1], I.ny), zm = wrapi(z - c[2], I.nz);
+  const int xm = wrap_near(x - c[0], I.nx), ym = wrap_near(y - c[1], I.ny), zm = wrap_near(z - c[2], I.nz);
   const double gtq = (double)Codec<S>::ld(b[pdf_at(((long long)zs * I.ny + ys) * I.nx + xs, q)]);
   const double gq_m = (double)Codec<S>::ld(b[pdf_at(cell, q)]);
   const double gqb = (double)Codec<S>::ld(b[pdf_at(((long long)zm * I.ny + ym) * I.nx + xm, qb)]);
@@ -466,18 +470,19 @@ __global__ __launch_bounds__(SUM_THREADS) void links_bc_kernel(int n_wall, const
   double ft[6];
   if (j == nlist) {
     for (int i = kb * SUM_THREADS + (int)threadIdx.x; i < n_wall; i += gridDim.x * SUM_THREADS)
-      link_rule<S>(i, L, wall_v, insts, P, buf, ft);
+      link_rule<S, false>(i, L, wall_v, insts, P, buf, 0, 0, ft);
     return;
   }
   const int nb = width;  // workgroups per particle: the rows of `partial` are this wide
   const int b = n_wall + lbeg[j], e = n_wall + lend[j];
+  const int p_row = list[j], inst_row = P.inst[p_row];
   const int nch = (e - b + SUM_THREADS - 1) / SUM_THREADS;
   if (kb >= nch || kb >= nb) return;  // no links for this workgroup; it takes no part
   double acc[6] = {0, 0, 0, 0, 0, 0};
   for (int ch = kb; ch < nch; ch += nb) {
     const int i = b + ch * SUM_THREADS + (int)threadIdx.x;
     if (i < e) {
-      link_rule<S>(i, L, wall_v, insts, P, buf, ft);
+      link_rule<S, true>(i, L, wall_v, insts, P, buf, p_row, inst_row, ft);
 #pragma unroll
       for (int k = 0; k < 6; ++k) acc[k] += ft[k];
     }
