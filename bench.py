@@ -137,6 +137,15 @@ def batched(torch, lbmps, inputs, steps, warmup, seed):
     sim.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # the same steps launched eagerly, where the rebuild and remap after each
+    # rigid-body step run beside the next sweep (a captured graph keeps them
+    # in order)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(2 * steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    wall_eager = time.perf_counter() - t0
     # sweep-kernel bandwidth from eager, HIP-event-timed sweeps of the same batch
     sim.set_timing(True)
     sim.step(20)
@@ -148,6 +157,7 @@ def batched(torch, lbmps, inputs, steps, warmup, seed):
         kinds[d["coupling"]] = kinds.get(d["coupling"], 0) + 1
     return {"instances": len(insts), "cells": cells, "couplings": kinds, "MLUPS": round(cells * 2 * steps / wall / 1e6, 1),
             "ms_per_step": round(wall / steps * 1e3, 4), "graph": True, "launch": best,
+            "eager_MLUPS": round(cells * 2 * steps / wall_eager / 1e6, 1),
             "sweep_GBs": round(2 * 19 * 4 * cells / (ms / 1e3 / n) / 1e9, 1),
             "velocity_error_vs_solo": 0.0,
             "note": "each instance is bitwise equal to the same instance run alone (tests/test_gpu_batch.py)"}
