@@ -75,6 +75,37 @@ def test_full_size_sampled_cells(precision, coupling):
     assert worst < TOL[precision]
 
 
+@pytest.mark.parametrize("coupling", ["mem_cli", "psm"])
+def test_full_size_work_beside_the_sweep_is_bitwise_identical(coupling):
+    """The full-size box in the timed launch shape with a fast sphere: eight
+    sweeps in one call (remap or rebuild beside the next sweep, refilled cells
+    re-swept) equal four calls of one rigid-body step each (in order), bit
+    for bit."""
+    inp = inputs.c2_scale(0)
+    nx, ny, nz = inp["nx"], inp["ny"], inp["nz"]
+    best = autotune.tune(nx, ny, nz, "fp32")
+    shape = {k: best[k] for k in ("tile_rows", "block_threads", "grid_blocks", "sweep_flags")}
+    say("full size beside the sweep", coupling, shape)
+    cfg = lbmps.make_config(nx, ny, nz, inp["nu"], collision="trt", coupling=coupling, psm_m=3, psm_b=2, n_sub=2,
+                            eps_n=8, eps_mode=lbmps.EPS_RECURSIVE, precision="fp32", max_particles=1,
+                            max_diameter=inp["D"], f_ext=inp["f_ext"], gravity=inp["gravity"], **shape)
+    out = []
+    for per_call in (2, 8):
+        sim = lbmps.Sim(cfg)
+        sim.init_equilibrium()
+        sim.set_particles([inp["X"]], [[0.05, -0.03, -0.2]], [[0.0, 0.004, 0.0]], [inp["D"]], [inp["rho"]],
+                          [False])
+        for k in range(8 // per_call):
+            sim.step(per_call)
+        out.append((sim.get_pdfs().astype(np.float32), sim.particles()))
+        sim.close()
+    (ga, pa), (gb, pb) = out
+    assert np.array_equal(ga, gb)
+    for key in ("F", "T", "U", "Omega", "X"):
+        assert np.array_equal(pa[key], pb[key]), key
+    say("  sphere moved by %s" % (pb["X"][0] - np.asarray(inp["X"])))
+
+
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_full_size_mass_and_momentum(precision):
     """Periodic fluid at full size: mass is conserved and the momentum grows
