@@ -82,9 +82,10 @@ def build_sim(lbmps, inp, coupling, precision, psm=(3, 2), eps_n=8, **launch):
 
 
 # HIP events bracket every TIMING_STRIDE-th sweep launch of a timed region
-# (odd, so both buffer directions are sampled); events around every launch
-# cost ~2 % of the whole-job rate on the 14 M-cell box.
-TIMING_STRIDE = 3
+# (odd, so both buffer directions are sampled): the pair of events around a
+# launch adds ~9 us of whole-job time on the 14 M-cell box (~2.5 % if every
+# launch were timed), so one launch in seven is timed (~58 of 400).
+TIMING_STRIDE = 7
 
 
 def timed_run(torch, sim, steps, warmup, n_sub, timing=True):
