@@ -28,6 +28,17 @@ lattice line to be bounded by fluid cells (particles not in contact; the
 paper defines no contact model); ``check_link_balance`` verifies the
 necessary per-direction link balance.
 
+Static wall groups carry one of two rules.  A velocity wall is bounce-back
+with the wall velocity (Eq. MEM_BB); with a wall velocity normal to the wall it
+is the velocity inflow of the settling-sphere frame (Sec. 4.1).  An outflow
+group is the pressure anti-bounce-back of that frame (Sec. 4.1, after Ginzburg):
+  f_qbar(x, t+1) = -f~_q(x, t) + 2 f^eq,+_q(rho_out, u(x, t)),
+with f^eq,+ the even part of Eq. LBM_EQ, w_q (rho + 9/2 (c_q.u)^2 - 3/2 u.u)
+(rho0 = 1 in the nonlinear terms), and u(x, t) the velocity of Eq. MacVel in
+the fluid cell x at time t (before its collision).  In deviation variables
+(w_q = w_qbar):
+  g_qbar = -g~_q + 2 w_q (rho_out - 1 + 9/2 (c_q.u)^2 - 3/2 u.u).
+
 Refill (Sec. 2.2.3, Eq. MEM_Reconstruction).  Readings (parity unpinned where
 noted):
 * normal n = (x - X_p)/|x - X_p| from the new particle position; q_n maximises
@@ -57,7 +68,7 @@ WALL = -2  # wall group k is stored as WALL - k
 SQRT1_2 = 0.7071067811865476  # 1/sqrt(2) rounded to double
 
 
-def build_links(owner, parts, radii, box_shape, v_walls):
+def build_links(owner, parts, radii, box_shape, v_walls, wall_outflow=None):
     """All links (x fluid, q) with x + c_q solid; returns a dict of arrays."""
     nz, ny, nx = box_shape
     fluid = owner == FLUID
@@ -99,14 +110,24 @@ def build_links(owner, parts, radii, box_shape, v_walls):
     L["is_particle"] = isp
     L["U"], L["Om"] = Ul, Oml
     vw = np.zeros((n, 3))
+    outflow = np.zeros(n, bool)
+    rho_out = np.ones(n)
     for k, v in enumerate(v_walls):
-        vw[L["p"] == WALL - k] = v
+        sel = L["p"] == WALL - k
+        vw[sel] = v
+        if wall_outflow is not None and wall_outflow[k] is not None:
+            outflow[sel] = True
+            rho_out[sel] = wall_outflow[k]
     L["v_wall"] = vw
+    L["outflow"] = outflow
+    L["rho_out"] = rho_out
     return L
 
 
-def link_boundary(gt, gn, L, scheme):
-    """Apply BB/CLI on every link and return per-link (F^q, T^q) and x_b - X_p."""
+def link_boundary(gt, gn, L, scheme, g=None, fext=None):
+    """Apply BB/CLI on every link (the outflow rule on outflow wall links, which
+    needs the pre-collision PDFs g and the body force for u(x, t)) and return
+    per-link (F^q, T^q)."""
     n = len(L["q"])
     if n == 0:
         return np.zeros((0, 3)), np.zeros((0, 3))
@@ -127,6 +148,14 @@ def link_boundary(gt, gn, L, scheme):
     alpha = 4.0 / (1.0 + 2.0 * delta)
     cli = gtq + k0 * gt[q, L["bz"], L["by"], L["bx"]] - k0 * gt[qb, iz, iy, ix] - 3.0 * alpha * wq * vc
     val = np.where(use_cli, cli, bb)
+    out = L["outflow"]
+    if out.any():
+        gc = g[:, iz[out], iy[out], ix[out]]  # f(x, t) of the links' fluid cells
+        u = (CF.T @ gc).T + 0.5 * np.asarray(fext, dtype=np.float64)  # Eq. MacVel, (n_out, 3)
+        cu = (c[out] * u).sum(axis=1)
+        uu = (u * u).sum(axis=1)
+        val = val.copy()
+        val[out] = -gtq[out] + 2.0 * wq[out] * ((L["rho_out"][out] - 1.0) + 4.5 * cu * cu - 1.5 * uu)
     gn[qb, iz, iy, ix] = val
     Fq = (c - v) * gtq[:, None] + (c + v) * val[:, None]
     Tq = np.cross(arm, Fq)

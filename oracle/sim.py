@@ -19,8 +19,8 @@ One call of ``step(n)`` advances n LBM time steps:
   fully covered cells and the sphere exchange an alternating momentum that
   grows by (1 + 2 rho_f/rho_p) per step, so moving M3 runs use n_sub = 2.)
 * none: collide -> stream.
-Static walls (half-way bounce-back with a wall velocity) are applied after the
-stream in every mode.
+Static walls (half-way bounce-back with a wall velocity, or the outflow rule of
+the settling-sphere frame, Sec. 4.1) are applied after the stream in every mode.
 """
 import numpy as np
 
@@ -54,6 +54,7 @@ class OracleSim:
         self.g = np.zeros((19,) + self.shape)
         self.owner = np.full(self.shape, mm.FLUID, dtype=np.int64)
         self.v_walls = []
+        self.wall_outflow = []  # per wall group: None (velocity wall) or rho_out (outflow)
         self.parts = []
         self.F = np.zeros((0, 3))
         self.T = np.zeros((0, 3))
@@ -81,6 +82,15 @@ class OracleSim:
         (half-way bounce-back, Eq. MEM_BB)."""
         self.owner[np.asarray(mask, dtype=bool)] = mm.WALL - len(self.v_walls)
         self.v_walls.append(np.asarray(v_wall, dtype=np.float64))
+        self.wall_outflow.append(None)
+        self._remap(initial=True)
+
+    def set_outflow(self, mask, rho_out=1.0):
+        """Add one group of outflow cells: the fluid cells next to them get the
+        pressure anti-bounce-back of Sec. 4.1 with density rho_out."""
+        self.owner[np.asarray(mask, dtype=bool)] = mm.WALL - len(self.v_walls)
+        self.v_walls.append(np.zeros(3))
+        self.wall_outflow.append(float(rho_out))
         self._remap(initial=True)
 
     def set_particles(self, X, U, Om, D, rho_p, fixed):
@@ -127,7 +137,8 @@ class OracleSim:
             self.overlaps = [geo.overlap_cells(self.shape, p["X"], p["D"] / 2.0, self.eps_n, self.eps_recursive,
                                               self.eps_estimator)
                              for p in self.parts]
-        self.links = mm.build_links(self.owner, self.parts, self._radii(), self.shape, self.v_walls)
+        self.links = mm.build_links(self.owner, self.parts, self._radii(), self.shape, self.v_walls,
+                                    self.wall_outflow)
         if self.coupling.startswith("mem"):
             mm.check_link_balance(self.links, len(self.parts))
 
@@ -136,7 +147,7 @@ class OracleSim:
         gt = fl.collide(self.g, self.collision, self.tau, self.magic, self.fext)
         gn = fl.stream(gt)
         scheme = "cli" if self.coupling == "mem_cli" else "bb"
-        Fq, Tq = mm.link_boundary(gt, gn, self.links, scheme)
+        Fq, Tq = mm.link_boundary(gt, gn, self.links, scheme, self.g, self.fext)
         P = len(self.parts)
         F = np.zeros((P, 3))
         T = np.zeros((P, 3))
@@ -153,7 +164,7 @@ class OracleSim:
                                                      self.magic, self.fext, self.msel, self.bsel)
         gn = fl.stream(gt)
         if len(self.links["q"]):
-            mm.link_boundary(gt, gn, self.links, "bb")
+            mm.link_boundary(gt, gn, self.links, "bb", self.g, self.fext)
         self.g = gn
         return F, T
 
@@ -161,7 +172,7 @@ class OracleSim:
         gt = fl.collide(self.g, self.collision, self.tau, self.magic, self.fext)
         gn = fl.stream(gt)
         if len(self.links["q"]):
-            mm.link_boundary(gt, gn, self.links, "bb")
+            mm.link_boundary(gt, gn, self.links, "bb", self.g, self.fext)
         self.g = gn
         self._mask_solid()
 

@@ -119,6 +119,50 @@ def test_rigid_euler_constant_force_closed_form():
     assert np.abs(Om - (Om0 + n * dt * T / inertia)).max() < 1e-16
 
 
+@pytest.mark.parametrize("coupling", ["mem_bb", "mem_cli", "psm"])
+def test_first_rigid_step_from_rest_is_reduced_gravity(coupling):
+    # A sphere released from rest in fluid at rest feels no hydrodynamic force
+    # in the first rigid-body step (f = w everywhere: no link force, and every
+    # solid operator vanishes), so the explicit Euler step gives the reduced
+    # gravity of Archimedes (Sec. 4.1): U_1 = dt (1 - rho_f/rho_p) g, X_1 = X_0;
+    # the next step moves X by dt U_1.  (A sphere weighed with rho_p instead of
+    # rho_p - rho_f, or without the fluid's buoyancy, fails.)
+    g = np.array([1e-4, -2e-4, -3e-4])
+    rho_p = 1.4
+    s = OracleSim(18, 18, 18, nu=0.05, collision="trt", coupling=coupling, psm_m=3, psm_b=2, gravity=g, n_sub=2,
+                  eps_n=4)
+    s.init_equilibrium()
+    X0 = np.array([9.3, 8.8, 9.1])
+    s.set_particles([X0], [[0, 0, 0]], [[0, 0, 0]], [6.0], [rho_p], [False])
+    s.step(2)
+    P = s.particles()
+    assert np.abs(P["F"]).max() == 0.0
+    U1 = 2.0 * (1.0 - 1.0 / rho_p) * g
+    assert np.abs(P["U"][0] - U1).max() < 1e-19
+    assert np.array_equal(P["X"][0], X0)
+    s.step(2)
+    assert np.abs(s.particles()["X"][0] - (X0 + 2.0 * U1)).max() < 1e-15
+
+
+def test_first_psm_step_from_rest_includes_body_force_buoyancy():
+    # PSM with one sweep per rigid-body step: the solid operators read the
+    # pre-collision PDFs, which are at rest in the first sweep, so the first
+    # step's hydrodynamic force is zero and U_1 = [(rho_p - 1) V g + V f_ext]/m:
+    # the fluid body force acts on the sphere's volume as on the fluid it
+    # displaces (the buoyancy of Sec. 3's F_b); without it, U_1 = (1 - 1/rho_p) g.
+    g = np.array([0.0, 0.0, -3e-4])
+    f = np.array([2e-5, 0.0, 1e-4])
+    rho_p = 1.25
+    s = OracleSim(18, 18, 18, nu=0.05, collision="bgk", coupling="psm", psm_m=2, psm_b=2, gravity=g, fext=f,
+                  n_sub=1, eps_n=4)
+    s.init_equilibrium()
+    s.set_particles([[9.3, 8.8, 9.1]], [[0, 0, 0]], [[0, 0, 0]], [6.0], [rho_p], [False])
+    s.step(1)
+    P = s.particles()
+    assert np.abs(P["F"]).max() == 0.0
+    assert np.abs(P["U"][0] - ((1.0 - 1.0 / rho_p) * g + f / rho_p)).max() < 1e-19
+
+
 # --------------------------------------------------------------------------- MEM
 def _mem_sim(scheme, nu=0.05, fext=(1e-5, 0, 0), n_sub=2, X=(8.3, 7.9, 8.2), U=(0, 0, 0), D=7.0):
     s = OracleSim(16, 16, 16, nu=nu, collision="trt", coupling=scheme, fext=fext, n_sub=n_sub)
@@ -262,6 +306,41 @@ def test_solid_operator_mass_and_closed_form_force(m, k):
     assert np.abs(om.sum(0)).max() < 1e-15
     mom = -(CF.T @ om)  # sum_q Omega_q c_qbar
     assert np.abs(mom - k * (U - vs)).max() < 1e-15
+
+
+def test_m2_with_solid_at_fluid_velocity_is_bgk():
+    # Eq. PSM_M2 with v_s = U: the bracket (1 - 1/tau)[f - f^eq(rho, U)] and
+    # f^eq(rho, v_s) - f combine to (f^eq - f)/tau, the BGK operator of
+    # Eq. LBM_SRT (a wrong coefficient on the bracket, e.g. 1 - tau or 1/tau,
+    # gives another multiple of f^eq - f)
+    n = 30
+    g = 1e-2 * RNG.standard_normal((Q, n))
+    rho, U = fl.moments(g)
+    for tau in (0.6, 0.8, 1.7):
+        om = ps.solid_operator(g, rho, U, U, tau, 2)
+        assert np.abs(om - (fl.geq(rho, U) - g) / tau).max() < 1e-17
+
+
+@pytest.mark.parametrize("coll", ["bgk", "trt"])
+def test_fully_covered_m2b2_cell_relaxes_as_bgk(coll):
+    # Through the whole PSM step: a cell inside the sphere has eps_s = 1, so
+    # B2 = 1 (Eq. PSM_B2) and Eq. LBM_Collide_PSM keeps only the solid term;
+    # with the particle moving at that cell's fluid velocity, M2 is BGK there
+    # (without the forcing, which is weighted by 1 - B = 0), whatever the fluid
+    # operator.  Pins B2 at eps = 1, the (1 - B) weights and M2's coefficient.
+    s = OracleSim(16, 16, 16, nu=0.1, collision=coll, coupling="psm", psm_m=2, psm_b=2, fext=(1e-5, 2e-5, 0),
+                  eps_n=4)
+    g0 = 1e-3 * RNG.standard_normal((Q, 16, 16, 16))
+    rho, U = fl.moments(g0)
+    cell = (8, 8, 8)  # (z, y, x): centre (8.5, 8.5, 8.5), 0.43 from the sphere centre
+    s.set_particles([[8.3, 7.9, 8.2]], [U[:, 8, 8, 8]], [[0, 0, 0]], [7.0], [1.5], [True])
+    iz, iy, ix, eps = s.overlaps[0]
+    k = np.nonzero((iz == 8) & (iy == 8) & (ix == 8))[0]
+    assert len(k) == 1 and eps[k[0]] == 1.0
+    gt, F, T, B, vB = ps.psm_collide(g0, s.overlaps, s.parts, coll, s.tau, s.magic, s.fext, 2, 2)
+    assert B[cell] == 1.0
+    expect = g0[:, 8, 8, 8] + (fl.geq(rho, U)[:, 8, 8, 8] - g0[:, 8, 8, 8]) / s.tau
+    assert np.abs(gt[:, 8, 8, 8] - expect).max() < 1e-17
 
 
 @pytest.mark.parametrize("m,b", [(1, 1), (2, 2), (3, 2)])
