@@ -159,6 +159,31 @@ lbmps_status lbmps_init_equilibrium(lbmps_ctx* ctx, int32_t inst, double rho, co
  * Errors: EINVAL, ENOMEM (wall_link_cap exceeded). */
 lbmps_status lbmps_set_static_solid(lbmps_ctx* ctx, int32_t inst, const uint8_t* host_mask, const double v_wall[3]);
 
+/* Mark the cells with host_mask[cell] != 0 as one group of outflow cells of
+ * instance `inst` (the top of the settling-sphere frame, Sec. 4.1): for every
+ * direction q from a fluid cell x into the group, after streaming,
+ *   f_qbar(x, t+1) = -f~_q(x, t) + 2 f^eq,+_q(rho_out, u(x, t)),
+ * the pressure anti-bounce-back with the even part of Eq. LBM_EQ,
+ * f^eq,+_q = w_q (rho_out + 9/2 (c_q.u)^2 - 3/2 u.u), and u(x, t) the velocity of
+ * Eq. MacVel from the cell's PDFs before its collision.  Outflow cells are
+ * never fluid (fields and PDFs read as for walls) and take one of the 16 wall
+ * groups of the instance.  The velocity inflow of the frame is a static wall
+ * group moving with the inflow velocity (lbmps_set_static_solid).  Call before
+ * lbmps_set_particles.
+ * Errors: EINVAL (null mask, rho_out not positive and finite, more than 16
+ * groups), ENOMEM (wall_link_cap exceeded), ESTATE (particles already set). */
+lbmps_status lbmps_set_outflow(lbmps_ctx* ctx, int32_t inst, const uint8_t* host_mask, double rho_out);
+
+/* Change the kinematic viscosity of instance `inst`: tau (Eq. Viscosity),
+ * the TRT/BGK rates and, for PSM, the B2 weights of the current overlaps are
+ * recomputed (the Galileo-number calibration of Sec. 4.1 adjusts nu between
+ * runs).  Synchronising.  Errors: EINVAL (nu not positive and finite). */
+lbmps_status lbmps_set_viscosity(lbmps_ctx* ctx, int32_t inst, double nu);
+
+/* Change the gravitational acceleration of instance `inst` (acting on
+ * (rho_p - 1) V of each particle).  Synchronising.  Errors: EINVAL. */
+lbmps_status lbmps_set_gravity(lbmps_ctx* ctx, int32_t inst, const double g[3]);
+
 /* Replace the particles of instance `inst` (n <= max_particles) and map them
  * into the lattice (MEM: solid cells and links; PSM: solid fractions).
  * Positions are wrapped into the box.  Particles must not touch each other

@@ -93,6 +93,15 @@ class OracleSim:
         self.wall_outflow.append(float(rho_out))
         self._remap(initial=True)
 
+    def set_viscosity(self, nu):
+        """New kinematic viscosity (Eq. Viscosity gives tau); the calibration
+        of Sec. 4.1 adjusts it between runs."""
+        self.nu = float(nu)
+        self.tau = fl.tau_from_nu(nu)
+
+    def set_gravity(self, g):
+        self.gravity = np.asarray(g, dtype=np.float64)
+
     def set_particles(self, X, U, Om, D, rho_p, fixed):
         self.parts = []
         for i in range(len(D)):

@@ -208,7 +208,7 @@ Layout make_layout(int n, const lbmps_config* cfgs) {
   L.o_redm = take((size_t)L.ptotal * L.link_blocks * 6 * 8 * std::max(1, L.mem_nsub));
   L.o_counts = take(16 * 4);
   L.o_links = take((size_t)(L.link_cap + L.wall_cap) * (5 * 4 + 8) + 2 * ALIGN);
-  L.o_wallv = take((size_t)n * 16 * 3 * 8);
+  L.o_wallv = take((size_t)n * WALL_GROUPS * WALL_REC * 8);
   L.o_pairs = take((size_t)L.pair_cap * (3 * 4 + 2 * 8 + 6 * 8) + 2 * ALIGN);
   L.o_refill = take((size_t)L.refill_cap * 2 * 4);
   L.o_scratch = take((size_t)L.chunk * 4 * 8);
@@ -230,6 +230,8 @@ Layout make_layout(int n, const lbmps_config* cfgs) {
 // overwrites their pushes), inside the sweep, or by the overlap kernel before
 // the sweep into a staging array that the sweep pushes.
 enum { PSM_SEPARATE = 0, PSM_FUSED = 1, PSM_STAGED = 2 };
+
+constexpr size_t TIMING_EVENTS = 4096;  // HIP events of the timing pool (start/stop pairs)
 
 struct lbmps_ctx {
   hipStream_t st = nullptr;
@@ -306,6 +308,20 @@ struct lbmps_ctx {
 };
 
 namespace {
+
+// tau from Eq. Viscosity (nu = (tau - 1/2)/3), lambda_+ = -1/tau and, for TRT,
+// lambda_- from the magic parameter (Eq. MEM_TRT); BGK: lambda_- = lambda_+.
+void set_relaxation(InstDev& I, const lbmps_config& cf) {
+  I.tau = 3.0 * cf.nu + 0.5;
+  I.mag = cf.magic > 0 ? cf.magic : 3.0 / 16.0;
+  I.lam_p = -1.0 / I.tau;
+  if (cf.collision == LBMPS_TRT) {
+    const double inv_m = I.mag / (0.5 + 1.0 / I.lam_p) - 0.5;
+    I.lam_m = 1.0 / inv_m;
+  } else {
+    I.lam_m = I.lam_p;
+  }
+}
 
 lbmps_status fail(lbmps_ctx* c, lbmps_status s, const std::string& msg) {
   if (c) c->last = msg;
@@ -645,15 +661,7 @@ lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* ws, s
     I.pdf_off = L.pdf_off[i];
     I.owner_off = L.owner_off[i];
     I.cellmap_off = L.cellmap_off[i];
-    I.tau = 3.0 * cf.nu + 0.5;
-    I.mag = cf.magic > 0 ? cf.magic : 3.0 / 16.0;
-    I.lam_p = -1.0 / I.tau;
-    if (cf.collision == LBMPS_TRT) {
-      const double inv_m = I.mag / (0.5 + 1.0 / I.lam_p) - 0.5;
-      I.lam_m = 1.0 / inv_m;
-    } else {
-      I.lam_m = I.lam_p;
-    }
+    set_relaxation(I, cf);
     for (int k = 0; k < 3; ++k) { I.fext[k] = cf.f_ext[k]; I.grav[k] = cf.gravity[k]; }
     I.part_begin = L.part_begin[i];
     I.part_count = 0;
@@ -729,13 +737,23 @@ lbmps_status lbmps_init_equilibrium(lbmps_ctx* c, int32_t inst, double rho, cons
   return LBMPS_OK;
 }
 
-lbmps_status lbmps_set_static_solid(lbmps_ctx* c, int32_t inst, const uint8_t* mask, const double v_wall[3]) {
+}  // extern "C"
+
+namespace {
+
+// One more group of static wall cells of instance `inst` (kind 0: velocity
+// wall with v_wall; 1: outflow with rho_out); every wall link of every
+// instance is rebuilt on the host from the owner fields.
+lbmps_status add_wall_group(lbmps_ctx* c, int32_t inst, const uint8_t* mask, const double v_wall[3], int kind,
+                            double rho_out) {
   lbmps_status s = check_inst(c, inst);
   if (s) return s;
   if (!mask || !v_wall) return fail(c, LBMPS_EINVAL, "null argument");
   if (c->n_mem + c->n_psm > 0) return fail(c, LBMPS_ESTATE, "set static walls before any particles");
+  if (!std::isfinite(v_wall[0]) || !std::isfinite(v_wall[1]) || !std::isfinite(v_wall[2]))
+    return fail(c, LBMPS_EINVAL, "non-finite wall velocity");
   drop_graph(c);
-  if (c->wall_groups[inst] >= 16) return fail(c, LBMPS_EINVAL, "at most 16 wall groups per instance");
+  if (c->wall_groups[inst] >= WALL_GROUPS) return fail(c, LBMPS_EINVAL, "at most 16 wall groups per instance");
   const lbmps_config& cf = c->cfg[inst];
   const int nx = cf.nx, ny = cf.ny, nz = cf.nz;
   const long long N = c->L.ncell[inst];
@@ -743,7 +761,7 @@ lbmps_status lbmps_set_static_solid(lbmps_ctx* c, int32_t inst, const uint8_t* m
   std::vector<int> own(N);
   HIPCHK(c, hipMemcpyAsync(own.data(), c->owner + c->L.owner_off[inst], N * 4, hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
-  const int gid = inst * 16 + c->wall_groups[inst];
+  const int gid = inst * WALL_GROUPS + c->wall_groups[inst];
   for (long long i = 0; i < N; ++i)
     if (mask[i]) own[i] = -2 - gid;
   // rebuild every wall link of every instance from the host owner fields
@@ -775,8 +793,8 @@ lbmps_status lbmps_set_static_solid(lbmps_ctx* c, int32_t inst, const uint8_t* m
   (void)nx; (void)ny; (void)nz;
   if ((long long)lc.size() > c->L.wall_cap) return fail(c, LBMPS_ENOMEM, "wall_link_cap exceeded");
   c->wall_groups[inst]++;
-  const double v[3] = {v_wall[0], v_wall[1], v_wall[2]};
-  HIPCHK(c, hipMemcpyAsync(c->wall_v + 3 * gid, v, 3 * 8, hipMemcpyHostToDevice, c->st));
+  double rec[WALL_REC] = {v_wall[0], v_wall[1], v_wall[2], (double)kind, rho_out, 0.0, 0.0, 0.0};
+  HIPCHK(c, hipMemcpyAsync(c->wall_v + WALL_REC * gid, rec, sizeof(rec), hipMemcpyHostToDevice, c->st));
   HIPCHK(c, hipMemcpyAsync(c->owner + c->L.owner_off[inst], own.data(), N * 4, hipMemcpyHostToDevice, c->st));
   const size_t nl = lc.size();
   std::vector<int> zeros(nl, 0);
@@ -792,6 +810,51 @@ lbmps_status lbmps_set_static_solid(lbmps_ctx* c, int32_t inst, const uint8_t* m
   c->n_wall = (int)nl;
   HIPCHK(c, hipStreamSynchronize(c->st));
   return LBMPS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbmps_status lbmps_set_static_solid(lbmps_ctx* c, int32_t inst, const uint8_t* mask, const double v_wall[3]) {
+  return add_wall_group(c, inst, mask, v_wall, 0, 1.0);
+}
+
+lbmps_status lbmps_set_outflow(lbmps_ctx* c, int32_t inst, const uint8_t* mask, double rho_out) {
+  if (!c) return LBMPS_EINVAL;
+  if (!std::isfinite(rho_out) || !(rho_out > 0.0)) return fail(c, LBMPS_EINVAL, "rho_out must be positive");
+  const double zero[3] = {0.0, 0.0, 0.0};
+  return add_wall_group(c, inst, mask, zero, 1, rho_out);
+}
+
+lbmps_status lbmps_set_viscosity(lbmps_ctx* c, int32_t inst, double nu) {
+  lbmps_status s = check_inst(c, inst);
+  if (s) return s;
+  if (!(nu > 0.0) || !std::isfinite(nu)) return fail(c, LBMPS_EINVAL, "nu must be positive");
+  drop_graph(c);
+  c->cfg[inst].nu = nu;
+  set_relaxation(c->inst_h[inst], c->cfg[inst]);
+  HIPCHK(c, hipMemcpyAsync(c->inst_d + inst, &c->inst_h[inst], sizeof(InstDev), hipMemcpyHostToDevice, c->st));
+  // the B2 weights of the overlap pairs depend on tau
+  if (c->cfg[inst].coupling == LBMPS_PSM && c->n_psm) {
+    s = rebuild_psm(c, c->st);
+    if (s) return s;
+  }
+  return check_device_errors(c);
+}
+
+lbmps_status lbmps_set_gravity(lbmps_ctx* c, int32_t inst, const double g[3]) {
+  lbmps_status s = check_inst(c, inst);
+  if (s) return s;
+  if (!g || !std::isfinite(g[0]) || !std::isfinite(g[1]) || !std::isfinite(g[2]))
+    return fail(c, LBMPS_EINVAL, "non-finite gravity");
+  drop_graph(c);
+  for (int k = 0; k < 3; ++k) {
+    c->cfg[inst].gravity[k] = g[k];
+    c->inst_h[inst].grav[k] = g[k];
+  }
+  HIPCHK(c, hipMemcpyAsync(c->inst_d + inst, &c->inst_h[inst], sizeof(InstDev), hipMemcpyHostToDevice, c->st));
+  return check_device_errors(c);
 }
 
 lbmps_status lbmps_set_particles(lbmps_ctx* c, int32_t inst, int32_t n, const lbmps_particle* hp) {
@@ -950,15 +1013,9 @@ static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
                                    c->cellmap, src, dst, c->stage, L.pair_cap, false, c->st));
     const bool timed = c->timing && (c->timing_seq++ % c->timing_stride) == 0;
     if (timed) {
-      if (c->ev_used + 2 > c->ev.size()) {
+      if (c->ev_used + 2 > c->ev.size()) {  // every event of the pool is recorded: read them out
         lbmps_status r = harvest_timing(c);
         if (r) return r;
-        while (c->ev.size() < 4096) {
-          hipEvent_t e;
-          // timestamps only (read after a stream synchronisation): no system-scope fence
-          HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
-          c->ev.push_back(e);
-        }
       }
       HIPCHK(c, hipEventRecord(c->ev[c->ev_used], c->st));
     }
@@ -993,7 +1050,7 @@ static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
       // and are added up (in sweep order) after the last one, below
       const int set = c->n_mem ? (int)(c->sweeps % L.mem_nsub) : 0;
       HIPCHK(c, launch_links_bc(L.prec, c->n_wall, mem_list(c), c->n_mem, c->lbeg, c->lend, L.link_blocks, c->links,
-                                c->wall_v, c->inst_d, c->parts, dst, c->red_mem, set, c->st));
+                                c->wall_v, c->inst_d, c->parts, src, dst, c->red_mem, set, c->st));
     }
     c->cur = 1 - c->cur;
     c->sweeps++;
@@ -1231,6 +1288,14 @@ lbmps_status lbmps_set_timing(lbmps_ctx* c, int32_t enable) {
   lbmps_status s = harvest_timing(c);
   if (s) return s;
   if (enable < 0) return fail(c, LBMPS_EINVAL, "timing stride must be >= 0");
+  // the event pool is created here, not at the first timed launch, so that a
+  // timed region pays only for recording the events
+  while (enable > 0 && c->ev.size() < TIMING_EVENTS) {
+    hipEvent_t e;
+    // timestamps only (read after a stream synchronisation): no system-scope fence
+    HIPCHK(c, hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+    c->ev.push_back(e);
+  }
   c->timing = enable != 0;
   c->timing_stride = enable > 0 ? enable : 1;
   c->timing_seq = 0;

@@ -111,6 +111,7 @@ struct PairDev {
 // into one 48th of the sphere), 8 / R (curvature relative to the cell size),
 // then zeros.
 __device__ __forceinline__ void eps_features(const double (&d)[3], double R, float (&x)[8]) {
+#pragma clang fp contract(off)
   double a = fabs(d[0]), b = fabs(d[1]), c = fabs(d[2]), t;
   if (a < b) { t = a; a = b; b = t; }
   if (b < c) { t = b; b = c; c = t; }
@@ -151,6 +152,61 @@ template <> struct Codec<_Float16> {
 template <> struct Codec<__bf16> {
   __device__ static inline float ld(__bf16 v) { return (float)v; }
   __device__ static inline __bf16 st(float v) { return (__bf16)v; }  // round to nearest even
+};
+
+// Stochastic rounding for the 16-bit storage types: x is stored as the
+// representable neighbour below or above it in magnitude, the upper one with
+// probability (|x| - lo) / (hi - lo), so that the stored value equals x in
+// expectation.  The uniform draw is a hash of x's bits and a key (the cell and
+// direction written), by the 32-bit finaliser of MurmurHash3 (Appleby): the
+// rounding is a deterministic function of what is stored where.  Used for the
+// post-collision values of PSM-overlapped cells, whose solid operator makes
+// many cells hold nearly equal values: there round-to-nearest errs the same way
+// in every cell, and the PSM force and torque (sums over those cells) collect
+// the error coherently.
+__device__ inline uint32_t fmix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85ebca6bu;
+  h ^= h >> 13;
+  h *= 0xc2b2ae35u;
+  h ^= h >> 16;
+  return h;
+}
+__device__ inline uint32_t sr_bits(float x, uint32_t key) { return fmix32(__float_as_uint(x) ^ fmix32(key)); }
+
+template <typename S> struct StochasticRound {  // 4- and 8-byte storage: the value is stored as computed
+  template <typename R> __device__ static inline R apply(R x, uint32_t) { return x; }
+};
+template <> struct StochasticRound<__bf16> {
+  // bfloat16 is the upper half of the FP32 pattern: adding 16 random bits to
+  // the magnitude and truncating rounds up with probability (low half) / 2^16
+  __device__ static inline float apply(float x, uint32_t key) {
+    const uint32_t b = __float_as_uint(x);
+    const uint32_t r = sr_bits(x, key) & 0xffffu;
+    return __uint_as_float((b + r) & 0xffff0000u);
+  }
+};
+template <> struct StochasticRound<_Float16> {
+  __device__ static inline float apply(float x, uint32_t key) {
+    const float a = fabsf(x);
+    const _Float16 n = (_Float16)a;  // nearest
+    const unsigned short nb = __builtin_bit_cast(unsigned short, n);
+    // the two half-precision magnitudes around a (bit patterns of positive
+    // halves are ordered like their values)
+    unsigned short lo, hi;
+    if ((float)n <= a) {
+      lo = nb;
+      hi = (unsigned short)(nb + 1);
+    } else {
+      hi = nb;
+      lo = (unsigned short)(nb - 1);
+    }
+    const float flo = (float)__builtin_bit_cast(_Float16, lo), fhi = (float)__builtin_bit_cast(_Float16, hi);
+    if (flo == a) return x;  // representable
+    const float frac = (a - flo) / (fhi - flo);                        // in (0, 1)
+    const float u = (float)(sr_bits(x, key) >> 8) * (1.0f / 16777216.0f);  // uniform in [0, 1)
+    return copysignf(u < frac ? fhi : flo, x);
+  }
 };
 
 // compute precision paired with each storage type

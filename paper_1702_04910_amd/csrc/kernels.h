@@ -101,9 +101,13 @@ hipError_t launch_mem_refill(int prec, const int* count, int cap, const int* rce
 // list[j].  Each particle's link force and torque chunk sums go to set `set` of partial (width workgroups per
 // particle, nlist * width * 6 doubles per set); after the last sweep of a rigid-body step, launch_finish_sums
 // over all sets (SUM_THREADS records per chunk, set_stride nlist * width * 6) adds them to Facc/Tacc.
+// Wall groups: WALL_REC doubles each, the wall velocity (3), WALL_KIND (0 a
+// velocity wall, bounce-back with that velocity; 1 an outflow) and WALL_RHO_OUT.
+// Outflow links read the pre-collision PDFs of their fluid cell from src.
+constexpr int WALL_REC = 8, WALL_KIND = 3, WALL_RHO_OUT = 4, WALL_GROUPS = 16;
 hipError_t launch_links_bc(int prec, int n_wall, const int* list, int nlist, const int* lbeg, const int* lend,
                            int width, LinkDev links, const double* wall_v, const InstDev* insts, PartDev parts,
-                           void* buf, double* partial, int set, hipStream_t st);
+                           const void* src, void* buf, double* partial, int set, hipStream_t st);
 
 // ---- psm.hip
 hipError_t launch_psm_classify(const int* list, int nlist, int side, int nsplit, const InstDev* insts, PartDev parts,

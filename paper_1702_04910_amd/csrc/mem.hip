@@ -18,8 +18,24 @@
 
 namespace lbm {
 
+// Squared distance ((x^2 + y^2) + z^2) with every product and sum rounded on
+// its own: no fused multiply-add may form across them (__dmul_rn / __dadd_rn
+// alone do not prevent that once inlined).
 __device__ __forceinline__ double sq3m(double x, double y, double z) {
-  return __dadd_rn(__dadd_rn(__dmul_rn(x, x), __dmul_rn(y, y)), __dmul_rn(z, z));
+#pragma clang fp contract(off)
+  return (x * x + y * y) + z * z;
+}
+
+// delta_q: the smallest root in (0, 1] of |d + delta c_q|^2 = R^2, as
+// e / (-b + sqrt(b^2 - a e)) with a = c.c, b = d.c, e = |d|^2 - R^2, each
+// operation rounded on its own as plain FP64 evaluates it (e cancels, so a
+// fused rounding would move delta by a few units of R^2 / |b|).
+__device__ __forceinline__ double link_delta(const double (&d)[3], double R, int q) {
+#pragma clang fp contract(off)
+  const double e = sq3m(d[0], d[1], d[2]) - R * R;
+  const double a = (double)speed2(q);
+  const double b = (d[0] * cx(q) + d[1] * cy(q)) + d[2] * cz(q);
+  return e / (-b + sqrt(b * b - a * e));
 }
 
 __device__ __forceinline__ void mem_bbox_lo(const PartDev& P, int p, int (&lo)[3]) {
@@ -212,13 +228,10 @@ __global__ __launch_bounds__(256) void mem_fill_links_kernel(const int* __restri
     if ((m & SLOT_LINKS) == 0) continue;
     double d[3];
     disp(I, P, p, ci, cj, ck, d);
-    const double e = sq3m(d[0], d[1], d[2]) - R * R;
     for (int q = 1; q < Q; ++q) {
       if (!(m & (1 << q))) continue;
       if (pos < base + cap) {
-        const double a = (double)speed2(q);
-        const double b = d[0] * cx(q) + d[1] * cy(q) + d[2] * cz(q);
-        const double delta = e / (-b + sqrt(b * b - a * e));
+        const double delta = link_delta(d, R, q);
         L.cell[pos] = cell;
         L.q[pos] = q;
         L.p[pos] = p;
@@ -393,7 +406,7 @@ __device__ __forceinline__ void link_rule(int i, const LinkDev& L, const double*
     }
   } else {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) Ub[k] = wall_v[3 * (-2 - p) + k];
+    for (int k = 0; k < 3; ++k) Ub[k] = wall_v[WALL_REC * (-2 - p) + k];
   }
   const InstDev& I = insts[inst];
   const int qb = opp(q);
@@ -450,6 +463,36 @@ __device__ __forceinline__ void link_rule(int i, const LinkDev& L, const double*
   }
 }
 
+// Outflow rule of a wall link i whose group is an outflow (Sec. 4.1, after
+// Ginzburg): f_qbar(x, t+1) = -f~_q(x, t) + 2 f^eq,+_q(rho_out, u(x, t)), in
+// deviations g_qbar = -g~_q + 2 w_q (rho_out - 1 + 9/2 (c_q.u)^2 - 3/2 u.u),
+// with u(x, t) = U + f_ext/2 (Eq. MacVel) from the fluid cell's PDFs before its
+// collision (src).  wp: the group's record (rho_out at WALL_RHO_OUT).
+template <typename S>
+__device__ __forceinline__ void outflow_rule(int i, const LinkDev& L, const double* __restrict__ wp,
+                                             const InstDev* __restrict__ insts, const S* __restrict__ src,
+                                             S* __restrict__ buf) {
+  const InstDev& I = insts[L.inst[i]];
+  const int cell = L.cell[i], q = L.q[i], qb = opp(q);
+  const int x = cell % I.nx, yz = cell / I.nx, y = yz % I.ny, z = yz / I.ny;
+  const int xs = wrap_near(x + cx(q), I.nx), ys = wrap_near(y + cy(q), I.ny), zs = wrap_near(z + cz(q), I.nz);
+  S* b = buf + I.pdf_off;
+  const S* a = src + I.pdf_off;
+  const double gtq = (double)Codec<S>::ld(b[pdf_at(((long long)zs * I.ny + ys) * I.nx + xs, q)]);
+  double U[3] = {0.0, 0.0, 0.0};
+  for (int r = 1; r < Q; ++r) {
+    const double g = (double)Codec<S>::ld(a[pdf_at(cell, r)]);
+    U[0] += cx(r) * g;
+    U[1] += cy(r) * g;
+    U[2] += cz(r) * g;
+  }
+  for (int k = 0; k < 3; ++k) U[k] += 0.5 * I.fext[k];
+  const double cu = U[0] * cx(q) + U[1] * cy(q) + U[2] * cz(q);
+  const double uu = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+  const double val = -gtq + 2.0 * wq(q) * ((wp[WALL_RHO_OUT] - 1.0) + 4.5 * cu * cu - 1.5 * uu);
+  b[pdf_at(cell, qb)] = Codec<S>::st((typename CompOf<S>::type)val);
+}
+
 // Row j < nlist of the grid: the links [n_wall + lbeg[j], n_wall + lend[j]) of
 // particle list[j], one link per thread in chunks of SUM_THREADS; workgroup
 // k < width takes chunks k, k + width, ... (the rest of the row is idle).
@@ -457,20 +500,26 @@ __device__ __forceinline__ void link_rule(int i, const LinkDev& L, const double*
 // stores their block_sum6 (in the sweep's set of `partial`), and after the
 // last sweep of the rigid-body step finish_sums_kernel adds a particle's
 // workgroup sums in a fixed order, so the total repeats bit for bit.
-// Row nlist: the wall links [0, n_wall), strided over the whole row.
+// Row nlist: the wall links [0, n_wall), strided over the whole row (velocity
+// walls by link_rule, outflow groups by outflow_rule).
 template <typename S>
 __global__ __launch_bounds__(SUM_THREADS) void links_bc_kernel(int n_wall, const int* __restrict__ list, int nlist,
                                                                const int* __restrict__ lbeg,
                                                                const int* __restrict__ lend, LinkDev L,
                                                                const double* __restrict__ wall_v,
                                                                const InstDev* __restrict__ insts, PartDev P,
-                                                               S* __restrict__ buf, double* __restrict__ partial,
-                                                               int width) {
+                                                               const S* __restrict__ src, S* __restrict__ buf,
+                                                               double* __restrict__ partial, int width) {
   const int j = blockIdx.y, kb = blockIdx.x;
   double ft[6];
   if (j == nlist) {
-    for (int i = kb * SUM_THREADS + (int)threadIdx.x; i < n_wall; i += gridDim.x * SUM_THREADS)
-      link_rule<S, false>(i, L, wall_v, insts, P, buf, 0, 0, ft);
+    for (int i = kb * SUM_THREADS + (int)threadIdx.x; i < n_wall; i += gridDim.x * SUM_THREADS) {
+      const double* wp = wall_v + WALL_REC * (-2 - L.p[i]);
+      if (wp[WALL_KIND] != 0.0)
+        outflow_rule<S>(i, L, wp, insts, src, buf);
+      else
+        link_rule<S, false>(i, L, wall_v, insts, P, buf, 0, 0, ft);
+    }
     return;
   }
   const int nb = width;  // workgroups per particle: the rows of `partial` are this wide
@@ -494,7 +543,7 @@ __global__ __launch_bounds__(SUM_THREADS) void links_bc_kernel(int n_wall, const
 
 hipError_t launch_links_bc(int prec, int n_wall, const int* list, int nlist, const int* lbeg, const int* lend,
                            int width, LinkDev links, const double* wall_v, const InstDev* insts, PartDev parts,
-                           void* buf, double* partial, int set, hipStream_t st) {
+                           const void* src, void* buf, double* partial, int set, hipStream_t st) {
   if (nlist <= 0 && n_wall <= 0) return hipSuccess;
   if (set < 0) return hipErrorInvalidValue;
   const long long set_stride = (long long)nlist * width * 6;
@@ -502,7 +551,7 @@ hipError_t launch_links_bc(int prec, int n_wall, const int* list, int nlist, con
   const int blocks = std::max(width, std::min(512, (n_wall + SUM_THREADS - 1) / SUM_THREADS));
   LBM_DISPATCH(prec, hipLaunchKernelGGL(links_bc_kernel<S>, dim3(blocks, nlist + (n_wall > 0 ? 1 : 0)),
                                         dim3(SUM_THREADS), 0, st, n_wall, list, nlist, lbeg, lend, links, wall_v,
-                                        insts, parts, (S*)buf, partial + set * set_stride, width));
+                                        insts, parts, (const S*)src, (S*)buf, partial + set * set_stride, width));
   return hipGetLastError();
 }
 

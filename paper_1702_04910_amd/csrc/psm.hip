@@ -21,8 +21,10 @@
 namespace lbm {
 
 
+// ((x^2 + y^2) + z^2), each operation rounded on its own (no fused multiply-add).
 __device__ __forceinline__ double sq3(double x, double y, double z) {
-  return __dadd_rn(__dadd_rn(__dmul_rn(x, x), __dmul_rn(y, y)), __dmul_rn(z, z));
+#pragma clang fp contract(off)
+  return (x * x + y * y) + z * z;
 }
 
 __device__ __forceinline__ double sample_off(int a, int n) { return __dadd_rn(__ddiv_rn((double)a + 0.5, (double)n), -0.5); }
@@ -182,6 +184,7 @@ __device__ __forceinline__ void centre_disp(const InstDev& I, const PartDev& P, 
 // intersection: the covered length of the cell's twelve edges over 12 (axis by
 // axis; the two other coordinates at (-,-), (+,-), (-,+), (+,+) half-cells).
 __device__ double eps_edge(const double (&d)[3], double R2) {
+#pragma clang fp contract(off)
   double total = 0.0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -555,7 +558,9 @@ hipError_t launch_psm_cellmap(int stage, const int* count, int cap, const InstDe
 // list is ordered by particle, slab and row, so neighbouring lanes touch
 // neighbouring cells and share cache lines).  The post-collision values are
 // pushed into dst, or with stage != nullptr stored at stage[q * sstride + L]
-// (whole cache lines; the next sweep pushes them).  MULTI = false: the cells with a
+// (whole cache lines; the next sweep pushes them).  With 16-bit storage they are
+// rounded stochastically (keyed by cell and direction), like the overlapped
+// cells that the sweep collides inline.  MULTI = false: the cells with a
 // single pair, with the solid operator M fixed at compile time (0: per
 // instance) -- the common case, compiled for four waves per SIMD where the
 // storage is below 8 bytes and M is fixed; MULTI = true: the cells shared by
@@ -580,6 +585,8 @@ __attribute__((amdgpu_waves_per_eu(MULTI || M == 0 || sizeof(S) == 8 ? 1 : 4))) 
 #pragma unroll
     for (int q = 0; q < Q; ++q) g[q] = Codec<S>::ld(s[pdf_at(c, q)]);
     psm_cell_collide<M, !MULTI, R>(g, out, I, P, pairs, L, c);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) out[q] = StochasticRound<S>::apply(out[q], (uint32_t)c * Q + q);
     if (stage) {  // the sweep pushes them
 #pragma unroll
       for (int q = 0; q < Q; ++q) stage[q * sstride + L] = Codec<S>::st(out[q]);

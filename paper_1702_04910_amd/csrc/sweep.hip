@@ -302,6 +302,8 @@ __device__ __forceinline__ void sweep_body(const InstDev* __restrict__ insts, co
           if (I.psm_m == 1) psm_cell_collide<1, true, R>(g, o, I, P, pairs, L, idx);
           else if (I.psm_m == 2) psm_cell_collide<2, true, R>(g, o, I, P, pairs, L, idx);
           else psm_cell_collide<3, true, R>(g, o, I, P, pairs, L, idx);
+#pragma unroll
+          for (int q = 0; q < Q; ++q) o[q] = StochasticRound<S>::apply(o[q], (uint32_t)idx * Q + q);
         } else {
           collide_cell<R>(g, o, lp, lm, fx, fy, fz);
         }

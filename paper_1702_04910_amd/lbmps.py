@@ -87,6 +87,12 @@ def lib():
         L.lbmps_init_equilibrium.argtypes = [P, I32, D, P]
         L.lbmps_set_static_solid.restype = I32
         L.lbmps_set_static_solid.argtypes = [P, I32, P, P]
+        L.lbmps_set_outflow.restype = I32
+        L.lbmps_set_outflow.argtypes = [P, I32, P, D]
+        L.lbmps_set_viscosity.restype = I32
+        L.lbmps_set_viscosity.argtypes = [P, I32, D]
+        L.lbmps_set_gravity.restype = I32
+        L.lbmps_set_gravity.argtypes = [P, I32, P]
         L.lbmps_set_particles.restype = I32
         L.lbmps_set_particles.argtypes = [P, I32, I32, P]
         L.lbmps_step.restype = I32
@@ -239,6 +245,18 @@ class Sim:
         assert m.size == self.ncell(inst)
         v = (ctypes.c_double * 3)(*v_wall)
         self._chk(lib().lbmps_set_static_solid(self._ctx, inst, m.ctypes.data, ctypes.addressof(v)))
+
+    def set_outflow(self, mask, rho_out=1.0, inst=0):
+        m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8).reshape(-1))
+        assert m.size == self.ncell(inst)
+        self._chk(lib().lbmps_set_outflow(self._ctx, inst, m.ctypes.data, float(rho_out)))
+
+    def set_viscosity(self, nu, inst=0):
+        self._chk(lib().lbmps_set_viscosity(self._ctx, inst, float(nu)))
+
+    def set_gravity(self, g, inst=0):
+        gg = (ctypes.c_double * 3)(*g)
+        self._chk(lib().lbmps_set_gravity(self._ctx, inst, ctypes.addressof(gg)))
 
     def set_particles(self, X, U, Om, D, rho_p, fixed, inst=0):
         n = len(D)

@@ -5,7 +5,8 @@ of the figure's pgf source.
 
 Each curve is matched to its legend label by stroke colour; the data axis is
 calibrated from the y tick labels (-0.2 ... 0.2) and the tau tick labels on the
-top axis.  Run:  python tests/golden/extract_fig1.py /root/reference/PAPER.md
+top axis.  Run:  python tests/golden/extract_fig1.py <text of the paper holding
+the figure's pgf source>
 """
 import json
 import os
@@ -63,4 +64,6 @@ def main(path):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "/root/reference/PAPER.md")
+    if len(sys.argv) != 2:
+        sys.exit("usage: extract_fig1.py <paper text holding the pgf source of Fig. 1>")
+    main(sys.argv[1])

@@ -85,3 +85,38 @@ def force_errors(ora, sim, inst=0):
         eT = np.linalg.norm(pg["T"][i] - po["T"][i]) / (R * nF)
         out.append((eF, eT, nF))
     return out, po, pg
+
+
+def link_set_errors(ora, sim):
+    """Compare the MEM particle link sets: the sorted (cell, q, particle)
+    triples must be equal (a discrete event); returns max |delta_gpu -
+    delta_oracle| over the links.  Raises AssertionError on a set mismatch."""
+    nz, ny, nx = ora.shape
+    Lo = ora.links
+    sel = Lo["p"] >= 0
+    inv = np.empty(19, np.int64)
+    inv[perm_gpu_to_oracle()] = np.arange(19)  # oracle q -> library q
+    key_o = ((((Lo["iz"][sel] * ny + Lo["iy"][sel]) * nx + Lo["ix"][sel]) * 19 + inv[Lo["q"][sel]]) * 64
+             + Lo["p"][sel])
+    L = sim.links()
+    key_g = (L["cell"].astype(np.int64) * 19 + L["q"]) * 64 + L["p"]
+    oo, og = np.argsort(key_o), np.argsort(key_g)
+    assert len(key_o) == len(key_g), (len(key_o), len(key_g))
+    assert np.array_equal(key_o[oo], key_g[og])
+    return float(np.abs(Lo["delta"][sel][oo] - L["delta"][og]).max()) if len(key_o) else 0.0
+
+
+def overlap_set_check(ora, sim):
+    """The PSM overlap lists (cell, particle, eps_s) must be equal exactly."""
+    nz, ny, nx = ora.shape
+    ko, eo = [], []
+    for p, (iz, iy, ix, eps) in enumerate(ora.overlaps):
+        ko.append(((iz * ny + iy) * nx + ix).astype(np.int64) * 64 + p)
+        eo.append(eps)
+    ko = np.concatenate(ko) if ko else np.zeros(0, np.int64)
+    eo = np.concatenate(eo) if eo else np.zeros(0)
+    ov = sim.overlaps()
+    kg = ov["cell"].astype(np.int64) * 64 + ov["p"]
+    o1, o2 = np.argsort(ko), np.argsort(kg)
+    assert np.array_equal(ko[o1], kg[o2])
+    assert np.array_equal(eo[o1], ov["eps"][o2])

@@ -123,3 +123,48 @@ def test_graph_needs_period_multiple():
     with pytest.raises(lbmps.LbmpsError):
         sim.step_graph(3)
     sim.close()
+
+
+def test_mixed_batch_instances_match_their_oracle_runs():
+    # A batch of MEM-CLI, PSM-M3B2 and MEM-BB instances of different box
+    # sizes, each with a moving sphere (FP64 storage): every instance against
+    # its own FP64 oracle run at 1e-12 (PDFs, force, torque), positions to 1e-13.
+    from oracle.sim import OracleSim
+    from gpu_util import oracle_to_gpu, gpu_to_oracle
+
+    specs = [(26, 24, 30, "mem_cli", 3, 2, [12.3, 11.6, 18.2], [0.01, -0.004, 0.0], 6.6, 1.4),
+             (24, 22, 28, "psm", 3, 2, [11.4, 10.7, 15.9], [-0.006, 0.008, 0.002], 7.0, 1.5),
+             (22, 26, 24, "mem_bb", 3, 2, [10.8, 13.1, 12.5], [0.0, 0.005, -0.01], 5.8, 1.25)]
+    dmax = max(s[8] for s in specs)
+    cfgs, oras = [], []
+    for (nx, ny, nz, cp, m, b, X, U, D, rho) in specs:
+        f = (1e-6, 0.0, 5e-7)
+        g = (0.0, 0.0, -2e-4)
+        cfgs.append(lbmps.make_config(nx, ny, nz, 0.06, collision="trt", coupling=cp, psm_m=m, psm_b=b, n_sub=2,
+                                      eps_n=4, precision="fp64", max_particles=1, max_diameter=dmax, f_ext=f,
+                                      gravity=g))
+        o = OracleSim(nx, ny, nz, 0.06, collision="trt", coupling=cp, psm_m=m, psm_b=b, fext=f, gravity=g, n_sub=2,
+                      eps_n=4)
+        o.init_equilibrium()
+        o.set_particles([X], [U], [[0.0, 0.001, 0.0]], [D], [rho], [False])
+        oras.append(o)
+    batch = lbmps.Sim(cfgs)
+    for i, (nx, ny, nz, cp, m, b, X, U, D, rho) in enumerate(specs):
+        batch.init_equilibrium(inst=i)
+        batch.set_particles([X], [U], [[0.0, 0.001, 0.0]], [D], [rho], [False], inst=i)
+    for chunk in range(3):
+        batch.step(12)
+        for i, o in enumerate(oras):
+            o.step(12)
+            go = o.get_pdfs()
+            gg = gpu_to_oracle(batch.get_pdfs(i))
+            fluid = o.owner == -1
+            e = np.abs(gg[:, fluid] - go[:, fluid]).max() / np.abs(go[:, fluid]).max()
+            po, pg = o.particles(), batch.particles(i)
+            nF = np.linalg.norm(po["F"][0])
+            eF = np.linalg.norm(pg["F"][0] - po["F"][0]) / nF
+            eT = np.linalg.norm(pg["T"][0] - po["T"][0]) / (0.5 * specs[i][8] * nF)
+            eX = np.abs(pg["X"][0] - po["X"][0]).max()
+            say("  t=%d inst %d (%s): e_f=%.2e e_F=%.2e e_T=%.2e eX=%.2e" % (o.time, i, specs[i][3], e, eF, eT, eX))
+            assert e < 1e-12 and eF < 1e-12 and eT < 1e-12 and eX < 1e-13
+    batch.close()

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_1702_04910_amd import lbmps
-from gpu_util import make_pair, pdf_error, force_errors, say
+from gpu_util import make_pair, pdf_error, force_errors, say, link_set_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -40,7 +40,7 @@ def test_sphere_crossing_periodic_faces(coupling, m, b):
         e, _ = pdf_error(ora, sim)
         eX = np.abs(pg["X"] - po["X"]).max()
         say("  t=%d X=%s e_f=%.2e e_F=%.2e e_T=%.2e" % (ora.time, pg["X"][0], e, eF, eT))
-        assert e < 1e-11 and eF < 1e-11 and eT < 1e-11 and eX < 1e-13
+        assert e < 1e-12 and eF < 1e-12 and eT < 1e-12 and eX < 1e-13
     # it has wrapped through x = 0 and z = 32
     assert pg["X"][0][0] > 12 and pg["X"][0][2] < 12
     sim.close()
@@ -59,10 +59,11 @@ def test_several_mem_spheres():
         errs, po, pg = force_errors(ora, sim)
         e, _ = pdf_error(ora, sim)
         say("  t=%d e_f=%.2e" % (ora.time, e), [("%.1e" % a, "%.1e" % b) for a, b, _ in errs])
-        assert e < 1e-11
+        assert e < 1e-12
         for eF, eT, _ in errs:
-            assert eF < 1e-11 and eT < 1e-11
+            assert eF < 1e-12 and eT < 1e-12
         assert np.abs(pg["X"] - po["X"]).max() < 1e-13
+        assert link_set_errors(ora, sim) <= 1e-15
     sim.close()
 
 
@@ -89,9 +90,9 @@ def test_mem_cli_falls_back_to_bounce_back_in_narrow_gaps():
         errs, po, pg = force_errors(ora, sim)
         e, _ = pdf_error(ora, sim)
         say("  t=%d e_f=%.2e" % (ora.time, e), [("%.1e" % a, "%.1e" % b) for a, b, _ in errs])
-        assert e < 1e-11
+        assert e < 1e-12
         for eF, eT, _ in errs:
-            assert eF < 1e-11 and eT < 1e-11
+            assert eF < 1e-12 and eT < 1e-12
         assert np.abs(pg["X"] - po["X"]).max() < 1e-13
     sim.close()
 
@@ -108,7 +109,7 @@ def test_largest_sphere(coupling):
     (eF, eT, _), = force_errors(ora, sim)[0]
     e, _ = pdf_error(ora, sim)
     say("  e_f=%.2e e_F=%.2e e_T=%.2e" % (e, eF, eT))
-    assert e < 1e-12 and eF < 1e-11 and eT < 1e-11
+    assert e < 1e-12 and eF < 1e-12 and eT < 1e-12
     sim.close()
 
 
@@ -121,13 +122,12 @@ def test_cell_centres_on_the_surface(coupling):
     ora, sim = make_pair(25, 25, 25, 0.05, coupling=coupling, collision="trt", psm_m=1, psm_b=1,
                          f_ext=(1e-6, 2e-6, 0), parts=parts, eps_n=4, n_sub=2)
     if coupling == "mem_cli":
-        L = sim.links()
-        assert len(L["cell"]) == len(ora.links["q"])
+        assert link_set_errors(ora, sim) <= 1e-15
     ora.step(10)
     sim.step(10)
     (eF, eT, _), = force_errors(ora, sim)[0]
     e, _ = pdf_error(ora, sim)
-    assert e < 1e-12 and eF < 1e-11 and eT < 1e-11
+    assert e < 1e-12 and eF < 1e-12 and eT < 1e-12
     sim.close()
 
 

@@ -1,0 +1,84 @@
+"""The settling-sphere frame of Sec. 4.1 on the GPU against the FP64 oracle:
+velocity inflow (a wall group moving with the inflow velocity) at the bottom,
+pressure outflow at the top, periodic in x and y, with a fixed or a moving
+sphere; and the viscosity and gravity changes of the Galileo-number
+calibration."""
+import numpy as np
+import pytest
+
+from gpu_util import pdf_error, force_errors, say
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+def _frame_pair(nx, ny, nz, u, coupling, precision, parts, nu=0.04, m=3, b=2):
+    from oracle.sim import OracleSim
+    from paper_1702_04910_amd import lbmps
+
+    n_p = len(parts["D"]) if parts else 0
+    ora = OracleSim(nx, ny, nz, nu, collision="trt", coupling=coupling, psm_m=m, psm_b=b, n_sub=2, eps_n=4)
+    sim = lbmps.Sim(lbmps.make_config(nx, ny, nz, nu, collision="trt", coupling=coupling, psm_m=m, psm_b=b,
+                                      n_sub=2, eps_n=4, precision=precision, max_particles=n_p,
+                                      max_diameter=max(parts["D"]) if parts else 0.0))
+    inflow = np.zeros((nz, ny, nx), bool)
+    inflow[0] = True
+    out = np.zeros((nz, ny, nx), bool)
+    out[-1] = True
+    for s in (ora, sim):
+        s.set_static_solid(inflow, (0.0, 0.0, u))
+        s.set_outflow(out, 1.0)
+    ora.init_equilibrium(1.0, (0.0, 0.0, u))
+    sim.init_equilibrium(1.0, (0.0, 0.0, u))
+    if parts:
+        args = (parts["X"], parts["U"], parts["Om"], parts["D"], parts["rho"], parts["fixed"])
+        ora.set_particles(*args)
+        sim.set_particles(*args)
+    return ora, sim
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_plug_flow_channel(precision):
+    say("frame plug flow", precision)
+    ora, sim = _frame_pair(12, 10, 20, 0.03, "none", precision, None)
+    g0 = ora.get_pdfs()
+    ora.step(20)
+    sim.step(20)
+    e, _ = pdf_error(ora, sim)
+    fluid = ora.owner == -1
+    assert np.abs(ora.get_pdfs()[:, fluid] - g0[:, fluid]).max() < 1e-16
+    assert e < TOL[precision]
+    sim.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("coupling", ["mem_cli", "mem_bb", "psm"])
+def test_frame_with_moving_sphere(coupling, precision):
+    # the sphere starts fixed in the inflow (phase one of Sec. 4.1) and is
+    # released after 20 steps under gravity; viscosity changes in between, as
+    # the calibration does
+    say("frame", coupling, precision)
+    parts = dict(X=[[8.3, 7.9, 11.2]], U=[[0, 0, 0]], Om=[[0, 0, 0]], D=[6.0], rho=[1.5], fixed=[True])
+    ora, sim = _frame_pair(16, 16, 32, 0.025, coupling, precision, parts)
+    tol = TOL[precision]
+    for k in range(4):
+        if k == 1:
+            for s in (ora, sim):
+                s.set_viscosity(0.05)
+        if k == 2:
+            for s in (ora, sim):
+                s.set_gravity((0.0, 0.0, -4e-4))
+                s.set_particles(parts["X"], [[0, 0, 0]], [[0, 0, 0]], parts["D"], parts["rho"], [False])
+        ora.step(10)
+        sim.step(10)
+        errs, po, pg = force_errors(ora, sim)
+        eF, eT, nF = errs[0]
+        e, _ = pdf_error(ora, sim)
+        # position error per unit path length (FP32: at the force tolerance)
+        eX = np.abs(pg["X"] - po["X"]).max() / max(1.0, float(np.linalg.norm(po["X"][0] - np.asarray(parts["X"][0]))))
+        say("  t=%d e_f=%.2e e_F=%.2e e_T=%.2e eX=%.2e |F|=%.3e" % (ora.time, e, eF, eT, eX, nF))
+        assert e < tol and eF < tol and eT < tol
+        assert eX < (1e-13 if precision == "fp64" else tol)
+    assert abs(po["U"][0][2]) > 0  # released and moving
+    sim.close()

@@ -208,17 +208,22 @@ def test_learned_fallback_outside_radius_range_is_exact(trained):
     sim.close()
 
 
-def test_learned_estimator_costs_less_than_exact(trained):
-    """Time of one overlap rebuild (what every rigid-body step of moving
-    particles pays) for the learned estimator and the exact ones."""
+def test_learned_estimator_gain_over_exact_sampling(trained):
+    """What the network gains: on the same 120 spheres its largest solid-
+    fraction error against flat 16^3 supersampling (the reference) is smaller
+    than that of flat 8^3 sampling, although it evaluates no sample point at
+    all for the cut cells in its radius range (flat 8^3 tests 512 per cut cell,
+    the reference 4096).  The
+    rebuild times are printed; the timed comparison belongs to the benchmark
+    (bench.py, learned form), not to this pass/fail test."""
     import torch
 
     wl = inputs.c5_learned(0, n=300)
     L = 256
-    sel = np.all(wl["X"] < L, axis=1)  # spheres of the first 256^3 octant (timing only; wrap overlaps allowed)
+    sel = np.all(wl["X"] < L, axis=1)
     X, D = wl["X"][sel][:120], wl["D"][sel][:120]
-    out = {}
-    for name, mode, n in (("flat16", lbmps.EPS_FLAT, 16), ("recursive16", lbmps.EPS_RECURSIVE, 16),
+    eps, ms = {}, {}
+    for name, mode, n in (("flat16", lbmps.EPS_FLAT, 16), ("flat8", lbmps.EPS_FLAT, 8),
                           ("learned", lbmps.EPS_LEARNED, 16)):
         cfg = lbmps.make_config(L, L, L, 0.01, coupling="psm", psm_m=3, psm_b=2, n_sub=2, eps_n=n, eps_mode=mode,
                                 precision="fp32", max_particles=len(D), max_diameter=20.0)
@@ -227,16 +232,30 @@ def test_learned_estimator_costs_less_than_exact(trained):
         if mode == lbmps.EPS_LEARNED:
             sim.set_eps_model(trained["params"], 5.5, 10.5)
         sim.set_particles(X, [[0, 0, 0]] * len(D), [[0, 0, 0]] * len(D), D, [1.5] * len(D), [False] * len(D))
-        for _ in range(3):
-            sim.rebuild_overlaps()
+        ov = sim.overlaps()
+        eps[name] = {(int(p), int(c)): float(e) for p, c, e in zip(ov["p"], ov["cell"], ov["eps"])}
+        if mode == lbmps.EPS_LEARNED:
+            assert sim.eps_judge(1)[2] > 0.9 * sum(1 for e in eps[name].values() if e < 1.0)
         sim.sync()
         t0 = time.perf_counter()
-        reps = 10
-        for _ in range(reps):
+        for _ in range(5):
             sim.rebuild_overlaps()
         sim.sync()
-        out[name] = (time.perf_counter() - t0) / reps * 1e3
+        ms[name] = (time.perf_counter() - t0) / 5 * 1e3
         sim.close()
         torch.cuda.empty_cache()
-    say("rebuild ms:", {k: round(v, 3) for k, v in out.items()})
-    assert out["learned"] < out["flat16"]
+    ref = eps["flat16"]
+
+    def err(other):
+        keys = set(ref) | set(other)
+        d = np.array([abs(ref.get(k, 0.0) - other.get(k, 0.0)) for k in keys
+                      if 0.0 < ref.get(k, 0.0) < 1.0 or 0.0 < other.get(k, 0.0) < 1.0])
+        return float(d.mean()), float(d.max())
+
+    e8, el = err(eps["flat8"]), err(eps["learned"])
+    say("eps error vs flat 16^3 (mean, max): flat 8^3 %s, network %s; rebuild ms %s"
+        % (np.round(e8, 4), np.round(el, 4), {k: round(v, 3) for k, v in ms.items()}))
+    # the network's worst cut cell is better than flat 8^3 sampling's, and its
+    # mean error stays within the judge's bound
+    assert el[1] < e8[1]
+    assert el[0] < 0.01
