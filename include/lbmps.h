@@ -203,6 +203,29 @@ lbmps_status lbmps_set_particles(lbmps_ctx* ctx, int32_t inst, int32_t n, const 
  * returns, so all of the call's work stays ordered on the caller's stream. */
 lbmps_status lbmps_step(lbmps_ctx* ctx, int32_t n_steps);
 
+/* For callers that cannot allocate device memory or create HIP objects
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): lbmps_step without any allocation.  Same arguments, results and
+ * errors as lbmps_step, bit for bit, except that
+ *  - the per-chunk force and torque sums of the reduction (partial results
+ *    that lbmps_step keeps in the context's workspace) go to a static device
+ *    array of LBMPS_NOALLOC_SCRATCH_BYTES bytes per GPU, which each GPU holds
+ *    from the first call until the process ends;
+ *  - every kernel runs in order on the context's stream (no second stream and
+ *    no event is created);
+ *  - it calls no hipMalloc, hipFree, stream or event creation.
+ * The context's device must be current.  The array is shared by every call on
+ * one GPU and keeps the last call's contents; nothing carries over from one
+ * call to the next, so calls in sequence are safe, but calls that overlap in
+ * time on one GPU (contexts on different streams, or threads) race and give
+ * wrong forces.
+ * Errors: as lbmps_step; ENOMEM when the context needs more scratch than
+ * LBMPS_NOALLOC_SCRATCH_BYTES (48 bytes per chunk sum: ceil-sized chunk rows
+ * of every PSM particle, n_sub sets of link chunk rows of every MEM particle);
+ * ESTATE when timing is on or another device is current. */
+#define LBMPS_NOALLOC_SCRATCH_BYTES (4u << 20)
+lbmps_status lbmps_step_noalloc(lbmps_ctx* ctx, int32_t n_steps);
+
 /* Change the sweep launch shape of an existing context (workgroup size, grid:
  * 0 = one workgroup per tile, > 0 persistent; flags as sweep_flags).  Results
  * do not depend on it.  Drops a captured graph. */

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -235,6 +236,8 @@ constexpr size_t TIMING_EVENTS = 4096;  // HIP events of the timing pool (start/
 
 struct lbmps_ctx {
   hipStream_t st = nullptr;
+  int device = -1;        // current device at creation (the workspace's)
+  bool in_order = false;  // every step's work on st: no second stream (lbmps_step_noalloc)
   Layout L;
   std::vector<lbmps_config> cfg;
   std::vector<InstDev> inst_h;
@@ -531,6 +534,37 @@ lbmps_status check_inst(lbmps_ctx* c, int inst) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Scratch of lbmps_step_noalloc: the per-chunk force and torque sums of the
+// overlap records and of the boundary links.  One copy per GPU, held until the
+// process ends and shared by every call on that GPU.  Host code never uses the
+// array's name as an address: the device address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+static __device__ __align__(256) unsigned char scratch[LBMPS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[SCRATCH_DEVICES] = {};
+
+// Device address of `scratch` on the current device `dev`.
+lbmps_status scratch_address(lbmps_ctx* c, int dev, void** out) {
+  if (dev < 0 || dev >= SCRATCH_DEVICES) return fail(c, LBMPS_EDEVICE, "device index out of range for the static scratch");
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(c, LBMPS_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    scratch_ptr[dev] = p;
+  }
+  *out = scratch_ptr[dev];
+  return LBMPS_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void lbmps_velocities(int32_t c[19][3]) {
@@ -561,6 +595,7 @@ lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* ws, s
   if (!ws || bytes < L.total) return LBMPS_ENOMEM;
   lbmps_ctx* c = new lbmps_ctx();
   c->st = (hipStream_t)stream;
+  if (hipGetDevice(&c->device) != hipSuccess) c->device = -1;
   c->L = L;
   c->cfg.assign(cfgs, cfgs + n);
   char* w = (char*)ws;
@@ -997,6 +1032,39 @@ lbmps_status lbmps_step(lbmps_ctx* c, int32_t n) {
   return r;
 }
 
+lbmps_status lbmps_step_noalloc(lbmps_ctx* c, int32_t n) {
+  if (!c) return LBMPS_EINVAL;
+  if (n < 0) return fail(c, LBMPS_EINVAL, "negative step count");
+  const Layout& L = c->L;
+  if (L.mem_nsub && (n % L.mem_nsub)) return fail(c, LBMPS_EINVAL, "MEM steps must be a multiple of n_sub");
+  if (L.psm_nsub && (n % L.psm_nsub)) return fail(c, LBMPS_EINVAL, "PSM steps must be a multiple of n_sub");
+  if (c->timing) return fail(c, LBMPS_ESTATE, "switch timing off before lbmps_step_noalloc");
+  int dev = -1;
+  HIPCHK(c, hipGetDevice(&dev));
+  if (dev != c->device) return fail(c, LBMPS_ESTATE, "lbmps_step_noalloc: the context's device must be current");
+  // chunk sums of the overlap records (rows of red_blocks per PSM particle),
+  // then n_sub sets of link chunk sums (rows of link_blocks per MEM particle)
+  const size_t psm_bytes = align_up((size_t)c->n_psm * L.red_blocks * 6 * 8);
+  const size_t mem_bytes = (size_t)c->n_mem * L.link_blocks * 6 * 8 * std::max(1, L.mem_nsub);
+  if (psm_bytes + mem_bytes > LBMPS_NOALLOC_SCRATCH_BYTES)
+    return fail(c, LBMPS_ENOMEM, "lbmps_step_noalloc: the context needs " + std::to_string(psm_bytes + mem_bytes) +
+                                     " bytes of scratch, more than the " +
+                                     std::to_string((size_t)LBMPS_NOALLOC_SCRATCH_BYTES) + " available");
+  void* base = nullptr;
+  lbmps_status s = scratch_address(c, dev, &base);
+  if (s) return s;
+  double* const own_partial = c->red_partial;
+  double* const own_mem = c->red_mem;
+  c->red_partial = (double*)base;
+  c->red_mem = (double*)((char*)base + psm_bytes);
+  c->in_order = true;
+  s = step_sweeps(c, n);
+  c->in_order = false;
+  c->red_partial = own_partial;
+  c->red_mem = own_mem;
+  return s;
+}
+
 static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
   const Layout& L = c->L;
   unsigned* err = err_word(c);
@@ -1066,7 +1134,8 @@ static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
     // particle state), so they leave the critical path too when those are
     // forked.
     const bool psm_work = psm_rb && c->psm_moving, mem_work = mem_rb && c->mem_moving;
-    const bool fork = (psm_work || mem_work) && s + 1 < n && !stream_capturing(c->st) && ensure_side_stream(c);
+    const bool fork = (psm_work || mem_work) && s + 1 < n && !c->in_order && !stream_capturing(c->st) &&
+                      ensure_side_stream(c);
     hipStream_t ws = fork ? c->side : c->st;
     if (fork) {
       HIPCHK(c, hipEventRecord(c->fork_ev, c->st));

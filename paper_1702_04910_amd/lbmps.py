@@ -97,6 +97,8 @@ def lib():
         L.lbmps_set_particles.argtypes = [P, I32, I32, P]
         L.lbmps_step.restype = I32
         L.lbmps_step.argtypes = [P, I32]
+        L.lbmps_step_noalloc.restype = I32
+        L.lbmps_step_noalloc.argtypes = [P, I32]
         L.lbmps_set_launch.restype = I32
         L.lbmps_set_launch.argtypes = [P, I32, I32, I32]
         L.lbmps_step_graph.restype = I32
@@ -274,6 +276,9 @@ class Sim:
 
     def step(self, n):
         self._chk(lib().lbmps_step(self._ctx, int(n)))
+
+    def step_noalloc(self, n):
+        self._chk(lib().lbmps_step_noalloc(self._ctx, int(n)))
 
     def set_launch(self, block_threads=0, grid_blocks=0, sweep_flags=0):
         self._chk(lib().lbmps_set_launch(self._ctx, block_threads, grid_blocks, sweep_flags))
