@@ -194,6 +194,10 @@ lbmps_status lbmps_set_particles(lbmps_ctx* ctx, int32_t inst, int32_t n, const 
 
 /* Advance every instance by n_steps LBM time steps (Alg. 1 / Alg. 2);
  * n_steps must be a multiple of every n_sub in the context.  Asynchronous.
+ * A rigid-body step that would move a particle by a cell or more, or give it
+ * a non-finite state, is not taken (the particle keeps its position and
+ * velocities) and is reported as LBMPS_EUNSTABLE by the next synchronising
+ * call; the fluid state after it is not meaningful.
  * Within one call, when its stream is not being captured, the PSM list
  * rebuild and the MEM remap after a rigid-body step run (one after the other)
  * on a second stream of the library beside the next sweep, which then leaves

@@ -344,7 +344,8 @@ lbmps_status check_device_errors(lbmps_ctx* c) {
   unsigned e = 0;
   HIPCHK(c, hipMemcpyAsync(&e, err_word(c), sizeof(unsigned), hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
-  if (e & ERR_UNSTABLE) return fail(c, LBMPS_EUNSTABLE, "non-finite particle state or a particle moved >= 1 cell per rigid-body step");
+  if (e & ERR_UNSTABLE)
+    return fail(c, LBMPS_EUNSTABLE, "unstable rigid-body step (a particle would move >= 1 cell or its state is not finite); not taken");
   if (e & ERR_LINK_CAP) return fail(c, LBMPS_ENOMEM, "boundary-link capacity exceeded");
   if (e & ERR_PAIR_CAP) return fail(c, LBMPS_ENOMEM, "overlap-pair capacity exceeded");
   if (e & ERR_REFILL_CAP) return fail(c, LBMPS_ENOMEM, "refill-list capacity exceeded");

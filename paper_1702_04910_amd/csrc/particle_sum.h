@@ -38,17 +38,30 @@ __device__ inline void rigid_update(int p, const InstDev* __restrict__ insts, co
     const double m = P.rho[p] * V;
     const double inertia = m * D * D / 10.0;
     const double L[3] = {(double)I.nx, (double)I.ny, (double)I.nz};
+    double Un[3], Xn[3], On[3];
     for (int k = 0; k < 3; ++k) {
       const double ftot = (F[k] + (P.rho[p] - 1.0) * V * I.grav[k]) + V * I.fext[k];
       const double u_old = P.U[3 * p + k];
-      P.U[3 * p + k] = u_old + dt * ftot / m;
+      Un[k] = u_old + dt * ftot / m;
       double x = P.X[3 * p + k] + dt * u_old;
       if (x >= L[k]) x -= L[k];
       if (x < 0.0) x += L[k];
-      P.X[3 * p + k] = x;
-      P.Om[3 * p + k] = P.Om[3 * p + k] + dt * T[k] / inertia;
-      bad |= !isfinite(P.U[3 * p + k]) || fabs(dt * u_old) >= 1.0;
+      Xn[k] = x;
+      On[k] = P.Om[3 * p + k] + dt * T[k] / inertia;
+      // a step of a cell or more (or a non-finite one) leaves the bounds the
+      // remap assumes (bounding boxes start at floor(X - R - 2), the cells
+      // uncovered since the last remap lie within one cell of the box)
+      bad |= !(fabs(dt * u_old) < 1.0) || !isfinite(Un[k]) || !isfinite(On[k]);
     }
+    // an unstable step is reported and not taken: the particle keeps a
+    // finite position inside the box, so every index derived from it stays
+    // in bounds until the caller sees LBMPS_EUNSTABLE
+    if (!bad)
+      for (int k = 0; k < 3; ++k) {
+        P.U[3 * p + k] = Un[k];
+        P.X[3 * p + k] = Xn[k];
+        P.Om[3 * p + k] = On[k];
+      }
   }
   if (bad) atomicOr(err, (unsigned)ERR_UNSTABLE);
 }

@@ -76,11 +76,16 @@ RE_PER_CELL_MAX = 8.0
 
 def c4_batch(seed=0, n=48):
     """48 settling-sphere instances: D from {8, 12, 16, 24}, box 6D x 6D x 12D,
-    density ratio in [1.1, 1.5], target Re in [185, 365] capped at
-    RE_PER_CELL_MAX * D (coarse spheres are not stable at the full Reynolds
-    number, Sec. 4.3 reports D = 18 already unstable at Ga = 178), nu = 0.1 D / Re
-    for a terminal speed ~0.1, coupling MEM-CLI or PSM-M2B2 by the seed (M3B2 was
-    not stable at the resulting relaxation times tau ~ 0.54 for D = 8)."""
+    density ratio in [1.1, 1.5], target Re drawn in [185, 365] and capped at
+    RE_PER_CELL_MAX * D (64, 96, 128, 192), nu = 0.1 D / Re for a terminal speed
+    ~0.1; coupling MEM-CLI or PSM-M2B2 by the seed (M3B2 was not stable at the
+    relaxation times tau ~ 0.54 of D = 8).  The cap is a deviation from the
+    configured Reynolds numbers: with the drawn values these spheres of 8-24
+    cells run at tau = 0.51-0.53, and a batch with the drawn values for D = 16
+    and 24 failed within its first 500 sweeps (taken to be a diverging sphere,
+    the failure the rigid-body step now reports as LBMPS_EUNSTABLE); the paper
+    itself resolves the sphere with 18-48 cells, and Sec. 4.3 reports D = 18
+    unstable already at Ga = 178 for some couplings."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(n):

@@ -171,3 +171,26 @@ def test_sampled_sweep_timing():
     assert sim.timing()[1] == 5
     sim.set_timing(False)
     sim.close()
+
+
+@pytest.mark.parametrize("coupling", ["mem_cli", "psm"])
+def test_unstable_rigid_step_is_reported_and_not_taken(coupling):
+    # A sphere set moving at two cells per sweep: its first rigid-body step
+    # (two sweeps) would move it by four cells.  The library reports
+    # LBMPS_EUNSTABLE and leaves the sphere where it was, so every index
+    # derived from its position stays inside the box.
+    say("unstable rigid step", coupling)
+    cfg = lbmps.make_config(24, 24, 24, 0.05, coupling=coupling, psm_m=2, psm_b=2, n_sub=2, eps_n=4,
+                            max_particles=1, max_diameter=6.0)
+    sim = lbmps.Sim(cfg)
+    sim.init_equilibrium()
+    X = [11.3, 12.2, 12.7]
+    sim.set_particles([X], [[2.0, 0.0, 0.0]], [[0, 0, 0]], [6.0], [1.5], [False])
+    sim.step(2)
+    with pytest.raises(lbmps.LbmpsError) as ei:
+        sim.sync()
+    assert ei.value.status == -4
+    with pytest.raises(lbmps.LbmpsError):  # the flag stays set
+        sim.particles()
+    sim.close()
+
