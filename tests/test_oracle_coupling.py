@@ -14,7 +14,6 @@ from oracle import rigid as rb
 from oracle.lattice import C, CF, W, OPP, Q
 from oracle.sim import OracleSim
 
-import drag_common as dc
 
 RNG = np.random.default_rng(99)
 
@@ -399,36 +398,3 @@ def test_psm_is_bgk_with_modified_relaxation_time():
     alt = g[:, mask] + (fl.geq(rho, U)[:, mask] - g[:, mask]) / tau_psm + solid_sum[:, mask] + \
         (1 - B[mask]) * fl.forcing(U, s.fext)[:, mask]
     assert np.abs(alt - gt[:, mask]).max() < 1e-17
-
-
-# --------------------------------------------------------------------------- Fig. 1
-class _OracleDrag:
-    def __init__(self, coupling, tau, m=0, b=0):
-        nu = (tau - 0.5) / 3.0
-        coll = "trt" if coupling.startswith("mem") else "bgk"
-        self.s = OracleSim(dc.L_BOX, dc.L_BOX, dc.L_BOX, nu, collision=coll, coupling=coupling, psm_m=m, psm_b=b,
-                           fext=(dc.A_FORCE, 0, 0), eps_n=8)
-        self.s.init_equilibrium()
-        c = dc.L_BOX / 2.0
-        self.s.set_particles([[c, c, c]], [[0, 0, 0]], [[0, 0, 0]], [dc.D_SPHERE], [1.0], [True])
-        self.nu = nu
-
-    def step(self, n):
-        self.s.step(n)
-
-    def force_x(self):
-        return self.s.F[0, 0]
-
-    def mean_ux(self):
-        return self.s.fields()[1][0].mean()
-
-
-@pytest.mark.slow
-@pytest.mark.parametrize("coupling,m,b,tol", [("mem_cli", 0, 0, 0.003), ("psm", 3, 2, 0.01)])
-def test_fig1_drag_error(coupling, m, b, tol):
-    tau = 1.5
-    sim = _OracleDrag(coupling, tau, m, b)
-    err, steps = dc.run_to_convergence(sim, sim.nu)
-    label = dc.LABELS[coupling] if coupling.startswith("mem") else dc.LABELS[(m, b)]
-    ref = dc.paper_value(label, tau)
-    assert abs(err - ref) < tol, (err, ref, steps)
