@@ -63,6 +63,9 @@ typedef int32_t lbmps_status;
 #define LBMPS_FP32 1
 #define LBMPS_FP16_DEV 2 /* IEEE half deviations g = f - w, round to nearest even */
 #define LBMPS_BF16_DEV 3 /* bfloat16 deviations g = f - w, round to nearest even */
+/* reconstruction of uncovered MEM cells (Sec. 2.2.3) */
+#define LBMPS_REFILL_EXTRAPOLATE 0
+#define LBMPS_REFILL_EQUILIBRIUM 1
 /* solid-fraction estimator (Sec. 2.3.2) */
 #define LBMPS_EPS_FLAT 0      /* eps_n^3 sub-cell sample points, every point tested */
 #define LBMPS_EPS_RECURSIVE 1 /* same points, octree blocks classified at once (eps_n power of 2) */
@@ -102,7 +105,10 @@ typedef struct lbmps_config {
                             reserving LDS (value 3 is invalid);
                             bit 7 two x-adjacent cells per sweep thread, moved as one word per direction
                             (needs an even nx; ignored with bit 3 and while bit 1 or 4 is in effect) */
-  int32_t reserved;
+  int32_t refill;        /* MEM reconstruction of uncovered cells (Sec. 2.2.3): LBMPS_REFILL_EXTRAPOLATE (0, the
+                            paper's: extrapolation along the surface normal, then fallbacks) or
+                            LBMPS_REFILL_EQUILIBRIUM (1: every uncovered cell takes the last fallback,
+                            f^eq(rho_bar, v)); both then impose the velocity */
   double max_diameter;   /* largest particle diameter that will be set (cells) */
   double nu;             /* kinematic viscosity, nu = (tau - 1/2)/3 (Eq. Viscosity) */
   double magic;          /* TRT parameter Lambda (default 3/16 when 0) */
@@ -328,6 +334,14 @@ lbmps_status lbmps_mlp_get_params(lbmps_mlp* m, float* host);
 /* Training set: n rows (R, d_x, d_y, d_z), FP64, host.  Features are formed
  * on the device.  Clears the targets.  Errors: EINVAL (n out of range, R <= 0). */
 lbmps_status lbmps_mlp_set_samples(lbmps_mlp* m, int64_t n, const double* host_rd);
+/* Inputs in use: 5 (default: |d| - R, the three sorted direction cosines,
+ * 8/R) or 3 (|d| - R and the two largest direction cosines, without the
+ * curvature term: the three-input variant the network's design is compared
+ * with).  Unused inputs are set to zero, so their weights get no gradient; a
+ * network trained with 3 inputs from zero weights on inputs 3 and 4 evaluates
+ * the same with all features present.  Recomputes the current samples'
+ * features.  Errors: EINVAL (n_inputs not 3 or 5). */
+lbmps_status lbmps_mlp_set_inputs(lbmps_mlp* m, int32_t n_inputs);
 /* Targets: eps_s of every sample by flat supersampling with eps_n^3 points
  * (count / eps_n^3, rounded to FP32). */
 lbmps_status lbmps_mlp_label(lbmps_mlp* m, int32_t eps_n);

@@ -171,8 +171,10 @@ def check_link_balance(L, P):
             raise ValueError("unbalanced links for particle %d: particles in contact are not supported" % p)
 
 
-def refill_cell(g, owner, newmask, cell, Xp, Up, Omp, fext, box_shape):
-    """PDF reconstruction of one newly uncovered cell (iz, iy, ix); returns g (19,)."""
+def refill_cell(g, owner, newmask, cell, Xp, Up, Omp, fext, box_shape, equilibrium=False):
+    """PDF reconstruction of one newly uncovered cell (iz, iy, ix); returns g (19,).
+    equilibrium=True skips the extrapolation: every uncovered cell takes the
+    last fallback, f^eq(rho_bar, v(x)) (then the same velocity constraint)."""
     nz, ny, nx = box_shape
     iz, iy, ix = cell
     d = np.array([float(centre_disp(ix, Xp[0], nx)), float(centre_disp(iy, Xp[1], ny)),
@@ -194,7 +196,7 @@ def refill_cell(g, owner, newmask, cell, Xp, Up, Omp, fext, box_shape):
     src = []
     for k in (1, 2, 3):
         z, y, x = (iz + k * cn[2]) % nz, (iy + k * cn[1]) % ny, (ix + k * cn[0]) % nx
-        if not ok(z, y, x):
+        if equilibrium or not ok(z, y, x):
             break
         src.append(g[:, z, y, x])
     v = surface_velocity(Up, Omp, d)

@@ -34,7 +34,7 @@ from . import rigid as rb
 class OracleSim:
     def __init__(self, nx, ny, nz, nu, collision="trt", magic=3.0 / 16.0, coupling="none",
                  psm_m=1, psm_b=1, fext=(0.0, 0.0, 0.0), gravity=(0.0, 0.0, 0.0), n_sub=None,
-                 eps_n=8, eps_recursive=False, eps_estimator=None):
+                 eps_n=8, eps_recursive=False, eps_estimator=None, refill="extrapolation"):
         self.shape = (nz, ny, nx)
         self.box = np.array([nx, ny, nz], dtype=np.float64)
         self.nu = float(nu)
@@ -50,7 +50,8 @@ class OracleSim:
         self.n_sub = n_sub
         self.eps_n = eps_n
         self.eps_recursive = eps_recursive
-        self.eps_estimator = eps_estimator  # None (supersampling), 'edge' or 'distance' 
+        self.eps_estimator = eps_estimator  # None (supersampling), 'edge' or 'distance'
+        self.refill_equilibrium = refill == "equilibrium"  # else the extrapolation of Sec. 2.2.3
         self.g = np.zeros((19,) + self.shape)
         self.owner = np.full(self.shape, mm.FLUID, dtype=np.int64)
         self.v_walls = []
@@ -138,7 +139,8 @@ class OracleSim:
                     p = old[iz, iy, ix]
                     part = self.parts[p]
                     gnew[:, iz, iy, ix] = mm.refill_cell(self.g, new, newly, (iz, iy, ix), part["X"], part["U"],
-                                                         part["Om"], self.fext, self.shape)
+                                                         part["Om"], self.fext, self.shape,
+                                                         equilibrium=self.refill_equilibrium)
                 self.g = gnew
                 self.refilled += len(cells)
             self._mask_solid()

@@ -89,6 +89,7 @@ bool valid_cfg(const lbmps_config& c, std::string& err) {
     err = "sweep_flags: the PSM modes (fused, separate, staged) are exclusive"; return false;
   }
   if (c.n_sub < 0) { err = "n_sub must be >= 0"; return false; }
+  if (c.refill != LBMPS_REFILL_EXTRAPOLATE && c.refill != LBMPS_REFILL_EQUILIBRIUM) { err = "unknown refill"; return false; }
   if (10LL * (long long)storage_size(c.precision) * c.nx > SWEEP_LDS_LIMIT) {
     err = "nx too large for the LDS-staged sweep (10 * nx * element size must be <= 64 KiB)"; return false;
   }
@@ -703,6 +704,7 @@ lbmps_status lbmps_batch_create(int32_t n, const lbmps_config* cfgs, void* ws, s
     I.part_count = 0;
     I.eps_n = cf.eps_n ? cf.eps_n : 8;
     I.eps_mode = cf.eps_mode;
+    I.refill = cf.refill;
     c->inst_h.push_back(I);
     const int tr = eff_tile_rows(cf);
     const int rows = cf.ny * cf.nz;
@@ -1066,6 +1068,18 @@ lbmps_status lbmps_step_noalloc(lbmps_ctx* c, int32_t n) {
   return s;
 }
 
+// Per-particle PSM force/torque of the sweep: the chunk sums the overlap kernel
+// formed (chunked) or a reduction of the per-pair records (inline mode), then
+// the fixed-order finishing sum, with the rigid-body step when insts is given.
+static hipError_t psm_sums(lbmps_ctx* c, bool chunked, const InstDev* insts, hipStream_t st) {
+  const Layout& L = c->L;
+  if (chunked)
+    return launch_finish_sums(psm_list(c), c->n_psm, c->pbeg, c->pend, RED_CHUNK, L.red_blocks, c->red_partial, 1, 0,
+                              c->parts, insts, err_word(c), st);
+  return launch_reduce(psm_list(c), c->n_psm, c->pbeg, c->pend, 0, c->pairs.out, c->pairs.ostride, c->parts,
+                       L.red_blocks, c->red_partial, insts, err_word(c), st);
+}
+
 static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
   const Layout& L = c->L;
   unsigned* err = err_word(c);
@@ -1077,9 +1091,13 @@ static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
     // (all modes give the same bits)
     const bool lists_pending = c->join_pending && c->join_lists;
     const int pm = c->n_psm && !lists_pending ? c->psm_mode : PSM_SEPARATE;
+    // outside the inline mode the overlap kernel also forms the chunk sums of
+    // the force/torque terms (no record round trip); finish_sums adds them
+    const PsmSums sums{psm_list(c), c->n_psm, c->pbeg, c->pend, L.red_blocks, c->red_partial};
+    const PsmSums* psum = pm == PSM_FUSED ? nullptr : &sums;
     if (pm == PSM_STAGED)  // overlapped cells first, from the same pre-collision values
       HIPCHK(c, launch_psm_collide(L.prec, L.psm_m, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs,
-                                   c->cellmap, src, dst, c->stage, L.pair_cap, false, c->st));
+                                   c->cellmap, src, dst, c->stage, L.pair_cap, false, c->st, psum));
     const bool timed = c->timing && (c->timing_seq++ % c->timing_stride) == 0;
     if (timed) {
       if (c->ev_used + 2 > c->ev.size()) {  // every event of the pool is recorded: read them out
@@ -1109,10 +1127,9 @@ static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
     if (c->n_psm) {
       if (pm != PSM_STAGED)  // after the sweep: every overlapped cell, or (inline mode) the shared ones
         HIPCHK(c, launch_psm_collide(L.prec, L.psm_m, c->counts + 1, L.pair_cap, c->inst_d, c->parts, c->pairs,
-                                     c->cellmap, src, dst, nullptr, 0, pm == PSM_FUSED, c->st));
+                                     c->cellmap, src, dst, nullptr, 0, pm == PSM_FUSED, c->st, psum));
       if (!psm_rb)  // the rigid-body sweep's sum goes with the rebuild, below
-        HIPCHK(c, launch_reduce(psm_list(c), c->n_psm, c->pbeg, c->pend, 0, c->pairs.out, c->pairs.ostride,
-                                c->parts, L.red_blocks, c->red_partial, nullptr, err, c->st));
+        HIPCHK(c, psm_sums(c, psum != nullptr, nullptr, c->st));
     }
     if (c->n_mem || c->n_wall) {
       // the link sums of the sweeps of a rigid-body step wait in their own sets
@@ -1143,8 +1160,7 @@ static lbmps_status step_sweeps(lbmps_ctx* c, int32_t n) {
       HIPCHK(c, hipStreamWaitEvent(c->side, c->fork_ev, 0));
     }
     if (psm_rb)
-      HIPCHK(c, launch_reduce(psm_list(c), c->n_psm, c->pbeg, c->pend, 0, c->pairs.out, c->pairs.ostride, c->parts,
-                              L.red_blocks, c->red_partial, c->inst_d, err, psm_work ? ws : c->st));
+      HIPCHK(c, psm_sums(c, psum != nullptr, c->inst_d, psm_work ? ws : c->st));
     if (mem_rb)
       HIPCHK(c, launch_finish_sums(mem_list(c), c->n_mem, c->lbeg, c->lend, SUM_THREADS, L.link_blocks, c->red_mem,
                                    L.mem_nsub, (long long)c->n_mem * L.link_blocks * 6, c->parts, c->inst_d, err,
@@ -1433,6 +1449,7 @@ struct lbmps_mlp {
         *partial = nullptr;
   double* rd = nullptr;
   int step = 0;
+  int n_inputs = 5;  // features in use (the rest are zero)
   bool labelled = false;
   std::string last;
 };
@@ -1553,10 +1570,21 @@ lbmps_status lbmps_mlp_set_samples(lbmps_mlp* m, int64_t n, const double* rd) {
     if (!ok) return mfail(m, LBMPS_EINVAL, "samples need finite values and R > 0");
   }
   MHIPCHK(m, hipMemcpyAsync(m->rd, rd, (size_t)n * 32, hipMemcpyHostToDevice, m->st));
-  MHIPCHK(m, launch_mlp_features(m->rd, n, m->X, m->st));
+  MHIPCHK(m, launch_mlp_features(m->rd, n, m->n_inputs, m->X, m->st));
   MHIPCHK(m, hipStreamSynchronize(m->st));
   m->n = n;
   m->labelled = false;
+  return LBMPS_OK;
+}
+
+lbmps_status lbmps_mlp_set_inputs(lbmps_mlp* m, int32_t n_inputs) {
+  if (!m) return LBMPS_EINVAL;
+  if (n_inputs != 3 && n_inputs != 5) return mfail(m, LBMPS_EINVAL, "n_inputs must be 3 or 5");
+  m->n_inputs = n_inputs;
+  if (m->n > 0) {  // the features of the current samples again (the targets stay)
+    MHIPCHK(m, launch_mlp_features(m->rd, m->n, m->n_inputs, m->X, m->st));
+    MHIPCHK(m, hipStreamSynchronize(m->st));
+  }
   return LBMPS_OK;
 }
 

@@ -79,6 +79,7 @@ struct InstDev {
   double fext[3];
   double grav[3];
   int part_begin, part_count, eps_n, eps_mode;
+  int refill, pad_;  // MEM reconstruction: 0 extrapolation (Sec. 2.2.3), 1 equilibrium for every uncovered cell
 };
 
 // Particle state, structure of arrays of doubles, global over all instances.

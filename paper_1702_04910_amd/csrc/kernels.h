@@ -133,16 +133,27 @@ hipError_t launch_psm_cellmap(int stage, const int* count, int cap, const InstDe
 // pushed into dst or,
 // with stage != nullptr, stored per leader pair for the sweep that follows.  psm_m: the solid operator shared by
 // every PSM instance (1..3), or 0 when they differ.
+// With sums (and not shared_only): the shared cells first, then the single-pair cells per particle (list
+// positions [0, nlist) with pair ranges [begin[j], end[j])), which also store the force/torque chunk sums of
+// every pair of the range (width chunk rows per particle, as launch_reduce) in partial, for launch_finish_sums
+// with chunk RED_CHUNK; no reduce launch is needed.
+struct PsmSums {
+  const int* list;
+  int nlist;
+  const int *begin, *end;
+  int width;
+  double* partial;
+};
 hipError_t launch_psm_collide(int prec, int psm_m, const int* count, int cap, const InstDev* insts, PartDev parts,
                               PairDev pairs, const int* cellmap, const void* src, void* dst, void* stage,
-                              long long sstride, bool shared_only, hipStream_t st);
+                              long long sstride, bool shared_only, hipStream_t st, const PsmSums* sums = nullptr);
 hipError_t launch_psm_fields(int prec, const int* count, int cap, const InstDev* insts, PartDev parts, PairDev pairs,
                              const int* cellmap, const void* buf, int inst, long long c0, long long n, double* out,
                              hipStream_t st);
 
 // ---- mlp.hip
 int mlp_nparam();
-hipError_t launch_mlp_features(const double* rd, long long n, float* X, hipStream_t st);
+hipError_t launch_mlp_features(const double* rd, long long n, int n_inputs, float* X, hipStream_t st);
 hipError_t launch_mlp_infer(const float* P, const float* X, long long n, float* y, hipStream_t st);
 hipError_t launch_mlp_infer_count(const float* P, const float* X, const int* count, long long cap, float* y,
                                   hipStream_t st);

@@ -263,7 +263,8 @@ hipError_t launch_mem_fill_links(const int* list, int nlist, int side, int nspli
 //  * sources x + k c_qn, k = 1..3, must be fluid cells that were fluid before the
 //    remap; quadratic 3 f1 - 3 f2 + f3, else linear 2 f1 - f2, else constant f1,
 //    else f^eq(rho0 + drho_bar, v(x)) with drho_bar the mean density fluctuation
-//    of the old-fluid neighbours (0 if there are none);
+//    of the old-fluid neighbours (0 if there are none); the equilibrium
+//    reconstruction (I.refill) takes that last rule for every uncovered cell;
 //  * velocity constraint: f_q += c_q.(j* - j)/10 with j* = v(x) - f_ext/2.
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -313,7 +314,7 @@ __global__ __launch_bounds__(256) void mem_refill_kernel(const int* __restrict__
     // all three owner entries and (below) source PDFs are read before any is
     // tested, so their loads are in flight together
     const int os[3] = {own[src_cell[0]], own[src_cell[1]], own[src_cell[2]]};
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 3 && !I.refill; ++k) {  // no extrapolation sources for the equilibrium reconstruction
       if (os[k] != OWN_FLUID) break;
       ++ns;
     }

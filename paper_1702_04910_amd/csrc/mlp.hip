@@ -359,21 +359,22 @@ __global__ void mlp_reduce_adam_kernel(float* __restrict__ P, const float* __res
   P[k] -= lr * mh / (sqrtf(vh) + eps);
 }
 
-// Features of samples (R, dx, dy, dz) given in FP64.
-__global__ void mlp_features_kernel(const double* __restrict__ rd, long long n, float* __restrict__ X) {
+// Features of samples (R, dx, dy, dz) given in FP64; features from index
+// n_inputs on are zero (a network trained so has no use for them).
+__global__ void mlp_features_kernel(const double* __restrict__ rd, long long n, int n_inputs, float* __restrict__ X) {
   const long long s = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
   const double d[3] = {rd[4 * s + 1], rd[4 * s + 2], rd[4 * s + 3]};
   float x[NIN];
   eps_features(d, rd[4 * s], x);
 #pragma unroll
-  for (int k = 0; k < NIN; ++k) X[s * NIN + k] = x[k];
+  for (int k = 0; k < NIN; ++k) X[s * NIN + k] = k < n_inputs ? x[k] : 0.f;
 }
 
 // ------------------------------------------------------------------------ launchers
-hipError_t launch_mlp_features(const double* rd, long long n, float* X, hipStream_t st) {
+hipError_t launch_mlp_features(const double* rd, long long n, int n_inputs, float* X, hipStream_t st) {
   if (n <= 0) return hipSuccess;
-  hipLaunchKernelGGL(mlp_features_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rd, n, X);
+  hipLaunchKernelGGL(mlp_features_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, rd, n, n_inputs, X);
   return hipGetLastError();
 }
 

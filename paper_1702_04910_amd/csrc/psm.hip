@@ -16,6 +16,7 @@
 #include "bbox.h"
 #include "common.h"
 #include "kernels.h"
+#include "particle_sum.h"
 #include "psm_cell.h"
 
 namespace lbm {
@@ -602,6 +603,70 @@ __attribute__((amdgpu_waves_per_eu(MULTI || M == 0 || sizeof(S) == 8 ? 1 : 4))) 
   }
 }
 
+// Cells of a single pair visited per particle: workgroup (k, j) takes the
+// chunks k, k + gridDim.x, ... of RED_CHUNK pairs of list position j's pair
+// range, each thread the pairs cb + t, cb + t + SUM_THREADS, ... of a chunk --
+// the order in which reduce_kernel reads force records.  A thread adds the
+// force/torque terms of its single-pair cells, computed here and kept in
+// registers, and the records of its pairs in shared cells (written before by
+// the shared-cell launch); the chunk sums are those reduce_kernel would form
+// from a complete record array, bit for bit, without writing and reading the
+// 48-byte record of every pair.  finish_sums_kernel adds them per particle.
+template <typename S, int M>
+__global__ __launch_bounds__(SUM_THREADS)
+__attribute__((amdgpu_waves_per_eu(M == 0 || sizeof(S) == 8 ? 1 : 4))) void psm_collide_sum_kernel(
+    const int* __restrict__ list, const int* __restrict__ begin, const int* __restrict__ end,
+    const InstDev* __restrict__ insts, PartDev P, PairDev pairs, const int* __restrict__ cellmap,
+    const S* __restrict__ src, S* __restrict__ dst, S* __restrict__ stage, long long sstride,
+    double* __restrict__ partial) {
+  using R = typename CompOf<S>::type;
+  const int j = blockIdx.y, kb = blockIdx.x, nb = gridDim.x;
+  const int b = begin[j], e = end[j];
+  const int nch = (e - b + RED_CHUNK - 1) / RED_CHUNK;
+  if (kb >= nch) return;  // no pairs for this workgroup; it takes no part
+  const InstDev& I = insts[P.inst[list[j]]];
+  const S* s = src + I.pdf_off;
+  S* d = dst + I.pdf_off;
+  double sum[6] = {0, 0, 0, 0, 0, 0};
+  for (int ch = kb; ch < nch; ch += nb) {
+    const int cb = b + ch * RED_CHUNK, ce = min(e, cb + RED_CHUNK);
+    double acc[6] = {0, 0, 0, 0, 0, 0}, t[6];
+    for (int L = cb + (int)threadIdx.x; L < ce; L += SUM_THREADS) {
+      const int c = pairs.cell[L];
+      double ft[6];
+      if (pairs.next[L] < 0 && cellmap[I.cellmap_off + c] == L) {  // the cell's only pair
+        R g[Q], out[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) g[q] = Codec<S>::ld(s[pdf_at(c, q)]);
+        psm_cell_collide<M, true, R, true>(g, out, I, P, pairs, L, c, ft);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) out[q] = StochasticRound<S>::apply(out[q], (uint32_t)c * Q + q);
+        if (stage) {
+#pragma unroll
+          for (int q = 0; q < Q; ++q) stage[q * sstride + L] = Codec<S>::st(out[q]);
+        } else {
+          const int nx = I.nx, ny = I.ny, nz = I.nz;
+          const int x = c % nx, yz = c / nx, y = yz % ny, z = yz / ny;
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            const int xa = wrapi(x + cx(q), nx), ya = wrapi(y + cy(q), ny), za = wrapi(z + cz(q), nz);
+            d[pdf_at(((long long)za * ny + ya) * nx + xa, q)] = Codec<S>::st(out[q]);
+          }
+        }
+      } else {  // a pair of a shared cell: its record
+#pragma unroll
+        for (int k = 0; k < 6; ++k) ft[k] = pairs.out[k * pairs.ostride + L];
+      }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) acc[k] += ft[k];
+    }
+    block_sum6(acc, t);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) sum[k] += t[k];
+  }
+  store_chunk_sum(j, kb, nb, sum, partial);
+}
+
 #define LBM_DISPATCH(prec, CALL)                          \
   switch (prec) {                                         \
     case PREC_FP64: { using S = double; CALL; } break;    \
@@ -613,11 +678,30 @@ __attribute__((amdgpu_waves_per_eu(MULTI || M == 0 || sizeof(S) == 8 ? 1 : 4))) 
 
 hipError_t launch_psm_collide(int prec, int psm_m, const int* count, int cap, const InstDev* insts, PartDev parts,
                               PairDev pairs, const int* cellmap, const void* src, void* dst, void* stage,
-                              long long sstride, bool shared_only, hipStream_t st) {
+                              long long sstride, bool shared_only, hipStream_t st, const PsmSums* sums) {
   const int grid = 2048;
 #define PSM_COLLIDE(MM, MULTI)                                                                                      \
   LBM_DISPATCH(prec, hipLaunchKernelGGL((psm_collide_kernel<S, MM, MULTI>), dim3(grid), dim3(256), 0, st, count, cap, \
                                         insts, parts, pairs, cellmap, (const S*)src, (S*)dst, (S*)stage, sstride))
+  if (sums && !shared_only) {
+    if (sums->nlist <= 0) return hipSuccess;
+    PSM_COLLIDE(0, true);  // shared cells first: their records are summed below
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const dim3 g2(sums->width, sums->nlist);
+#define PSM_SUM(MM)                                                                                                \
+  LBM_DISPATCH(prec, hipLaunchKernelGGL((psm_collide_sum_kernel<S, MM>), g2, dim3(SUM_THREADS), 0, st, sums->list,  \
+                                        sums->begin, sums->end, insts, parts, pairs, cellmap, (const S*)src,       \
+                                        (S*)dst, (S*)stage, sstride, sums->partial))
+    switch (psm_m) {
+      case 1: PSM_SUM(1); break;
+      case 2: PSM_SUM(2); break;
+      case 3: PSM_SUM(3); break;
+      default: PSM_SUM(0); break;
+    }
+#undef PSM_SUM
+    return hipGetLastError();
+  }
   if (!shared_only) {
     switch (psm_m) {
       case 1: PSM_COLLIDE(1, false); break;

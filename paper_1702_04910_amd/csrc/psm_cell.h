@@ -114,14 +114,16 @@ __device__ __forceinline__ void add_solid_operator(const R (&g)[Q], R (&acc)[Q],
 
 // g: pre-collision deviations of cell c (instance I), L: the cell's leader
 // pair.  Writes the post-collision deviations to out and the six force/torque
-// components of every member pair to pairs.out.  M in {1, 2, 3} fixes the
-// solid operator at compile time (0: I.psm_m decides); SINGLE declares that L
-// is the cell's only pair.  Both only narrow what is compiled: every
-// specialisation evaluates the same expressions in the same order.
-template <int M, bool SINGLE, typename R>
+// components of every member pair to pairs.out (with FT_REGS, for a SINGLE
+// cell, to ft instead).  M in {1, 2, 3} fixes the solid operator at compile
+// time (0: I.psm_m decides); SINGLE declares that L is the cell's only pair.
+// These only narrow what is compiled: every specialisation evaluates the same
+// expressions in the same order.
+template <int M, bool SINGLE, typename R, bool FT_REGS = false>
 __device__ __forceinline__ void psm_cell_collide(const R (&g)[Q], R (&out)[Q], const InstDev& I, const PartDev& P,
-                                                 const PairDev& pairs, int L, int c) {
+                                                 const PairDev& pairs, int L, int c, double* ft = nullptr) {
 #pragma clang fp contract(off)
+  static_assert(SINGLE || !FT_REGS, "force terms in registers only for cells of a single pair");
   int mem[SINGLE ? 1 : KMAX];
   int k = 1;
   if constexpr (SINGLE)
@@ -178,14 +180,23 @@ __device__ __forceinline__ void psm_cell_collide(const R (&g)[Q], R (&out)[Q], c
       add_solid_operator<3, R>(g, acc, (R)Bm, baseU, ux, uy, uz, baseV, vx, vy, vz, omit, mv);
     // F_s = B_s sum_q Omega_q c_qbar, T_s = (x_s - X_p) x F_s
     const double Fx = Bm * (double)mv[0], Fy = Bm * (double)mv[1], Fz = Bm * (double)mv[2];
-    double* o = pairs.out + mem[m];
-    const long long s = pairs.ostride;
-    o[0] = Fx;
-    o[s] = Fy;
-    o[2 * s] = Fz;
-    o[3 * s] = r[1] * Fz - r[2] * Fy;
-    o[4 * s] = r[2] * Fx - r[0] * Fz;
-    o[5 * s] = r[0] * Fy - r[1] * Fx;
+    if constexpr (FT_REGS) {
+      ft[0] = Fx;
+      ft[1] = Fy;
+      ft[2] = Fz;
+      ft[3] = r[1] * Fz - r[2] * Fy;
+      ft[4] = r[2] * Fx - r[0] * Fz;
+      ft[5] = r[0] * Fy - r[1] * Fx;
+    } else {
+      double* o = pairs.out + mem[m];
+      const long long s = pairs.ostride;
+      o[0] = Fx;
+      o[s] = Fy;
+      o[2 * s] = Fz;
+      o[3 * s] = r[1] * Fz - r[2] * Fy;
+      o[4 * s] = r[2] * Fx - r[0] * Fz;
+      o[5 * s] = r[0] * Fy - r[1] * Fx;
+    }
   }
   const R omB = (R)(1.0 - Bsum);
   // fluid operator and forcing, then Eq. LBM_Collide_PSM:

@@ -24,6 +24,8 @@ MLP_MAX_BATCH = 65536
 COUPLING = {"none": NONE, "mem_bb": MEM_BB, "mem_cli": MEM_CLI, "psm": PSM}
 PRECISION = {"fp64": FP64, "fp32": FP32, "fp16": FP16_DEV, "bf16": BF16_DEV}
 STORAGE_BYTES = {FP64: 8, FP32: 4, FP16_DEV: 2, BF16_DEV: 2}
+REFILL_EXTRAPOLATE, REFILL_EQUILIBRIUM = 0, 1
+REFILL = {"extrapolation": REFILL_EXTRAPOLATE, "equilibrium": REFILL_EQUILIBRIUM}
 
 
 class Config(ctypes.Structure):
@@ -34,7 +36,7 @@ class Config(ctypes.Structure):
         ("eps_n", ctypes.c_int32), ("eps_mode", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("max_particles", ctypes.c_int32), ("tile_rows", ctypes.c_int32), ("block_threads", ctypes.c_int32),
         ("grid_blocks", ctypes.c_int32), ("wall_link_cap", ctypes.c_int32),
-        ("sweep_flags", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("sweep_flags", ctypes.c_int32), ("refill", ctypes.c_int32),
         ("max_diameter", ctypes.c_double), ("nu", ctypes.c_double), ("magic", ctypes.c_double),
         ("f_ext", ctypes.c_double * 3), ("gravity", ctypes.c_double * 3),
     ]
@@ -147,6 +149,8 @@ def lib():
             f.argtypes = [P, P]
         L.lbmps_mlp_set_samples.restype = I32
         L.lbmps_mlp_set_samples.argtypes = [P, I64, P]
+        L.lbmps_mlp_set_inputs.restype = I32
+        L.lbmps_mlp_set_inputs.argtypes = [P, I32]
         L.lbmps_mlp_label.restype = I32
         L.lbmps_mlp_label.argtypes = [P, I32]
         L.lbmps_mlp_gradient.restype = I32
@@ -168,7 +172,7 @@ def velocities():
 def make_config(nx, ny, nz, nu, collision="trt", coupling="none", psm_m=1, psm_b=1, n_sub=0, eps_n=8,
                 eps_mode=EPS_FLAT, precision="fp64", max_particles=0, max_diameter=0.0, magic=3.0 / 16.0,
                 f_ext=(0.0, 0.0, 0.0), gravity=(0.0, 0.0, 0.0), tile_rows=0, block_threads=0, grid_blocks=0,
-                wall_link_cap=0, sweep_flags=0):
+                wall_link_cap=0, sweep_flags=0, refill=0):
     c = Config()
     c.nx, c.ny, c.nz = nx, ny, nz
     c.collision = TRT if collision == "trt" else BGK
@@ -179,6 +183,7 @@ def make_config(nx, ny, nz, nu, collision="trt", coupling="none", psm_m=1, psm_b
     c.max_particles = max_particles
     c.tile_rows, c.block_threads, c.grid_blocks, c.wall_link_cap = tile_rows, block_threads, grid_blocks, wall_link_cap
     c.sweep_flags = sweep_flags
+    c.refill = REFILL[refill] if isinstance(refill, str) else refill
     c.max_diameter, c.nu, c.magic = max_diameter, nu, magic
     for k in range(3):
         c.f_ext[k] = f_ext[k]
@@ -417,6 +422,9 @@ class Mlp:
         rd = np.ascontiguousarray(np.asarray(rd, dtype=np.float64).reshape(-1, 4))
         self._chk(lib().lbmps_mlp_set_samples(self._m, len(rd), rd.ctypes.data))
         self.n = len(rd)
+
+    def set_inputs(self, n_inputs):
+        self._chk(lib().lbmps_mlp_set_inputs(self._m, int(n_inputs)))
 
     def label(self, eps_n):
         self._chk(lib().lbmps_mlp_label(self._m, int(eps_n)))

@@ -34,18 +34,18 @@ def oracle_to_gpu(g):
 
 def make_pair(nx, ny, nz, nu, coupling="none", collision="trt", psm_m=1, psm_b=1, f_ext=(0, 0, 0),
               gravity=(0, 0, 0), precision="fp64", eps_n=8, eps_mode=0, parts=None, g0=None, n_sub=0,
-              walls=None, tile_rows=0, block_threads=0, grid_blocks=0, sweep_flags=0):
+              walls=None, tile_rows=0, block_threads=0, grid_blocks=0, sweep_flags=0, refill="extrapolation"):
     """parts: dict(X, U, Om, D, rho, fixed) lists; walls: list of (mask, v)."""
     ora = OracleSim(nx, ny, nz, nu, collision=collision, coupling=coupling, psm_m=psm_m, psm_b=psm_b, fext=f_ext,
                     gravity=gravity, n_sub=(n_sub or None), eps_n=eps_n, eps_recursive=(eps_mode == 1),
-                    eps_estimator={3: "edge", 4: "distance"}.get(eps_mode))
+                    eps_estimator={3: "edge", 4: "distance"}.get(eps_mode), refill=refill)
     np_ = len(parts["D"]) if parts else 0
     dmax = max(parts["D"]) if parts else 0.0
     cfg = lbmps.make_config(nx, ny, nz, nu, collision=collision, coupling=coupling, psm_m=psm_m, psm_b=psm_b,
                             n_sub=n_sub, eps_n=eps_n, eps_mode=eps_mode, precision=precision,
                             max_particles=np_, max_diameter=dmax, f_ext=f_ext, gravity=gravity,
                             tile_rows=tile_rows, block_threads=block_threads, grid_blocks=grid_blocks,
-                            sweep_flags=sweep_flags)
+                            sweep_flags=sweep_flags, refill=refill)
     sim = lbmps.Sim(cfg)
     if g0 is None:
         ora.init_equilibrium()

@@ -142,6 +142,28 @@ def test_moving_mem_sphere_with_refill(coupling, precision):
     assert ora.refilled > 20
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_moving_mem_sphere_with_equilibrium_refill(precision):
+    # the equilibrium reconstruction of uncovered cells (every cell takes the
+    # last fallback of Sec. 2.2.3) against the oracle's
+    say("moving MEM, equilibrium refill", precision)
+    X0 = np.array([16.3, 15.8, 20.2])
+    parts = dict(X=[X0], U=[[0.01, -0.005, 0.0]], Om=[[0.0, 0.001, 0.0]], D=[7.0], rho=[1.5], fixed=[False])
+    ora, sim = make_pair(32, 32, 40, 0.05, coupling="mem_cli", collision="trt", f_ext=(0, 0, 1e-6),
+                         gravity=(0, 0, -1e-3), parts=parts, precision=precision, refill="equilibrium")
+    tol = TOL[precision]
+    for k in range(3):
+        ora.step(40)
+        sim.step(40)
+        errs, po, pg = force_errors(ora, sim)
+        eF, eT, nF = errs[0]
+        e, _ = pdf_error(ora, sim)
+        say("  t=%d refilled=%d e_f=%.3e e_F=%.3e e_T=%.3e" % (ora.time, ora.refilled, e, eF, eT))
+        assert e < tol and eF < tol and eT < tol
+        assert link_set_errors(ora, sim) <= (1e-15 if precision == "fp64" else 1e-5)
+    assert ora.refilled > 10
+
+
 @pytest.mark.parametrize("coupling,precision", [("mem_cli", "fp64"), ("mem_cli", "fp32"), ("mem_cli", "fp16"),
                                                 ("mem_cli", "bf16"), ("psm", "fp64"), ("psm", "fp16"),
                                                 ("psm_staged", "fp64"), ("psm_staged", "fp32")])
