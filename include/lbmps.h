@@ -104,7 +104,10 @@ typedef struct lbmps_config {
                             bits 5-6: at most 3 (value 1) or 2 (value 2) sweep workgroups per CU, by
                             reserving LDS (value 3 is invalid);
                             bit 7 two x-adjacent cells per sweep thread, moved as one word per direction
-                            (needs an even nx; ignored with bit 3 and while bit 1 or 4 is in effect) */
+                            (needs an even nx; ignored with bit 3 and while bit 1 or 4 is in effect);
+                            bit 8 four x-adjacent cells per sweep thread, one 8-byte word per direction
+                            (FP16/BF16 storage and nx a multiple of 4 only; not with bits 3 or 7; ignored
+                            while bit 1 or 4 is in effect) */
   int32_t refill;        /* MEM reconstruction of uncovered cells (Sec. 2.2.3): LBMPS_REFILL_EXTRAPOLATE (0, the
                             paper's: extrapolation along the surface normal, then fallbacks) or
                             LBMPS_REFILL_EQUILIBRIUM (1: every uncovered cell takes the last fallback,

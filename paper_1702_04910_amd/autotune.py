@@ -5,8 +5,8 @@ recorded by the library around every launch) over a grid of launch shapes:
 rows per tile (sized by the LDS staging they need), workgroup size, a
 persistent grid or one workgroup per tile, plain or non-temporal loads, the
 six-wave build, a cap on the sweep workgroups resident per CU (fewer
-concurrent streams can raise the achieved HBM bandwidth) and one or two cells
-per thread.  The timing instance
+concurrent streams can raise the achieved HBM bandwidth) and one, two or four
+cells per thread.  The timing instance
 is a coupling-free copy of the box (the sweep kernel does not depend on the
 coupling); one instance per row count, the other parameters switched with
 set_launch.  Results are cached in a JSON file keyed by the device name, shape
@@ -48,6 +48,19 @@ def _key(nx, ny, nz, precision):
 CAPS = (0, lbmps.SWEEP_WG_CAP3, lbmps.SWEEP_WG_CAP2)
 
 
+def _cells_per_thread(nx, s, flags):
+    """Flags for one, two (even nx) or four (2-byte storage, nx a multiple of
+    4) cells per sweep thread; neither with the six-wave build (bit 3)."""
+    if flags & lbmps.SWEEP_OCC6:
+        return (0,)
+    out = [0]
+    if nx % 2 == 0:
+        out.append(lbmps.SWEEP_CELL_PAIRS)
+    if s == 2 and nx % 4 == 0:
+        out.append(lbmps.SWEEP_CELL_QUADS)
+    return tuple(out)
+
+
 def candidates(nx, precision):
     """Launch shapes to time, grouped by tile_rows (one timing instance each)."""
     s = lbmps.STORAGE_BYTES[lbmps.PRECISION[precision]]
@@ -59,9 +72,9 @@ def candidates(nx, precision):
             for grid in (0, 2048):
                 for flags in ((0, 1, 8, 9) if s < 8 else (0, 1)):  # + six-wave build (bit 3) for 4/2-byte storage
                     for cap in CAPS:
-                        for pairs in ((0, lbmps.SWEEP_CELL_PAIRS) if nx % 2 == 0 and not flags & 8 else (0,)):
+                        for cells in _cells_per_thread(nx, s, flags):
                             out.append(dict(tile_rows=r, block_threads=block, grid_blocks=grid,
-                                            sweep_flags=flags | cap | pairs))
+                                            sweep_flags=flags | cap | cells))
     return out
 
 
@@ -141,10 +154,10 @@ def tune_batch(make_sim, tile_cells=(256, 512, 1024), grids=(0, 1024, 2048, 4096
         try:
             for grid in grids:
                 for flags in [f | cap | pr for f in (0, 1, 8, 9) for cap in CAPS
-                              for pr in ((0,) if f & 8 else (0, lbmps.SWEEP_CELL_PAIRS))]:
+                              for pr in ((0,) if f & 8 else (0, lbmps.SWEEP_CELL_PAIRS, lbmps.SWEEP_CELL_QUADS))]:
                     try:
                         sim.set_launch(256, grid, flags)
-                    except lbmps.LbmpsError:  # cell pairs need every instance's nx even
+                    except lbmps.LbmpsError:  # cell pairs / quads need every instance's nx even / 2-byte storage
                         continue
                     sim.set_timing(True)
                     sim.step(sweeps)

@@ -20,6 +20,11 @@ CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # and mixed-precision FMAs: one with an FP16 result fuses an FMA with the
+    # conversion to FP16 storage (one rounding instead of two), and whether it
+    # is formed depends on the surrounding kernel, so the stored bits of the
+    # same cell update would differ between sweep variants
+    "-Xclang", "-target-feature", "-Xclang", "-fma-mix-insts",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
     "-Wno-unused-command-line-argument",
 ]

@@ -59,6 +59,13 @@ struct Layout {
   int max_tile_cells = 0;
 };
 
+// The four-cells-per-thread sweep (bit 8): 2-byte storage, whole 8-byte words per row.
+static bool quads_ok(int flags, int precision, int nx) {
+  if (!(flags & SWEEP_CELL_QUADS)) return true;
+  return (precision == LBMPS_FP16_DEV || precision == LBMPS_BF16_DEV) && nx % 4 == 0 &&
+         !(flags & (SWEEP_OCC6 | SWEEP_CELL_PAIRS));
+}
+
 bool valid_cfg(const lbmps_config& c, std::string& err) {
   if (c.nx < 1 || c.ny < 1 || c.nz < 1) { err = "box dimensions must be positive"; return false; }
   if ((long long)c.nx * c.ny * c.nz >= (1LL << 31)) { err = "box too large (>= 2^31 cells)"; return false; }
@@ -85,6 +92,9 @@ bool valid_cfg(const lbmps_config& c, std::string& err) {
   if (c.sweep_flags & ~SWEEP_FLAGS_ALL) { err = "unknown sweep_flags bits"; return false; }
   if ((c.sweep_flags & SWEEP_WG_CAP_MASK) == SWEEP_WG_CAP_MASK) { err = "sweep_flags: workgroup cap 3 is invalid"; return false; }
   if ((c.sweep_flags & SWEEP_CELL_PAIRS) && (c.nx & 1)) { err = "sweep_flags: cell pairs need an even nx"; return false; }
+  if (!quads_ok(c.sweep_flags, c.precision, c.nx)) {
+    err = "sweep_flags: cell quads need FP16/BF16 storage, nx a multiple of 4, and neither bit 3 nor bit 7"; return false;
+  }
   if (__builtin_popcount(c.sweep_flags & SWEEP_PSM_MODES) > 1) {
     err = "sweep_flags: the PSM modes (fused, separate, staged) are exclusive"; return false;
   }
@@ -1189,6 +1199,9 @@ lbmps_status lbmps_set_launch(lbmps_ctx* c, int32_t block_threads, int32_t grid_
   if (sweep_flags & SWEEP_CELL_PAIRS)
     for (const auto& cf : c->cfg)
       if (cf.nx & 1) return fail(c, LBMPS_EINVAL, "cell pairs need an even nx");
+  for (const auto& cf : c->cfg)
+    if (!quads_ok(sweep_flags, cf.precision, cf.nx))
+      return fail(c, LBMPS_EINVAL, "cell quads need FP16/BF16 storage, nx a multiple of 4, and neither bit 3 nor bit 7");
   drop_graph(c);
   c->block = block_threads ? block_threads : 256;
   c->grid = grid_blocks > 0 ? std::min(grid_blocks, c->ntiles) : c->ntiles;

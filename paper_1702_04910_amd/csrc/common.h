@@ -148,7 +148,12 @@ template <> struct Codec<float> {
 };
 template <> struct Codec<_Float16> {
   __device__ static inline float ld(_Float16 v) { return (float)v; }
-  __device__ static inline _Float16 st(float v) { return (_Float16)v; }  // round to nearest even
+  // Round to nearest even from the FP32 value as computed.  The empty asm pins
+  // v as an FP32 register value: otherwise the compiler may fuse the
+  // conversion into the FMA that produced v (a mixed-precision FMA with an FP16
+  // result rounds once instead of twice), and whether it does depends on the
+  // surrounding kernel, so the stored bits would differ between kernels.
+  __device__ static inline _Float16 st(float v) { return (_Float16)v; }
 };
 template <> struct Codec<__bf16> {
   __device__ static inline float ld(__bf16 v) { return (float)v; }

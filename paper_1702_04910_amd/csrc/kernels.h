@@ -22,11 +22,14 @@ inline int unit_grid(int units, int nlist) {
 // share of overlapped cells); bits 5-6 cap the sweep workgroups resident per
 // CU (0 no cap, 1 three, 2 two; 3 is invalid) by reserving LDS; bit 7 every
 // sweep thread handles two x-adjacent cells (needs even nx; not used with bit 3
-// or while the sweep handles overlapped cells, bits 1 and 4).  Results never
-// depend on them.
+// or while the sweep handles overlapped cells, bits 1 and 4); bit 8 four
+// x-adjacent cells per thread in 8-byte words (2-byte storage, nx a multiple
+// of 4; not with bits 3 or 7; not used while the sweep handles overlapped
+// cells).  Results never depend on them.
 enum {
   SWEEP_NT_LOADS = 1, SWEEP_PSM_FUSED = 2, SWEEP_PSM_SEPARATE = 4, SWEEP_OCC6 = 8, SWEEP_PSM_STAGED = 16,
-  SWEEP_WG_CAP_SHIFT = 5, SWEEP_WG_CAP_MASK = 3 << SWEEP_WG_CAP_SHIFT, SWEEP_CELL_PAIRS = 128, SWEEP_FLAGS_ALL = 255,
+  SWEEP_WG_CAP_SHIFT = 5, SWEEP_WG_CAP_MASK = 3 << SWEEP_WG_CAP_SHIFT, SWEEP_CELL_PAIRS = 128, SWEEP_CELL_QUADS = 256,
+  SWEEP_FLAGS_ALL = 511,
   SWEEP_PSM_MODES = SWEEP_PSM_FUSED | SWEEP_PSM_SEPARATE | SWEEP_PSM_STAGED
 };
 constexpr int LDS_PER_CU = 160 * 1024;

@@ -40,55 +40,79 @@ __device__ __forceinline__ R dot3(R x, R y, R z) {
   else return (R)0;
 }
 
-// TRT collision of the pair (QA, QA + 1) in deviation variables; see the
-// collision operator of Eq. MEM_TRT with f^+- = (f_q +- f_qbar)/2 and the
-// forcing of Eq. Forcing split into its symmetric and antisymmetric parts.
-// As in the partially saturated cell collision, contraction is off and the
-// fused multiply-adds are explicit (fmac): every sweep variant, whatever code
-// surrounds this, produces the same bits.
-template <typename R, int QA>
-__device__ __forceinline__ void trt_pair(const R (&g)[Q], R (&o)[Q], R base, R ux, R uy, R uz, R fx, R fy, R fz,
-                                         R fu, R lp, R lm) {
+// Pair p = 0..8 holds the opposite directions (2p + 1, 2p + 2); PAIR_C[k][p]
+// is component k of c_{2p+1}.  The moment sums below are written out from this
+// table, which is checked against the velocity set at compile time.
+constexpr int PAIR_C[3][9] = {{1, 0, 0, 1, 1, 1, 1, 0, 0}, {0, 1, 0, 1, -1, 0, 0, 1, 1}, {0, 0, 1, 0, 0, 1, -1, 1, -1}};
+constexpr bool pair_table_ok() {
+  for (int p = 0; p < 9; ++p)
+    if (PAIR_C[0][p] != cx(2 * p + 1) || PAIR_C[1][p] != cy(2 * p + 1) || PAIR_C[2][p] != cz(2 * p + 1) ||
+        opp(2 * p + 1) != 2 * p + 2)
+      return false;
+  return true;
+}
+static_assert(pair_table_ok(), "pair table does not match the velocity set");
+
+// TRT collision of the pair (QA, QA + 1) in deviation variables: Eq. MEM_TRT
+// with f^+- = (f_q +- f_qbar)/2, f^eq+ = w (base + 4.5 (c.u)^2), f^eq- = 3 w c.u,
+// and the forcing of Eq. Forcing split into its symmetric part w (9 (c.u)(c.F)
+// - 3 u.F) and antisymmetric part 3 w c.F.  With s = g_q + g_qbar and
+// d = g_q - g_qbar the two changes are
+//   c+ = lp (s/2 - f^eq+) + w (9 cu cf - 3 fu) = (lp/2) s + w (A + cu (9 cf - 4.5 lp cu)),
+//   c- = lm (d/2 - f^eq-) + 3 w cf             = (lm/2) d + 3 w (cf - lm cu),
+// with the per-cell A = -lp base - 3 fu; g_q gains c+ + c-, g_qbar c+ - c-.
+// The quadratic term is formed as lp (-4.5 cu), not with a rounded constant
+// -4.5 lp: that constant's fixed rounding error, multiplied by cu^2 >= 0 in
+// every cell, would bias the mass by a few 1e-12 per cell and sweep in FP32.
+// Contraction is off and the fused multiply-adds are explicit (fmac), so every
+// sweep variant, whatever code surrounds this, produces the same bits.
+template <typename R, int P>
+__device__ __forceinline__ void trt_pair(const R (&g)[Q], const R (&s)[9], const R (&d)[9], R (&o)[Q], R A, R ux,
+                                         R uy, R uz, R fx, R fy, R fz, R hp, R hm, R lp, R lm) {
 #pragma clang fp contract(off)
-  constexpr int QB = QA + 1;
+  constexpr int QA = 2 * P + 1, QB = QA + 1;
   const R w = (R)wq(QA);
   const R cu = dot3<R, cx(QA), cy(QA), cz(QA)>(ux, uy, uz);
   const R cf = dot3<R, cx(QA), cy(QA), cz(QA)>(fx, fy, fz);
-  // f^+- - f^eq+-, with f^eq+ = w (base + 4.5 cu^2) and f^eq- = w 3 cu
-  const R gp = (R)0.5 * (g[QA] + g[QB]);
-  const R gm = (R)0.5 * (g[QA] - g[QB]);
-  const R dp = fmac<R>(-w, fmac<R>((R)4.5 * cu, cu, base), gp);
-  const R dm = fmac<R>(-w, (R)3 * cu, gm);
-  const R Fp = w * fmac<R>((R)9 * cu, cf, (R)-3 * fu);
-  const R Fm = w * ((R)3 * cf);
-  const R cp = fmac<R>(lp, dp, Fp);
-  const R cm = fmac<R>(lm, dm, Fm);
+  const R cp = fmac<R>(w, fmac<R>(cu, fmac<R>((R)9, cf, lp * ((R)-4.5 * cu)), A), hp * s[P]);
+  const R cm = fmac<R>((R)(3.0 * wq(QA)), fmac<R>(-lm, cu, cf), hm * d[P]);
   o[QA] = (g[QA] + cp) + cm;
   o[QB] = (g[QB] + cp) - cm;
 }
 
+// One cell's TRT collision with body force (lp, lm: the relaxation factors of
+// the symmetric and antisymmetric parts, negative).  The moments are taken from
+// the pair sums and differences that the collision needs anyway: drho = g_0 +
+// sum s_p, j = sum_p c_{2p+1} d_p.
 template <typename R>
 __device__ __forceinline__ void collide_cell(const R (&g)[Q], R (&o)[Q], R lp, R lm, R fx, R fy, R fz) {
 #pragma clang fp contract(off)
-  R drho = g[0];
+  R s[9], d[9];
 #pragma unroll
-  for (int q = 1; q < Q; ++q) drho += g[q];
-  const R ux = (g[1] - g[2]) + (g[7] - g[8]) + (g[9] - g[10]) + (g[11] - g[12]) + (g[13] - g[14]);
-  const R uy = (g[3] - g[4]) + (g[7] - g[8]) + (g[10] - g[9]) + (g[15] - g[16]) + (g[17] - g[18]);
-  const R uz = (g[5] - g[6]) + (g[11] - g[12]) + (g[14] - g[13]) + (g[15] - g[16]) + (g[18] - g[17]);
+  for (int p = 0; p < 9; ++p) {
+    s[p] = g[2 * p + 1] + g[2 * p + 2];
+    d[p] = g[2 * p + 1] - g[2 * p + 2];
+  }
+  const R drho = (((g[0] + s[0]) + (s[1] + s[2])) + ((s[3] + s[4]) + (s[5] + s[6]))) + (s[7] + s[8]);
+  const R ux = ((d[0] + d[3]) + d[4]) + (d[5] + d[6]);
+  const R uy = ((d[1] + d[3]) - d[4]) + (d[7] + d[8]);
+  const R uz = ((d[2] + d[5]) - d[6]) + (d[7] - d[8]);
   const R uu = fmac<R>(uz, uz, fmac<R>(uy, uy, ux * ux));
   const R fu = fmac<R>(uz, fz, fmac<R>(uy, fy, ux * fx));
   const R base = fmac<R>((R)-1.5, uu, drho);
-  o[0] = fmac<R>(-(R)wq(0) * (R)3, fu, fmac<R>(lp, fmac<R>(-(R)wq(0), base, g[0]), g[0]));
-  trt_pair<R, 1>(g, o, base, ux, uy, uz, fx, fy, fz, fu, lp, lm);
-  trt_pair<R, 3>(g, o, base, ux, uy, uz, fx, fy, fz, fu, lp, lm);
-  trt_pair<R, 5>(g, o, base, ux, uy, uz, fx, fy, fz, fu, lp, lm);
-  trt_pair<R, 7>(g, o, base, ux, uy, uz, fx, fy, fz, fu, lp, lm);
-  trt_pair<R, 9>(g, o, base, ux, uy, uz, fx, fy, fz, fu, lp, lm);
-  trt_pair<R, 11>(g, o, base, ux, uy, uz, fx, fy, fz, fu, lp, lm);
-  trt_pair<R, 13>(g, o, base, ux, uy, uz, fx, fy, fz, fu, lp, lm);
-  trt_pair<R, 15>(g, o, base, ux, uy, uz, fx, fy, fz, fu, lp, lm);
-  trt_pair<R, 17>(g, o, base, ux, uy, uz, fx, fy, fz, fu, lp, lm);
+  const R A = fmac<R>(-lp, base, (R)-3 * fu);
+  const R hp = (R)0.5 * lp, hm = (R)0.5 * lm;
+  // rest direction: g_0 + lp (g_0 - w_0 base) - 3 w_0 fu = g_0 + lp g_0 + w_0 A
+  o[0] = fmac<R>(lp, g[0], fmac<R>((R)wq(0), A, g[0]));
+  trt_pair<R, 0>(g, s, d, o, A, ux, uy, uz, fx, fy, fz, hp, hm, lp, lm);
+  trt_pair<R, 1>(g, s, d, o, A, ux, uy, uz, fx, fy, fz, hp, hm, lp, lm);
+  trt_pair<R, 2>(g, s, d, o, A, ux, uy, uz, fx, fy, fz, hp, hm, lp, lm);
+  trt_pair<R, 3>(g, s, d, o, A, ux, uy, uz, fx, fy, fz, hp, hm, lp, lm);
+  trt_pair<R, 4>(g, s, d, o, A, ux, uy, uz, fx, fy, fz, hp, hm, lp, lm);
+  trt_pair<R, 5>(g, s, d, o, A, ux, uy, uz, fx, fy, fz, hp, hm, lp, lm);
+  trt_pair<R, 6>(g, s, d, o, A, ux, uy, uz, fx, fy, fz, hp, hm, lp, lm);
+  trt_pair<R, 7>(g, s, d, o, A, ux, uy, uz, fx, fy, fz, hp, hm, lp, lm);
+  trt_pair<R, 8>(g, s, d, o, A, ux, uy, uz, fx, fy, fz, hp, hm, lp, lm);
 }
 
 template <int q>
@@ -259,6 +283,99 @@ __device__ __forceinline__ void sweep_body_twin(const InstDev* __restrict__ inst
   }
 }
 
+// The sweep with every thread handling four x-adjacent cells x .. x + 3, x a
+// multiple of 4 (nx a multiple of 4), for 2-byte storage: each load and store
+// moves one 8-byte word of four values, and the address arithmetic is shared by
+// four cells.  The c_x = +-1 values are staged in LDS as whole words at the
+// position of the cell that produced them; the write-out assembles each
+// destination word from the staged word at the same position and the last
+// (c_x = +1) or first (c_x = -1) value of its neighbour word in the row
+// (periodic).  No overlapped-cell handling (PSM collided after the sweep).
+template <typename S, bool NTLD>
+__device__ __forceinline__ void sweep_body_quad(const InstDev* __restrict__ insts, const int4* __restrict__ tiles,
+                                                int ntiles, const S* __restrict__ src, S* __restrict__ dst) {
+  static_assert(sizeof(S) == 2, "four cells per word: 2-byte storage only");
+  using R = typename CompOf<S>::type;
+  using W = unsigned long long;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  W* sh = reinterpret_cast<W*>(smem_raw);
+  for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int4 tl = tiles[t];
+    const InstDev& I = insts[tl.x];
+    const int nx = I.nx, ny = I.ny, nz = I.nz;
+    const S* __restrict__ s = src + I.pdf_off;
+    S* __restrict__ d = dst + I.pdf_off;
+    const R lp = (R)I.lam_p, lm = (R)I.lam_m;
+    const R fx = (R)I.fext[0], fy = (R)I.fext[1], fz = (R)I.fext[2];
+    const int nxq = nx >> 2;
+    const int nq = tl.z * nxq;  // words per staged direction in this tile
+    for (int iq = threadIdx.x; iq < nq; iq += blockDim.x) {
+      const int r = iq / nxq;
+      const int x = (iq - r * nxq) << 2;
+      const int row = tl.y + r;
+      const int z = row / ny;
+      const int y = row - z * ny;
+      const int idx = row * nx + x;
+      W win[Q], wout[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const W* a = reinterpret_cast<const W*>(&s[pdf_at(idx, q)]);
+        win[q] = NTLD ? __builtin_nontemporal_load(a) : *a;
+        wout[q] = 0;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        R g[Q], o[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) g[q] = Codec<S>::ld(__builtin_bit_cast(S, (unsigned short)(win[q] >> (16 * k))));
+        collide_cell<R>(g, o, lp, lm, fx, fy, fz);
+#pragma unroll
+        for (int q = 0; q < Q; ++q)
+          wout[q] |= (W)__builtin_bit_cast(unsigned short, Codec<S>::st(o[q])) << (16 * k);
+      }
+      const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+      const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+#define LBM_PUSH4(qq)                                                                       \
+  if constexpr (cx(qq) == 0) {                                                              \
+    const int ya = pick<cy(qq)>(ym, y, yp), za = pick<cz(qq)>(zm, z, zp);                   \
+    __builtin_nontemporal_store(wout[qq], reinterpret_cast<W*>(&d[pdf_at((za * ny + ya) * nx + x, qq)])); \
+  } else {                                                                                  \
+    sh[xslot(qq) * nq + iq] = wout[qq];                                                     \
+  }
+      LBM_PUSH4(0) LBM_PUSH4(1) LBM_PUSH4(2) LBM_PUSH4(3) LBM_PUSH4(4) LBM_PUSH4(5) LBM_PUSH4(6)
+      LBM_PUSH4(7) LBM_PUSH4(8) LBM_PUSH4(9) LBM_PUSH4(10) LBM_PUSH4(11) LBM_PUSH4(12) LBM_PUSH4(13)
+      LBM_PUSH4(14) LBM_PUSH4(15) LBM_PUSH4(16) LBM_PUSH4(17) LBM_PUSH4(18)
+#undef LBM_PUSH4
+    }
+    __syncthreads();
+    for (int iq = threadIdx.x; iq < nq; iq += blockDim.x) {
+      const int r = iq / nxq;
+      const int xq = iq - r * nxq;
+      const int x = xq << 2;
+      const int row = tl.y + r;
+      const int z = row / ny;
+      const int y = row - z * ny;
+      const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+      const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
+      // neighbour words in the same row, periodic in x
+      const int iprev = xq == 0 ? iq + nxq - 1 : iq - 1;
+      const int inext = xq == nxq - 1 ? iq - nxq + 1 : iq + 1;
+#define LBM_FLUSH4(qq)                                                                      \
+  {                                                                                         \
+    const int ya = pick<cy(qq)>(ym, y, yp), za = pick<cz(qq)>(zm, z, zp);                   \
+    const W cur = sh[xslot(qq) * nq + iq];                                                  \
+    const W v = cx(qq) > 0 ? (cur << 16) | (sh[xslot(qq) * nq + iprev] >> 48)               \
+                           : (cur >> 16) | (sh[xslot(qq) * nq + inext] << 48);              \
+    __builtin_nontemporal_store(v, reinterpret_cast<W*>(&d[pdf_at((za * ny + ya) * nx + x, qq)])); \
+  }
+      LBM_FLUSH4(1) LBM_FLUSH4(2) LBM_FLUSH4(7) LBM_FLUSH4(8) LBM_FLUSH4(9) LBM_FLUSH4(10) LBM_FLUSH4(11)
+      LBM_FLUSH4(12) LBM_FLUSH4(13) LBM_FLUSH4(14)
+#undef LBM_FLUSH4
+    }
+    __syncthreads();
+  }
+}
+
 // PSM: 0 no overlapped cells, 1 collide single-pair cells inline, 2 take the
 // staged post-collision values of overlapped cells (stage[q * sstride +
 // leader pair]).
@@ -369,6 +486,13 @@ __global__ __launch_bounds__(256) void sweep_kernel_twin(const InstDev* __restri
                                                          const int4* __restrict__ tiles, int ntiles,
                                                          const S* __restrict__ src, S* __restrict__ dst) {
   sweep_body_twin<S, NTLD>(insts, tiles, ntiles, src, dst);
+}
+
+template <typename S, bool NTLD>
+__global__ __launch_bounds__(256) void sweep_kernel_quad(const InstDev* __restrict__ insts,
+                                                         const int4* __restrict__ tiles, int ntiles,
+                                                         const S* __restrict__ src, S* __restrict__ dst) {
+  sweep_body_quad<S, NTLD>(insts, tiles, ntiles, src, dst);
 }
 
 // The same sweep compiled for six waves per SIMD (at most 80 registers per
@@ -483,10 +607,17 @@ __global__ __launch_bounds__(256) void resweep_cells_kernel(const int* __restric
 template <typename S, bool NTLD>
 hipError_t launch_sweep_n(const InstDev* insts, const int4* tiles, int ntiles, int grid, int block, size_t lds,
                           int psm_mode, const void* src, void* dst, const int* cellmap, PairDev pairs, PartDev parts,
-                          const void* stage, long long sstride, bool occ6, bool twin, hipStream_t st) {
+                          const void* stage, long long sstride, bool occ6, bool twin, bool quad, hipStream_t st) {
   if constexpr (sizeof(S) < 8) {
     if (occ6 && psm_mode == 0) {  // single cells only: the pair variant would spill within 80 registers
       hipLaunchKernelGGL((sweep_kernel_occ6<S, NTLD>), dim3(grid), dim3(block), lds, st, insts, tiles, ntiles,
+                         (const S*)src, (S*)dst);
+      return hipGetLastError();
+    }
+  }
+  if constexpr (sizeof(S) == 2) {
+    if (quad && psm_mode == 0) {
+      hipLaunchKernelGGL((sweep_kernel_quad<S, NTLD>), dim3(grid), dim3(block), lds, st, insts, tiles, ntiles,
                          (const S*)src, (S*)dst);
       return hipGetLastError();
     }
@@ -510,12 +641,13 @@ hipError_t launch_sweep_t(const InstDev* insts, const int4* tiles, int ntiles, i
                           int flags, int psm_mode, const void* src, void* dst, const int* cellmap, PairDev pairs,
                           PartDev parts, const void* stage, long long sstride, hipStream_t st) {
   const size_t lds = sweep_lds_bytes((size_t)NXSHIFT * max_tile_cells * sizeof(S), flags);
-  const bool occ6 = (flags & SWEEP_OCC6) != 0, twin = (flags & SWEEP_CELL_PAIRS) != 0;
+  const bool occ6 = (flags & SWEEP_OCC6) != 0, twin = (flags & SWEEP_CELL_PAIRS) != 0,
+             quad = (flags & SWEEP_CELL_QUADS) != 0;
   if (flags & SWEEP_NT_LOADS)
     return launch_sweep_n<S, true>(insts, tiles, ntiles, grid, block, lds, psm_mode, src, dst, cellmap, pairs, parts,
-                                   stage, sstride, occ6, twin, st);
+                                   stage, sstride, occ6, twin, quad, st);
   return launch_sweep_n<S, false>(insts, tiles, ntiles, grid, block, lds, psm_mode, src, dst, cellmap, pairs, parts,
-                                  stage, sstride, occ6, twin, st);
+                                  stage, sstride, occ6, twin, quad, st);
 }
 hipError_t launch_sweep(int prec, const InstDev* insts, const int4* tiles, int ntiles, int grid, int block,
                         int max_tile_cells, int flags, int psm_mode, const void* src, void* dst, const int* cellmap,

@@ -19,6 +19,7 @@ EPS_FLAT, EPS_RECURSIVE, EPS_LEARNED, EPS_EDGE, EPS_DISTANCE = 0, 1, 2, 3, 4
 SWEEP_NT_LOADS, SWEEP_PSM_FUSED, SWEEP_PSM_SEPARATE, SWEEP_OCC6, SWEEP_PSM_STAGED = 1, 2, 4, 8, 16
 SWEEP_WG_CAP3, SWEEP_WG_CAP2 = 32, 64  # at most three / two sweep workgroups per CU
 SWEEP_CELL_PAIRS = 128  # two x-adjacent cells per sweep thread (even nx)
+SWEEP_CELL_QUADS = 256  # four x-adjacent cells per sweep thread (FP16/BF16 storage, nx a multiple of 4)
 MLP_NPARAM = 4801
 MLP_MAX_BATCH = 65536
 COUPLING = {"none": NONE, "mem_bb": MEM_BB, "mem_cli": MEM_CLI, "psm": PSM}

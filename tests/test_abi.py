@@ -49,7 +49,11 @@ def test_workspace_bytes_valid_and_invalid():
         lbmps.make_config(32, 32, 64, 0.1, eps_n=6, eps_mode=lbmps.EPS_RECURSIVE),
         lbmps.make_config(32, 32, 64, 0.1, block_threads=100),
         lbmps.make_config(32, 32, 64, 0.1, coupling="psm", n_sub=-1),
-        lbmps.make_config(32, 32, 64, 0.1, sweep_flags=256),
+        lbmps.make_config(32, 32, 64, 0.1, sweep_flags=512),
+        lbmps.make_config(32, 32, 64, 0.1, sweep_flags=lbmps.SWEEP_CELL_QUADS),  # FP32 storage
+        lbmps.make_config(34, 32, 64, 0.1, precision="fp16", sweep_flags=lbmps.SWEEP_CELL_QUADS),
+        lbmps.make_config(32, 32, 64, 0.1, precision="bf16", sweep_flags=lbmps.SWEEP_CELL_QUADS | lbmps.SWEEP_CELL_PAIRS),
+        lbmps.make_config(32, 32, 64, 0.1, precision="bf16", sweep_flags=lbmps.SWEEP_CELL_QUADS | lbmps.SWEEP_OCC6),
         lbmps.make_config(32, 32, 64, 0.1, sweep_flags=96),
         lbmps.make_config(33, 32, 64, 0.1, sweep_flags=lbmps.SWEEP_CELL_PAIRS),
         lbmps.make_config(32, 32, 64, 0.1, sweep_flags=lbmps.SWEEP_PSM_STAGED | lbmps.SWEEP_PSM_SEPARATE),

@@ -353,6 +353,32 @@ def test_sweep_launch_variants_are_bitwise_identical(precision):
         assert np.array_equal(out[0], o)
 
 
+@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+def test_cell_quad_sweep_is_bitwise_identical(precision):
+    # four x-adjacent cells per thread (nx a multiple of 4, several 8-byte
+    # words per row and the periodic wrap of the staged words), tiles of one
+    # and of several rows, with a moving MEM sphere on top of the sweep
+    from paper_1702_04910_amd import lbmps
+
+    nx, ny, nz = 44, 23, 21
+    parts = dict(X=[[20.3, 11.8, 10.1]], U=[[0.01, -0.004, 0.006]], Om=[[0.0, 0.001, 0.0]], D=[7.4], rho=[1.5],
+                 fixed=[False])
+    out = []
+    Q4 = lbmps.SWEEP_CELL_QUADS
+    for rows, flags in ((1, 0), (1, Q4), (3, Q4 | lbmps.SWEEP_NT_LOADS | lbmps.SWEEP_WG_CAP2), (5, Q4)):
+        say("cell quads", precision, rows, flags)
+        ora, sim = make_pair(nx, ny, nz, 0.05, coupling="mem_cli", collision="trt", f_ext=(1e-5, 0, 2e-6),
+                             gravity=(0, 0, -1e-4), parts=parts, precision=precision, n_sub=2, sweep_flags=flags,
+                             tile_rows=rows)
+        sim.step(8)
+        out.append((sim.get_pdfs(), sim.particles()))
+        sim.close()
+    for g, p in out[1:]:
+        assert np.array_equal(out[0][0], g)
+        for k in ("F", "T", "U", "X"):
+            assert np.array_equal(out[0][1][k], p[k]), k
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16", "bf16"])
 def test_cell_pair_sweep_is_bitwise_identical(precision):
     # two x-adjacent cells per thread (even nx), with a moving MEM sphere so

@@ -12,7 +12,8 @@ from paper_1702_04910_amd import autotune, counters, lbmps
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-@pytest.mark.parametrize("nx,precision", [(192, "fp32"), (512, "fp32"), (192, "fp16"), (37, "fp32"), (96, "fp64")])
+@pytest.mark.parametrize("nx,precision", [(192, "fp32"), (512, "fp32"), (192, "fp16"), (512, "bf16"), (38, "fp16"),
+                                         (37, "fp32"), (96, "fp64")])
 def test_tuner_candidates_are_valid_configurations(nx, precision):
     cands = autotune.candidates(nx, precision)
     assert len(cands) == len({tuple(sorted(c.items())) for c in cands})  # no duplicates
@@ -23,12 +24,14 @@ def test_tuner_candidates_are_valid_configurations(nx, precision):
         assert lbmps.workspace_bytes(cfg) > 0, c  # the library accepts it
         assert c["tile_rows"] * nx * 10 * s <= 65536  # LDS staging fits
         assert not (f & lbmps.SWEEP_CELL_PAIRS and (nx % 2 or f & lbmps.SWEEP_OCC6))
+        assert not (f & lbmps.SWEEP_CELL_QUADS and (nx % 4 or s != 2 or f & (lbmps.SWEEP_OCC6 | lbmps.SWEEP_CELL_PAIRS)))
         assert not (f & lbmps.SWEEP_OCC6 and s == 8)  # six-wave build only for 4- and 2-byte storage
         assert (f & (lbmps.SWEEP_WG_CAP3 | lbmps.SWEEP_WG_CAP2)) != (lbmps.SWEEP_WG_CAP3 | lbmps.SWEEP_WG_CAP2)
     # every option is offered where it applies
     flags = {c["sweep_flags"] for c in cands}
     assert any(f & lbmps.SWEEP_WG_CAP2 for f in flags) and any(f & lbmps.SWEEP_WG_CAP3 for f in flags)
     assert any(f & lbmps.SWEEP_CELL_PAIRS for f in flags) == (nx % 2 == 0)
+    assert any(f & lbmps.SWEEP_CELL_QUADS for f in flags) == (nx % 4 == 0 and s == 2)
 
 
 def test_counter_hash_follows_the_sweep_sources():
@@ -47,3 +50,13 @@ def test_bench_refuses_several_gpus():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_build_flags_keep_rounding_identical_across_kernels():
+    # no packed FP32 and no mixed-precision FMAs (an FMA fused with the
+    # conversion to FP16 storage rounds once, so its use would make the stored
+    # bits depend on the kernel)
+    from paper_1702_04910_amd import build
+
+    flags = " ".join(build.CFLAGS)
+    assert "-packed-fp32-ops" in flags and "-fma-mix-insts" in flags
