@@ -50,6 +50,14 @@ def tuned_shape(inp, precision):
     return {k: best[k] for k in ("tile_rows", "block_threads", "grid_blocks", "sweep_flags")}
 
 
+def _shape_source():
+    """Where the last launch shape came from: the shipped table of shapes
+    tuned on this kind of GPU, the user's cache, or timed just now."""
+    from paper_1702_04910_amd import autotune
+
+    return autotune.LAST_SOURCE
+
+
 COUNTERS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "sweep_kernel_c2_fp32_hbm_counters.txt")
 
 
@@ -606,7 +614,7 @@ def main():
                      "kernel": "sweep_kernel<float>", "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_us": round(sweep_s * 1e6, 2), "launches": launches,
                      "timed_every_nth_launch": TIMING_STRIDE,
-                     "launch_shape": tuned_shape(inp, "fp32")},
+                     "launch_shape": tuned_shape(inp, "fp32"), "launch_shape_from": _shape_source()},
     }
 
     # ---- storage forms and couplings against the FP64 run, fixed horizons

@@ -40,9 +40,17 @@ def _shipped():
 
 
 def _key(nx, ny, nz, precision):
+    """Cache key: the GPU's architecture and compute-unit count (not its
+    marketing name, which depends on the driver's name table), box, precision."""
     import torch
 
-    return "%s|%dx%dx%d|%s" % (torch.cuda.get_device_name(0), nx, ny, nz, precision)
+    prop = torch.cuda.get_device_properties(0)
+    arch = getattr(prop, "gcnArchName", "") or torch.cuda.get_device_name(0)
+    return "%s|%dCU|%dx%dx%d|%s" % (arch.split(":")[0], prop.multi_processor_count, nx, ny, nz, precision)
+
+
+# where the last tune() result came from: "cache", "shipped" or "timed"
+LAST_SOURCE = None
 
 
 CAPS = (0, lbmps.SWEEP_WG_CAP3, lbmps.SWEEP_WG_CAP2)
@@ -113,12 +121,16 @@ def tune(nx, ny, nz, precision, sweeps=20, cache=CACHE, force=False, verbose=Fal
             db = json.load(open(cache))
         except ValueError:
             db = {}
+    global LAST_SOURCE
     if key in db and not force:
+        LAST_SOURCE = "cache"
         return db[key]
     if not force:
         ship = _shipped()
         if key in ship:
+            LAST_SOURCE = "shipped"
             return ship[key]
+    LAST_SOURCE = "timed"
     best = None
     cands = candidates(nx, precision)
     for r in sorted({c["tile_rows"] for c in cands}):

@@ -5,8 +5,9 @@ It launches, in this order:
   * a plain device-to-device copy of COPY_BYTES (torch's copy kernel), five
     times: the calibration of the counters (bytes read and written are known);
   * the sweep kernel of the primary workload (settling sphere D = 24 in a
-    192x192x384 periodic box, MEM-CLI, FP32 deviation storage, autotuned
-    launch shape), SWEEPS times after a short warm-up.
+    192x192x384 periodic box, MEM-CLI, FP32 deviation storage unless
+    --precision says otherwise, autotuned launch shape), SWEEPS times after a
+    short warm-up.
 
 The per-dispatch counter values of both kernels, and the source hash that
 names the sweep kernel they were taken on, go into the text summary under
@@ -56,6 +57,8 @@ def main(argv=None):
 
     ap = argparse.ArgumentParser()
     ap.add_argument("--shape", default=None, help="tile_rows,block_threads,grid_blocks,sweep_flags")
+    ap.add_argument("--precision", default="fp32", choices=("fp64", "fp32", "fp16", "bf16"),
+                    help="storage precision of the primary workload's sweep")
     ap.add_argument("--workload", default="primary", choices=("primary", "spheres"),
                     help="spheres: 2000 moving spheres in 512^3, PSM-M3B2, flat 8^3 solid fractions")
     args = ap.parse_args(argv)
@@ -66,10 +69,10 @@ def main(argv=None):
     if args.shape:
         shape = dict(zip(keys, (int(v) for v in args.shape.split(","))))
     else:
-        best = tune(inp["nx"], inp["ny"], inp["nz"], "fp32")
+        best = tune(inp["nx"], inp["ny"], inp["nz"], args.precision)
         shape = {k: best[k] for k in keys}
     cfg = lbmps.make_config(inp["nx"], inp["ny"], inp["nz"], inp["nu"], collision="trt", coupling="mem_cli",
-                            n_sub=2, precision="fp32", max_particles=1, max_diameter=inp["D"], f_ext=inp["f_ext"],
+                            n_sub=2, precision=args.precision, max_particles=1, max_diameter=inp["D"], f_ext=inp["f_ext"],
                             gravity=inp["gravity"], **shape)
     sim = lbmps.Sim(cfg)
     sim.init_equilibrium()
@@ -78,8 +81,9 @@ def main(argv=None):
     sim.step(SWEEPS)
     sim.sync()
     sim.close()
-    print("counters workload done: copy %d B x5, %d sweeps of %dx%dx%d, shape %s, sweep source %s"
-          % (COPY_BYTES, SWEEPS, inp["nx"], inp["ny"], inp["nz"], shape, sweep_source_hash()), flush=True)
+    print("counters workload done: copy %d B x5, %d sweeps of %dx%dx%d %s, shape %s, sweep source %s"
+          % (COPY_BYTES, SWEEPS, inp["nx"], inp["ny"], inp["nz"], args.precision, shape, sweep_source_hash()),
+          flush=True)
     return 0
 
 
@@ -102,9 +106,14 @@ def spheres(args):
     sim.step(2)
     sim.step(4)
     sim.sync()
+    ov = sim.overlaps()
     sim.close()
-    print("counters workload done: %d spheres in %d^3, PSM-M3B2 flat 8^3, 6 sweeps, shape %s" % (n, L, shape),
-          flush=True)
+    import numpy as np
+
+    cells, per_cell = np.unique(ov["cell"], return_counts=True)
+    print("counters workload done: %d spheres in %d^3, PSM-M3B2 flat 8^3, 6 sweeps, shape %s; %d particle-cell "
+          "pairs, %d overlapped cells (%d shared)" % (n, L, shape, len(ov["cell"]), len(cells),
+                                                       int((per_cell > 1).sum())), flush=True)
     return 0
 
 

@@ -215,6 +215,11 @@ template <> struct StochasticRound<_Float16> {
   }
 };
 
+// Staging array of the overlapped cells' post-collision values: the 19
+// values of the cell led by pair L side by side, so that the cells of one
+// sphere row (consecutive pairs) occupy one contiguous span.
+__device__ inline long long stage_at(int L, int q) { return (long long)L * Q + q; }
+
 // compute precision paired with each storage type
 template <typename S> struct CompOf { using type = float; };
 template <> struct CompOf<double> { using type = double; };

@@ -42,7 +42,7 @@ inline size_t sweep_lds_bytes(size_t need, int flags) {
   return need > floor ? need : floor;
 }
 // psm_mode: 0 no PSM cells (or they are re-collided afterwards), 1 single-particle cells inline (shared ones are
-// re-collided afterwards), 2 staged (stage[q * sstride + leader pair], written by launch_psm_collide).
+// re-collided afterwards), 2 staged (stage[stage_at(leader pair, q)], written by launch_psm_collide).
 hipError_t launch_sweep(int prec, const InstDev* insts, const int4* tiles, int ntiles, int grid, int block,
                         int max_tile_cells, int flags, int psm_mode, const void* src, void* dst, const int* cellmap,
                         PairDev pairs, PartDev parts, const void* stage, long long sstride, hipStream_t st);

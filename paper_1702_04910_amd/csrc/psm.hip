@@ -558,7 +558,7 @@ hipError_t launch_psm_cellmap(int stage, const int* count, int cap, const InstDe
 // Overlapped cells, visited through their leader pairs in pair order (the
 // list is ordered by particle, slab and row, so neighbouring lanes touch
 // neighbouring cells and share cache lines).  The post-collision values are
-// pushed into dst, or with stage != nullptr stored at stage[q * sstride + L]
+// pushed into dst, or with stage != nullptr stored at stage[stage_at(L, q)]
 // (whole cache lines; the next sweep pushes them).  With 16-bit storage they are
 // rounded stochastically (keyed by cell and direction), like the overlapped
 // cells that the sweep collides inline.  MULTI = false: the cells with a
@@ -590,7 +590,7 @@ __attribute__((amdgpu_waves_per_eu(MULTI || M == 0 || sizeof(S) == 8 ? 1 : 4))) 
     for (int q = 0; q < Q; ++q) out[q] = StochasticRound<S>::apply(out[q], (uint32_t)c * Q + q);
     if (stage) {  // the sweep pushes them
 #pragma unroll
-      for (int q = 0; q < Q; ++q) stage[q * sstride + L] = Codec<S>::st(out[q]);
+      for (int q = 0; q < Q; ++q) stage[stage_at(L, q)] = Codec<S>::st(out[q]);
       continue;
     }
     const int nx = I.nx, ny = I.ny, nz = I.nz;
@@ -612,9 +612,11 @@ __attribute__((amdgpu_waves_per_eu(MULTI || M == 0 || sizeof(S) == 8 ? 1 : 4))) 
 // the shared-cell launch); the chunk sums are those reduce_kernel would form
 // from a complete record array, bit for bit, without writing and reading the
 // 48-byte record of every pair.  finish_sums_kernel adds them per particle.
+// Built for three waves per SIMD where the storage is below 8 bytes and M is
+// fixed (~136 registers): capped at four it spills, and took ~3 % longer.
 template <typename S, int M>
 __global__ __launch_bounds__(SUM_THREADS)
-__attribute__((amdgpu_waves_per_eu(M == 0 || sizeof(S) == 8 ? 1 : 4))) void psm_collide_sum_kernel(
+__attribute__((amdgpu_waves_per_eu(M == 0 || sizeof(S) == 8 ? 1 : 3))) void psm_collide_sum_kernel(
     const int* __restrict__ list, const int* __restrict__ begin, const int* __restrict__ end,
     const InstDev* __restrict__ insts, PartDev P, PairDev pairs, const int* __restrict__ cellmap,
     const S* __restrict__ src, S* __restrict__ dst, S* __restrict__ stage, long long sstride,
@@ -643,7 +645,7 @@ __attribute__((amdgpu_waves_per_eu(M == 0 || sizeof(S) == 8 ? 1 : 4))) void psm_
         for (int q = 0; q < Q; ++q) out[q] = StochasticRound<S>::apply(out[q], (uint32_t)c * Q + q);
         if (stage) {
 #pragma unroll
-          for (int q = 0; q < Q; ++q) stage[q * sstride + L] = Codec<S>::st(out[q]);
+          for (int q = 0; q < Q; ++q) stage[stage_at(L, q)] = Codec<S>::st(out[q]);
         } else {
           const int nx = I.nx, ny = I.ny, nz = I.nz;
           const int x = c % nx, yz = c / nx, y = yz % ny, z = yz / ny;

@@ -377,8 +377,8 @@ __device__ __forceinline__ void sweep_body_quad(const InstDev* __restrict__ inst
 }
 
 // PSM: 0 no overlapped cells, 1 collide single-pair cells inline, 2 take the
-// staged post-collision values of overlapped cells (stage[q * sstride +
-// leader pair]).
+// staged post-collision values of overlapped cells (stage[stage_at(leader
+// pair, q)]).
 template <typename S, bool NTLD, int PSM>
 __device__ __forceinline__ void sweep_body(const InstDev* __restrict__ insts, const int4* __restrict__ tiles,
                                            int ntiles, const S* __restrict__ src, S* __restrict__ dst,
@@ -428,7 +428,7 @@ __device__ __forceinline__ void sweep_body(const InstDev* __restrict__ insts, co
         const int L = I.cellmap_off >= 0 ? cellmap[I.cellmap_off + idx] : INT_MAX;
         if (L != INT_MAX) {
 #pragma unroll
-          for (int q = 0; q < Q; ++q) o[q] = Codec<S>::ld(stage[q * sstride + L]);
+          for (int q = 0; q < Q; ++q) o[q] = Codec<S>::ld(stage[stage_at(L, q)]);
         } else {
           collide_cell<R>(g, o, lp, lm, fx, fy, fz);
         }
