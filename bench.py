@@ -122,9 +122,9 @@ TIMING_STRIDE = 7
 # c2 PSM-M3B2 and MEM-CLI with the equilibrium reconstruction over 20k sweeps
 # (the workload's configured length, about 30 t_ref of the settling), the
 # other PSM variants over 4k, MEM with the extrapolating reconstruction over
-# 1k (its stable window); c3 over 2.2k sweeps (about two t_ref of its D = 48
-# sphere)
-C2_SWEEPS, C2_SHORT_SWEEPS, C2_MEM_SWEEPS, C3_SWEEPS = 20000, 4000, 1000, 2200
+# 800 (inside its stable window, which ends at ~1000); c3 over 2.2k sweeps
+# (about two t_ref of its D = 48 sphere)
+C2_SWEEPS, C2_SHORT_SWEEPS, C2_MEM_SWEEPS, C3_SWEEPS = 20000, 4000, 800, 2200
 
 
 def timed_run(torch, sim, steps, warmup, n_sub, timing=True):
@@ -277,6 +277,34 @@ def horizon_run(torch, lbmps, inp, coupling, prec, psm, sweeps, samples, refill=
     return ent, U, F
 
 
+def sweep_alone(torch, lbmps, inp, precisions, sweeps):
+    """The sweep kernel by itself: a coupling-free context of the same box and
+    tuned launch shape, `sweeps` launches back to back between two host
+    synchronisations (no per-launch events, whose own cost is ~2 % of a
+    180 us launch); per precision the microseconds per sweep (launch gaps
+    included) and the algorithmic bandwidth 2*19*s bytes per cell."""
+    N = inp["nx"] * inp["ny"] * inp["nz"]
+    out = {}
+    for prec in precisions:
+        shape = tuned_shape(inp, prec)
+        sim = lbmps.Sim(lbmps.make_config(inp["nx"], inp["ny"], inp["nz"], inp["nu"], precision=prec, **shape))
+        sim.init_equilibrium()
+        sim.step(4)
+        sim.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(sweeps)
+        sim.sync()
+        torch.cuda.synchronize()
+        us = (time.perf_counter() - t0) / sweeps * 1e6
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        gbs = 2 * 19 * lbmps.STORAGE_BYTES[lbmps.PRECISION[prec]] * N / us / 1e3
+        out[prec] = {"us": round(us, 1), "GBs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4), "shape": shape}
+    return out
+
+
 def compare_to_fp64(ent, U, F, U64, F64, every):
     """Sphere-velocity error |U - U_64| / |U_64| at every sample both runs
     reached (max over the window and at its end) and the drag (force) error
@@ -332,6 +360,8 @@ def precision_c3(torch, lbmps, inputs, seed, sweeps=C3_SWEEPS):
     runs = [("mem_cli", "mem_cli", (3, 2), ("fp64", "fp32", "fp16", "bf16"), sweeps, 10),
             ("psm_m3b2", "psm", (3, 2), ("fp64", "fp32", "fp16", "bf16"), sweeps, 10)]
     out.update(storage_forms(torch, lbmps, inp, runs, "  c3 "))
+    log("  c3 sweep kernel alone")
+    out["sweep_alone"] = sweep_alone(torch, lbmps, inp, ("fp64", "fp32", "fp16", "bf16"), 20)
     return out
 
 
@@ -622,7 +652,7 @@ def main():
         all4 = ("fp64", "fp32", "fp16", "bf16")
         # MEM with the paper's reconstruction of uncovered cells (extrapolation)
         # becomes unstable once the falling sphere reaches about 0.07 cells per
-        # sweep here (~1000 sweeps): its errors are stated over 1000 sweeps; the
+        # sweep here (~1000 sweeps): its errors are stated over 800 sweeps; the
         # equilibrium reconstruction runs the full horizon
         runs = [("mem_cli", "mem_cli", (3, 2), all4, C2_MEM_SWEEPS, 10),
                 ("mem_cli_eqrefill", "mem_cli", (3, 2), all4, C2_SWEEPS, 20, "equilibrium"),
@@ -631,6 +661,8 @@ def main():
                 ("psm_m2b2", "psm", (2, 2), all4, C2_SHORT_SWEEPS, 8),
                 ("mem_bb", "mem_bb", (3, 2), ("fp64", "fp32"), C2_MEM_SWEEPS, 10)]
         line["forms"] = storage_forms(torch, lbmps, inp, runs)
+        log("sweep kernel alone, 192x192x384")
+        line["forms"]["sweep_alone"] = sweep_alone(torch, lbmps, inp, all4, 100)
 
     if not args.no_batch:
         log("batched form (48 instances)")

@@ -3,8 +3,9 @@
 // eps_features (signed distance from the surface, sorted direction cosines,
 // scaled curvature, zero padding).
 //
-// All GEMMs run on MFMA (v_mfma_f32_32x32x8bf16_1k: bf16 operands, fp32
-// accumulation).  Layers are chained with the weights as the A operand
+// All GEMMs run on MFMA (bf16 operands, fp32 accumulation): the K = 64 layer
+// of the forward pass on v_mfma_f32_32x32x16_bf16, the others on
+// v_mfma_f32_32x32x8bf16_1k.  Layers are chained with the weights as the A operand
 // (M = output features) and the activations as the B operand (N = 32 samples
 // per wave): the 32x32 fp32 result of one layer, converted to bf16, is in
 // exactly the lane/item order of the next layer's B operand.  Operand layout of
@@ -25,6 +26,8 @@
 namespace lbm {
 
 typedef short s4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f16v __attribute__((ext_vector_type(16)));
 
 constexpr int NIN = 8, NH = 64;
@@ -36,6 +39,20 @@ __device__ __forceinline__ float bfval(float x) { return (float)(__bf16)x; }
 
 __device__ __forceinline__ f16v mfma(s4 a, s4 b, f16v c) {
   return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// The K = 16 form of gfx950 (twice the work per instruction).  A sum over k
+// does not depend on which k an operand slot holds as long as A and B agree,
+// so the 64-feature contraction of layer 2 takes its 16 features per step in
+// the order the layer-1 result already has in registers: step m, lane half h,
+// item e holds feature 32 (m / 2) + 16 (m % 2) + 4 h + e for e < 4 and
+// 32 (m / 2) + 16 (m % 2) + 8 + 4 h + (e - 4) for e >= 4, i.e. the items of
+// the two K = 8 groups s = 2 (m % 2) and s + 1 of tile m / 2 side by side.
+__device__ __forceinline__ f16v mfma16(s8 a, s8 b, f16v c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+}
+__device__ __forceinline__ int k16_feature(int m, int h, int e) {
+  return 32 * (m >> 1) + 16 * (m & 1) + (e < 4 ? 4 * h + e : 8 + 4 * h + (e - 4));
 }
 
 __device__ __forceinline__ f16v zero16() {
@@ -58,7 +75,7 @@ struct Fwd {
 // once, reused for every tile of samples a wave processes).
 struct MlpA {
   s4 w1[2];
-  s4 w2[2][2][4];
+  s8 w2[2][4];  // [output tile][K = 16 step]
 };
 
 __device__ __forceinline__ void mlp_load_a(const float* __restrict__ P, MlpA& A) {
@@ -70,12 +87,9 @@ __device__ __forceinline__ void mlp_load_a(const float* __restrict__ P, MlpA& A)
 #pragma unroll
   for (int t2 = 0; t2 < 2; ++t2)
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          A.w2[t2][t][s][e] = bfbits(P[OFF_W2 + (32 * t2 + i) * NH + 32 * t + 8 * s + 4 * h + e]);
+      for (int e = 0; e < 8; ++e) A.w2[t2][m][e] = bfbits(P[OFF_W2 + (32 * t2 + i) * NH + k16_feature(m, h, e)]);
 }
 
 // Biases and output weights are read through V (b1[64] b2[64] W3[64] b3, the
@@ -112,9 +126,16 @@ __device__ __forceinline__ void mlp_forward(const MlpV& V, const MlpA& A, const 
   for (int t2 = 0; t2 < 2; ++t2) {
     f16v acc = zero16();
 #pragma unroll
-    for (int t = 0; t < 2; ++t)
+    for (int m = 0; m < 4; ++m) {
+      const s4 lo = f.h1b[m >> 1][2 * (m & 1)], hi = f.h1b[m >> 1][2 * (m & 1) + 1];
+      s8 b;
 #pragma unroll
-      for (int s = 0; s < 4; ++s) acc = mfma(A.w2[t2][t][s], f.h1b[t][s], acc);
+      for (int e = 0; e < 4; ++e) {
+        b[e] = lo[e];
+        b[4 + e] = hi[e];
+      }
+      acc = mfma16(A.w2[t2][m], b, acc);
+    }
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc[e] += V.b2[32 * t2 + 8 * (e >> 2) + 4 * h + (e & 3)];
     f.z2[t2] = acc;
