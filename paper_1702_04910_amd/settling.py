@@ -42,6 +42,19 @@ TAB1_UPV = {
     ("psm_m2b2", 18): -1.2363, ("psm_m2b2", 24): -1.2490, ("psm_m2b2", 36): -1.2588, ("psm_m2b2", 48): -1.2616,
     ("psm_m3b2", 18): -1.2128, ("psm_m3b2", 24): -1.2309, ("psm_m3b2", 36): -1.2453, ("psm_m3b2", 48): -1.2513,
 }
+# u_pV, u_pH, omega_pH of Tab. 2 (case B, steady oblique regime) by coupling and resolution D
+TAB2 = {
+    ("mem_bb", 24): (-1.3097, 0.0494, 0.0605), ("mem_bb", 36): (-1.3265, 0.0652, 0.0490),
+    ("mem_bb", 48): (-1.3325, 0.0722, 0.0367),
+    ("mem_cli", 24): (-1.3056, 0.0883, 0.0230), ("mem_cli", 36): (-1.3267, 0.0934, 0.0175),
+    ("mem_cli", 48): (-1.3328, 0.0991, 0.0104),
+    ("psm_m1b1", 24): (-1.2455, 0.1171, 0.0332), ("psm_m1b1", 36): (-1.2795, 0.1153, 0.0220),
+    ("psm_m1b1", 48): (-1.2944, 0.1159, 0.0186),
+    ("psm_m2b2", 24): (-1.3040, 0.1329, 0.0437), ("psm_m2b2", 36): (-1.3218, 0.1238, 0.0255),
+    ("psm_m2b2", 48): (-1.3278, 0.1209, 0.0198),
+    ("psm_m3b2", 24): (-1.2904, 0.1150, 0.0223), ("psm_m3b2", 36): (-1.3112, 0.1128, 0.0135),
+    ("psm_m3b2", 48): (-1.3192, 0.1124, 0.0108),
+}
 VARIANTS = {"mem_bb": ("mem_bb", 1, 1), "mem_cli": ("mem_cli", 1, 1), "psm_m1b1": ("psm", 1, 1),
             "psm_m2b2": ("psm", 2, 2), "psm_m3b2": ("psm", 3, 2)}
 
@@ -147,3 +160,83 @@ class Frame:
 
     def close(self):
         self.sim.close()
+
+
+def run_case(D, regime, variant, release_tref, offset=(0.0, 0.0, 0.0), average_tref=0.0, precision="fp32",
+             log=None):
+    """Calibrate, release, and run `release_tref` reference times; the state
+    at the end, and (average_tref > 0) u_pV, u_pH, w_pH averaged over the last
+    average_tref reference times (sampled every t_ref / 4)."""
+    import time
+
+    t0 = time.perf_counter()
+    fr = Frame(D, regime, variant, precision, offset=offset)
+    try:
+        hist = fr.calibrate(log=log)
+        upv_fixed = -fr.u_inf / fr.u_ref()
+        fr.release()
+        tr = fr.t_ref()
+        total = int(release_tref * tr) // 2 * 2
+        avg_from = total - int(average_tref * tr) // 2 * 2
+        every = max(2, int(tr / 4) // 2 * 2)
+        samples, done = [], 0
+        while done < total:
+            n = min(every, total - done)
+            fr.step(n)
+            done += n
+            if average_tref > 0 and done >= avg_from:
+                samples.append(fr.state())
+        st = fr.state()
+        out = dict(D=D, regime=regime, variant=variant, u_pV=st["u_pV"], u_pH=st["u_pH"], w_pH=st["w_pH"],
+                   u_pV_fixed=upv_fixed, nu_calibrated=hist[-1]["nu"], Ga=hist[-1]["Ga"],
+                   calibration_rounds=len(hist), t_ref_sweeps=tr, released_t_ref=release_tref, sweeps=fr.steps,
+                   X=st["X"])
+        if samples:
+            for k in ("u_pV", "u_pH", "w_pH"):
+                v = np.array([x[k] for x in samples])
+                out[k + "_mean"] = float(v.mean())
+                out[k + "_spread"] = float(v.max() - v.min())
+        out["MLUPS"] = fr.nx * fr.ny * fr.nz * fr.steps / (time.perf_counter() - t0) / 1e6
+        return out
+    finally:
+        fr.close()
+
+
+def main(argv=None):
+    """Tab. 1 / Tab. 2 runs on one GPU, one JSON object per run on stdout.
+
+        python -m paper_1702_04910_amd.settling --regime A --variants mem_cli,psm_m3b2 --D 24 --release 5
+        python -m paper_1702_04910_amd.settling --regime B --D 24 --release 250 --average 50 --offset 0.35,0.2
+    """
+    import argparse
+    import json
+    import sys
+
+    ap = argparse.ArgumentParser(description=main.__doc__)
+    ap.add_argument("--regime", default="A", choices=sorted(REGIMES))
+    ap.add_argument("--variants", default=",".join(VARIANTS))
+    ap.add_argument("--D", default="24", help="comma-separated sphere diameters in cells")
+    ap.add_argument("--release", type=float, default=5.0, help="reference times after the release")
+    ap.add_argument("--average", type=float, default=0.0, help="reference times averaged at the end")
+    ap.add_argument("--offset", default="0,0", help="horizontal offset of the sphere from the box centre (cells)")
+    ap.add_argument("--precision", default="fp32")
+    args = ap.parse_args(argv)
+    off = [float(v) for v in args.offset.split(",")] + [0.0]
+
+    def log(*a):
+        print(*a, file=sys.stderr, flush=True)
+
+    for D in (int(v) for v in args.D.split(",")):
+        for v in args.variants.split(","):
+            log("D %d %s regime %s" % (D, v, args.regime))
+            r = run_case(D, args.regime, v, args.release, (off[0], off[1], 0.0), args.average, args.precision, log)
+            if args.regime == "A" and (v, D) in TAB1_UPV:
+                r["tab1_u_pV"] = TAB1_UPV[(v, D)]
+            if args.regime == "B" and (v, D) in TAB2:
+                r["tab2"] = dict(zip(("u_pV", "u_pH", "w_pH"), TAB2[(v, D)]))
+            print(json.dumps(r), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
