@@ -55,6 +55,19 @@ TAB2 = {
     ("psm_m3b2", 24): (-1.2904, 0.1150, 0.0223), ("psm_m3b2", 36): (-1.3112, 0.1128, 0.0135),
     ("psm_m3b2", 48): (-1.3192, 0.1124, 0.0108),
 }
+# Tab. 3 (case C, oblique oscillating): mean u_pV, u_pH, omega_pH, their fluctuations, frequency f
+TAB3 = {
+    ("mem_bb", 36): (-1.3479, 0.0624, 0.0452, 0.0108, 0.0624, 0.0439, 0.0415),
+    ("mem_bb", 48): (-1.3540, 0.0678, 0.0351, 0.0126, 0.0678, 0.0350, 0.0356),
+    ("mem_cli", 36): (-1.3461, 0.1001, 0.0284, 0.0053, 0.0333, 0.0120, 0.0637),
+    ("mem_cli", 48): (-1.3527, 0.1076, 0.0195, 0.0058, 0.0307, 0.0087, 0.0668),
+    ("psm_m1b1", 36): (-1.2978, 0.1295, 0.0223, 0.0015, 0.0065, 0.0019, 0.0680),
+    ("psm_m1b1", 48): (-1.3131, 0.1306, 0.0173, 0.0013, 0.0049, 0.0013, 0.0669),
+    ("psm_m2b2", 36): (-1.3389, 0.1363, 0.0250, 0.0015, 0.0072, 0.0018, 0.0690),
+    ("psm_m2b2", 48): (-1.3455, 0.1355, 0.0185, 0.0013, 0.0052, 0.0013, 0.0712),
+    ("psm_m3b2", 36): (-1.3283, 0.1245, 0.0117, 0.0016, 0.0086, 0.0021, 0.0733),
+    ("psm_m3b2", 48): (-1.3371, 0.1240, 0.0084, 0.0017, 0.0095, 0.0021, 0.0729),
+}
 VARIANTS = {"mem_bb": ("mem_bb", 1, 1), "mem_cli": ("mem_cli", 1, 1), "psm_m1b1": ("psm", 1, 1),
             "psm_m2b2": ("psm", 2, 2), "psm_m3b2": ("psm", 3, 2)}
 
@@ -162,6 +175,25 @@ class Frame:
         self.sim.close()
 
 
+def dominant_frequency(t, v):
+    """Frequency (per unit of t) of the largest peak of the discrete Fourier
+    transform of v(t) sampled at equal steps, mean removed, Hann window, the
+    peak located by a parabola through the three largest bins of the
+    magnitude (sixteen-fold zero padding)."""
+    if len(v) < 8:
+        return None
+    dt = float(t[1] - t[0])
+    x = (v - v.mean()) * np.hanning(len(v))
+    n = 16 * len(v)
+    mag = np.abs(np.fft.rfft(x, n))
+    k = int(np.argmax(mag[1:])) + 1
+    if 1 <= k < len(mag) - 1:
+        a, b, c = mag[k - 1], mag[k], mag[k + 1]
+        den = a - 2 * b + c
+        k = k + (0.5 * (a - c) / den if den != 0 else 0.0)
+    return float(k / (n * dt))
+
+
 def run_case(D, regime, variant, release_tref, offset=(0.0, 0.0, 0.0), average_tref=0.0, precision="fp32",
              log=None):
     """Calibrate, release, and run `release_tref` reference times; the state
@@ -196,6 +228,9 @@ def run_case(D, regime, variant, release_tref, offset=(0.0, 0.0, 0.0), average_t
                 v = np.array([x[k] for x in samples])
                 out[k + "_mean"] = float(v.mean())
                 out[k + "_spread"] = float(v.max() - v.min())
+                out[k + "_rms"] = float(v.std())
+            t = np.array([x["t"] for x in samples], float) / tr
+            out["frequency"] = dominant_frequency(t, np.array([x["u_pH"] for x in samples]))
         out["MLUPS"] = fr.nx * fr.ny * fr.nz * fr.steps / (time.perf_counter() - t0) / 1e6
         return out
     finally:
@@ -234,6 +269,9 @@ def main(argv=None):
                 r["tab1_u_pV"] = TAB1_UPV[(v, D)]
             if args.regime == "B" and (v, D) in TAB2:
                 r["tab2"] = dict(zip(("u_pV", "u_pH", "w_pH"), TAB2[(v, D)]))
+            if args.regime == "C" and (v, D) in TAB3:
+                r["tab3"] = dict(zip(("u_pV", "u_pH", "w_pH", "u_pV_fluct", "u_pH_fluct", "w_pH_fluct", "f"),
+                                     TAB3[(v, D)]))
             print(json.dumps(r), flush=True)
     return 0
 

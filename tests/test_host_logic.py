@@ -60,3 +60,18 @@ def test_build_flags_keep_rounding_identical_across_kernels():
 
     flags = " ".join(build.CFLAGS)
     assert "-packed-fp32-ops" in flags and "-fma-mix-insts" in flags
+
+
+def test_dominant_frequency_of_a_sampled_oscillation():
+    # the frame driver's DFT frequency estimate (Tab. 3's f): a sine of known
+    # frequency plus noise and an offset, sampled every quarter time unit
+    import numpy as np
+
+    from paper_1702_04910_amd.settling import dominant_frequency
+
+    rng = np.random.default_rng(3)
+    t = np.arange(0.0, 150.0, 0.25)
+    for f in (0.0415, 0.071, 0.2):
+        v = 0.12 + 0.02 * np.sin(2 * np.pi * f * t + 1.0) + 1e-3 * rng.standard_normal(len(t))
+        assert abs(dominant_frequency(t, v) - f) < 0.002
+    assert dominant_frequency(t[:5], t[:5]) is None
