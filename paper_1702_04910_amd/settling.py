@@ -211,13 +211,18 @@ def run_case(D, regime, variant, release_tref, offset=(0.0, 0.0, 0.0), average_t
         total = int(release_tref * tr) // 2 * 2
         avg_from = total - int(average_tref * tr) // 2 * 2
         every = max(2, int(tr / 4) // 2 * 2)
-        samples, done = [], 0
+        samples, done, logged = [], 0, 0
         while done < total:
             n = min(every, total - done)
             fr.step(n)
             done += n
             if average_tref > 0 and done >= avg_from:
                 samples.append(fr.state())
+            if log and done - logged >= 25 * tr:
+                x = fr.state()
+                log("  t = %.0f t_ref: u_pV %.5f u_pH %.5f w_pH %.5f z %.1f" % (done / tr, x["u_pV"], x["u_pH"],
+                                                                               x["w_pH"], x["X"][2]))
+                logged = done
         st = fr.state()
         out = dict(D=D, regime=regime, variant=variant, u_pV=st["u_pV"], u_pH=st["u_pH"], w_pH=st["w_pH"],
                    u_pV_fixed=upv_fixed, nu_calibrated=hist[-1]["nu"], Ga=hist[-1]["Ga"],
