@@ -82,3 +82,20 @@ def test_frame_with_moving_sphere(coupling, precision):
         assert eX < (1e-13 if precision == "fp64" else tol)
     assert abs(po["U"][0][2]) > 0  # released and moving
     sim.close()
+
+
+@pytest.mark.gpu
+def test_frame_driver_small_case():
+    # the Tab. 1 / Tab. 2 driver end to end at the paper's smallest resolution
+    # (D = 18; with nu0 = 0.01 the inflow of a smaller sphere would be too fast
+    # for the lattice): Galileo number matched, u_pV at Tab. 1's value, the
+    # averages and the frequency fields present and finite
+    from paper_1702_04910_amd import settling
+
+    say("frame driver, D = 18, case A")
+    r = settling.run_case(18, "A", "mem_cli", release_tref=4.0, average_tref=3.0)
+    assert abs(r["Ga"] / 144.0 - 1.0) < 1e-4
+    assert abs(r["u_pV"] / settling.TAB1_UPV[("mem_cli", 18)] - 1.0) < 5e-3
+    assert abs(r["u_pV"] - r["u_pV_fixed"]) < 1e-3
+    for k in ("u_pV_mean", "u_pH_mean", "w_pH_mean", "u_pV_rms", "frequency"):
+        assert k in r and np.isfinite(r[k])
