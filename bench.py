@@ -289,7 +289,7 @@ def sweep_alone(torch, lbmps, inp, precisions, sweeps):
         shape = tuned_shape(inp, prec)
         sim = lbmps.Sim(lbmps.make_config(inp["nx"], inp["ny"], inp["nz"], inp["nu"], precision=prec, **shape))
         sim.init_equilibrium()
-        sim.step(4)
+        sim.step(max(4, sweeps // 2))  # warm-up: first touch of the buffers, clocks
         sim.sync()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
