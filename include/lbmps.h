@@ -62,7 +62,7 @@ typedef int32_t lbmps_status;
 #define LBMPS_FP64 0
 #define LBMPS_FP32 1
 #define LBMPS_FP16_DEV 2 /* IEEE half deviations g = f - w, round to nearest even */
-#define LBMPS_BF16_DEV 3 /* bfloat16 deviations g = f - w, round to nearest even */
+#define LBMPS_BF16_DEV 3 /* bfloat16 deviations g = f - w; the sweep rounds stored values stochastically */
 /* reconstruction of uncovered MEM cells (Sec. 2.2.3) */
 #define LBMPS_REFILL_EXTRAPOLATE 0
 #define LBMPS_REFILL_EQUILIBRIUM 1

@@ -220,6 +220,31 @@ template <> struct StochasticRound<_Float16> {
 // sphere row (consecutive pairs) occupy one contiguous span.
 __device__ inline long long stage_at(int L, int q) { return (long long)L * Q + q; }
 
+// Stochastic rounding of all 19 post-collision values of a cell before they
+// are stored as bfloat16 (other storage types: stored as computed).  BF16
+// keeps 8 bits: round-to-nearest of the nearly uniform deviations of a slow
+// flow errs the same way in many cells and steps, and that bias, not the
+// size of the rounding, drove the BF16 runs' drift.  The random bits: one
+// hash of the cell index and of the bits of the cell's post-collision rest
+// value (so they change from step to step), spread over the directions by a
+// Weyl sequence (additions only); 16 bits per value.  A value already
+// representable in BF16 (low half zero) is left as it is.
+template <typename S> struct CellRound {
+  template <typename R> __device__ static inline void apply(R (&)[19], long long) {}
+};
+template <> struct CellRound<__bf16> {
+  __device__ static inline void apply(float (&o)[19], long long cell) {
+    const uint32_t h = fmix32((uint32_t)cell * 0x9E3779B9u ^ __float_as_uint(o[0]));
+    const uint32_t step = 2u * h + 0x632BE5ABu;
+    uint32_t x = h;
+#pragma unroll
+    for (int q = 0; q < 19; ++q) {
+      o[q] = __uint_as_float((__float_as_uint(o[q]) + (x >> 16)) & 0xffff0000u);
+      x += step;
+    }
+  }
+};
+
 // compute precision paired with each storage type
 template <typename S> struct CompOf { using type = float; };
 template <> struct CompOf<double> { using type = double; };

@@ -241,6 +241,8 @@ __device__ __forceinline__ void sweep_body_twin(const InstDev* __restrict__ inst
       }
       collide_cell<R>(g0, o0, lp, lm, fx, fy, fz);
       collide_cell<R>(g1, o1, lp, lm, fx, fy, fz);
+      CellRound<S>::apply(o0, idx);
+      CellRound<S>::apply(o1, idx + 1);
       const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
       const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
       const int xm = x == 0 ? nx - 1 : x - 1, xpp = x + 2 == nx ? 0 : x + 2;
@@ -329,6 +331,7 @@ __device__ __forceinline__ void sweep_body_quad(const InstDev* __restrict__ inst
 #pragma unroll
         for (int q = 0; q < Q; ++q) g[q] = Codec<S>::ld(__builtin_bit_cast(S, (unsigned short)(win[q] >> (16 * k))));
         collide_cell<R>(g, o, lp, lm, fx, fy, fz);
+        CellRound<S>::apply(o, idx + k);
 #pragma unroll
         for (int q = 0; q < Q; ++q)
           wout[q] |= (W)__builtin_bit_cast(unsigned short, Codec<S>::st(o[q])) << (16 * k);
@@ -435,6 +438,7 @@ __device__ __forceinline__ void sweep_body(const InstDev* __restrict__ insts, co
       } else {
         collide_cell<R>(g, o, lp, lm, fx, fy, fz);
       }
+      CellRound<S>::apply(o, idx);
       const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
       const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
       const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
@@ -594,6 +598,7 @@ __global__ __launch_bounds__(256) void resweep_cells_kernel(const int* __restric
 #pragma unroll
     for (int q = 0; q < Q; ++q) g[q] = Codec<S>::ld(s[pdf_at(cell, q)]);
     collide_cell<R>(g, o, (R)I.lam_p, (R)I.lam_m, (R)I.fext[0], (R)I.fext[1], (R)I.fext[2]);
+    CellRound<S>::apply(o, cell);
     const int x = cell % nx, yz = cell / nx, y = yz % ny, z = yz / ny;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {

@@ -3,7 +3,7 @@ FP32) against the FP64 oracle.
 
 Tolerance, derived from the arithmetic: starting from a state the storage
 holds exactly, one sweep computes in FP32 (relative error ~1e-7) and rounds
-once to nearest even on store.  So every stored value equals the oracle's
+once on store (FP16: to nearest even).  So every stored value equals the oracle's
 FP64 result rounded once to the storage type, except where the FP32 and FP64
 values straddle a rounding midpoint: there the two differ by one unit in the
 last place (plus the FP32 absolute error, ~2^-20 of the largest deviation,
@@ -20,10 +20,11 @@ sweep has already stored, i.e. rounded: each link term may carry up to
 and conserves the rest, so the error stays below 4 k u of the largest
 deviation.
 
-The values pushed by PSM-overlapped cells are rounded stochastically (to one of
-the two neighbours of the FP32 result, the upper with probability equal to the
-distance from the lower in units of their spacing), so those are checked to
-lie within one spacing of the exact value.
+The values pushed by PSM-overlapped cells, and with BF16 storage every stored
+post-collision value, are rounded stochastically (to one of the two neighbours
+of the FP32 result, the upper with probability equal to the distance from the
+lower in units of their spacing), so those are checked to lie within one
+spacing of the exact value, with about a quarter of them not the nearest.
 
 Over a long horizon the error of the sphere's velocity and force is measured
 at full size by the benchmark (bench.py, precision forms)."""
@@ -60,26 +61,30 @@ def _check_rounded_once(go, gg, mask, kind, extra=None, stochastic=None):
     """mask: [z, y, x] cells compared; extra: optional [q, z, y, x] absolute
     allowance added to the tolerance (values built from stored inputs);
     stochastic: optional [q, z, y, x] mask of the values pushed by overlapped
-    PSM cells, which are rounded stochastically: each must be one of the two
-    neighbours of the exact value (within one spacing of it), and they are left
-    out of the exact-match fraction."""
-    sr = np.zeros(go.shape, bool) if stochastic is None else stochastic
-    sel = mask[None, :, :, :] & ~sr
-    ref = round_store(go[sel], kind)
-    got = gg[sel]
-    diff = np.abs(got - ref)
+    PSM cells, which are rounded stochastically (with BF16 storage every value
+    is): each must be one of the two neighbours of the exact value (within one
+    spacing of it), and they are left out of the exact-match fraction."""
+    sr = np.zeros(go.shape, bool) if stochastic is None else stochastic.copy()
+    if kind == "bf16":  # BF16 storage rounds every post-collision value stochastically
+        sr[:] = True
     slack = 2.0 ** -20 * np.abs(go[:, mask]).max()
-    tol = ulp_store(go[sel], kind) + slack
-    if extra is not None:
-        tol = tol + extra[sel]
-    exact = float(np.mean(got == ref))
-    say("  exact fraction %.5f, max diff / tolerance %.2f" % (exact, float((diff / tol).max())))
-    assert np.all(diff <= tol)
-    assert exact >= 0.99
-    if stochastic is not None:
-        ssel = mask[None, :, :, :] & sr
+    sel = mask[None, :, :, :] & ~sr
+    if sel.any():
+        ref = round_store(go[sel], kind)
+        got = gg[sel]
+        diff = np.abs(got - ref)
+        tol = ulp_store(go[sel], kind) + slack
+        if extra is not None:
+            tol = tol + extra[sel]
+        exact = float(np.mean(got == ref))
+        say("  exact fraction %.5f, max diff / tolerance %.2f" % (exact, float((diff / tol).max())))
+        assert np.all(diff <= tol)
+        assert exact >= 0.99
+    ssel = mask[None, :, :, :] & sr
+    if ssel.any():
         x, y = go[ssel], gg[ssel]
-        assert np.all(np.abs(y - x) <= ulp_store(x, kind) + slack)
+        tol = ulp_store(x, kind) + slack + (extra[ssel] if extra is not None else 0.0)
+        assert np.all(np.abs(y - x) <= tol)
         differs = float(np.mean(y != round_store(x, kind)))
         say("  %d stochastically rounded values, %.3f of them not the nearest" % (x.size, differs))
         assert 0.05 < differs < 0.5
