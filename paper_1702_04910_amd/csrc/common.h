@@ -148,11 +148,11 @@ template <> struct Codec<float> {
 };
 template <> struct Codec<_Float16> {
   __device__ static inline float ld(_Float16 v) { return (float)v; }
-  // Round to nearest even from the FP32 value as computed.  The empty asm pins
-  // v as an FP32 register value: otherwise the compiler may fuse the
-  // conversion into the FMA that produced v (a mixed-precision FMA with an FP16
-  // result rounds once instead of twice), and whether it does depends on the
-  // surrounding kernel, so the stored bits would differ between kernels.
+  // Round to nearest even from the FP32 value as computed.  The library is
+  // built without gfx950's mixed-precision FMAs: one with an FP16 result would
+  // fuse this conversion into the FMA that produced v (one rounding instead of
+  // two), and whether the compiler forms it depends on the surrounding kernel,
+  // so the stored bits would differ between kernels.
   __device__ static inline _Float16 st(float v) { return (_Float16)v; }
 };
 template <> struct Codec<__bf16> {
@@ -180,16 +180,20 @@ __device__ inline uint32_t fmix32(uint32_t h) {
 }
 __device__ inline uint32_t sr_bits(float x, uint32_t key) { return fmix32(__float_as_uint(x) ^ fmix32(key)); }
 
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
 template <typename S> struct StochasticRound {  // 4- and 8-byte storage: the value is stored as computed
   template <typename R> __device__ static inline R apply(R x, uint32_t) { return x; }
 };
 template <> struct StochasticRound<__bf16> {
   // bfloat16 is the upper half of the FP32 pattern: adding 16 random bits to
-  // the magnitude and truncating rounds up with probability (low half) / 2^16
+  // the magnitude and truncating rounds up with probability (low half) / 2^16;
+  // gfx950's v_cvt_sr_bf16_f32 does that with the upper 16 bits of its random
+  // word (the result is put in the upper half of a zero word: the FP32 value
+  // of the stored BF16)
   __device__ static inline float apply(float x, uint32_t key) {
-    const uint32_t b = __float_as_uint(x);
-    const uint32_t r = sr_bits(x, key) & 0xffffu;
-    return __uint_as_float((b + r) & 0xffff0000u);
+    const bf16x2 v = __builtin_amdgcn_cvt_sr_bf16_f32(bf16x2{}, x, sr_bits(x, key) << 16, true);
+    return __uint_as_float(__builtin_bit_cast(uint32_t, v));
   }
 };
 template <> struct StochasticRound<_Float16> {
@@ -220,29 +224,66 @@ template <> struct StochasticRound<_Float16> {
 // sphere row (consecutive pairs) occupy one contiguous span.
 __device__ inline long long stage_at(int L, int q) { return (long long)L * Q + q; }
 
-// Stochastic rounding of all 19 post-collision values of a cell before they
+// Stochastic rounding of all 19 post-collision values of a cell when they
 // are stored as bfloat16 (other storage types: stored as computed).  BF16
 // keeps 8 bits: round-to-nearest of the nearly uniform deviations of a slow
 // flow errs the same way in many cells and steps, and that bias, not the
 // size of the rounding, drove the BF16 runs' drift.  The random bits: one
 // hash of the cell index and of the bits of the cell's post-collision rest
 // value (so they change from step to step), spread over the directions by a
-// Weyl sequence (additions only); 16 bits per value.  A value already
-// representable in BF16 (low half zero) is left as it is.
-template <typename S> struct CellRound {
-  template <typename R> __device__ static inline void apply(R (&)[19], long long) {}
+// Weyl sequence (additions only), one 32-bit word per value in the order
+// q = 0..18.  The rounding itself is gfx950's conversion with stochastic
+// rounding (v_cvt_sr_bf16_f32), one instruction per value: it adds the upper
+// 16 bits of the random word to the FP32 pattern (the magnitude: sign and
+// magnitude are separate) and keeps the upper half, so the value rounds away
+// from zero with probability (lower half) / 2^16 and a value already
+// representable in BF16 is stored as it is.
+template <typename S> struct CellBits {  // no random bits for the other storage types
+  __device__ CellBits(float, long long) {}
+  __device__ uint32_t next() { return 0u; }
 };
-template <> struct CellRound<__bf16> {
-  __device__ static inline void apply(float (&o)[19], long long cell) {
-    const uint32_t h = fmix32((uint32_t)cell * 0x9E3779B9u ^ __float_as_uint(o[0]));
-    const uint32_t step = 2u * h + 0x632BE5ABu;
-    uint32_t x = h;
-#pragma unroll
-    for (int q = 0; q < 19; ++q) {
-      o[q] = __uint_as_float((__float_as_uint(o[q]) + (x >> 16)) & 0xffff0000u);
-      x += step;
-    }
+template <> struct CellBits<__bf16> {
+  uint32_t x, step;
+  __device__ CellBits(float o0, long long cell) : x(fmix32((uint32_t)cell * 0x9E3779B9u ^ __float_as_uint(o0))) {
+    step = 2u * x + 0x632BE5ABu;
   }
+  __device__ uint32_t next() {
+    const uint32_t r = x;
+    x += step;
+    return r;
+  }
+};
+// v rounded stochastically with the random bits r into the low (hi false) or
+// high half of the word w; the other half is kept
+__device__ inline uint32_t bf16_sr_put(uint32_t w, float v, uint32_t r, bool hi) {
+  const bf16x2 o = __builtin_bit_cast(bf16x2, w);
+  return __builtin_bit_cast(uint32_t, hi ? __builtin_amdgcn_cvt_sr_bf16_f32(o, v, r, true)
+                                         : __builtin_amdgcn_cvt_sr_bf16_f32(o, v, r, false));
+}
+
+// One post-collision value converted for storage with the cell's random bits
+// r: BF16 rounded stochastically, the other types as Codec<S>::st.
+template <typename S> struct CellStore {
+  template <typename R> __device__ static inline S st(R v, uint32_t) { return Codec<S>::st(v); }
+};
+template <> struct CellStore<__bf16> {
+  __device__ static inline __bf16 st(float v, uint32_t r) {
+    return __builtin_bit_cast(__bf16, (unsigned short)bf16_sr_put(0u, v, r, false));
+  }
+};
+
+// A 2-byte stored value put into the low or high half of a 32-bit word whose
+// other half is kept: FP16 rounded to nearest even, BF16 stochastically with
+// the cell's random bits r (the same result as CellStore).
+template <typename S> struct Half16;
+template <> struct Half16<_Float16> {
+  __device__ static inline uint32_t put(uint32_t w, float v, uint32_t, bool hi) {
+    const uint32_t b = __builtin_bit_cast(unsigned short, Codec<_Float16>::st(v));
+    return w | (hi ? b << 16 : b);
+  }
+};
+template <> struct Half16<__bf16> {
+  __device__ static inline uint32_t put(uint32_t w, float v, uint32_t r, bool hi) { return bf16_sr_put(w, v, r, hi); }
 };
 
 // compute precision paired with each storage type

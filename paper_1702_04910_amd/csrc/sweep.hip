@@ -178,6 +178,15 @@ __device__ __forceinline__ typename Twin<S>::W twin_pack(S a, S b) {
     return (W)ua | ((W)ub << (8 * sizeof(S)));  // the lower address holds the low bits
   }
 }
+// The stored word of a cell pair from the two post-collision values and the
+// cells' random bits (2-byte storage: each value converted into its half).
+template <typename S, typename R>
+__device__ __forceinline__ typename Twin<S>::W twin_word(R a, R b, uint32_t ra, uint32_t rb) {
+  if constexpr (sizeof(S) == 2)
+    return Half16<S>::put(Half16<S>::put(0u, a, ra, false), b, rb, true);
+  else
+    return twin_pack<S>(CellStore<S>::st(a, ra), CellStore<S>::st(b, rb));
+}
 template <typename S>
 __device__ __forceinline__ void twin_unpack(typename Twin<S>::W w, S& a, S& b) {
   using U = typename Twin<S>::U;
@@ -241,20 +250,21 @@ __device__ __forceinline__ void sweep_body_twin(const InstDev* __restrict__ inst
       }
       collide_cell<R>(g0, o0, lp, lm, fx, fy, fz);
       collide_cell<R>(g1, o1, lp, lm, fx, fy, fz);
-      CellRound<S>::apply(o0, idx);
-      CellRound<S>::apply(o1, idx + 1);
+      CellBits<S> rb0(o0[0], idx), rb1(o1[0], idx + 1);
       const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
       const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
       const int xm = x == 0 ? nx - 1 : x - 1, xpp = x + 2 == nx ? 0 : x + 2;
       const int lrow = r * nx;
 #define LBM_PUSH2(qq)                                                                       \
-  if constexpr (cx(qq) == 0) {                                                              \
-    const int ya = pick<cy(qq)>(ym, y, yp), za = pick<cz(qq)>(zm, z, zp);                   \
-    twin_st_nt<S>(&d[pdf_at((za * ny + ya) * nx + x, qq)],                                  \
-                  twin_pack<S>(Codec<S>::st(o0[qq]), Codec<S>::st(o1[qq])));                \
-  } else {                                                                                  \
-    sh[xslot(qq) * ncells + lrow + (cx(qq) > 0 ? x + 1 : xm)] = Codec<S>::st(o0[qq]);      \
-    sh[xslot(qq) * ncells + lrow + (cx(qq) > 0 ? xpp : x)] = Codec<S>::st(o1[qq]);         \
+  {                                                                                         \
+    const uint32_t r0 = rb0.next(), r1 = rb1.next();                                        \
+    if constexpr (cx(qq) == 0) {                                                            \
+      const int ya = pick<cy(qq)>(ym, y, yp), za = pick<cz(qq)>(zm, z, zp);                 \
+      twin_st_nt<S>(&d[pdf_at((za * ny + ya) * nx + x, qq)], twin_word<S>(o0[qq], o1[qq], r0, r1)); \
+    } else {                                                                                \
+      sh[xslot(qq) * ncells + lrow + (cx(qq) > 0 ? x + 1 : xm)] = CellStore<S>::st(o0[qq], r0); \
+      sh[xslot(qq) * ncells + lrow + (cx(qq) > 0 ? xpp : x)] = CellStore<S>::st(o1[qq], r1);    \
+    }                                                                                       \
   }
       LBM_PUSH2(0) LBM_PUSH2(1) LBM_PUSH2(2) LBM_PUSH2(3) LBM_PUSH2(4) LBM_PUSH2(5) LBM_PUSH2(6)
       LBM_PUSH2(7) LBM_PUSH2(8) LBM_PUSH2(9) LBM_PUSH2(10) LBM_PUSH2(11) LBM_PUSH2(12) LBM_PUSH2(13)
@@ -319,11 +329,12 @@ __device__ __forceinline__ void sweep_body_quad(const InstDev* __restrict__ inst
       const int y = row - z * ny;
       const int idx = row * nx + x;
       W win[Q], wout[Q];
+      uint32_t wlo[Q], whi[Q];  // cells 0, 1 and cells 2, 3 of the word
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const W* a = reinterpret_cast<const W*>(&s[pdf_at(idx, q)]);
         win[q] = NTLD ? __builtin_nontemporal_load(a) : *a;
-        wout[q] = 0;
+        wlo[q] = whi[q] = 0u;
       }
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -331,11 +342,15 @@ __device__ __forceinline__ void sweep_body_quad(const InstDev* __restrict__ inst
 #pragma unroll
         for (int q = 0; q < Q; ++q) g[q] = Codec<S>::ld(__builtin_bit_cast(S, (unsigned short)(win[q] >> (16 * k))));
         collide_cell<R>(g, o, lp, lm, fx, fy, fz);
-        CellRound<S>::apply(o, idx + k);
+        CellBits<S> rb(o[0], idx + k);
 #pragma unroll
-        for (int q = 0; q < Q; ++q)
-          wout[q] |= (W)__builtin_bit_cast(unsigned short, Codec<S>::st(o[q])) << (16 * k);
+        for (int q = 0; q < Q; ++q) {
+          uint32_t& w = k < 2 ? wlo[q] : whi[q];
+          w = Half16<S>::put(w, o[q], rb.next(), (k & 1) != 0);
+        }
       }
+#pragma unroll
+      for (int q = 0; q < Q; ++q) wout[q] = (W)whi[q] << 32 | wlo[q];
       const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
       const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
 #define LBM_PUSH4(qq)                                                                       \
@@ -438,17 +453,20 @@ __device__ __forceinline__ void sweep_body(const InstDev* __restrict__ insts, co
       } else {
         collide_cell<R>(g, o, lp, lm, fx, fy, fz);
       }
-      CellRound<S>::apply(o, idx);
+      CellBits<S> rb(o[0], idx);
       const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
       const int zm = z == 0 ? nz - 1 : z - 1, zp = z == nz - 1 ? 0 : z + 1;
       const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
       const int lrow = r * nx;
 #define LBM_PUSH(qq)                                                                        \
-  if constexpr (cx(qq) == 0) {                                                              \
-    const int ya = pick<cy(qq)>(ym, y, yp), za = pick<cz(qq)>(zm, z, zp);                   \
-    st_nt(&d[pdf_at((za * ny + ya) * nx + x, qq)], Codec<S>::st(o[qq]));                   \
-  } else {                                                                                  \
-    sh[xslot(qq) * ncells + lrow + pick<cx(qq)>(xm, x, xp)] = Codec<S>::st(o[qq]);          \
+  {                                                                                         \
+    const S v = CellStore<S>::st(o[qq], rb.next());                                         \
+    if constexpr (cx(qq) == 0) {                                                            \
+      const int ya = pick<cy(qq)>(ym, y, yp), za = pick<cz(qq)>(zm, z, zp);                 \
+      st_nt(&d[pdf_at((za * ny + ya) * nx + x, qq)], v);                                    \
+    } else {                                                                                \
+      sh[xslot(qq) * ncells + lrow + pick<cx(qq)>(xm, x, xp)] = v;                          \
+    }                                                                                       \
   }
       LBM_PUSH(0) LBM_PUSH(1) LBM_PUSH(2) LBM_PUSH(3) LBM_PUSH(4) LBM_PUSH(5) LBM_PUSH(6)
       LBM_PUSH(7) LBM_PUSH(8) LBM_PUSH(9) LBM_PUSH(10) LBM_PUSH(11) LBM_PUSH(12) LBM_PUSH(13)
@@ -598,12 +616,12 @@ __global__ __launch_bounds__(256) void resweep_cells_kernel(const int* __restric
 #pragma unroll
     for (int q = 0; q < Q; ++q) g[q] = Codec<S>::ld(s[pdf_at(cell, q)]);
     collide_cell<R>(g, o, (R)I.lam_p, (R)I.lam_m, (R)I.fext[0], (R)I.fext[1], (R)I.fext[2]);
-    CellRound<S>::apply(o, cell);
+    CellBits<S> rb(o[0], cell);
     const int x = cell % nx, yz = cell / nx, y = yz % ny, z = yz / ny;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const int xa = wrapi(x + cx(q), nx), ya = wrapi(y + cy(q), ny), za = wrapi(z + cz(q), nz);
-      d[pdf_at(((long long)za * ny + ya) * nx + xa, q)] = Codec<S>::st(o[q]);
+      d[pdf_at(((long long)za * ny + ya) * nx + xa, q)] = CellStore<S>::st(o[q], rb.next());
     }
   }
 }
