@@ -422,12 +422,20 @@ __device__ __forceinline__ void sweep_body(const InstDev* __restrict__ insts, co
       const int z = row / ny;
       const int y = row - z * ny;
       const int idx = row * nx + x;
+      // staged mode: the cell map is read before the PDFs and every cell is
+      // collided (the result replaced for overlapped cells), so that the PDF
+      // loads stay ahead of the test of the map and the staged values are
+      // requested while they are still in flight
+      int Lst = INT_MAX;
+      if constexpr (PSM == 2) Lst = I.cellmap_off >= 0 ? cellmap[I.cellmap_off + idx] : INT_MAX;
       R g[Q], o[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         const S* a = &s[pdf_at(idx, q)];
         g[q] = Codec<S>::ld(NTLD ? ld_nt(a) : *a);
       }
+      // keep the test of the map (and its wait) behind the PDF loads
+      if constexpr (PSM == 2) __builtin_amdgcn_sched_barrier(0);
       if constexpr (PSM == 1) {
         // cells of a single pair are collided here, with the solid operator
         // fixed per branch; cells shared by several particles get the fluid
@@ -443,12 +451,15 @@ __device__ __forceinline__ void sweep_body(const InstDev* __restrict__ insts, co
           collide_cell<R>(g, o, lp, lm, fx, fy, fz);
         }
       } else if constexpr (PSM == 2) {
-        const int L = I.cellmap_off >= 0 ? cellmap[I.cellmap_off + idx] : INT_MAX;
-        if (L != INT_MAX) {
+        R st[Q];
+        if (Lst != INT_MAX) {
 #pragma unroll
-          for (int q = 0; q < Q; ++q) o[q] = Codec<S>::ld(stage[stage_at(L, q)]);
-        } else {
-          collide_cell<R>(g, o, lp, lm, fx, fy, fz);
+          for (int q = 0; q < Q; ++q) st[q] = Codec<S>::ld(stage[stage_at(Lst, q)]);
+        }
+        collide_cell<R>(g, o, lp, lm, fx, fy, fz);
+        if (Lst != INT_MAX) {
+#pragma unroll
+          for (int q = 0; q < Q; ++q) o[q] = st[q];
         }
       } else {
         collide_cell<R>(g, o, lp, lm, fx, fy, fz);
