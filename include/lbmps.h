@@ -61,8 +61,9 @@ typedef int32_t lbmps_status;
 /* PDF storage precision (compute is FP64 for FP64 storage, FP32 otherwise) */
 #define LBMPS_FP64 0
 #define LBMPS_FP32 1
-#define LBMPS_FP16_DEV 2 /* IEEE half deviations g = f - w, round to nearest even */
-#define LBMPS_BF16_DEV 3 /* bfloat16 deviations g = f - w; the sweep rounds stored values stochastically */
+#define LBMPS_FP16_DEV 2 /* IEEE half deviations g = f - w, round to nearest even (stochastically in
+                            PSM-overlapped cells) */
+#define LBMPS_BF16_DEV 3 /* bfloat16 deviations g = f - w; post-collision values rounded stochastically */
 /* reconstruction of uncovered MEM cells (Sec. 2.2.3) */
 #define LBMPS_REFILL_EXTRAPOLATE 0
 #define LBMPS_REFILL_EQUILIBRIUM 1
