@@ -155,9 +155,12 @@ def tune(nx, ny, nz, precision, sweeps=20, cache=CACHE, force=False, verbose=Fal
     return best
 
 
-def tune_batch(make_sim, tile_cells=(256, 512, 1024), grids=(0, 1024, 2048, 4096), sweeps=10, verbose=False):
+def tune_batch(make_sim, tile_cells=(256, 288, 384, 512, 1024), grids=(0, 1024, 2048, 4096), sweeps=10,
+               verbose=False):
     """Launch shape for a batched context.  make_sim(tile_cells) must return a
-    ready Sim whose configurations use rows = max(1, tile_cells // nx).  Times
+    ready Sim whose configurations use rows = max(1, tile_cells // nx) (288 and
+    384 give two rows of the 144-wide boxes and two to four of the 96-wide
+    ones, among the fastest tiles of those widths alone).  Times
     the batched sweep for each tile size x grid x load kind; returns the best
     dict(tile_cells, block_threads, grid_blocks, sweep_flags, us)."""
     best = None
