@@ -264,6 +264,36 @@ __global__ __launch_bounds__(256) void psm_classify_kernel(const int* __restrict
   }
 }
 
+// Exclusive prefix count of a 0/1 flag over the 256 threads of a workgroup
+// (thread order) and its total, from the waves' ballots.
+__device__ __forceinline__ int block_flag_scan256(bool f, int* sh, int* total) {
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const unsigned long long m = __ballot(f);
+  const int below = __popcll(m & ((1ull << lane) - 1ull));
+  if (lane == 0) sh[w] = __popcll(m);
+  __syncthreads();
+  int before = 0, all = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int s = sh[k];
+    before += k < w ? s : 0;
+    all += s;
+  }
+  *total = all;
+  __syncthreads();  // sh is reused by the next round
+  return before + below;
+}
+
+// The cells of a unit in rounds of 256 consecutive cells, thread t taking cell
+// c = 256 r + t of round r (coalesced reads of the slots and writes of the
+// lists); the (row, column) cursor (dy, dx) steps by 256 cells per round.
+// Every thread runs every round (the rounds hold workgroup scans); in_unit
+// says whether its cell exists.
+#define UNIT_ROUNDS(c0, ncu, y0, ext, dy, dx, in_unit)                                            \
+  for (int c0 = 0, dy = (y0) + (int)threadIdx.x / (ext), dx = (int)threadIdx.x % (ext), in_unit = 0; \
+       c0 < (ncu) && ((in_unit = c0 + (int)threadIdx.x < (ncu)), true);                            \
+       c0 += 256, dx += 256 % (ext), dy += 256 / (ext), (dx >= (ext) ? (dx -= (ext), ++dy) : 0))
+
 // Stage 1b: the cut cells of each unit, in cell order, at the unit's scanned
 // offset: slot index, particle and centre displacement.
 __global__ __launch_bounds__(256) void psm_cut_fill_kernel(const int* __restrict__ list, int side, int nsplit,
@@ -280,16 +310,13 @@ __global__ __launch_bounds__(256) void psm_cut_fill_kernel(const int* __restrict
   for (int ub = blockIdx.x; ub < side * nsplit; ub += gridDim.x) {
     const Unit U = unit_of(ub, side, nsplit);
     const int ncu = unit_cells(U, ext);
-    const int chunk = (ncu + 255) / 256;
-    const int a = min(ncu, (int)threadIdx.x * chunk), b = min(ncu, a + chunk);
-    int local = 0;
-    BBOX_FOR_CELLS(c, a, b, U.y0, ext, dy, dx) local += slots[slot_index(j, side, U.z, dy, dx)] < 0 ? 1 : 0;
-    int total;
-    int pos = offsets[j * (side * nsplit) + ub] + block_excl_scan256(local, sh, &total);
-    BBOX_FOR_CELLS(c, a, b, U.y0, ext, dy, dx) {
+    int base = offsets[j * (side * nsplit) + ub];
+    UNIT_ROUNDS(c0, ncu, U.y0, ext, dy, dx, in_unit) {
       const long long si = slot_index(j, side, U.z, dy, dx);
-      if (slots[si] >= 0) continue;
-      if (pos < cap) {
+      const bool cut = in_unit && slots[si] < 0;
+      int total;
+      const int pos = base + block_flag_scan256(cut, sh, &total);
+      if (cut && pos < cap) {
         const int i = wrap_near(lo[0] + dx, I.nx), jj = wrap_near(lo[1] + dy, I.ny), k = wrap_near(lo[2] + U.z, I.nz);
         double dc[3];
         centre_disp(I, P, p, i, jj, k, dc);
@@ -300,7 +327,7 @@ __global__ __launch_bounds__(256) void psm_cut_fill_kernel(const int* __restrict
         cuts.d[3 * pos + 1] = dc[1];
         cuts.d[3 * pos + 2] = dc[2];
       }
-      ++pos;
+      base += total;
     }
   }
 }
@@ -494,16 +521,13 @@ __global__ __launch_bounds__(256) void psm_fill_kernel(const int* __restrict__ l
   for (int ub = blockIdx.x; ub < side * nsplit; ub += gridDim.x) {
     const Unit U = unit_of(ub, side, nsplit);
     const int ncu = unit_cells(U, ext);
-    const int chunk = (ncu + 255) / 256;
-    const int a = min(ncu, (int)threadIdx.x * chunk), b = min(ncu, a + chunk);
-    int local = 0;
-    BBOX_FOR_CELLS(c, a, b, U.y0, ext, dy, dx) local += slots[slot_index(j, side, U.z, dy, dx)] > 0 ? 1 : 0;
-    int total;
-    int pos = offsets[j * (side * nsplit) + ub] + block_excl_scan256(local, sh, &total);
-    BBOX_FOR_CELLS(c, a, b, U.y0, ext, dy, dx) {
-      const int v = slots[slot_index(j, side, U.z, dy, dx)];
-      if (v <= 0) continue;
-      if (pos < cap) {
+    int base = offsets[j * (side * nsplit) + ub];
+    UNIT_ROUNDS(c0, ncu, U.y0, ext, dy, dx, in_unit) {
+      const int v = in_unit ? slots[slot_index(j, side, U.z, dy, dx)] : 0;
+      int total;
+      const int pos = base + block_flag_scan256(v > 0, sh, &total);
+      base += total;
+      if (v > 0 && pos < cap) {
         const int i = wrap_near(lo[0] + dx, I.nx), jj = wrap_near(lo[1] + dy, I.ny), k = wrap_near(lo[2] + U.z, I.nz);
         const double eps = (double)v / nn;
         pairs.cell[pos] = (k * I.ny + jj) * I.nx + i;
@@ -512,7 +536,6 @@ __global__ __launch_bounds__(256) void psm_fill_kernel(const int* __restrict__ l
         pairs.B[pos] = I.psm_b == 1 ? eps : eps * t / ((1.0 - eps) + t);
         pairs.next[pos] = -1;
       }
-      ++pos;
     }
   }
 }
